@@ -1,0 +1,103 @@
+"""Pins of the oracle's line quantities and Voigt function (CPU only).
+
+Each check compares the oracle with something other than its own formula:
+values printed in the paper, closed-form scalings, physical sum rules, and
+the Faddeeva function of scipy (the reference the paper itself used).
+"""
+import numpy as np
+import pytest
+from scipy import integrate
+from scipy.special import wofz
+
+from paper_2001_11252_amd import workloads as W
+
+
+def test_voigt_parameter_printed_values(orc):
+    # Sect. 3.4.2 prints a ~ 0.0149, 0.0047, 0.00047 for Lya at 10, 1e2, 1e4 K
+    for T, a_printed in ((10.0, 0.0149), (1e2, 0.0047), (1e4, 0.00047)):
+        a = orc.line_quantities(W.LYA, T)["a"]
+        assert abs(a / a_printed - 1) < 0.005, (T, a)
+
+
+def test_voigt_parameter_scalings(orc):
+    # a is proportional to T^-1/2 and, at fixed T, to A_ul m^1/2 lambda (Sect. 3.3.2)
+    a1 = orc.line_quantities(W.LYA, 1e2)["a"]
+    a2 = orc.line_quantities(W.LYA, 1e4)["a"]
+    assert abs(a1 / a2 - 10.0) < 1e-12
+    am = orc.line_quantities(W.MGII_2796, 1e4)["a"]
+    pred = (W.MGII_2796.A_ul / W.LYA.A_ul) * (W.MGII_2796.lambda0_A / W.LYA.lambda0_A) \
+        * np.sqrt(W.MGII_2796.mass_amu / W.LYA.mass_amu)
+    assert abs(am / a2 / pred - 1) < 1e-12
+
+
+def test_thermal_speed_and_doppler_width(orc):
+    # hydrogen at 1e4 K: v_th = 12.85 km/s; dnu_D = nu0 v_th / c
+    q = orc.line_quantities(W.LYA, 1e4)
+    assert abs(q["vth"] / 12.85e5 - 1) < 1e-3
+    assert abs(q["nu0"] * 1215.67e-8 / 2.99792458e10 - 1) < 1e-15
+    assert abs(q["dnu"] / (q["nu0"] * q["vth"] / 2.99792458e10) - 1) < 1e-14
+
+
+def test_cross_section_sum_rule(orc):
+    # integral of sigma over frequency is (pi e^2 / m_e c) f = 0.026540 f cm^2 Hz;
+    # sigma = sigma0 H(a,x) and the exact H integrates to sqrt(pi) over x
+    for ln in (W.LYA, W.MGII_2796, W.MGII_2804):
+        q = orc.line_quantities(ln, 1e3)
+        a = q["a"]
+        val, err = integrate.quad(lambda x: wofz(x + 1j * a).real, -np.inf, np.inf, limit=500,
+                                  epsabs=0, epsrel=1e-10)
+        total = q["sigma0"] * q["dnu"] * val
+        assert abs(total / (0.026540 * ln.f_lu) - 1) < 2e-4, ln.name
+
+
+def test_faddeeva_reference_against_quadrature():
+    # H(a,x) = (a/pi) int exp(-y^2)/((y-x)^2+a^2) dy  ==  Re w(x + i a)
+    for a in (1e-3, 1e-2):
+        for x in (0.0, 0.7, 2.5, 6.0):
+            f = lambda y: np.exp(-y * y) / ((y - x) ** 2 + a * a)
+            pts = [x - 50 * a, x, x + 50 * a]
+            val = 0.0
+            edges = [-np.inf, -12.0] + sorted(set(pts + [0.0])) + [12.0 + abs(x), np.inf]
+            for lo, hi in zip(edges[:-1], edges[1:]):
+                v, _ = integrate.quad(f, lo, hi, limit=400, epsabs=0, epsrel=1e-12)
+                val += v
+            H = a / np.pi * val
+            assert abs(H / wofz(x + 1j * a).real - 1) < 1e-9, (a, x)
+
+
+# maximum relative error of the production H (Tasitsiomi 2006 form) found
+# against the Faddeeva function at these a; the paper reports ~1% at Lya
+# 1e4 K, degrading with a (Sect. 3.3.2)
+ENVELOPE = {4.72e-4: 0.0123, 4.72e-3: 0.0174, 1.49e-2: 0.0214, 2.2e-2: 0.0250}
+
+
+@pytest.mark.parametrize("a", sorted(ENVELOPE))
+def test_voigt_production_accuracy(orc, a):
+    xs = np.linspace(0.0, 60.0, 12001)
+    h = np.array([orc.voigt_h(a, x) for x in xs])
+    ref = wofz(xs + 1j * a).real
+    rel = np.abs(h / ref - 1)
+    assert rel.max() <= 1.25 * ENVELOPE[a]
+    assert np.median(rel) < 1.5e-3
+    # the form is even in x
+    hm = np.array([orc.voigt_h(a, -x) for x in xs[::97]])
+    assert np.array_equal(hm, h[::97])
+
+
+def test_voigt_special_values(orc):
+    for a in (1e-4, 4.7e-4, 1e-2):
+        assert orc.voigt_h(a, 0.0) == 1.0
+        # Lorentz wing: H -> a / (sqrt(pi) x^2)
+        for x in (200.0, 1000.0):
+            assert abs(orc.voigt_h(a, x) / (a / (np.sqrt(np.pi) * x * x)) - 1) < 2e-3
+
+
+def test_voigt_derivative_matches_finite_differences(orc):
+    a = 4.7e-4
+    for x in (0.1, 0.5, 1.2, 2.0, 3.3, 7.0, 20.0, -1.7):
+        if abs(x * x - 0.855) < 1e-3:
+            continue
+        h = 1e-6 * max(1.0, abs(x))
+        fd = (orc.voigt_h(a, x + h) - orc.voigt_h(a, x - h)) / (2 * h)
+        an = orc.voigt_dhdx(a, x)
+        assert abs(an - fd) <= 1e-6 * max(abs(fd), 1e-8), (x, an, fd)

@@ -1,0 +1,133 @@
+"""Pins of the oracle's random draws (CPU only): every sampler against the
+exact density it is meant to draw from (Kolmogorov-Smirnov), closed-form
+moments, and the single-scattering frequency redistribution against
+Hummer's (1962) R_II-A function, which the paper uses as its own check
+(Sect. 3.4.1)."""
+import numpy as np
+import pytest
+from scipy import integrate, stats
+from scipy.special import wofz
+
+from paper_2001_11252_amd import workloads as W
+
+N = 100_000
+
+
+def test_uniform_stream_properties(orc):
+    r = (orc.sample_mu(400_000, "iso", seed=11) + 1.0) / 2.0
+    assert r.min() > 0.0 and r.max() < 1.0
+    counts, _ = np.histogram(r, bins=200, range=(0, 1))
+    chi2 = ((counts - len(r) / 200) ** 2 / (len(r) / 200)).sum()
+    assert stats.chi2.sf(chi2, 199) > 1e-3
+    # different packets, events and slots give unrelated values
+    u = [orc.uniform(5, pid, ev, j) for pid in range(4) for ev in range(3) for j in range(6)]
+    assert len(set(u)) == len(u)
+    # the two words of a block feed two different uniforms; lag-1 correlation
+    seq = np.array([orc.uniform(9, 3, 7, j) for j in range(20000)])
+    assert abs(np.corrcoef(seq[:-1], seq[1:])[0, 1]) < 0.03
+    # keyed by the seed
+    assert orc.uniform(1, 0, 0, 0) != orc.uniform(2, 0, 0, 0)
+
+
+def _upar_cdf(x, a):
+    """Exact CDF of f(u) ~ exp(-u^2)/(a^2+(x-u)^2) (Sect. 3.2.1) on a grid
+    that resolves both the Gaussian and the Lorentzian spike at u = x."""
+    th = np.linspace(-np.pi / 2, np.pi / 2, 200_001)[1:-1]
+    g1 = x + a * np.tan(th)
+    g2 = np.linspace(-9.0, 9.0 + abs(x), 200_001)
+    u = np.unique(np.concatenate([g1[(g1 > -9) & (g1 < 9 + abs(x))], g2]))
+    f = np.exp(-u * u) / (a * a + (x - u) ** 2)
+    c = np.concatenate([[0.0], np.cumsum(0.5 * (f[1:] + f[:-1]) * np.diff(u))])
+    return u, c / c[-1]
+
+
+@pytest.mark.parametrize("a", [4.72e-4, 4.72e-3, 1.49e-2])
+@pytest.mark.parametrize("x", [0.0, 0.5, 1.5, 2.0, 3.5, 5.0, 7.5, -2.5])
+def test_upar_rejection_matches_exact_density(orc, x, a):
+    s = orc.sample_upar(N, x, a, seed=1000 + int(10 * abs(x)))
+    grid, cdf = _upar_cdf(x, a)
+    p = stats.kstest(s, lambda v: np.interp(v, grid, cdf)).pvalue
+    assert p > 1e-3, (x, a, p)
+
+
+def test_upar_symmetry(orc):
+    for x in (0.3, 2.2, 6.0):
+        assert np.array_equal(orc.sample_upar(2000, -x, 1e-3, seed=4),
+                              -orc.sample_upar(2000, x, 1e-3, seed=4))
+
+
+def test_upar_gaussian_branch(orc):
+    # |x| >= 8: Gaussian of variance 1/2 centred at 1/x
+    for x in (8.0, 15.0, -20.0):
+        s = orc.sample_upar(N, x, 4.7e-4, seed=3)
+        assert abs(s.mean() - 1.0 / x) < 4 * np.sqrt(0.5 / N)
+        assert abs(s.var() - 0.5) < 4 * 0.5 * np.sqrt(2.0 / N)
+        assert stats.kstest(s, stats.norm(loc=1.0 / x, scale=np.sqrt(0.5)).cdf).pvalue > 1e-3
+
+
+def test_phase_function_inversions(orc):
+    core = orc.sample_mu(N, "core", seed=21)
+    wing = orc.sample_mu(N, "wing", seed=22)
+    # CDFs of P_core = 11/24 + 3 mu^2/24 and P_wing = 3(1+mu^2)/8 on [-1,1]
+    Fc = lambda m: (11 * (m + 1) + (m ** 3 + 1)) / 24.0
+    Fw = lambda m: (3 * (m + 1) + (m ** 3 + 1)) / 8.0
+    assert stats.kstest(core, Fc).pvalue > 1e-3
+    assert stats.kstest(wing, Fw).pvalue > 1e-3
+    # <mu^2> = 11/36 + 1/20 = 0.35556 (core) and 2/5 (wing); odd moments vanish
+    assert abs((core ** 2).mean() - (11 / 36 + 1 / 20)) < 4 * np.sqrt(0.09 / N)
+    assert abs((wing ** 2).mean() - 0.4) < 4 * np.sqrt(0.1 / N)
+    assert abs(core.mean()) < 4 * np.sqrt(0.36 / N)
+    assert np.all(np.abs(core) <= 1) and np.all(np.abs(wing) <= 1)
+
+
+@pytest.mark.parametrize("g", [0.73, 0.3, -0.5])
+def test_henyey_greenstein_inversion(orc, g):
+    m = orc.sample_mu(N, "hg", g=g, seed=31)
+    assert np.all(np.abs(m) <= 1 + 1e-12)
+    # exact CDF of P_HG(mu) = (1-g^2) / (2 (1+g^2-2 g mu)^{3/2})
+    F = lambda mu: (1 - g * g) / (2 * g) * (1 / np.sqrt(1 + g * g - 2 * g * mu) - 1 / (1 + g))
+    assert stats.kstest(m, F).pvalue > 1e-3
+    assert abs(m.mean() - g) < 5 * m.std() / np.sqrt(N)
+
+
+def test_isotropic(orc):
+    m = orc.sample_mu(N, "iso", seed=41)
+    assert stats.kstest(m, stats.uniform(loc=-1, scale=2).cdf).pvalue > 1e-3
+
+
+# ----------------------------------------------- frequency redistribution
+def _hummer_r2a(x, xp, a):
+    """Hummer's R_II-A (signed form), normalised over x' for fixed x:
+    R(x,x') = pi^-3/2 int_{|xbar-xlow|/2}^inf exp(-u^2) [atan((xlow+u)/a) - atan((xbar-u)/a)] du
+    with xlow = min(x,x'), xbar = max(x,x')."""
+    lo, hi = min(x, xp), max(x, xp)
+    f = lambda u: np.exp(-u * u) * (np.arctan((lo + u) / a) - np.arctan((hi - u) / a))
+    u0 = abs(hi - lo) / 2.0
+    v, _ = integrate.quad(f, u0, u0 + 8.0, limit=400, points=[abs(hi + lo) / 2.0] if abs(hi + lo) / 2.0 < u0 + 8 else None)
+    return v / np.pi ** 1.5
+
+
+@pytest.mark.parametrize("x_in", [0.0, 1.0, 2.0, 3.0, 4.0, 5.0])
+def test_single_scattering_matches_hummer_r2a(orc, x_in):
+    # T = 100 K, isotropic angular redistribution, no recoil (Fig. of Sect. 3.4.1)
+    T = 100.0
+    line = W.Line("Lya_iso", W.LYA.lambda0_A, W.LYA.A_ul, W.LYA.f_lu, W.LYA.mass_amu, 1.0, W.PHASE_ISO, 0)
+    a = orc.line_quantities(line, T)["a"]
+    n = 200_000
+    xs = orc.single_scatter(n, line, T, x_in, seed=77 + int(x_in))
+    edges = np.linspace(-6.0, 6.0 + x_in, 121)
+    counts, _ = np.histogram(xs, bins=edges)
+    phi = wofz(x_in + 1j * a).real / np.sqrt(np.pi)
+    exp = []
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        xm = np.linspace(lo, hi, 5)
+        vals = np.array([_hummer_r2a(x_in, xp, a) for xp in xm])
+        exp.append(integrate.simpson(vals, x=xm) / phi * n)
+    exp = np.array(exp)
+    sel = exp >= 20
+    z = (counts[sel] - exp[sel]) / np.sqrt(exp[sel])
+    chi2dof = (z ** 2).sum() / sel.sum()
+    assert chi2dof < 1.5, (x_in, chi2dof)
+    assert (np.abs(z) > 3).sum() <= max(2, int(0.02 * sel.sum())), (x_in, np.abs(z).max())
+    # the normalised R_II-A carries all the probability inside the window
+    assert abs(exp.sum() / n - 1) < 0.01
