@@ -375,7 +375,12 @@ void wrap_slab(const orc_problem &pb, double p[3], const double k[3]) {
  * Sect. 3.1: total opacity is the sum over lines plus dust, each line
  * evaluated at the photon frequency in the gas frame,
  * nu_cell = nu_ext / (1 + k.v/c) (the inverse of the printed frame relation
- * nu_ext = nu (1 + k.v/c)). */
+ * nu_ext = nu (1 + k.v/c)).
+ *
+ * Frequencies are carried as offsets dnu = nu - nu_ref from the reference
+ * line centre (still in Hz): an absolute frequency of ~1e15 Hz would only
+ * resolve x to ~5e-12, an offset resolves it to ~1e-15.  Every relation
+ * below is the printed one rewritten for offsets. */
 struct Problem {
   const orc_problem *pb;
   Mesh mesh;
@@ -383,7 +388,7 @@ struct Problem {
 };
 
 struct Opac {
-  double nu_cell;
+  double dnu_cell;
   double kd;
   double kl[4];
   double x[4];
@@ -391,30 +396,53 @@ struct Opac {
   double ktot;
 };
 
-void opacity(const Problem &P, int64_t c, double nu_ext, const double k[3], Opac &o) {
+void opacity(const Problem &P, int64_t c, double dnu_ext, const double k[3], Opac &o) {
   const orc_problem &pb = *P.pb;
   double vc[3] = {pb.v[3 * c], pb.v[3 * c + 1], pb.v[3 * c + 2]};
   double beta = dot3(k, vc) / C_LIGHT;
-  o.nu_cell = nu_ext / (1.0 + beta);
+  o.dnu_cell = (dnu_ext - P.nu_ref * beta) / (1.0 + beta);
   o.kd = pb.kappa_d[c];
   o.ktot = o.kd;
   for (int i = 0; i < pb.n_lines; ++i) {
     o.q[i] = line_q(pb.lines[i], pb.T[c]);
-    o.x[i] = (o.nu_cell - o.q[i].nu0) / o.q[i].dnu;
+    o.x[i] = (o.dnu_cell - (o.q[i].nu0 - P.nu_ref)) / o.q[i].dnu;
     o.kl[i] = pb.n_hi[c] * pb.lines[i].abundance * o.q[i].sigma0 * voigt_h(o.q[i].a, o.x[i]);
     o.ktot += o.kl[i];
   }
 }
 
-double nu_from_x(const Problem &P, double x) { return P.nu_ref + x * P.dnu_ref; }
-double x_from_nu(const Problem &P, double nu) { return (nu - P.nu_ref) / P.dnu_ref; }
+double dnu_from_x(const Problem &P, double x) { return x * P.dnu_ref; }
+double x_from_dnu(const Problem &P, double dnu) { return dnu / P.dnu_ref; }
+
+/* external-frame offset of a packet with cell-frame offset dnu_cell moving
+ * along k through gas of velocity vc: nu_ext = nu_cell (1 + k.v/c) */
+double to_external(const Problem &P, double dnu_cell, const double k[3], const double vc[3]) {
+  double beta = dot3(k, vc) / C_LIGHT;
+  return dnu_cell + (P.nu_ref + dnu_cell) * beta;
+}
+
+/* Eq. for nu_out (Sect. 3.2.1): coherent in the atom frame,
+ * nu_out = nu_in [1 + (k_out - k_in).v_X/c] / [1 + (1-mu) h nu_in/(m_X c^2)],
+ * the denominator being recoil; returned as an offset from nu_ref. */
+double scatter_dnu(const Problem &P, double dnu_in, const double kin[3], const double kout[3],
+                   const double vatom[3], const orc_line &ln) {
+  double nu_in = P.nu_ref + dnu_in;
+  double dk[3] = {kout[0] - kin[0], kout[1] - kin[1], kout[2] - kin[2]};
+  double shift = nu_in * dot3(dk, vatom) / C_LIGHT;
+  double R = 0.0;
+  if (ln.recoil) {
+    double mu = dot3(kin, kout);
+    R = (1.0 - mu) * H_PLANCK * nu_in / (ln.mass_amu * AMU_G * C_LIGHT * C_LIGHT);
+  }
+  return (dnu_in + shift - P.nu_ref * R) / (1.0 + R);
+}
 
 /* --------------------------------------------------------- ray casting
  * Optical depth from p along k to the domain border at a fixed external
  * frequency (the peel-off integral and the tau probe).  Every visited
  * leaf adds kappa * l * box.  `visit` receives (leaf, segment, Opac). */
 template <class F>
-double ray_tau(const Problem &P, const double p0[3], const double k[3], double nu_ext,
+double ray_tau(const Problem &P, const double p0[3], const double k[3], double dnu_ext,
                int64_t *ncross, F visit) {
   const orc_problem &pb = *P.pb;
   double p[3] = {p0[0], p0[1], p0[2]};
@@ -422,7 +450,7 @@ double ray_tau(const Problem &P, const double p0[3], const double k[3], double n
   double tau = 0.0;
   Opac o;
   while (c >= 0) {
-    opacity(P, c, nu_ext, k, o);
+    opacity(P, c, dnu_ext, k, o);
     double pn[3];
     double te = exit_step(P.mesh, c, p, k, pn);
     double tdom = domain_dist(pb, p, k);
@@ -491,39 +519,35 @@ struct ThreadOut {
  * domain border at the frequency the packet would have after scattering
  * into k_o. */
 void peel_deposit(const Problem &P, int n_obs, const orc_observer *obs, ThreadOut &to,
-                  const double p[3], int kind, const double kin[3], double nu_in_cell,
+                  const double p[3], int kind, const double kin[3], double dnu_in_cell,
                   const double vatom[3], const orc_line *ln, int core, const double vcell[3],
-                  double nu_ext_emit) {
+                  double dnu_ext_emit) {
   const orc_problem &pb = *P.pb;
   for (int o = 0; o < n_obs; ++o) {
     const orc_observer &ob = obs[o];
     const double *ko = ob.k;
-    double weight, nu_ext_o;
+    double weight, dnu_ext_o;
     if (kind == 0) { /* emission */
       weight = 1.0 / (4.0 * PI);
-      nu_ext_o = nu_ext_emit;
-    } else if (kind == 1) { /* line scattering */
+      dnu_ext_o = dnu_ext_emit;
+    } else if (kind == 1) { /* line scattering, same atom velocity */
       double mu = dot3(kin, ko);
       double P_ = (ln->phase == ORC_PHASE_ISO) ? 0.5 : (core ? p_core(mu) : p_wing(mu));
       weight = P_ / (2.0 * PI);
-      double dk[3] = {ko[0] - kin[0], ko[1] - kin[1], ko[2] - kin[2]};
-      double num = 1.0 + dot3(dk, vatom) / C_LIGHT;
-      double den = 1.0;
-      if (ln->recoil) den = 1.0 + (1.0 - mu) * H_PLANCK * nu_in_cell / (ln->mass_amu * AMU_G * C_LIGHT * C_LIGHT);
-      double nu_out = nu_in_cell * num / den;
-      nu_ext_o = nu_out * (1.0 + dot3(ko, vcell) / C_LIGHT);
+      double dnu_out = scatter_dnu(P, dnu_in_cell, kin, ko, vatom, *ln);
+      dnu_ext_o = to_external(P, dnu_out, ko, vcell);
     } else { /* dust scattering: coherent in the cell frame */
       double mu = dot3(kin, ko);
       weight = p_hg(mu, pb.g_hg) / (2.0 * PI);
-      nu_ext_o = nu_in_cell * (1.0 + dot3(ko, vcell) / C_LIGHT);
+      dnu_ext_o = to_external(P, dnu_in_cell, ko, vcell);
     }
     int64_t nc = 0;
-    double tau = ray_tau(P, p, ko, nu_ext_o, &nc, [](int64_t, double, const Opac &) {});
+    double tau = ray_tau(P, p, ko, dnu_ext_o, &nc, [](int64_t, double, const Opac &) {});
     to.st.peel_rays += 1;
     to.st.peel_crossings += nc;
     double w = weight * std::exp(-tau);
     int64_t pix = pixel_of(ob, p);
-    int64_t b = bin_of(ob, x_from_nu(P, nu_ext_o));
+    int64_t b = bin_of(ob, x_from_dnu(P, dnu_ext_o));
     if (pix < 0 || b < 0) { to.st.peel_dropped += 1; continue; }
     to.cubes[o][(size_t)pix * ob.nbins + b] += w;
   }
@@ -555,14 +579,14 @@ void transport_packet(const Problem &P, uint64_t seed, uint64_t pid, const doubl
     double s = std::sqrt(1.0 - mu * mu);
     k[0] = s * std::cos(phi); k[1] = s * std::sin(phi); k[2] = mu;
   }
-  double nu_ext = nu_from_x(P, src_x);
+  double dnu_ext = dnu_from_x(P, src_x);
   double tau_ev = -std::log(rng.u(J_TAU));
   double path = 0.0;
   int32_t nscat = 0;
   to.st.emitted += 1;
   {
     double zero[3] = {0.0, 0.0, 0.0};
-    peel_deposit(P, n_obs, obs, to, p, 0, k, 0.0, zero, nullptr, 0, zero, nu_ext);
+    peel_deposit(P, n_obs, obs, to, p, 0, k, 0.0, zero, nullptr, 0, zero, dnu_ext);
   }
   int64_t c = locate(P.mesh, p, k);
   uint32_t event = 0;
@@ -573,7 +597,7 @@ void transport_packet(const Problem &P, uint64_t seed, uint64_t pid, const doubl
       out.status = ORC_ST_ESCAPED;
       break;
     }
-    opacity(P, c, nu_ext, k, o);
+    opacity(P, c, dnu_ext, k, o);
     double pn[3];
     double te = exit_step(P.mesh, c, p, k, pn);
     double tdom = domain_dist(pb, p, k);
@@ -610,7 +634,7 @@ void transport_packet(const Problem &P, uint64_t seed, uint64_t pid, const doubl
         to.st.dust_scatterings += 1;
         double kin[3] = {k[0], k[1], k[2]};
         double zero[3] = {0.0, 0.0, 0.0};
-        peel_deposit(P, n_obs, obs, to, p, 2, kin, o.nu_cell, zero, nullptr, 0, vc, 0.0);
+        peel_deposit(P, n_obs, obs, to, p, 2, kin, o.dnu_cell, zero, nullptr, 0, vc, 0.0);
         if (!pb.forward_only) {
           double mu = mu_hg(rng.u(J_MU), pb.g_hg);
           double phi = 2.0 * PI * rng.u(J_PHI);
@@ -619,7 +643,7 @@ void transport_packet(const Problem &P, uint64_t seed, uint64_t pid, const doubl
           double s = std::sqrt(std::max(0.0, 1.0 - mu * mu));
           for (int d = 0; d < 3; ++d)
             k[d] = mu * kin[d] + s * (std::cos(phi) * e1[d] + std::sin(phi) * e2[d]);
-          nu_ext = o.nu_cell * (1.0 + dot3(k, vc) / C_LIGHT);
+          dnu_ext = to_external(P, o.dnu_cell, k, vc);
         }
       } else {
         /* resonant scattering in line i (Sect. 3.2.1) */
@@ -628,7 +652,7 @@ void transport_packet(const Problem &P, uint64_t seed, uint64_t pid, const doubl
         while (i < pb.n_lines - 1 && r >= o.kl[i]) { r -= o.kl[i]; ++i; }
         const orc_line &ln = pb.lines[i];
         const LineQ &q = o.q[i];
-        double nu_in = o.nu_cell;
+        double dnu_in = o.dnu_cell;
         double x_in = o.x[i];
         double upar;
         if (!sample_upar(x_in, q.a, rng, &upar)) { out.status = ORC_ST_STUCK; break; }
@@ -641,12 +665,12 @@ void transport_packet(const Problem &P, uint64_t seed, uint64_t pid, const doubl
         double vatom[3];
         for (int d = 0; d < 3; ++d) vatom[d] = (upar * kin[d] + up1 * e1[d] + up2 * e2[d]) * q.vth;
         /* core or wing, from the frequency seen by the atom,
-         * nu_scat,in = nu_in (1 - k_in . v_X / c), within 0.2 dnu_D */
-        double nu_scat = nu_in * (1.0 - dot3(kin, vatom) / C_LIGHT);
-        int core = std::fabs(nu_scat - q.nu0) < 0.2 * q.dnu;
+         * nu_scat,in = nu_in (1 - k_in . v_X / c), within 0.2 dnu_D of nu_lu */
+        double off = (dnu_in - (q.nu0 - P.nu_ref)) - (P.nu_ref + dnu_in) * dot3(kin, vatom) / C_LIGHT;
+        int core = std::fabs(off) < 0.2 * q.dnu;
         nscat += 1;
         to.st.scatterings += 1;
-        peel_deposit(P, n_obs, obs, to, p, 1, kin, nu_in, vatom, &ln, core, vc, 0.0);
+        peel_deposit(P, n_obs, obs, to, p, 1, kin, dnu_in, vatom, &ln, core, vc, 0.0);
         if (!pb.forward_only) {
           double ru = rng.u(J_MU);
           double mu = (ln.phase == ORC_PHASE_ISO) ? 2.0 * ru - 1.0 : (core ? mu_core(ru) : mu_wing(ru));
@@ -654,14 +678,8 @@ void transport_packet(const Problem &P, uint64_t seed, uint64_t pid, const doubl
           double s = std::sqrt(std::max(0.0, 1.0 - mu * mu));
           for (int d = 0; d < 3; ++d)
             k[d] = mu * kin[d] + s * (std::cos(phi) * e1[d] + std::sin(phi) * e2[d]);
-          /* Eq. for nu_out: coherent in the atom frame, recoil in the
-           * denominator */
-          double dk[3] = {k[0] - kin[0], k[1] - kin[1], k[2] - kin[2]};
-          double num = 1.0 + dot3(dk, vatom) / C_LIGHT;
-          double den = 1.0;
-          if (ln.recoil) den = 1.0 + (1.0 - mu) * H_PLANCK * nu_in / (ln.mass_amu * AMU_G * C_LIGHT * C_LIGHT);
-          double nu_out = nu_in * num / den;
-          nu_ext = nu_out * (1.0 + dot3(k, vc) / C_LIGHT);
+          double dnu_out = scatter_dnu(P, dnu_in, kin, k, vatom, ln);
+          dnu_ext = to_external(P, dnu_out, k, vc);
         }
       }
       tau_ev = -std::log(rng.u(J_TAU));
@@ -682,7 +700,7 @@ void transport_packet(const Problem &P, uint64_t seed, uint64_t pid, const doubl
   if (out.status == ORC_ST_ESCAPED) to.st.escaped += 1;
   else if (out.status == ORC_ST_ABSORBED) to.st.absorbed += 1;
   else to.st.stuck += 1;
-  out.x = x_from_nu(P, nu_ext);
+  out.x = x_from_dnu(P, dnu_ext);
   for (int d = 0; d < 3; ++d) { out.k[d] = k[d]; out.pos[d] = p[d]; }
   out.path = path;
   out.nscat = nscat;
@@ -759,7 +777,11 @@ void orc_sample_mu(int64_t n, int kind, double g, uint64_t seed, double *out) {
 void orc_single_scatter(int64_t n, const orc_line *ln, double T, double x_in, uint64_t seed,
                         double *x_out) {
   LineQ q = line_q(*ln, T);
-  double nu_in = q.nu0 + x_in * q.dnu;
+  Problem P;
+  P.pb = nullptr;
+  P.nu_ref = q.nu0;
+  P.dnu_ref = q.dnu;
+  double dnu_in = x_in * q.dnu;
   for (int64_t i = 0; i < n; ++i) {
     Rng rng{seed, (uint64_t)i, 1};
     /* incoming direction drawn isotropically so the pinned basis is
@@ -777,20 +799,15 @@ void orc_single_scatter(int64_t n, const orc_line *ln, double T, double x_in, ui
     perp_basis(kin, e1, e2);
     double vatom[3];
     for (int d = 0; d < 3; ++d) vatom[d] = (upar * kin[d] + up1 * e1[d] + up2 * e2[d]) * q.vth;
-    double nu_scat = nu_in * (1.0 - dot3(kin, vatom) / C_LIGHT);
-    int core = std::fabs(nu_scat - q.nu0) < 0.2 * q.dnu;
+    double off = dnu_in - (q.nu0 + dnu_in) * dot3(kin, vatom) / C_LIGHT;
+    int core = std::fabs(off) < 0.2 * q.dnu;
     double ru = rng.u(J_MU);
     double mu = (ln->phase == ORC_PHASE_ISO) ? 2.0 * ru - 1.0 : (core ? mu_core(ru) : mu_wing(ru));
     double phi = 2.0 * PI * rng.u(J_PHI);
     double s = std::sqrt(std::max(0.0, 1.0 - mu * mu));
     double k[3];
     for (int d = 0; d < 3; ++d) k[d] = mu * kin[d] + s * (std::cos(phi) * e1[d] + std::sin(phi) * e2[d]);
-    double dk[3] = {k[0] - kin[0], k[1] - kin[1], k[2] - kin[2]};
-    double num = 1.0 + dot3(dk, vatom) / C_LIGHT;
-    double den = 1.0;
-    if (ln->recoil) den = 1.0 + (1.0 - mu) * H_PLANCK * nu_in / (ln->mass_amu * AMU_G * C_LIGHT * C_LIGHT);
-    double nu_out = nu_in * num / den;
-    x_out[i] = (nu_out - q.nu0) / q.dnu;
+    x_out[i] = scatter_dnu(P, dnu_in, kin, k, vatom, *ln) / q.dnu;
   }
 }
 
@@ -879,7 +896,7 @@ int orc_tau(const orc_problem *pb, int64_t n, const double *orig, const double *
   if (rc) return rc;
   for (int64_t r = 0; r < n; ++r) {
     int64_t nc = 0;
-    tau_out[r] = ray_tau(P, orig + 3 * r, dir + 3 * r, nu_from_x(P, x_ext[r]), &nc,
+    tau_out[r] = ray_tau(P, orig + 3 * r, dir + 3 * r, dnu_from_x(P, x_ext[r]), &nc,
                          [](int64_t, double, const Opac &) {});
   }
   return 0;
@@ -958,10 +975,10 @@ int orc_raycast_image(const orc_problem *pb, const orc_observer *ob, int64_t n_r
       if (r >= n_rays) break;
       const double *p = orig + 3 * r;
       pix[r] = pixel_of(*ob, p);
-      double nu = nu_from_x(P, x_ext[r]);
+      double dnu = dnu_from_x(P, x_ext[r]);
       int64_t nc = 0;
       std::vector<std::pair<int64_t, double>> cross;
-      tau[r] = ray_tau(P, p, ob->k, nu, &nc, [&](int64_t c, double seg, const Opac &) {
+      tau[r] = ray_tau(P, p, ob->k, dnu, &nc, [&](int64_t c, double seg, const Opac &) {
         cross.emplace_back(c, seg);
       });
       if (!grad_image || pix[r] < 0) continue;
@@ -972,15 +989,17 @@ int orc_raycast_image(const orc_problem *pb, const orc_observer *ob, int64_t n_r
         int64_t c = cs.first;
         double l = cs.second * pb->box_cm;
         Opac o;
-        opacity(P, c, nu, ob->k, o);
+        opacity(P, c, dnu, ob->k, o);
         double vc[3] = {pb->v[3 * c], pb->v[3 * c + 1], pb->v[3 * c + 2]};
         double beta = dot3(ob->k, vc) / C_LIGHT;
         double dn = 0.0, dv = 0.0;
         for (int i = 0; i < pb->n_lines; ++i) {
           double ab = pb->lines[i].abundance;
           dn += ab * o.q[i].sigma0 * voigt_h(o.q[i].a, o.x[i]);
-          /* x = (nu/(1+beta) - nu0)/dnu  =>  dx/dv_los = -nu/(c (1+beta)^2 dnu) */
-          double dxdv = -nu / (C_LIGHT * (1.0 + beta) * (1.0 + beta) * o.q[i].dnu);
+          /* x = (nu_ext/(1+beta) - nu0)/dnu_D  =>
+           * dx/dv_los = -nu_ext / (c (1+beta)^2 dnu_D) */
+          double nu_ext = P.nu_ref + dnu;
+          double dxdv = -nu_ext / (C_LIGHT * (1.0 + beta) * (1.0 + beta) * o.q[i].dnu);
           dv += pb->n_hi[c] * ab * o.q[i].sigma0 * voigt_dhdx(o.q[i].a, o.x[i]) * dxdv;
         }
         recs[r].push_back(Rec{c, g * l * dn, g * l, g * l * dv});
