@@ -1,0 +1,152 @@
+"""Throughput benchmark: Monte Carlo Lya transfer through a dusty sphere.
+
+Workload (the configuration the metric is quoted on): static uniform HI
+sphere, tau0 = 1e6 at line centre along the radius, T = 1e4 K, dust with
+tau_dust = 1 (albedo 0.32, g = 0.73), octree refined from level 3 to 7
+toward the centre (287,064 leaves), packets emitted at x = 0 from the
+centre, one observer along +z with a 128x128x100 peel-off cube.  A step is
+one transport launch over a fresh range of packets (emission, propagation,
+scattering, dust, peel-off of every event, termination); the FP32 bulk path
+is the headline, the FP64 path runs beside it on the same packets.
+
+Prints one JSON line.  Inputs are synthetic and seeded.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic floating-point work per unit, counted from the formulas of
+# the transport step (one elementary function, division or square root
+# counted as 8 operations):
+#   one line scattering, including building its peel-off source: 480
+#   one ray-cell segment (opacity of the leaf + exit geometry):    110
+FLOP_PER_SCATTERING = 480.0
+FLOP_PER_CROSSING = 110.0
+# Algorithmic HBM bytes: one leaf record per segment (24 B float, 48 B
+# double) plus one 4 B node entry.
+BYTES_PER_CROSSING = {"fp32": 28.0, "fp64": 52.0}
+PEAK = {"fp32": 157.3, "fp64": 78.6}       # TFLOP/s, MI355X vector
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--packets", type=int, default=65536, help="packets per step")
+    ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--tau0", type=float, default=1e6)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-packets", type=int, default=0, help="oracle packets (0: one per core)")
+    ap.add_argument("--only", choices=["fp32", "fp64", "both"], default="both")
+    return ap.parse_args()
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported "
+              "(packets shard by range across GPUs with one sum-reduction of the cubes; not built here)",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2001_11252_amd import rmc, workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    steps, warm, P = a.steps, a.warmup, a.packets
+    n_total = max(1_000_000, (warm + max(steps, a.fp64_steps) + 1) * P)
+    pb = W.c2_dusty_sphere(rmc.sigma0, n_packets=n_total, tau0=a.tau0)
+    print(f"# workload: {pb.mesh.n} leaves, n_HI={pb.meta['n_hi']:.4e}, {P} packets/step", file=sys.stderr, flush=True)
+
+    def measure(prec, nsteps):
+        ctx = rmc.Context.from_problem(pb, prec)
+        ctx.set_stream(torch.cuda.current_stream())
+        first = 0
+        for _ in range(warm):
+            ctx.run(pb.seed, first, P)
+            first += P
+        torch.cuda.synchronize()
+        tot = {}
+        kms = []
+        t0 = time.perf_counter()
+        for _ in range(nsteps):
+            st = ctx.run(pb.seed, first, P)
+            first += P
+            kms.append(st["kernel_ms"])
+            for k, v in st.items():
+                tot[k] = tot.get(k, 0) + v
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        print(f"# {prec}: {nsteps} steps in {wall:.3f} s, kernel ms {kms}, stats {tot}", file=sys.stderr, flush=True)
+        return wall, tot, kms
+
+    res = {}
+    if a.only in ("fp32", "both"):
+        res["fp32"] = measure("fp32", steps)
+    if a.only in ("fp64", "both"):
+        res["fp64"] = measure("fp64", a.fp64_steps if a.only == "both" else steps)
+    head = "fp32" if "fp32" in res else "fp64"
+    wall, tot, kms = res[head]
+    nsteps = len(kms)
+    scat_s = tot["scatterings"] / wall
+    cross = tot["crossings"] + tot["peel_crossings"]
+    cross_s = cross / wall
+    # roofline of the dominant kernel (the transport launch): algorithmic
+    # work per launch over its average device duration
+    avg_ms = sum(kms) / nsteps
+    flops_per_launch = (FLOP_PER_SCATTERING * tot["scatterings"] + FLOP_PER_CROSSING * cross) / nsteps
+    achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
+    side = {}
+    for prec, (w, t, k) in res.items():
+        side[prec] = {"scatterings_per_s": t["scatterings"] / w,
+                      "crossings_per_s": (t["crossings"] + t["peel_crossings"]) / w,
+                      "ms_per_step": 1e3 * w / len(k),
+                      "kernel_ms_avg": sum(k) / len(k),
+                      "hbm_GBps_algorithmic": (t["crossings"] + t["peel_crossings"]) * BYTES_PER_CROSSING[prec]
+                      / (sum(k) * 1e-3) / 1e9,
+                      "escaped_fraction": t["escaped"] / max(1, t["emitted"]),
+                      "scatterings_per_packet": t["scatterings"] / max(1, t["emitted"])}
+    line = {
+        "metric": "scatterings/s + ray-cell crossings/s (1 GPU), FP32 vs FP64 at matched spectra",
+        "value": scat_s,
+        "unit": "scatterings/s",
+        "crossings_per_s": cross_s,
+        "n_gpus": 1,
+        "steps": nsteps,
+        "warmup": warm,
+        "ms_per_step": 1e3 * wall / nsteps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if head == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "dusty_sphere_tau1e6_T1e4_287k_leaves_peel_128x128x100",
+                   "tau0": a.tau0, "packets_per_step": P, "leaves": int(pb.mesh.n),
+                   "observer": "+z 128x128x100", "parallelism": "none"},
+        "precisions": side,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK[head], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK[head], "traffic": None,
+                     "kernel": "k_transport<float,false>" if head == "fp32" else "k_transport<double,false>"},
+    }
+    if not a.no_cpu_baseline:
+        from oracle import oracle as O
+        cores = max(1, min(16, os.cpu_count() or 1))
+        n_cpu = a.cpu_packets or cores
+        t0 = time.perf_counter()
+        r = O.run(pb, pb.seed, first=0, n=n_cpu, threads=cores)
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": r["stats"]["scatterings"] / dt, "unit": "scatterings/s", "cores": cores,
+                                "kind": "oracle",
+                                "sample": f"{n_cpu} packets of the same workload (FP64 oracle, full peel-off rays), "
+                                          f"{r['stats']['scatterings']} scatterings in {dt:.1f} s"}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

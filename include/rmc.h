@@ -1,0 +1,208 @@
+/*
+ * rmc.h -- C ABI of librmc: Monte Carlo resonant-line radiative transfer on
+ * an adaptive octree, on AMD MI355X (gfx950).
+ *
+ * Method: Michel-Dansac et al. 2020, "RASCAS: RAdiation SCattering in
+ * Astrophysical Simulations" (A&A 635, A154).  The library runs the
+ * per-photon-packet propagation loop of the paper on one GPU: leaf location
+ * and ray-cell traversal (Sect. 4.3), optical depth to the next event
+ * (Sect. 3), line opacity with the Voigt profile (Sect. 3.1.1, 3.3.2) and
+ * dust opacity (Sect. 3.1.2), the choice of interaction (Sect. 3.2),
+ * resonant scattering with the parallel-velocity sampler, core/wing or
+ * isotropic phase functions and recoil (Sect. 3.2.1, 3.3.1, 3.3.3), dust
+ * absorption or Henyey-Greenstein scattering (Sect. 3.2.2) and peel-off of
+ * each emission and scattering toward observers (Sect. 5.1).
+ *
+ * Conventions (all calls):
+ *  - Every call returns an rmc_status; nothing throws across the ABI.  On
+ *    failure rmc_last_error() gives a message owned by the context, valid
+ *    until the next call on it.
+ *  - The caller owns every buffer it passes.  Setters copy what they are
+ *    given (host -> device) and keep no pointer.  Buffers flagged
+ *    RMC_DEVICE are device pointers on the context's device; work on them
+ *    is ordered on the context's stream (rmc_set_stream), and calls return
+ *    once that work is complete.
+ *  - Positions are in box units: the octree spans [0,1)^3 and the box has
+ *    physical side box_cm.  Densities cm^-3, temperatures K, velocities
+ *    cm/s, dust opacity cm^-1.
+ *  - Packet frequencies are x_ext: external-frame offset from the rest
+ *    frequency of the first line, in Doppler widths of that line at the
+ *    reference temperature T_ref given to rmc_set_lines.
+ *  - A context is thread-compatible, not thread-safe.
+ */
+#ifndef RMC_H
+#define RMC_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rmc_ctx rmc_ctx;
+
+typedef enum {
+  RMC_OK = 0,
+  RMC_EINVAL = -1,       /* bad argument, NaN or negative physical input   */
+  RMC_ENOMEM = -2,       /* device or host allocation failed               */
+  RMC_EDEVICE = -3,      /* HIP runtime or kernel launch error             */
+  RMC_EMESH = -4,        /* leaves overlap, leave a gap, or are not 2:1    */
+  RMC_ESTATE = -5,       /* call made before the inputs it needs           */
+  RMC_EUNSUPPORTED = -6  /* valid request the library does not handle      */
+} rmc_status;
+
+enum { RMC_FP64 = 0, RMC_FP32_BULK = 1 };          /* context precision        */
+enum { RMC_HOST = 0, RMC_DEVICE = 1 };             /* where a buffer lives     */
+enum { RMC_F32 = 0, RMC_F64 = 1 };                 /* element type of outputs  */
+enum { RMC_DOM_BOX = 0, RMC_DOM_SLAB_Z = 1, RMC_DOM_SPHERE = 2 };
+enum { RMC_PHASE_LYA_DIPOLE = 0, RMC_PHASE_ISOTROPIC = 1 };
+enum { RMC_ST_NONE = 0, RMC_ST_ESCAPED = 1, RMC_ST_ABSORBED = 2, RMC_ST_STUCK = 3 };
+enum {
+  RMC_OPT_FORWARD_ONLY = 1,  /* 1: scatterings keep direction and frequency
+                                (the precision test of Sect. 4.5)            */
+  RMC_OPT_MAX_EVENTS = 2,    /* >0: a packet stops, status STUCK, at its
+                                max_events-th interaction (0: no limit)     */
+  RMC_OPT_BLOCK = 3,         /* threads per block of the transport kernel    */
+  RMC_OPT_WAVES_PER_CU = 4,  /* resident waves per CU the grid is sized for  */
+  RMC_OPT_REFILL = 5,        /* idle lanes a wave gathers before it takes new
+                                packets (1..64)                              */
+  RMC_OPT_PEEL_DEFER = 6     /* 1: peel-off rays go through a queue to a
+                                separate ray-cast kernel                     */
+};
+
+/* One transition (Table 1 of the paper). */
+typedef struct {
+  double lambda0_A;   /* vacuum rest wavelength, Angstrom                   */
+  double A_ul;        /* Einstein coefficient, s^-1                         */
+  double f_lu;        /* oscillator strength                                */
+  double mass_amu;    /* mass of the scatterer                              */
+  double abundance;   /* scatterer density / n_HI                           */
+  int phase;          /* RMC_PHASE_LYA_DIPOLE (core/wing) or ISOTROPIC      */
+  int recoil;         /* 1: recoil term of the outgoing-frequency relation  */
+} rmc_line;
+
+typedef struct {
+  uint64_t emitted, escaped, absorbed, stuck;
+  uint64_t scatterings;       /* line scatterings                            */
+  uint64_t dust_scatterings;
+  uint64_t crossings;         /* transport ray-cell segments run to their end */
+  uint64_t peel_rays;
+  uint64_t peel_crossings;    /* ray-cell segments of peel-off rays           */
+  uint64_t peel_dropped;      /* peel-off deposits outside a cube             */
+  double kernel_ms;           /* device time of the transport launch(es)      */
+} rmc_run_stats;
+
+/* ------------------------------------------------------------- lifetime */
+/* Create a context on HIP device `device`; precision RMC_FP64 (all
+ * physics in double) or RMC_FP32_BULK (frequency, direction and cross-
+ * section work in float; position, path length and optical depths double). */
+rmc_status rmc_create(rmc_ctx **out, int device, int precision);
+void rmc_destroy(rmc_ctx *ctx);
+const char *rmc_last_error(const rmc_ctx *ctx);
+/* Stream for all device work of this context (a hipStream_t; NULL = the
+ * null stream).  The stream must outlive its use by the context. */
+rmc_status rmc_set_stream(rmc_ctx *ctx, void *hip_stream);
+rmc_status rmc_set_option(rmc_ctx *ctx, int option, int64_t value);
+
+/* ---------------------------------------------------------------- inputs */
+/* Leaves of a graded octree (Sect. 4.3): level[n] in [0,16], ijk[3n] the
+ * integer coordinates of each leaf at its own level.  Host arrays.  The
+ * leaves must tile the unit cube without overlap and face neighbours may
+ * differ by at most one level, else RMC_EMESH.  Builds the breadth-first
+ * node array on the host and uploads it. */
+rmc_status rmc_set_mesh(rmc_ctx *ctx, int64_t n_leaves, const int8_t *level,
+                        const int32_t *ijk, double box_cm);
+/* Per-leaf gas (host arrays of n_leaves, v is [3n]): n_HI, T, bulk
+ * velocity, dust opacity kappa_d (Sect. 3.1.2 tau_dust = int kappa_d dl).
+ * Needs the mesh and the lines.  Non-finite or negative values: RMC_EINVAL. */
+rmc_status rmc_set_gas(rmc_ctx *ctx, const double *n_hi, const double *T_K,
+                       const double *v_cms, const double *kappa_d);
+/* Up to 4 lines; line 0 and T_ref define the x_ext unit. */
+rmc_status rmc_set_lines(rmc_ctx *ctx, int n_lines, const rmc_line *lines, double T_ref);
+/* Dust albedo (probability of scattering at a dust interaction) and HG
+ * asymmetry g (Sect. 3.2.2; defaults 0.32 and 0.73). */
+rmc_status rmc_set_dust(rmc_ctx *ctx, double albedo, double g_hg);
+/* Computational domain (Sect. 4): BOX = the unit cube; SLAB_Z: params
+ * (zc, half_z), periodic in x and y; SPHERE: (cx, cy, cz, R) inside the
+ * unit cube. */
+rmc_status rmc_set_domain(rmc_ctx *ctx, int kind, const double params[4]);
+/* Packet initial conditions (the paper's PPIC lists, Sect. 2): pos[3n],
+ * dir[3n] unit vectors or NULL for isotropic emission, x_ext[n].  Packet i
+ * is identified by its index i, which keys its random numbers. */
+rmc_status rmc_set_sources(rmc_ctx *ctx, int64_t n, const double *pos, const double *dir,
+                           const double *x_ext, int mem);
+/* Peel-off observer (Sect. 5.1): direction k_obs (unit), image nx by ny
+ * over fov = (u0,u1,v0,v1) in box units relative to the box centre along
+ * e1 = normalize(z x k) (x if k is along z) and e2 = k x e1, and nbins
+ * spectral bins over [x_min, x_max).  The cube is [ny][nx][nbins], per
+ * steradian per emitted packet, accumulated over runs until reset. */
+rmc_status rmc_add_observer(rmc_ctx *ctx, const double k_obs[3], int nx, int ny, int nbins,
+                            const double fov[4], double x_min, double x_max, int *id);
+rmc_status rmc_reset_cubes(rmc_ctx *ctx);
+
+/* ------------------------------------------------------------- transport */
+/* Propagate packets [first, first+n) of the sources until each escapes,
+ * is absorbed or stops at the event limit.  `seed` keys the counter-based
+ * generator, so any split of a packet range gives the same packets. */
+rmc_status rmc_run(rmc_ctx *ctx, uint64_t seed, int64_t first, int64_t n,
+                   rmc_run_stats *stats);
+/* Per-packet results of the last run (any pointer may be NULL): status,
+ * escaped x_ext, final direction k[3n], final position pos[3n], line
+ * scattering count, path length in box units. */
+rmc_status rmc_get_packets(rmc_ctx *ctx, int32_t *status, double *x_out, double *k_out,
+                           double *pos_out, int32_t *n_scat, double *path_out, int mem);
+/* Histogram (counts) of x_ext of the escaped packets of the last run. */
+rmc_status rmc_get_spectrum(rmc_ctx *ctx, int nbins, double x_min, double x_max, double *hist,
+                            int mem);
+/* Peel-off cube of observer `id`, [ny][nx][nbins], as RMC_F32 or RMC_F64. */
+rmc_status rmc_get_cube(rmc_ctx *ctx, int id, void *out, int dtype, int mem);
+
+/* --------------------------------------------------- deterministic probes */
+/* Leaves crossed by rays from orig[3n] along dir[3n] (unit) up to the
+ * domain border: leaf_out[n*max_cells], seg_out[n*max_cells] (box units),
+ * n_out[n].  Traversal rule: a point on a face belongs to the leaf the ray
+ * enters; the exit axes are snapped onto the face. */
+rmc_status rmc_trace_cells(rmc_ctx *ctx, int64_t n, const double *orig, const double *dir,
+                           int32_t max_cells, int32_t *leaf_out, double *seg_out, int32_t *n_out,
+                           int mem);
+/* Optical depth from orig along dir to the domain border at external
+ * frequency x_ext (no events). */
+rmc_status rmc_tau(rmc_ctx *ctx, int64_t n, const double *orig, const double *dir,
+                   const double *x_ext, double *tau_out, int mem);
+
+/* ---------------------------------------- peel-off image and its adjoint */
+/* Image (ny*nx, frequency-integrated over the observer's spectral range) of
+ * fixed rays toward observer `id`: image[p] = sum_r w_r exp(-tau_r) for the
+ * rays whose origin projects onto pixel p. */
+rmc_status rmc_raycast_image(rmc_ctx *ctx, int id, int64_t n_rays, const double *orig,
+                             const double *x_ext, const double *w, double *image, int mem);
+/* Gradient of L = sum_p grad_image[p] image[p] with respect to per-leaf
+ * n_HI, kappa_d and v_los = k_obs . v (cm/s), by replaying each ray:
+ * outputs g_nhi, g_kd, g_vlos [n_leaves], overwritten. */
+rmc_status rmc_raycast_image_backward(rmc_ctx *ctx, int id, int64_t n_rays, const double *orig,
+                                      const double *x_ext, const double *w,
+                                      const double *grad_image, double *g_nhi, double *g_kd,
+                                      double *g_vlos, int mem);
+
+/* ---------------------------------------------------------------- batches */
+/* Run many independent problems (contexts on one device with the same
+ * precision) in one persistent launch: problem i propagates packets
+ * [0, n_packets_i) with seed seeds[i].  per_problem[i] (may be NULL)
+ * receives the per-problem counts; total the sums and the kernel time. */
+rmc_status rmc_batch_run(rmc_ctx *const *problems, int n_problems, const uint64_t *seeds,
+                         const int64_t *n_packets, rmc_run_stats *per_problem,
+                         rmc_run_stats *total);
+
+/* ------------------------------------------------ host-only helpers */
+/* Mesh check without a device: RMC_OK or RMC_EMESH/RMC_EINVAL with a
+ * message in msg (may be NULL). */
+rmc_status rmc_mesh_check(int64_t n_leaves, const int8_t *level, const int32_t *ijk, char *msg,
+                          int msg_len);
+/* Line quantities at T (Sect. 3.1.1): out = {nu0 [Hz], v_th [cm/s],
+ * dnu_D [Hz], a, sigma0 [cm^2]}. */
+rmc_status rmc_line_quantities(const rmc_line *line, double T_K, double out[5]);
+int rmc_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -69,18 +69,20 @@ double uniform(uint64_t seed, uint64_t pid, uint32_t event, uint32_t j) {
   return (double)(2 * m + 1) * 0x1p-53;
 }
 
-/* Fixed slots of the uniforms used by one interaction event. */
+/* Fixed slots of the uniforms used by one event.  Slots 6.. are shared by
+ * branches that never occur in the same event (dust albedo, the |x| >= 8
+ * Gaussian, the rejection rounds). */
 enum {
-  J_CHANNEL = 0,  /* dust or which line                       */
-  J_ALBEDO = 1,   /* dust: scatter or absorb                  */
-  J_MU = 2,       /* cosine of the scattering angle           */
-  J_PHI = 3,      /* azimuth of the new direction             */
-  J_TAU = 4,      /* optical depth to the next event          */
-  J_PERP1 = 5,    /* Box-Muller pair for the two u_perp       */
-  J_PERP2 = 6,
-  J_GAUSS1 = 7,   /* Box-Muller pair for the |x| >= 8 branch  */
-  J_GAUSS2 = 8,
-  J_REJ = 9       /* rejection iteration i uses 9+3i..11+3i   */
+  J_CHANNEL = 0,  /* dust or which line                        */
+  J_MU = 1,       /* cosine of the scattering angle            */
+  J_PHI = 2,      /* azimuth of the new direction              */
+  J_TAU = 3,      /* optical depth to the next event           */
+  J_PERP1 = 4,    /* Box-Muller pair for the two u_perp        */
+  J_PERP2 = 5,
+  J_ALBEDO = 6,   /* dust: scatter or absorb                   */
+  J_GAUSS1 = 6,   /* line, |x| >= 8: Box-Muller pair           */
+  J_GAUSS2 = 7,
+  J_REJ = 6       /* line, |x| < 8: round i uses 6+3i .. 8+3i  */
 };
 
 struct Rng {
@@ -164,7 +166,8 @@ double u0_fit(double x, double a) {
   return c0 + x * (c1 + x * (c2 + x * (c3 + x * (c4 + x * c5))));
 }
 
-/* returns false only if the rejection loop exceeds its (huge) cap */
+/* returns false only if the rejection loop exceeds 2^20 rounds (the packet
+ * then stops with status stuck) */
 bool sample_upar(double x, double a, const Rng &rng, double *u_out) {
   if (std::fabs(x) >= 8.0) {
     double g = std::sqrt(-std::log(rng.u(J_GAUSS1))) * std::cos(2.0 * PI * rng.u(J_GAUSS2));
@@ -178,7 +181,7 @@ bool sample_upar(double x, double a, const Rng &rng, double *u_out) {
   double th0 = std::atan((u0 - xa) / a);
   double e0 = std::exp(-u0 * u0);
   double p1 = (th0 + PI / 2.0) / ((1.0 - e0) * th0 + (1.0 + e0) * PI / 2.0);
-  for (uint32_t it = 0; it < 10000000u; ++it) {
+  for (uint32_t it = 0; it < (1u << 20); ++it) {
     double r1 = rng.u(J_REJ + 3 * it);
     double r2 = rng.u(J_REJ + 3 * it + 1);
     double r3 = rng.u(J_REJ + 3 * it + 2);
@@ -247,6 +250,10 @@ double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * 
  * map keyed by (level, i, j, k) and finds the leaf holding a point by
  * probing every level from the root down. */
 const int MAX_LEVEL = 18;
+/* A packet or ray that has crossed this many leaves is stopped (a packet
+ * gets status stuck): it bounds the walk of a ray running parallel to a
+ * periodic slab. */
+const int64_t MAX_CROSS = (int64_t)1 << 24;
 
 uint64_t mkey(int lev, int64_t i, int64_t j, int64_t k) {
   return ((uint64_t)lev << 57) | ((uint64_t)i << 38) | ((uint64_t)j << 19) | (uint64_t)k;
@@ -449,7 +456,8 @@ double ray_tau(const Problem &P, const double p0[3], const double k[3], double d
   int64_t c = locate(P.mesh, p, k);
   double tau = 0.0;
   Opac o;
-  while (c >= 0) {
+  int64_t steps = 0;
+  while (c >= 0 && steps++ < MAX_CROSS) {
     opacity(P, c, dnu_ext, k, o);
     double pn[3];
     double te = exit_step(P.mesh, c, p, k, pn);
@@ -590,6 +598,7 @@ void transport_packet(const Problem &P, uint64_t seed, uint64_t pid, const doubl
   }
   int64_t c = locate(P.mesh, p, k);
   uint32_t event = 0;
+  int64_t ncross_pk = 0;
   out.status = ORC_ST_ESCAPED;
   Opac o;
   while (true) {
@@ -688,6 +697,10 @@ void transport_packet(const Problem &P, uint64_t seed, uint64_t pid, const doubl
     tau_ev -= tau_seg;
     path += lmax;
     to.st.crossings += 1;
+    if (++ncross_pk >= MAX_CROSS) {
+      out.status = ORC_ST_STUCK;
+      break;
+    }
     if (tdom <= te) {
       for (int d = 0; d < 3; ++d) p[d] = std::fma(tdom, k[d], p[d]);
       out.status = ORC_ST_ESCAPED;

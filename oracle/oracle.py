@@ -47,6 +47,12 @@ class OrcStats(C.Structure):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
 
 
+def _threads(n):
+    if n and n > 0:
+        return n
+    return max(1, min(16, os.cpu_count() or 1))
+
+
 def lib():
     global _LIB
     if _LIB is None:
@@ -250,7 +256,7 @@ def run(pb, seed, first=0, n=None, threads=0, forward_only=False, max_events=0, 
     st = OrcStats()
     rc = lib().orc_run(C.byref(P.s), n_src, _ptr(pos), _ptr(dirs), _ptr(xs), seed, first, n, n_obs,
                        obs_arr, cube_ptrs, _ptr(status), _ptr(x_out), _ptr(k_out), _ptr(pos_out),
-                       _ptr(n_scat), _ptr(path), threads, C.byref(st))
+                       _ptr(n_scat), _ptr(path), _threads(threads), C.byref(st))
     if rc:
         raise RuntimeError(f"orc_run failed: {rc}")
     return dict(status=status, x=x_out, k=k_out, pos=pos_out, n_scat=n_scat, path=path,
@@ -273,7 +279,7 @@ def raycast_image(pb, observer, orig, x_ext, w, grad_image=None, threads=0):
     gk = np.zeros(nl) if G is not None else None
     gv = np.zeros(nl) if G is not None else None
     rc = lib().orc_raycast_image(C.byref(P.s), C.byref(ob), len(o), _ptr(o), _ptr(x), _ptr(ww),
-                                 _ptr(img), _ptr(G), _ptr(gn), _ptr(gk), _ptr(gv), threads)
+                                 _ptr(img), _ptr(G), _ptr(gn), _ptr(gk), _ptr(gv), _threads(threads))
     if rc:
         raise RuntimeError(f"orc_raycast_image failed: {rc}")
     if G is None:

@@ -1,0 +1,1054 @@
+// rmc_api.cpp -- host runtime behind include/rmc.h: contexts, mesh
+// validation and breadth-first octree build, per-leaf records, launches.
+#include "rmc.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "rmc_launch.h"
+
+// observer bases and pixel spans must be the exact IEEE results of the
+// written expressions
+#pragma clang fp contract(off)
+
+using namespace rmc;
+
+namespace {
+
+// CGS constants (CODATA 2018)
+const double C_LIGHT = 2.99792458e10;
+const double H_PLANCK = 6.62607015e-27;
+const double K_BOLTZ = 1.380649e-16;
+const double E_CHARGE = 4.80320471e-10;
+const double M_ELECTRON = 9.1093837015e-28;
+const double AMU_G = 1.66053906660e-24;
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  hipError_t ensure(size_t n) {
+    if (n <= bytes && p) return hipSuccess;
+    release();
+    hipError_t e = hipMalloc(&p, n ? n : 1);
+    if (e == hipSuccess) bytes = n;
+    else p = nullptr;
+    return e;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T> T *as() const { return (T *)p; }
+};
+
+struct ObsHost {
+  ObsK k;
+  size_t n_elems;
+  DevBuf cube;
+};
+
+struct LineQ {
+  double nu0, vth, dnu, a, sigma0;
+};
+
+// Sect. 3.1.1 line quantities at temperature T.
+LineQ line_q(const rmc_line &ln, double T) {
+  LineQ q;
+  q.nu0 = C_LIGHT / (ln.lambda0_A * 1e-8);
+  q.vth = std::sqrt(2.0 * K_BOLTZ * T / (ln.mass_amu * AMU_G));
+  q.dnu = q.nu0 * q.vth / C_LIGHT;
+  q.a = ln.A_ul / (4.0 * 3.14159265358979323846 * q.dnu);
+  q.sigma0 = std::sqrt(3.14159265358979323846) * E_CHARGE * E_CHARGE * ln.f_lu / (M_ELECTRON * C_LIGHT * q.dnu);
+  return q;
+}
+
+}  // namespace
+
+struct rmc_ctx {
+  int device = 0;
+  int precision = RMC_FP64;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int forward_only = 0;
+  int64_t max_events = 0;
+  int block = 256;
+  int waves_per_cu = 8;
+  int refill = 1;
+  int peel_defer = 0;
+  // mesh
+  bool has_mesh = false;
+  int64_t n_leaves = 0;
+  int L = 0;
+  double box_cm = 0.0;
+  int64_t n_nodes = 0;
+  DevBuf nodes;
+  // lines
+  bool has_lines = false;
+  int n_lines = 0;
+  rmc_line lines[MAX_LINES];
+  double T_ref = 0.0;
+  // gas
+  bool has_gas = false;
+  std::vector<double> gn, gT, gv, gk;
+  DevBuf leaves;
+  double albedo = 0.32, g_hg = 0.73;
+  int domain = RMC_DOM_BOX;
+  double dom[4] = {0, 0, 0, 0};
+  // sources
+  int64_t n_src = 0;
+  bool src_dir = false;
+  DevBuf spos, sdir, sx;
+  std::vector<ObsHost> obs;
+  // outputs of the last run
+  int64_t last_n = 0;
+  DevBuf o_status, o_x, o_k, o_pos, o_nscat, o_path;
+  DevBuf d_stats, d_next, d_prob, d_starts, tmp1, tmp2, tmp3, tmp4, tmp5;
+  ProblemK pb_host;
+  int64_t starts_host[2];
+  int num_cus = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // batch launches
+  DevBuf b_probs, b_starts;
+  std::vector<ProblemK> b_host;
+  std::vector<int64_t> b_starts_host;
+  hipGraphExec_t b_graph = nullptr;
+  std::string b_key;
+};
+
+namespace {
+
+rmc_status fail(rmc_ctx *c, rmc_status s, const char *fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return s;
+}
+
+#define HIPCHK(ctx, expr)                                                                   \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return fail(ctx, e_ == hipErrorOutOfMemory ? RMC_ENOMEM : RMC_EDEVICE, "%s: %s", #expr, \
+                  hipGetErrorString(e_));                                                   \
+  } while (0)
+
+bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
+
+uint64_t spread3(uint64_t v) {
+  v &= 0xFFFFull;
+  v = (v | (v << 16)) & 0x0000FF0000FFull;
+  v = (v | (v << 8)) & 0x00F00F00F00F00Full;
+  v = (v | (v << 4)) & 0x0C30C30C30C30C3ull;
+  v = (v | (v << 2)) & 0x249249249249249ull;
+  return v;
+}
+// Morton code with x in the lowest bit of each triple: the child octant
+// index of the node array is x | y<<1 | z<<2.
+uint64_t morton(uint32_t x, uint32_t y, uint32_t z) { return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2); }
+
+bool sorted_has(const std::vector<uint64_t> &v, uint64_t key) { return std::binary_search(v.begin(), v.end(), key); }
+
+// Validate the leaves (Sect. 4.3 graded octree) and build the breadth-first
+// node array: nodes of each level in Morton order, which is the order a
+// breadth-first walk visiting children by octant produces.
+rmc_status build_tree(int64_t n, const int8_t *level, const int32_t *ijk, std::vector<int32_t> &nodes, int &L,
+                      std::string &msg) {
+  char buf[256];
+  if (n <= 0 || !level || !ijk) {
+    msg = "empty mesh";
+    return RMC_EINVAL;
+  }
+  if (n >= (int64_t)1 << 31) {
+    msg = "too many leaves";
+    return RMC_EINVAL;
+  }
+  L = 0;
+  for (int64_t c = 0; c < n; ++c) {
+    if (level[c] < 0 || level[c] > MAX_LEVEL) {
+      snprintf(buf, sizeof buf, "leaf %lld: level %d outside [0,%d]", (long long)c, (int)level[c], MAX_LEVEL);
+      msg = buf;
+      return RMC_EMESH;
+    }
+    L = std::max(L, (int)level[c]);
+  }
+  std::vector<std::vector<std::pair<uint64_t, int32_t>>> lv(L + 1);
+  for (int64_t c = 0; c < n; ++c) {
+    const int l = level[c];
+    const int64_t side = (int64_t)1 << l;
+    const int64_t i = ijk[3 * c], j = ijk[3 * c + 1], k = ijk[3 * c + 2];
+    if (i < 0 || j < 0 || k < 0 || i >= side || j >= side || k >= side) {
+      snprintf(buf, sizeof buf, "leaf %lld: coordinates out of range for level %d", (long long)c, l);
+      msg = buf;
+      return RMC_EMESH;
+    }
+    lv[l].emplace_back(morton((uint32_t)i, (uint32_t)j, (uint32_t)k), (int32_t)c);
+  }
+  std::vector<std::vector<uint64_t>> leafkeys(L + 1), inner(L + 1);
+  for (int l = 0; l <= L; ++l) {
+    std::sort(lv[l].begin(), lv[l].end());
+    leafkeys[l].resize(lv[l].size());
+    for (size_t q = 0; q < lv[l].size(); ++q) {
+      leafkeys[l][q] = lv[l][q].first;
+      if (q && leafkeys[l][q] == leafkeys[l][q - 1]) {
+        snprintf(buf, sizeof buf, "duplicate leaf at level %d (leaf %d)", l, lv[l][q].second);
+        msg = buf;
+        return RMC_EMESH;
+      }
+    }
+  }
+  for (int l = L; l >= 1; --l) {
+    std::vector<uint64_t> &par = inner[l - 1];
+    par.reserve(leafkeys[l].size() / 4 + inner[l].size() / 4 + 1);
+    for (uint64_t m : leafkeys[l]) par.push_back(m >> 3);
+    for (uint64_t m : inner[l]) par.push_back(m >> 3);
+    std::sort(par.begin(), par.end());
+    par.erase(std::unique(par.begin(), par.end()), par.end());
+  }
+  for (int l = 0; l <= L; ++l) {
+    // a leaf that is also an ancestor of other leaves overlaps them
+    std::vector<uint64_t> both;
+    std::set_intersection(leafkeys[l].begin(), leafkeys[l].end(), inner[l].begin(), inner[l].end(),
+                          std::back_inserter(both));
+    if (!both.empty()) {
+      snprintf(buf, sizeof buf, "overlapping leaves: a level-%d leaf contains finer leaves", l);
+      msg = buf;
+      return RMC_EMESH;
+    }
+  }
+  nodes.clear();
+  if (L == 0) {
+    if (n != 1) {
+      msg = "more than one level-0 leaf";
+      return RMC_EMESH;
+    }
+    return RMC_OK;
+  }
+  std::vector<int64_t> off(L + 1, 0);
+  for (int l = 1; l <= L; ++l) off[l] = off[l - 1] + (int64_t)inner[l - 1].size();
+  const int64_t n_nodes = off[L];
+  if (n_nodes >= (int64_t)1 << 31) {
+    msg = "too many nodes";
+    return RMC_EINVAL;
+  }
+  nodes.assign((size_t)n_nodes * 8, 0);
+  for (int l = 0; l < L; ++l) {
+    const auto &in_next = inner[l + 1];
+    const auto &lf_next = leafkeys[l + 1];
+    for (size_t r = 0; r < inner[l].size(); ++r) {
+      const uint64_t m = inner[l][r];
+      for (int oct = 0; oct < 8; ++oct) {
+        const uint64_t cm = (m << 3) | (uint64_t)oct;
+        int32_t v;
+        auto it = std::lower_bound(in_next.begin(), in_next.end(), cm);
+        if (it != in_next.end() && *it == cm) {
+          v = (int32_t)(off[l + 1] + (it - in_next.begin()));
+        } else {
+          auto jt = std::lower_bound(lf_next.begin(), lf_next.end(), cm);
+          if (jt == lf_next.end() || *jt != cm) {
+            snprintf(buf, sizeof buf, "gap: level-%d cell under node %lld octant %d is not covered", l + 1,
+                     (long long)(off[l] + (int64_t)r), oct);
+            msg = buf;
+            return RMC_EMESH;
+          }
+          v = -(lv[l + 1][jt - lf_next.begin()].second) - 1;
+        }
+        nodes[(size_t)(off[l] + (int64_t)r) * 8 + oct] = v;
+      }
+    }
+  }
+  // 2:1 grading across faces: the level-(l-2) ancestor of each same-size
+  // face neighbour must be refined (an inner node)
+  std::vector<int> bad_t;
+  const int nt = std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
+  std::vector<int64_t> bad(nt, -1);
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t) {
+    th.emplace_back([&, t]() {
+      for (int64_t c = t; c < n; c += nt) {
+        const int l = level[c];
+        if (l < 2) continue;
+        const int64_t side = (int64_t)1 << l;
+        for (int d = 0; d < 3; ++d)
+          for (int sg = -1; sg <= 1; sg += 2) {
+            int64_t nb[3] = {ijk[3 * c], ijk[3 * c + 1], ijk[3 * c + 2]};
+            nb[d] += sg;
+            if (nb[d] < 0 || nb[d] >= side) continue;
+            const uint64_t a = morton((uint32_t)(nb[0] >> 2), (uint32_t)(nb[1] >> 2), (uint32_t)(nb[2] >> 2));
+            if (!sorted_has(inner[l - 2], a)) {
+              bad[t] = c;
+              return;
+            }
+          }
+      }
+    });
+  }
+  for (auto &x : th) x.join();
+  for (int t = 0; t < nt; ++t)
+    if (bad[t] >= 0) {
+      snprintf(buf, sizeof buf, "not 2:1 graded: leaf %lld has a face neighbour two or more levels coarser",
+               (long long)bad[t]);
+      msg = buf;
+      return RMC_EMESH;
+    }
+  return RMC_OK;
+}
+
+rmc_status enter(rmc_ctx *c) {
+  if (!c) return RMC_EINVAL;
+  c->err.clear();
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return fail(c, RMC_EDEVICE, "hipSetDevice: %s", hipGetErrorString(e));
+  return RMC_OK;
+}
+
+rmc_status upload(rmc_ctx *c, DevBuf &dst, const void *src, size_t bytes, int mem) {
+  HIPCHK(c, dst.ensure(bytes));
+  if (bytes == 0) return RMC_OK;
+  HIPCHK(c, hipMemcpyAsync(dst.p, src, bytes, mem == RMC_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                           c->stream));
+  return RMC_OK;
+}
+
+rmc_status download(rmc_ctx *c, void *dst, const void *src, size_t bytes, int mem) {
+  if (!dst || bytes == 0) return RMC_OK;
+  HIPCHK(c, hipMemcpyAsync(dst, src, bytes, mem == RMC_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                           c->stream));
+  return RMC_OK;
+}
+
+// Per-leaf records relative to T_ref (see rmc_device.h).
+rmc_status build_leaves(rmc_ctx *c) {
+  const LineQ q0 = line_q(c->lines[0], c->T_ref);
+  const double vth_ref = q0.vth;
+  const int64_t n = c->n_leaves;
+  const bool f32 = c->precision == RMC_FP32_BULK;
+  const size_t esz = f32 ? 4 : 8;
+  std::vector<unsigned char> host((size_t)n * LEAF_STRIDE * esz, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    const double irho = std::sqrt(c->T_ref / c->gT[i]);
+    const double rec[6] = {c->gn[i] * c->box_cm * irho, irho, c->gk[i] * c->box_cm,
+                           c->gv[3 * i] / vth_ref, c->gv[3 * i + 1] / vth_ref, c->gv[3 * i + 2] / vth_ref};
+    for (int q = 0; q < 6; ++q) {
+      if (f32) ((float *)host.data())[(size_t)i * LEAF_STRIDE + q] = (float)rec[q];
+      else ((double *)host.data())[(size_t)i * LEAF_STRIDE + q] = rec[q];
+    }
+  }
+  HIPCHK(c, c->leaves.ensure(host.size()));
+  HIPCHK(c, hipMemcpy(c->leaves.p, host.data(), host.size(), hipMemcpyHostToDevice));
+  return RMC_OK;
+}
+
+void make_problem(rmc_ctx *c, int64_t first, int64_t n, uint64_t seed, ProblemK &pb) {
+  std::memset(&pb, 0, sizeof pb);
+  pb.nodes = c->nodes.as<int32_t>();
+  pb.leaves = c->leaves.p;
+  pb.L = c->L;
+  pb.n_lines = c->n_lines;
+  const LineQ q0 = line_q(c->lines[0], c->T_ref);
+  pb.b_ref = q0.vth / C_LIGHT;
+  for (int i = 0; i < c->n_lines; ++i) {
+    const rmc_line &ln = c->lines[i];
+    const LineQ q = line_q(ln, c->T_ref);
+    LineK &k = pb.lines[i];
+    k.s = ln.lambda0_A / c->lines[0].lambda0_A;                    // nu_ref / nu_i
+    k.delta = ((ln.lambda0_A - c->lines[0].lambda0_A) / c->lines[0].lambda0_A) / pb.b_ref;
+    k.inv_s = c->lines[0].lambda0_A / ln.lambda0_A;
+    k.mu = std::sqrt(c->lines[0].mass_amu / ln.mass_amu);
+    k.inv_mu = std::sqrt(ln.mass_amu / c->lines[0].mass_amu);
+    k.alpha = q.a;
+    k.kfac = ln.abundance * q.sigma0;
+    k.rec = H_PLANCK * q.nu0 / (ln.mass_amu * AMU_G * C_LIGHT * C_LIGHT);
+    k.phase = ln.phase;
+    k.recoil = ln.recoil;
+  }
+  pb.box_cm = c->box_cm;
+  pb.domain = c->domain;
+  for (int d = 0; d < 4; ++d) pb.dom[d] = c->dom[d];
+  pb.albedo = c->albedo;
+  pb.g_hg = c->g_hg;
+  pb.forward_only = c->forward_only;
+  pb.max_events = c->max_events;
+  pb.src_pos = c->spos.as<double>();
+  pb.src_dir = c->src_dir ? c->sdir.as<double>() : nullptr;
+  pb.src_x = c->sx.as<double>();
+  pb.first = first;
+  pb.n = n;
+  pb.seed = seed;
+  pb.status = c->o_status.as<int32_t>();
+  pb.nscat = c->o_nscat.as<int32_t>();
+  pb.x_out = c->o_x.as<double>();
+  pb.k_out = c->o_k.as<double>();
+  pb.pos_out = c->o_pos.as<double>();
+  pb.path_out = c->o_path.as<double>();
+  pb.n_obs = (int)c->obs.size();
+  for (int o = 0; o < pb.n_obs; ++o) pb.obs[o] = c->obs[o].k;
+  pb.stats = c->d_stats.as<unsigned long long>();
+}
+
+rmc_status ready(rmc_ctx *c, bool need_sources) {
+  if (!c->has_mesh) return fail(c, RMC_ESTATE, "no mesh (rmc_set_mesh)");
+  if (!c->has_lines) return fail(c, RMC_ESTATE, "no lines (rmc_set_lines)");
+  if (!c->has_gas) return fail(c, RMC_ESTATE, "no gas (rmc_set_gas)");
+  if (need_sources && c->n_src <= 0) return fail(c, RMC_ESTATE, "no sources (rmc_set_sources)");
+  if (c->domain == RMC_DOM_SLAB_Z)
+    for (auto &o : c->obs)
+      if (o.k.k[2] == 0.0) return fail(c, RMC_EINVAL, "slab domain: observers need k_z != 0");
+  return RMC_OK;
+}
+
+rmc_status ensure_outputs(rmc_ctx *c, int64_t n) {
+  const size_t m = (size_t)std::max<int64_t>(n, 1);
+  HIPCHK(c, c->o_status.ensure(m * 4));
+  HIPCHK(c, c->o_nscat.ensure(m * 4));
+  HIPCHK(c, c->o_x.ensure(m * 8));
+  HIPCHK(c, c->o_k.ensure(m * 24));
+  HIPCHK(c, c->o_pos.ensure(m * 24));
+  HIPCHK(c, c->o_path.ensure(m * 8));
+  HIPCHK(c, c->d_stats.ensure(N_STATS * 8));
+  HIPCHK(c, c->d_next.ensure(8));
+  return RMC_OK;
+}
+
+int grid_for(rmc_ctx *c, int64_t n) {
+  const int64_t lanes = (int64_t)c->num_cus * c->waves_per_cu * 64;
+  int64_t g = lanes / c->block;
+  const int64_t need = (n + c->block - 1) / c->block;
+  g = std::min(g, need);
+  return (int)std::max<int64_t>(g, 1);
+}
+
+void fill_stats(rmc_run_stats *s, const unsigned long long *h, double ms) {
+  s->emitted = h[S_EMITTED];
+  s->escaped = h[S_ESCAPED];
+  s->absorbed = h[S_ABSORBED];
+  s->stuck = h[S_STUCK];
+  s->scatterings = h[S_SCAT];
+  s->dust_scatterings = h[S_DUST_SCAT];
+  s->crossings = h[S_CROSS];
+  s->peel_rays = h[S_PEEL_RAYS];
+  s->peel_crossings = h[S_PEEL_CROSS];
+  s->peel_dropped = h[S_PEEL_DROPPED];
+  s->kernel_ms = ms;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rmc_abi_version(void) { return 1; }
+
+rmc_status rmc_create(rmc_ctx **out, int device, int precision) {
+  if (!out) return RMC_EINVAL;
+  *out = nullptr;
+  if (precision != RMC_FP64 && precision != RMC_FP32_BULK) return RMC_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return RMC_EDEVICE;
+  rmc_ctx *c = new (std::nothrow) rmc_ctx();
+  if (!c) return RMC_ENOMEM;
+  c->device = device;
+  c->precision = precision;
+  if (hipSetDevice(device) != hipSuccess ||
+      hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+      hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+    delete c;
+    return RMC_EDEVICE;
+  }
+  *out = c;
+  return RMC_OK;
+}
+
+void rmc_destroy(rmc_ctx *c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  if (c->b_graph) (void)hipGraphExecDestroy(c->b_graph);
+  DevBuf *bufs[] = {&c->nodes, &c->leaves, &c->spos, &c->sdir, &c->sx, &c->o_status, &c->o_x, &c->o_k,
+                    &c->o_pos, &c->o_nscat, &c->o_path, &c->d_stats, &c->d_next, &c->d_prob, &c->d_starts,
+                    &c->tmp1, &c->tmp2, &c->tmp3, &c->tmp4, &c->tmp5, &c->b_probs, &c->b_starts};
+  for (DevBuf *b : bufs) b->release();
+  for (auto &o : c->obs) o.cube.release();
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  delete c;
+}
+
+const char *rmc_last_error(const rmc_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+rmc_status rmc_set_stream(rmc_ctx *c, void *s) {
+  rmc_status r = enter(c);
+  if (r) return r;
+  c->stream = (hipStream_t)s;
+  return RMC_OK;
+}
+
+rmc_status rmc_set_option(rmc_ctx *c, int opt, int64_t v) {
+  rmc_status r = enter(c);
+  if (r) return r;
+  switch (opt) {
+    case RMC_OPT_FORWARD_ONLY: c->forward_only = v ? 1 : 0; break;
+    case RMC_OPT_MAX_EVENTS:
+      if (v < 0) return fail(c, RMC_EINVAL, "max_events < 0");
+      c->max_events = v;
+      break;
+    case RMC_OPT_BLOCK:
+      if (v != 64 && v != 128 && v != 256) return fail(c, RMC_EINVAL, "block must be 64, 128 or 256");
+      c->block = (int)v;
+      break;
+    case RMC_OPT_WAVES_PER_CU:
+      if (v < 1 || v > 32) return fail(c, RMC_EINVAL, "waves per CU in [1,32]");
+      c->waves_per_cu = (int)v;
+      break;
+    case RMC_OPT_REFILL:
+      if (v < 1 || v > 64) return fail(c, RMC_EINVAL, "refill in [1,64]");
+      c->refill = (int)v;
+      break;
+    case RMC_OPT_PEEL_DEFER:
+      if (v) return fail(c, RMC_EUNSUPPORTED, "deferred peel-off queue not built");
+      c->peel_defer = 0;
+      break;
+    default: return fail(c, RMC_EINVAL, "unknown option %d", opt);
+  }
+  return RMC_OK;
+}
+
+rmc_status rmc_set_mesh(rmc_ctx *c, int64_t n, const int8_t *level, const int32_t *ijk, double box_cm) {
+  rmc_status r = enter(c);
+  if (r) return r;
+  if (!(box_cm > 0.0) || !std::isfinite(box_cm)) return fail(c, RMC_EINVAL, "box_cm must be > 0");
+  std::vector<int32_t> nodes;
+  int L = 0;
+  std::string msg;
+  r = build_tree(n, level, ijk, nodes, L, msg);
+  if (r) return fail(c, r, "%s", msg.c_str());
+  HIPCHK(c, c->nodes.ensure(std::max<size_t>(nodes.size() * 4, 32)));
+  if (!nodes.empty()) HIPCHK(c, hipMemcpy(c->nodes.p, nodes.data(), nodes.size() * 4, hipMemcpyHostToDevice));
+  c->n_leaves = n;
+  c->n_nodes = (int64_t)nodes.size() / 8;
+  c->L = L;
+  c->box_cm = box_cm;
+  c->has_mesh = true;
+  c->has_gas = false;
+  return RMC_OK;
+}
+
+rmc_status rmc_set_lines(rmc_ctx *c, int n, const rmc_line *lines, double T_ref) {
+  rmc_status r = enter(c);
+  if (r) return r;
+  if (n < 1 || n > MAX_LINES || !lines) return fail(c, RMC_EINVAL, "1..%d lines", MAX_LINES);
+  if (!(T_ref > 0.0) || !std::isfinite(T_ref)) return fail(c, RMC_EINVAL, "T_ref must be > 0");
+  for (int i = 0; i < n; ++i) {
+    const rmc_line &l = lines[i];
+    if (!(l.lambda0_A > 0) || !(l.A_ul > 0) || !(l.f_lu >= 0) || !(l.mass_amu > 0) || !finite_nonneg(l.abundance) ||
+        (l.phase != RMC_PHASE_LYA_DIPOLE && l.phase != RMC_PHASE_ISOTROPIC))
+      return fail(c, RMC_EINVAL, "line %d: bad parameters", i);
+    c->lines[i] = l;
+  }
+  c->n_lines = n;
+  c->T_ref = T_ref;
+  c->has_lines = true;
+  if (c->has_gas) return build_leaves(c);
+  return RMC_OK;
+}
+
+rmc_status rmc_set_gas(rmc_ctx *c, const double *n_hi, const double *T, const double *v, const double *kd) {
+  rmc_status r = enter(c);
+  if (r) return r;
+  if (!c->has_mesh) return fail(c, RMC_ESTATE, "rmc_set_mesh first");
+  if (!c->has_lines) return fail(c, RMC_ESTATE, "rmc_set_lines first");
+  if (!n_hi || !T || !v || !kd) return fail(c, RMC_EINVAL, "null gas array");
+  const int64_t n = c->n_leaves;
+  for (int64_t i = 0; i < n; ++i) {
+    if (!finite_nonneg(n_hi[i]) || !(T[i] > 0.0) || !std::isfinite(T[i]) || !finite_nonneg(kd[i]) ||
+        !std::isfinite(v[3 * i]) || !std::isfinite(v[3 * i + 1]) || !std::isfinite(v[3 * i + 2]))
+      return fail(c, RMC_EINVAL, "leaf %lld: non-finite or negative gas value", (long long)i);
+    if (std::fabs(v[3 * i]) >= 0.1 * C_LIGHT || std::fabs(v[3 * i + 1]) >= 0.1 * C_LIGHT ||
+        std::fabs(v[3 * i + 2]) >= 0.1 * C_LIGHT)
+      return fail(c, RMC_EINVAL, "leaf %lld: |v| >= 0.1 c", (long long)i);
+  }
+  c->gn.assign(n_hi, n_hi + n);
+  c->gT.assign(T, T + n);
+  c->gv.assign(v, v + 3 * n);
+  c->gk.assign(kd, kd + n);
+  r = build_leaves(c);
+  if (r) return r;
+  c->has_gas = true;
+  return RMC_OK;
+}
+
+rmc_status rmc_set_dust(rmc_ctx *c, double albedo, double g) {
+  rmc_status r = enter(c);
+  if (r) return r;
+  if (!(albedo >= 0.0 && albedo <= 1.0) || !(g > -1.0 && g < 1.0)) return fail(c, RMC_EINVAL, "albedo in [0,1], |g| < 1");
+  c->albedo = albedo;
+  c->g_hg = g;
+  return RMC_OK;
+}
+
+rmc_status rmc_set_domain(rmc_ctx *c, int kind, const double p[4]) {
+  rmc_status r = enter(c);
+  if (r) return r;
+  double q[4] = {0, 0, 0, 0};
+  if (kind != RMC_DOM_BOX) {
+    if (!p) return fail(c, RMC_EINVAL, "domain parameters needed");
+    for (int d = 0; d < 4; ++d) q[d] = p[d];
+  }
+  if (kind == RMC_DOM_SLAB_Z) {
+    if (!(q[1] > 0) || q[0] - q[1] < 0.0 || q[0] + q[1] > 1.0) return fail(c, RMC_EINVAL, "slab must lie in [0,1]");
+  } else if (kind == RMC_DOM_SPHERE) {
+    if (!(q[3] > 0) || q[0] - q[3] < 0 || q[0] + q[3] > 1 || q[1] - q[3] < 0 || q[1] + q[3] > 1 || q[2] - q[3] < 0 ||
+        q[2] + q[3] > 1)
+      return fail(c, RMC_EINVAL, "sphere must lie inside the unit cube");
+  } else if (kind != RMC_DOM_BOX) {
+    return fail(c, RMC_EINVAL, "unknown domain kind %d", kind);
+  }
+  c->domain = kind;
+  for (int d = 0; d < 4; ++d) c->dom[d] = q[d];
+  return RMC_OK;
+}
+
+rmc_status rmc_set_sources(rmc_ctx *c, int64_t n, const double *pos, const double *dir, const double *x, int mem) {
+  rmc_status r = enter(c);
+  if (r) return r;
+  if (n <= 0 || !pos || !x) return fail(c, RMC_EINVAL, "need n > 0, positions and frequencies");
+  if (mem == RMC_HOST) {
+    for (int64_t i = 0; i < n; ++i) {
+      for (int d = 0; d < 3; ++d)
+        if (!(pos[3 * i + d] >= 0.0 && pos[3 * i + d] <= 1.0)) return fail(c, RMC_EINVAL, "source %lld outside the box", (long long)i);
+      if (!std::isfinite(x[i])) return fail(c, RMC_EINVAL, "source %lld: non-finite x", (long long)i);
+      if (dir) {
+        const double nn = dir[3 * i] * dir[3 * i] + dir[3 * i + 1] * dir[3 * i + 1] + dir[3 * i + 2] * dir[3 * i + 2];
+        if (!(std::fabs(nn - 1.0) < 1e-6)) return fail(c, RMC_EINVAL, "source %lld: direction not unit", (long long)i);
+      }
+    }
+  }
+  r = upload(c, c->spos, pos, (size_t)n * 24, mem);
+  if (r) return r;
+  r = upload(c, c->sx, x, (size_t)n * 8, mem);
+  if (r) return r;
+  c->src_dir = dir != nullptr;
+  if (dir) {
+    r = upload(c, c->sdir, dir, (size_t)n * 24, mem);
+    if (r) return r;
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->n_src = n;
+  return RMC_OK;
+}
+
+rmc_status rmc_add_observer(rmc_ctx *c, const double k[3], int nx, int ny, int nbins, const double fov[4], double x_min,
+                            double x_max, int *id) {
+  rmc_status r = enter(c);
+  if (r) return r;
+  if ((int)c->obs.size() >= MAX_OBS) return fail(c, RMC_EUNSUPPORTED, "at most %d observers", MAX_OBS);
+  if (!k || !fov || nx <= 0 || ny <= 0 || nbins <= 0 || !(x_max > x_min) || !(fov[1] > fov[0]) || !(fov[3] > fov[2]))
+    return fail(c, RMC_EINVAL, "bad observer");
+  const double nn = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+  if (!(std::fabs(nn - 1.0) < 1e-12)) return fail(c, RMC_EINVAL, "observer direction must be a unit vector");
+  ObsHost o;
+  std::memset(&o.k, 0, sizeof o.k);
+  for (int d = 0; d < 3; ++d) o.k.k[d] = k[d];
+  // image basis: e1 = normalize(z x k) (x when k is along z), e2 = k x e1
+  double e1[3];
+  if (k[0] == 0.0 && k[1] == 0.0) {
+    e1[0] = 1.0; e1[1] = 0.0; e1[2] = 0.0;
+  } else {
+    const double nrm = std::sqrt(k[1] * k[1] + k[0] * k[0]);
+    e1[0] = -k[1] / nrm; e1[1] = k[0] / nrm; e1[2] = 0.0;
+  }
+  const double e2[3] = {k[1] * e1[2] - k[2] * e1[1], k[2] * e1[0] - k[0] * e1[2], k[0] * e1[1] - k[1] * e1[0]};
+  for (int d = 0; d < 3; ++d) {
+    o.k.e1[d] = e1[d];
+    o.k.e2[d] = e2[d];
+  }
+  o.k.u0 = fov[0];
+  o.k.uspan = fov[1] - fov[0];
+  o.k.v0 = fov[2];
+  o.k.vspan = fov[3] - fov[2];
+  o.k.x_min = x_min;
+  o.k.xspan = x_max - x_min;
+  o.k.nx = nx;
+  o.k.ny = ny;
+  o.k.nbins = nbins;
+  o.n_elems = (size_t)nx * ny * nbins;
+  const size_t esz = c->precision == RMC_FP32_BULK ? 4 : 8;
+  HIPCHK(c, o.cube.ensure(o.n_elems * esz));
+  HIPCHK(c, hipMemsetAsync(o.cube.p, 0, o.n_elems * esz, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  o.k.cube = o.cube.p;
+  c->obs.push_back(o);
+  if (id) *id = (int)c->obs.size() - 1;
+  return RMC_OK;
+}
+
+rmc_status rmc_reset_cubes(rmc_ctx *c) {
+  rmc_status r = enter(c);
+  if (r) return r;
+  const size_t esz = c->precision == RMC_FP32_BULK ? 4 : 8;
+  for (auto &o : c->obs) HIPCHK(c, hipMemsetAsync(o.cube.p, 0, o.n_elems * esz, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return RMC_OK;
+}
+
+rmc_status rmc_run(rmc_ctx *c, uint64_t seed, int64_t first, int64_t n, rmc_run_stats *stats) {
+  rmc_status r = enter(c);
+  if (r) return r;
+  r = ready(c, true);
+  if (r) return r;
+  if (first < 0 || n < 0 || first + n > c->n_src) return fail(c, RMC_EINVAL, "packet range outside the sources");
+  r = ensure_outputs(c, n);
+  if (r) return r;
+  c->last_n = n;
+  make_problem(c, first, n, seed, c->pb_host);
+  c->starts_host[0] = 0;
+  c->starts_host[1] = n;
+  HIPCHK(c, c->d_prob.ensure(sizeof(ProblemK)));
+  HIPCHK(c, c->d_starts.ensure(16));
+  HIPCHK(c, hipMemcpyAsync(c->d_prob.p, &c->pb_host, sizeof(ProblemK), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_starts.p, c->starts_host, 16, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, launch_batch_reset(c->d_prob.as<ProblemK>(), 1, c->d_next.as<unsigned long long>(), c->stream));
+  const int levels = std::max(c->L, 1);
+  HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+  if (n > 0)
+    HIPCHK(c, launch_transport(c->precision == RMC_FP32_BULK, false, c->d_prob.as<ProblemK>(),
+                               c->d_starts.as<int64_t>(), 1, c->d_next.as<unsigned long long>(), c->refill, levels,
+                               grid_for(c, n), c->block, c->stream));
+  HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+  unsigned long long h[N_STATS];
+  HIPCHK(c, hipMemcpyAsync(h, c->d_stats.p, sizeof h, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  float ms = 0.f;
+  HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  if (stats) fill_stats(stats, h, ms);
+  if ((int64_t)h[S_EMITTED] != n)
+    return fail(c, RMC_EDEVICE, "transport finished %llu of %lld packets", h[S_EMITTED], (long long)n);
+  return RMC_OK;
+}
+
+rmc_status rmc_get_packets(rmc_ctx *c, int32_t *status, double *x, double *k, double *pos, int32_t *nscat,
+                           double *path, int mem) {
+  rmc_status r = enter(c);
+  if (r) return r;
+  const int64_t n = c->last_n;
+  if (n <= 0) return fail(c, RMC_ESTATE, "no run yet");
+  if ((r = download(c, status, c->o_status.p, n * 4, mem))) return r;
+  if ((r = download(c, x, c->o_x.p, n * 8, mem))) return r;
+  if ((r = download(c, k, c->o_k.p, n * 24, mem))) return r;
+  if ((r = download(c, pos, c->o_pos.p, n * 24, mem))) return r;
+  if ((r = download(c, nscat, c->o_nscat.p, n * 4, mem))) return r;
+  if ((r = download(c, path, c->o_path.p, n * 8, mem))) return r;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return RMC_OK;
+}
+
+rmc_status rmc_get_spectrum(rmc_ctx *c, int nbins, double x_min, double x_max, double *hist, int mem) {
+  rmc_status r = enter(c);
+  if (r) return r;
+  if (nbins <= 0 || !(x_max > x_min) || !hist) return fail(c, RMC_EINVAL, "bad histogram");
+  if (c->last_n <= 0) return fail(c, RMC_ESTATE, "no run yet");
+  HIPCHK(c, c->tmp1.ensure((size_t)nbins * 8));
+  HIPCHK(c, c->tmp2.ensure((size_t)nbins * 8));
+  HIPCHK(c, launch_fill_u64(c->tmp1.as<unsigned long long>(), nbins, 0ull, c->stream));
+  HIPCHK(c, launch_hist(c->last_n, c->o_status.as<int32_t>(), c->o_x.as<double>(), nbins, x_min, x_max - x_min,
+                        c->tmp1.as<unsigned long long>(), c->stream));
+  double *dst = mem == RMC_DEVICE ? hist : c->tmp2.as<double>();
+  HIPCHK(c, launch_u64_to_f64(c->tmp1.as<unsigned long long>(), dst, nbins, c->stream));
+  if (mem != RMC_DEVICE)
+    HIPCHK(c, hipMemcpyAsync(hist, c->tmp2.p, (size_t)nbins * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return RMC_OK;
+}
+
+rmc_status rmc_get_cube(rmc_ctx *c, int id, void *out, int dtype, int mem) {
+  rmc_status r = enter(c);
+  if (r) return r;
+  if (id < 0 || id >= (int)c->obs.size() || !out) return fail(c, RMC_EINVAL, "bad observer id");
+  ObsHost &o = c->obs[id];
+  const bool f32 = c->precision == RMC_FP32_BULK;
+  const int64_t n = (int64_t)o.n_elems;
+  if ((dtype == RMC_F64) == !f32) {
+    const size_t bytes = n * (f32 ? 4 : 8);
+    HIPCHK(c, hipMemcpyAsync(out, o.cube.p, bytes, mem == RMC_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                             c->stream));
+  } else {
+    const size_t bytes = n * (dtype == RMC_F64 ? 8 : 4);
+    void *dst = out;
+    if (mem != RMC_DEVICE) {
+      HIPCHK(c, c->tmp3.ensure(bytes));
+      dst = c->tmp3.p;
+    }
+    if (dtype == RMC_F64) HIPCHK(c, launch_f32_to_f64(o.cube.as<float>(), (double *)dst, n, c->stream));
+    else HIPCHK(c, launch_f64_to_f32(o.cube.as<double>(), (float *)dst, n, c->stream));
+    if (mem != RMC_DEVICE) HIPCHK(c, hipMemcpyAsync(out, dst, bytes, hipMemcpyDeviceToHost, c->stream));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return RMC_OK;
+}
+
+rmc_status rmc_trace_cells(rmc_ctx *c, int64_t n, const double *orig, const double *dir, int32_t max_cells,
+                           int32_t *leaf_out, double *seg_out, int32_t *n_out, int mem) {
+  rmc_status r = enter(c);
+  if (r) return r;
+  if (!c->has_mesh) return fail(c, RMC_ESTATE, "no mesh");
+  if (n <= 0 || max_cells <= 0 || !orig || !dir || !leaf_out || !seg_out || !n_out) return fail(c, RMC_EINVAL, "bad trace arguments");
+  ProblemK pb;
+  std::memset(&pb, 0, sizeof pb);
+  pb.nodes = c->nodes.as<int32_t>();
+  pb.L = c->L;
+  pb.domain = c->domain;
+  for (int d = 0; d < 4; ++d) pb.dom[d] = c->dom[d];
+  const double *o = orig, *k = dir;
+  int32_t *lo = leaf_out, *no = n_out;
+  double *so = seg_out;
+  const size_t cells = (size_t)n * max_cells;
+  if (mem != RMC_DEVICE) {
+    if ((r = upload(c, c->tmp1, orig, n * 24, RMC_HOST))) return r;
+    if ((r = upload(c, c->tmp2, dir, n * 24, RMC_HOST))) return r;
+    HIPCHK(c, c->tmp3.ensure(cells * 4));
+    HIPCHK(c, c->tmp4.ensure(cells * 8));
+    HIPCHK(c, c->tmp5.ensure(n * 4));
+    o = c->tmp1.as<double>();
+    k = c->tmp2.as<double>();
+    lo = c->tmp3.as<int32_t>();
+    so = c->tmp4.as<double>();
+    no = c->tmp5.as<int32_t>();
+  }
+  HIPCHK(c, launch_trace(pb, n, o, k, max_cells, lo, so, no, c->stream));
+  if (mem != RMC_DEVICE) {
+    HIPCHK(c, hipMemcpyAsync(leaf_out, lo, cells * 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(seg_out, so, cells * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(n_out, no, n * 4, hipMemcpyDeviceToHost, c->stream));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return RMC_OK;
+}
+
+rmc_status rmc_tau(rmc_ctx *c, int64_t n, const double *orig, const double *dir, const double *x_ext, double *tau_out,
+                   int mem) {
+  rmc_status r = enter(c);
+  if (r) return r;
+  r = ready(c, false);
+  if (r) return r;
+  if (n <= 0 || !orig || !dir || !x_ext || !tau_out) return fail(c, RMC_EINVAL, "bad tau arguments");
+  ProblemK pb;
+  make_problem(c, 0, 0, 0, pb);
+  const double *o = orig, *k = dir, *x = x_ext;
+  double *t = tau_out;
+  if (mem != RMC_DEVICE) {
+    if ((r = upload(c, c->tmp1, orig, n * 24, RMC_HOST))) return r;
+    if ((r = upload(c, c->tmp2, dir, n * 24, RMC_HOST))) return r;
+    if ((r = upload(c, c->tmp3, x_ext, n * 8, RMC_HOST))) return r;
+    HIPCHK(c, c->tmp4.ensure(n * 8));
+    o = c->tmp1.as<double>();
+    k = c->tmp2.as<double>();
+    x = c->tmp3.as<double>();
+    t = c->tmp4.as<double>();
+  }
+  HIPCHK(c, launch_tau(c->precision == RMC_FP32_BULK, pb, n, o, k, x, t, c->stream));
+  if (mem != RMC_DEVICE) HIPCHK(c, hipMemcpyAsync(tau_out, t, n * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return RMC_OK;
+}
+
+static rmc_status image_common(rmc_ctx *c, int id, int64_t n, const double *orig, const double *x_ext, const double *w,
+                               int mem, const double **o, const double **x, const double **ww) {
+  rmc_status r = ready(c, false);
+  if (r) return r;
+  if (id < 0 || id >= (int)c->obs.size()) return fail(c, RMC_EINVAL, "bad observer id");
+  if (n <= 0 || !orig || !x_ext || !w) return fail(c, RMC_EINVAL, "bad ray arguments");
+  *o = orig;
+  *x = x_ext;
+  *ww = w;
+  if (mem != RMC_DEVICE) {
+    if ((r = upload(c, c->tmp1, orig, n * 24, RMC_HOST))) return r;
+    if ((r = upload(c, c->tmp2, x_ext, n * 8, RMC_HOST))) return r;
+    if ((r = upload(c, c->tmp3, w, n * 8, RMC_HOST))) return r;
+    *o = c->tmp1.as<double>();
+    *x = c->tmp2.as<double>();
+    *ww = c->tmp3.as<double>();
+  }
+  HIPCHK(c, c->d_stats.ensure(N_STATS * 8));
+  HIPCHK(c, launch_fill_u64(c->d_stats.as<unsigned long long>(), N_STATS, 0ull, c->stream));
+  return RMC_OK;
+}
+
+rmc_status rmc_raycast_image(rmc_ctx *c, int id, int64_t n, const double *orig, const double *x_ext, const double *w,
+                             double *image, int mem) {
+  rmc_status r = enter(c);
+  if (r) return r;
+  const double *o, *x, *ww;
+  if ((r = image_common(c, id, n, orig, x_ext, w, mem, &o, &x, &ww))) return r;
+  if (!image) return fail(c, RMC_EINVAL, "null image");
+  ProblemK pb;
+  make_problem(c, 0, 0, 0, pb);
+  const size_t npix = (size_t)c->obs[id].k.nx * c->obs[id].k.ny;
+  double *img = image;
+  if (mem != RMC_DEVICE) {
+    HIPCHK(c, c->tmp4.ensure(npix * 8));
+    img = c->tmp4.as<double>();
+  }
+  HIPCHK(c, hipMemsetAsync(img, 0, npix * 8, c->stream));
+  HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+  HIPCHK(c, launch_image_fwd(c->precision == RMC_FP32_BULK, pb, id, n, o, x, ww, img,
+                             c->d_stats.as<unsigned long long>() + S_PEEL_CROSS, c->stream));
+  HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+  if (mem != RMC_DEVICE) HIPCHK(c, hipMemcpyAsync(image, img, npix * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return RMC_OK;
+}
+
+rmc_status rmc_raycast_image_backward(rmc_ctx *c, int id, int64_t n, const double *orig, const double *x_ext,
+                                      const double *w, const double *G, double *gn, double *gk, double *gv, int mem) {
+  rmc_status r = enter(c);
+  if (r) return r;
+  const double *o, *x, *ww;
+  if ((r = image_common(c, id, n, orig, x_ext, w, mem, &o, &x, &ww))) return r;
+  if (!G || !gn || !gk || !gv) return fail(c, RMC_EINVAL, "null gradient buffer");
+  ProblemK pb;
+  make_problem(c, 0, 0, 0, pb);
+  const size_t npix = (size_t)c->obs[id].k.nx * c->obs[id].k.ny;
+  const size_t nl = (size_t)c->n_leaves;
+  const double *Gd = G;
+  double *a = gn, *b = gk, *d = gv;
+  if (mem != RMC_DEVICE) {
+    if ((r = upload(c, c->tmp4, G, npix * 8, RMC_HOST))) return r;
+    Gd = c->tmp4.as<double>();
+    HIPCHK(c, c->tmp5.ensure(nl * 24));
+    a = c->tmp5.as<double>();
+    b = a + nl;
+    d = b + nl;
+  }
+  HIPCHK(c, hipMemsetAsync(a, 0, nl * 8, c->stream));
+  HIPCHK(c, hipMemsetAsync(b, 0, nl * 8, c->stream));
+  HIPCHK(c, hipMemsetAsync(d, 0, nl * 8, c->stream));
+  const double inv_vth_ref = 1.0 / line_q(c->lines[0], c->T_ref).vth;
+  HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+  HIPCHK(c, launch_image_bwd(c->precision == RMC_FP32_BULK, pb, id, n, o, x, ww, Gd, inv_vth_ref, a, b, d,
+                             c->d_stats.as<unsigned long long>() + S_PEEL_CROSS, c->stream));
+  HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+  if (mem != RMC_DEVICE) {
+    HIPCHK(c, hipMemcpyAsync(gn, a, nl * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(gk, b, nl * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(gv, d, nl * 8, hipMemcpyDeviceToHost, c->stream));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return RMC_OK;
+}
+
+rmc_status rmc_batch_run(rmc_ctx *const *P, int np, const uint64_t *seeds, const int64_t *npk,
+                         rmc_run_stats *per, rmc_run_stats *total) {
+  if (!P || np <= 0 || !seeds || !npk) return RMC_EINVAL;
+  rmc_ctx *c0 = P[0];
+  rmc_status r = enter(c0);
+  if (r) return r;
+  int maxL = 1;
+  for (int i = 0; i < np; ++i) {
+    rmc_ctx *c = P[i];
+    if (!c || c->device != c0->device || c->precision != c0->precision)
+      return fail(c0, RMC_EINVAL, "problem %d: contexts must share device and precision", i);
+    r = ready(c, true);
+    if (r) return fail(c0, r, "problem %d: %s", i, c->err.c_str());
+    if (npk[i] < 0 || npk[i] > c->n_src) return fail(c0, RMC_EINVAL, "problem %d: packet count outside the sources", i);
+    r = ensure_outputs(c, npk[i]);
+    if (r) return fail(c0, r, "problem %d: %s", i, c->err.c_str());
+    maxL = std::max(maxL, c->L);
+  }
+  c0->b_host.resize(np);
+  c0->b_starts_host.assign(np + 1, 0);
+  for (int i = 0; i < np; ++i) {
+    P[i]->last_n = npk[i];
+    make_problem(P[i], 0, npk[i], seeds[i], c0->b_host[i]);
+    c0->b_starts_host[i + 1] = c0->b_starts_host[i] + npk[i];
+  }
+  const int64_t tot = c0->b_starts_host[np];
+  HIPCHK(c0, c0->b_probs.ensure(sizeof(ProblemK) * np));
+  HIPCHK(c0, c0->b_starts.ensure(8 * (np + 1)));
+  HIPCHK(c0, c0->d_next.ensure(8));
+  HIPCHK(c0, hipMemcpyAsync(c0->b_probs.p, c0->b_host.data(), sizeof(ProblemK) * np, hipMemcpyHostToDevice, c0->stream));
+  HIPCHK(c0, hipMemcpyAsync(c0->b_starts.p, c0->b_starts_host.data(), 8 * (np + 1), hipMemcpyHostToDevice, c0->stream));
+  const int grid = grid_for(c0, tot);
+  // the launch sequence is captured once per shape and replayed
+  char key[256];
+  snprintf(key, sizeof key, "%p/%p/%d/%d/%d/%d/%d/%d", c0->b_probs.p, c0->b_starts.p, np, grid, c0->block, c0->refill,
+           maxL, c0->precision);
+  if (c0->b_key != key || !c0->b_graph) {
+    if (c0->b_graph) {
+      (void)hipGraphExecDestroy(c0->b_graph);
+      c0->b_graph = nullptr;
+    }
+    hipStream_t cap = nullptr;
+    HIPCHK(c0, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) e = launch_batch_reset(c0->b_probs.as<ProblemK>(), np, c0->d_next.as<unsigned long long>(), cap);
+    if (e == hipSuccess)
+      e = launch_transport(c0->precision == RMC_FP32_BULK, true, c0->b_probs.as<ProblemK>(), c0->b_starts.as<int64_t>(),
+                           np, c0->d_next.as<unsigned long long>(), c0->refill, maxL, grid, c0->block, cap);
+    hipError_t e2 = hipStreamEndCapture(cap, &g);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&c0->b_graph, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) return fail(c0, RMC_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+    c0->b_key = key;
+  }
+  HIPCHK(c0, hipEventRecord(c0->ev0, c0->stream));
+  HIPCHK(c0, hipGraphLaunch(c0->b_graph, c0->stream));
+  HIPCHK(c0, hipEventRecord(c0->ev1, c0->stream));
+  std::vector<unsigned long long> h((size_t)np * N_STATS);
+  for (int i = 0; i < np; ++i)
+    HIPCHK(c0, hipMemcpyAsync(h.data() + (size_t)i * N_STATS, P[i]->d_stats.p, N_STATS * 8, hipMemcpyDeviceToHost,
+                              c0->stream));
+  HIPCHK(c0, hipStreamSynchronize(c0->stream));
+  float ms = 0.f;
+  HIPCHK(c0, hipEventElapsedTime(&ms, c0->ev0, c0->ev1));
+  unsigned long long t[N_STATS] = {0};
+  for (int i = 0; i < np; ++i) {
+    if (per) fill_stats(per + i, h.data() + (size_t)i * N_STATS, ms);
+    for (int s = 0; s < N_STATS; ++s) t[s] += h[(size_t)i * N_STATS + s];
+    if ((int64_t)h[(size_t)i * N_STATS + S_EMITTED] != npk[i])
+      return fail(c0, RMC_EDEVICE, "problem %d finished %llu of %lld packets", i, h[(size_t)i * N_STATS + S_EMITTED],
+                  (long long)npk[i]);
+  }
+  if (total) fill_stats(total, t, ms);
+  return RMC_OK;
+}
+
+rmc_status rmc_mesh_check(int64_t n, const int8_t *level, const int32_t *ijk, char *msg, int msg_len) {
+  std::vector<int32_t> nodes;
+  int L = 0;
+  std::string m;
+  rmc_status r = build_tree(n, level, ijk, nodes, L, m);
+  if (msg && msg_len > 0) {
+    std::strncpy(msg, m.c_str(), (size_t)msg_len - 1);
+    msg[msg_len - 1] = 0;
+  }
+  return r;
+}
+
+rmc_status rmc_line_quantities(const rmc_line *ln, double T, double out[5]) {
+  if (!ln || !out || !(T > 0) || !(ln->lambda0_A > 0) || !(ln->mass_amu > 0)) return RMC_EINVAL;
+  const LineQ q = line_q(*ln, T);
+  out[0] = q.nu0;
+  out[1] = q.vth;
+  out[2] = q.dnu;
+  out[3] = q.a;
+  out[4] = q.sigma0;
+  return RMC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,513 @@
+// rmc_device.h -- device-side data layout and building blocks of the
+// resonant-line Monte Carlo kernels (gfx950).
+//
+// Method: Michel-Dansac et al. 2020 (RASCAS).  Frequencies are carried as
+// x_ext, the external-frame offset from the first line's rest frequency in
+// Doppler widths of that line at T_ref; every per-cell quantity is expressed
+// relative to T_ref so that all float work stays O(1):
+//   per leaf   nl = n_HI box / rho, irho = 1/rho, rho = sqrt(T/T_ref),
+//              kd = kappa_d box, u = v / v_th,ref
+//   per line   s = nu_ref/nu_i, delta = (s-1)/b_ref, inv_mu = sqrt(m_i/m_ref),
+//              alpha = a_i(T_ref), kfac = abundance sigma0_i(T_ref)
+// so that in a leaf, for a packet moving along k with w = k.u,
+//   x_i = (delta + s x_ext - w) irho inv_mu / (1 + b_ref w)
+//   kappa_i box = nl kfac H(alpha irho, x_i)
+// (Sect. 3.1.1 cross-section, Sect. 3 frame relation nu_ext = nu(1+k.v/c)).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rmc {
+
+constexpr int MAX_LEVEL = 16;
+constexpr int MAX_LINES = 4;
+constexpr int MAX_OBS = 4;
+constexpr int LEAF_STRIDE = 8;   // values per leaf record (6 used, padded)
+// A packet or ray that has crossed this many leaves is stopped (a packet
+// gets status stuck): it bounds the walk of a ray parallel to a periodic slab.
+constexpr uint32_t MAX_CROSS = 1u << 24;
+constexpr double PI_D = 3.14159265358979323846;
+
+enum { DOM_BOX = 0, DOM_SLAB_Z = 1, DOM_SPHERE = 2 };
+enum { PHASE_LYA = 0, PHASE_ISO = 1 };
+enum { ST_NONE = 0, ST_ESCAPED = 1, ST_ABSORBED = 2, ST_STUCK = 3 };
+enum {
+  S_EMITTED = 0, S_ESCAPED, S_ABSORBED, S_STUCK, S_SCAT, S_DUST_SCAT, S_CROSS,
+  S_PEEL_RAYS, S_PEEL_CROSS, S_PEEL_DROPPED, N_STATS
+};
+
+struct LineK {
+  double delta, s, inv_s, inv_mu, mu, alpha, kfac;
+  double rec;      // h nu_i / (m_i c^2)
+  int phase, recoil;
+};
+
+struct ObsK {
+  double k[3], e1[3], e2[3];
+  double u0, uspan, v0, vspan, x_min, xspan;
+  int nx, ny, nbins, pad;
+  void *cube;      // [ny][nx][nbins], float or double by precision
+};
+
+struct ProblemK {
+  const int32_t *nodes;     // [n_nodes][8]: >=0 child node, <0: -(leaf+1)
+  const void *leaves;       // [n_leaves][LEAF_STRIDE] float or double
+  int L;                    // deepest leaf level
+  int n_lines;
+  LineK lines[MAX_LINES];
+  double b_ref;             // v_th(T_ref, line 0) / c
+  double box_cm;
+  int domain;
+  double dom[4];
+  double albedo, g_hg;
+  int forward_only;
+  int64_t max_events;
+  // sources (device)
+  const double *src_pos, *src_dir, *src_x;
+  int64_t first, n;         // packet range of this run
+  uint64_t seed;
+  // per-packet outputs, indexed pid - first
+  int32_t *status, *nscat;
+  double *x_out, *k_out, *pos_out, *path_out;
+  int n_obs;
+  ObsK obs[MAX_OBS];
+  unsigned long long *stats; // [N_STATS]
+};
+
+// ------------------------------------------------------------------ Philox
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
+    c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+    k.x += 0x9E3779B9u;
+    k.y += 0xBB67AE85u;
+  }
+  return c;
+}
+
+// Slots of the uniforms of one event (counter = pid, event, block).
+enum {
+  J_CHANNEL = 0,  // dust or which line
+  J_MU = 1,       // scattering-angle cosine (emission: direction cosine)
+  J_PHI = 2,      // azimuth
+  J_TAU = 3,      // optical depth to the next event
+  J_PERP1 = 4,    // Box-Muller pair for the two perpendicular atom velocities
+  J_PERP2 = 5,
+  J_ALBEDO = 6,   // dust: scatter or absorb
+  J_GAUSS1 = 6,   // line, |x| >= 8: Box-Muller pair for the Gaussian
+  J_GAUSS2 = 7,
+  J_REJ = 6       // line, |x| < 8: rejection round i uses J_REJ+3i .. +2
+};
+
+// Uniforms of one event.  Double: draw j uses the word pair (2(j%2),
+// 2(j%2)+1) of block j/2 and returns (2m+1) 2^-53 with m the top 52 bits.
+// Float: draw j uses word j%4 of block j/4 and returns (2m+1) 2^-24 with m
+// the top 23 bits.  Both lie strictly inside (0,1).
+template <class R> struct EventRng;
+
+template <> struct EventRng<double> {
+  uint2 key;
+  uint32_t plo, phi, ev;
+  uint32_t cur;
+  uint4 w;
+  __device__ EventRng(uint64_t seed, uint64_t pid, uint32_t event)
+      : key(make_uint2((uint32_t)seed, (uint32_t)(seed >> 32))), plo((uint32_t)pid),
+        phi((uint32_t)(pid >> 32)), ev(event), cur(0xffffffffu) {}
+  __device__ double u(uint32_t j) {
+    const uint32_t b = j >> 1;
+    if (b != cur) {
+      w = philox4x32_10(make_uint4(plo, phi, ev, b), key);
+      cur = b;
+    }
+    const uint32_t hi = (j & 1) ? w.z : w.x;
+    const uint32_t lo = (j & 1) ? w.w : w.y;
+    const uint64_t m = ((uint64_t)hi << 20) | (uint64_t)(lo >> 12);
+    return (double)(2 * m + 1) * 0x1p-53;
+  }
+};
+
+template <> struct EventRng<float> {
+  uint2 key;
+  uint32_t plo, phi, ev;
+  uint32_t cur;
+  uint4 w;
+  __device__ EventRng(uint64_t seed, uint64_t pid, uint32_t event)
+      : key(make_uint2((uint32_t)seed, (uint32_t)(seed >> 32))), plo((uint32_t)pid),
+        phi((uint32_t)(pid >> 32)), ev(event), cur(0xffffffffu) {}
+  __device__ float u(uint32_t j) {
+    const uint32_t b = j >> 2;
+    if (b != cur) {
+      w = philox4x32_10(make_uint4(plo, phi, ev, b), key);
+      cur = b;
+    }
+    const uint32_t q = j & 3;
+    const uint32_t x = q == 0 ? w.x : (q == 1 ? w.y : (q == 2 ? w.z : w.w));
+    return (float)(2u * (x >> 9) + 1u) * 0x1p-24f;
+  }
+};
+
+// ------------------------------------------------------------ math policy
+template <class R> struct M;
+template <> struct M<double> {
+  static __device__ __forceinline__ double exp(double x) { return ::exp(x); }
+  static __device__ __forceinline__ double log(double x) { return ::log(x); }
+  static __device__ __forceinline__ double log10(double x) { return ::log10(x); }
+  static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
+  static __device__ __forceinline__ double cbrt(double x) { return ::cbrt(x); }
+  static __device__ __forceinline__ double atan(double x) { return ::atan(x); }
+  static __device__ __forceinline__ double tan(double x) { return ::tan(x); }
+  static __device__ __forceinline__ void sincos2pi(double r, double *s, double *c) {
+    ::sincospi(2.0 * r, s, c);
+  }
+  static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+};
+template <> struct M<float> {
+  static __device__ __forceinline__ float exp(float x) { return __expf(x); }
+  static __device__ __forceinline__ float log(float x) { return __logf(x); }
+  static __device__ __forceinline__ float log10(float x) { return __log10f(x); }
+  static __device__ __forceinline__ float sqrt(float x) { return __fsqrt_rn(x); }
+  static __device__ __forceinline__ float cbrt(float x) { return ::cbrtf(x); }
+  static __device__ __forceinline__ float atan(float x) { return ::atanf(x); }
+  static __device__ __forceinline__ float tan(float x) {
+    float s, c;
+    __sincosf(x, &s, &c);
+    return __fdividef(s, c);
+  }
+  static __device__ __forceinline__ void sincos2pi(float r, float *s, float *c) {
+    ::sincospif(2.0f * r, s, c);
+  }
+  static __device__ __forceinline__ float rcp(float x) { return __frcp_rn(x); }
+};
+
+// ---------------------------------------------------------------- Voigt H
+// Tasitsiomi (2006) form named in Sect. 3.3.2:
+//   z = (x^2 - 0.855)/(x^2 + 3.42); q = 0 (z <= 0) else
+//   z (1 + 21/x^2) (a/pi)/(x^2+1) (((5.674 z - 9.207) z + 4.421) z + 0.1117)
+//   H = sqrt(pi) q + exp(-x^2)
+template <class R> __device__ __forceinline__ R voigt_h(R a, R x) {
+  const R x2 = x * x;
+  const R z = (x2 - R(0.855)) / (x2 + R(3.42));
+  R h = M<R>::exp(-x2);
+  if (z > R(0)) {
+    const R P = ((R(5.674) * z - R(9.207)) * z + R(4.421)) * z + R(0.1117);
+    const R q = z * (R(1) + R(21) / x2) * (a * R(1.0 / PI_D)) / (x2 + R(1)) * P;
+    h += R(1.7724538509055160273) * q;
+  }
+  return h;
+}
+
+// dH/dx of the same form.
+template <class R> __device__ __forceinline__ R voigt_dhdx(R a, R x) {
+  const R x2 = x * x;
+  const R z = (x2 - R(0.855)) / (x2 + R(3.42));
+  R d = R(-2) * x * M<R>::exp(-x2);
+  if (z > R(0)) {
+    const R den = x2 + R(3.42);
+    const R dz = R(2) * x * R(4.275) / (den * den);
+    const R P = ((R(5.674) * z - R(9.207)) * z + R(4.421)) * z + R(0.1117);
+    const R dP = (R(17.022) * z - R(18.414)) * z + R(4.421);
+    const R f2 = R(1) + R(21) / x2, df2 = R(-42) / (x2 * x);
+    const R f3 = (a * R(1.0 / PI_D)) / (x2 + R(1));
+    const R df3 = -f3 * R(2) * x / (x2 + R(1));
+    const R dq = dz * f2 * f3 * P + z * df2 * f3 * P + z * f2 * df3 * P + z * f2 * f3 * dP * dz;
+    d += R(1.7724538509055160273) * dq;
+  }
+  return d;
+}
+
+// ---------------------------------------------------- atom velocity draw
+// Sect. 3.3.3: rejection sampling of f(u) ~ exp(-u^2)/(a^2+(x-u)^2) with a
+// two-piece Lorentzian envelope split at u0(x, log10 a) (the paper's fit,
+// clamped at 0 where it goes negative); |x| >= 8: Gaussian of variance 1/2
+// centred at 1/x; negative x by symmetry.
+template <class R> __device__ __forceinline__ R u0_fit(R x, R la) {
+  const R c0 = R(2.648963) + la * (R(2.014446) + la * R(0.351479));
+  const R c1 = R(-4.058673) + la * (R(-3.675859) + la * R(-0.640003));
+  const R c2 = R(3.017395) + la * (R(2.117133) + la * R(0.370294));
+  const R c3 = R(-0.869789) + la * (R(-0.565886) + la * R(-0.096312));
+  const R c4 = R(0.110987) + la * (R(0.070103) + la * R(0.011557));
+  const R c5 = R(-0.005200) + la * (R(-0.003240) + la * R(-0.000519));
+  return c0 + x * (c1 + x * (c2 + x * (c3 + x * (c4 + x * c5))));
+}
+
+// Rejection rounds allowed per draw; a packet that exhausts them stops
+// with status stuck (never reached for finite x and a > 0).
+constexpr uint32_t MAX_REJECT = 1u << 20;
+
+template <class R>
+__device__ __forceinline__ bool sample_upar(R x, R a, EventRng<R> &rng, uint32_t *iters, R *out) {
+  if (fabs(x) >= R(8)) {
+    R s, c;
+    M<R>::sincos2pi(rng.u(J_GAUSS2), &s, &c);
+    *out = R(1) / x + M<R>::sqrt(-M<R>::log(rng.u(J_GAUSS1))) * c;
+    return true;
+  }
+  const R sg = x < R(0) ? R(-1) : R(1);
+  const R xa = fabs(x);
+  R u0 = u0_fit(xa, M<R>::log10(a));
+  u0 = u0 < R(0) ? R(0) : u0;
+  const R th0 = M<R>::atan((u0 - xa) / a);
+  const R e0 = M<R>::exp(-u0 * u0);
+  const R hp = R(0.5 * PI_D);
+  const R p1 = (th0 + hp) / ((R(1) - e0) * th0 + (R(1) + e0) * hp);
+  const R u02 = u0 * u0;
+  for (uint32_t it = 0; it < MAX_REJECT; ++it) {
+    const R r1 = rng.u(J_REJ + 3 * it);
+    const R r2 = rng.u(J_REJ + 3 * it + 1);
+    const R r3 = rng.u(J_REJ + 3 * it + 2);
+    R th, lim;
+    if (r1 < p1) {
+      th = -hp + r2 * (th0 + hp);
+      lim = R(0);
+    } else {
+      th = th0 + r2 * (hp - th0);
+      lim = u02;
+    }
+    const R u = xa + a * M<R>::tan(th);
+    if (r3 < M<R>::exp(lim - u * u)) {
+      *iters += it + 1;
+      *out = sg * u;
+      return true;
+    }
+  }
+  *out = R(0);
+  return false;
+}
+
+// Sect. 3.3.1 inverse CDFs.
+template <class R> __device__ __forceinline__ R mu_core(R r) {
+  const R B = R(6) * (R(2) * r - R(1));
+  const R A = M<R>::sqrt(B * B + R(11.0 * 11.0 * 11.0 / 27.0));
+  return M<R>::cbrt(A + B) - M<R>::cbrt(A - B);
+}
+template <class R> __device__ __forceinline__ R mu_wing(R r) {
+  const R B = R(4) * r - R(2);
+  const R A = M<R>::sqrt(B * B + R(1));
+  return M<R>::cbrt(A + B) - M<R>::cbrt(A - B);
+}
+// Henyey-Greenstein inverse, with the square of the exact inverse.
+template <class R> __device__ __forceinline__ R mu_hg(R r, R g) {
+  if (g == R(0)) return R(2) * r - R(1);
+  const R t = (R(1) - g * g) / (R(1) - g + R(2) * g * r);
+  return (R(1) + g * g - t * t) / (R(2) * g);
+}
+template <class R> __device__ __forceinline__ R p_core(R mu) { return R(11.0 / 24.0) + R(3.0 / 24.0) * mu * mu; }
+template <class R> __device__ __forceinline__ R p_wing(R mu) { return R(3.0 / 8.0) * (R(1) + mu * mu); }
+template <class R> __device__ __forceinline__ R p_hg(R mu, R g) {
+  const R d = R(1) + g * g - R(2) * g * mu;
+  return R(0.5) * (R(1) - g * g) / (d * M<R>::sqrt(d));
+}
+
+// Orthonormal pair perpendicular to k: e1 = normalize(k x z) (k x x when
+// |k_z| > 0.9), e2 = k x e1.
+template <class R> __device__ __forceinline__ void perp_basis(const R k[3], R e1[3], R e2[3]) {
+  R c0, c1, c2;
+  if (fabs(k[2]) > R(0.9)) { c0 = R(0); c1 = k[2]; c2 = -k[1]; }
+  else { c0 = k[1]; c1 = -k[0]; c2 = R(0); }
+  const R n = R(1) / M<R>::sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+  e1[0] = c0 * n; e1[1] = c1 * n; e1[2] = c2 * n;
+  e2[0] = k[1] * e1[2] - k[2] * e1[1];
+  e2[1] = k[2] * e1[0] - k[0] * e1[2];
+  e2[2] = k[0] * e1[1] - k[1] * e1[0];
+}
+
+// ------------------------------------------------------------- geometry
+// All traversal arithmetic is double, uncontracted, with the fma written
+// out, so that the cell sequence is an exact function of the inputs.
+#pragma clang fp contract(off)
+
+struct Cell {
+  int leaf;        // leaf index
+  int level;       // leaf level
+  int ox, oy, oz;  // origin in deepest-level integer units
+};
+
+// Distance along k from p to the face through which the packet leaves the
+// cell; exit axes are flagged in *emask.
+__device__ __forceinline__ double exit_dist(const Cell &c, int L, const double p[3],
+                                            const double k[3], double face[3], double lo[3],
+                                            double hi[3], int *emask) {
+  const double inv = ldexp(1.0, -L);
+  const int s = 1 << (L - c.level);
+  const int o[3] = {c.ox, c.oy, c.oz};
+  double td[3];
+  double t = __builtin_inf();
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = (double)o[d] * inv;
+    hi[d] = (double)(o[d] + s) * inv;
+    if (k[d] > 0.0) { face[d] = hi[d]; td[d] = (face[d] - p[d]) / k[d]; }
+    else if (k[d] < 0.0) { face[d] = lo[d]; td[d] = (face[d] - p[d]) / k[d]; }
+    else { face[d] = 0.0; td[d] = __builtin_inf(); }
+    t = td[d] < t ? td[d] : t;
+  }
+  if (t < 0.0) t = 0.0;
+  int m = 0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) m |= (td[d] <= t) ? (1 << d) : 0;
+  *emask = m;
+  return t;
+}
+
+// The point where the packet leaves: exit axes snapped onto the face, the
+// others advanced by one fma and clamped into the cell.
+__device__ __forceinline__ void exit_point(double t, int emask, const double p[3], const double k[3],
+                                           const double face[3], const double lo[3],
+                                           const double hi[3], double pn[3]) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (emask & (1 << d)) pn[d] = face[d];
+    else {
+      const double q = fma(t, k[d], p[d]);
+      pn[d] = fmin(fmax(q, lo[d]), hi[d]);
+    }
+  }
+}
+
+// Distance along k to the domain border (Sect. 4 domain classes).
+__device__ __forceinline__ double domain_dist(int kind, const double dom[4], const double p[3],
+                                              const double k[3]) {
+  double t = __builtin_inf();
+  if (kind == DOM_BOX) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      double td = __builtin_inf();
+      if (k[d] > 0.0) td = (1.0 - p[d]) / k[d];
+      else if (k[d] < 0.0) td = (0.0 - p[d]) / k[d];
+      t = td < t ? td : t;
+    }
+  } else if (kind == DOM_SLAB_Z) {
+    if (k[2] > 0.0) t = ((dom[0] + dom[1]) - p[2]) / k[2];
+    else if (k[2] < 0.0) t = ((dom[0] - dom[1]) - p[2]) / k[2];
+  } else {
+    const double dx = p[0] - dom[0], dy = p[1] - dom[1], dz = p[2] - dom[2];
+    const double R = dom[3];
+    const double b = dx * k[0] + dy * k[1] + dz * k[2];
+    const double q = dx * dx + dy * dy + dz * dz - R * R;
+    const double disc = b * b - q;
+    if (disc < 0.0) return 0.0;
+    const double sq = sqrt(disc);
+    t = (b > 0.0) ? -q / (b + sq) : -b + sq;
+  }
+  return t < 0.0 ? 0.0 : t;
+}
+
+__device__ __forceinline__ void wrap_slab(int kind, double p[3], const double k[3]) {
+  if (kind != DOM_SLAB_Z) return;
+#pragma unroll
+  for (int d = 0; d < 2; ++d) {
+    if (k[d] > 0.0 && p[d] >= 1.0) p[d] = 0.0;
+    else if (k[d] < 0.0 && p[d] <= 0.0) p[d] = 1.0;
+  }
+}
+
+// Integer point location: floor(p 2^L) along k_d >= 0, ceil(p 2^L) - 1
+// otherwise; false if outside the unit cube.
+__device__ __forceinline__ bool int_coords(int L, const double p[3], const double k[3], int X[3]) {
+  const double sc = (double)(1 << L);
+  const int side = 1 << L;
+  bool in = true;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double s = p[d] * sc;
+    const double f = (k[d] >= 0.0) ? floor(s) : ceil(s) - 1.0;
+    in = in && (f >= 0.0) && (f < (double)side);
+    X[d] = in ? (int)f : 0;
+  }
+  return in;
+}
+
+// Descend the breadth-first node array from `node` at `level` to the leaf
+// holding integer point X, recording the nodes passed in the per-lane LDS
+// stack (stack[level*stride]).
+__device__ __forceinline__ void descend(const int32_t *__restrict__ nodes, int L, int node, int level,
+                                        const int X[3], int *stack, int stride, Cell &c) {
+  if (L == 0) {  // a single leaf covers the cube
+    c.leaf = 0; c.level = 0; c.ox = c.oy = c.oz = 0;
+    return;
+  }
+  while (true) {
+    stack[level * stride] = node;
+    const int sh = L - level - 1;
+    const int oct = ((X[0] >> sh) & 1) | (((X[1] >> sh) & 1) << 1) | (((X[2] >> sh) & 1) << 2);
+    const int ch = nodes[node * 8 + oct];
+    ++level;
+    if (ch < 0) {
+      c.leaf = -ch - 1;
+      c.level = level;
+      const int clr = ~((1 << (L - level)) - 1);
+      c.ox = X[0] & clr; c.oy = X[1] & clr; c.oz = X[2] & clr;
+      return;
+    }
+    node = ch;
+  }
+}
+
+// Move to the leaf holding X after leaving cell c: restart the descent at
+// the deepest common ancestor of c and X, read from the LDS stack.
+__device__ __forceinline__ void relocate(const int32_t *__restrict__ nodes, int L, const int X[3],
+                                         int *stack, int stride, Cell &c) {
+  const unsigned diff = (unsigned)((X[0] ^ c.ox) | (X[1] ^ c.oy) | (X[2] ^ c.oz));
+  if (diff == 0u) return;
+  const int b = 31 - __builtin_clz(diff);
+  const int la = L - 1 - b;   // level of the common ancestor node
+  descend(nodes, L, stack[la * stride], la, X, stack, stride, c);
+}
+
+#pragma clang fp contract(fast)
+
+// ------------------------------------------------------------- leaf data
+template <class R> struct LeafRec {
+  R nl, irho, kd, ux, uy, uz;
+};
+
+template <class R>
+__device__ __forceinline__ LeafRec<R> load_leaf(const void *leaves, int i) {
+  LeafRec<R> r;
+  const R *p = (const R *)leaves + (size_t)i * LEAF_STRIDE;
+  if constexpr (sizeof(R) == 4) {
+    const float4 a = *(const float4 *)p;
+    const float2 b = *(const float2 *)(p + 4);
+    r.nl = a.x; r.irho = a.y; r.kd = a.z; r.ux = a.w; r.uy = b.x; r.uz = b.y;
+  } else {
+    const double2 a = *(const double2 *)p;
+    const double2 b = *(const double2 *)(p + 2);
+    const double2 c = *(const double2 *)(p + 4);
+    r.nl = a.x; r.irho = a.y; r.kd = b.x; r.ux = b.y; r.uy = c.x; r.uz = c.y;
+  }
+  return r;
+}
+
+// Opacity (times box size) of a leaf for a packet at x_ext along k.
+template <class R> struct Opac {
+  R kd, kl[MAX_LINES], x[MAX_LINES], ktot, w;
+};
+
+// The numerator delta + s x_ext - w is formed in double in both precisions:
+// for gas moving many thermal widths it is a small difference of large
+// terms, and float would lose the core of the profile.
+template <class R>
+__device__ __forceinline__ void opacity(const ProblemK &pb, const LeafRec<R> &lf, double x_ext, const R k[3],
+                                        Opac<R> &o) {
+  const double wd = (double)k[0] * (double)lf.ux + (double)k[1] * (double)lf.uy + (double)k[2] * (double)lf.uz;
+  o.w = (R)wd;
+  const R inv_den = R(1) / (R(1) + R(pb.b_ref) * o.w);
+  o.kd = lf.kd;
+  o.ktot = lf.kd;
+#pragma unroll
+  for (int i = 0; i < MAX_LINES; ++i) {
+    o.x[i] = R(0);
+    o.kl[i] = R(0);
+    if (i < pb.n_lines) {
+      const LineK &ln = pb.lines[i];
+      o.x[i] = (R)(ln.delta + ln.s * x_ext - wd) * lf.irho * R(ln.inv_mu) * inv_den;
+      o.kl[i] = lf.nl * R(ln.kfac) * voigt_h<R>(R(ln.alpha) * lf.irho, o.x[i]);
+      o.ktot += o.kl[i];
+    }
+  }
+}
+
+}  // namespace rmc

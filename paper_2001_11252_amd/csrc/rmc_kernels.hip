@@ -1,0 +1,751 @@
+// rmc_kernels.hip -- gfx950 kernels of the resonant-line Monte Carlo path.
+//
+// k_transport   persistent per-packet propagation loop (Sect. 3, 3.2, 4.3)
+//               with peel-off toward observers at each emission and
+//               scattering (Sect. 5.1); one packet per lane, lanes of a
+//               wave refilled from a global queue with one atomic per wave
+//               (ballot + mbcnt compaction of the idle lanes).
+// k_trace       deterministic cell sequence of rays (probe)
+// k_tau         optical depth of rays to the domain border (probe)
+// k_image_fwd   peel-off image of fixed rays
+// k_image_bwd   its adjoint with respect to per-leaf n_HI, kappa_d, v_los
+// k_hist        spectrum of escaped packets
+#include "rmc_device.h"
+#include "rmc_launch.h"
+
+namespace rmc {
+
+// exp(-tau) is exactly zero (round to nearest) from these optical depths
+// on: a ray may stop integrating there without changing any deposit.
+template <class R> struct TauCut;
+template <> struct TauCut<double> { static constexpr double v = 746.0; };
+template <> struct TauCut<float> { static constexpr double v = 104.0; };
+
+__device__ __forceinline__ void atomic_add_real(float *p, float v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void atomic_add_real(double *p, double v) { unsafeAtomicAdd(p, v); }
+
+// --------------------------------------------------------------- ray cast
+// Optical depth from p along k to the domain border at fixed x_ext (the
+// peel-off integral); stops once tau >= tau_cut.  Uses its own LDS stack.
+template <class R>
+__device__ double ray_tau(const ProblemK &pb, const double p0[3], const double k[3], double x_ext,
+                          double tau_cut, int *stk, int stride, uint32_t *ncross) {
+  double p[3] = {p0[0], p0[1], p0[2]};
+  int X[3];
+  if (!int_coords(pb.L, p, k, X)) return 0.0;
+  const R kr[3] = {(R)k[0], (R)k[1], (R)k[2]};
+  Cell c;
+  descend(pb.nodes, pb.L, 0, 0, X, stk, stride, c);
+  double tau = 0.0;
+  for (uint32_t steps = 0; steps < MAX_CROSS; ++steps) {
+    const LeafRec<R> lf = load_leaf<R>(pb.leaves, c.leaf);
+    Opac<R> o;
+    opacity(pb, lf, x_ext, kr, o);
+    double face[3], lo[3], hi[3];
+    int em;
+    const double te = exit_dist(c, pb.L, p, k, face, lo, hi, &em);
+    const double td = domain_dist(pb.domain, pb.dom, p, k);
+    ++*ncross;
+    if (td <= te) {
+      tau += (double)o.ktot * td;
+      break;
+    }
+    tau += (double)o.ktot * te;
+    if (tau >= tau_cut) break;
+    double pn[3];
+    exit_point(te, em, p, k, face, lo, hi, pn);
+    p[0] = pn[0]; p[1] = pn[1]; p[2] = pn[2];
+    wrap_slab(pb.domain, p, k);
+    if (!int_coords(pb.L, p, k, X)) break;
+    relocate(pb.nodes, pb.L, X, stk, stride, c);
+  }
+  return tau;
+}
+
+// Pixel of position p in observer ob's image, -1 outside.
+__device__ __forceinline__ int pixel_of(const ObsK &ob, const double p[3]) {
+#pragma clang fp contract(off)
+  const double q0 = p[0] - 0.5, q1 = p[1] - 0.5, q2 = p[2] - 0.5;
+  const double u = q0 * ob.e1[0] + q1 * ob.e1[1] + q2 * ob.e1[2];
+  const double v = q0 * ob.e2[0] + q1 * ob.e2[1] + q2 * ob.e2[2];
+  const double fu = (u - ob.u0) / ob.uspan * ob.nx;
+  const double fv = (v - ob.v0) / ob.vspan * ob.ny;
+  if (!(fu >= 0.0 && fu < ob.nx && fv >= 0.0 && fv < ob.ny)) return -1;
+  const int ix = (int)floor(fu), iy = (int)floor(fv);
+  if (ix >= ob.nx || iy >= ob.ny) return -1;
+  return iy * ob.nx + ix;
+}
+
+__device__ __forceinline__ int bin_of(const ObsK &ob, double x) {
+#pragma clang fp contract(off)
+  const double fb = (x - ob.x_min) / ob.xspan * ob.nbins;
+  if (!(fb >= 0.0 && fb < ob.nbins)) return -1;
+  const int b = (int)floor(fb);
+  return b >= ob.nbins ? -1 : b;
+}
+
+struct LaneCount {
+  uint32_t cross, peel_rays, peel_cross, peel_drop, dust_scat;
+};
+
+// What a scattering (or emission) needs to be redone toward an observer.
+template <class R> struct PeelSrc {
+  int kind;        // 0 emission, 1 line, 2 dust
+  R kin[3];
+  R x;             // emission / dust: x_ext of the packet; line: cell-frame x
+  R w;             // k_in . u of the cell (dust)
+  R U[3];          // atom velocity / v_th of the line (line)
+  R bc;            // v_th,line,cell / c (line)
+  R rho;           // sqrt(T/T_ref) (line)
+  int line, core;
+  R ux, uy, uz;    // cell bulk velocity / v_th,ref
+};
+
+template <class R>
+__device__ void peel_all(const ProblemK &pb, const double p[3], const PeelSrc<R> &s, int *stk,
+                         int stride, LaneCount &cnt) {
+  for (int oi = 0; oi < pb.n_obs; ++oi) {
+    const ObsK &ob = pb.obs[oi];
+    const R ko[3] = {(R)ob.k[0], (R)ob.k[1], (R)ob.k[2]};
+    R weight, xo;
+    if (s.kind == 0) {
+      weight = R(1.0 / (4.0 * PI_D));
+      xo = s.x;
+    } else if (s.kind == 1) {
+      const LineK &ln = pb.lines[s.line];
+      const R mu = s.kin[0] * ko[0] + s.kin[1] * ko[1] + s.kin[2] * ko[2];
+      const R P = ln.phase == PHASE_ISO ? R(0.5) : (s.core ? p_core(mu) : p_wing(mu));
+      weight = P * R(1.0 / (2.0 * PI_D));
+      const R dkU = (ko[0] - s.kin[0]) * s.U[0] + (ko[1] - s.kin[1]) * s.U[1] + (ko[2] - s.kin[2]) * s.U[2];
+      const R g1 = R(1) + s.bc * s.x;
+      const R Rr = ln.recoil ? (R(1) - mu) * R(ln.rec) * g1 : R(0);
+      const R xc = (s.x + g1 * dkU - Rr / s.bc) / (R(1) + Rr);
+      const R wo = ko[0] * s.ux + ko[1] * s.uy + ko[2] * s.uz;
+      xo = (R(-ln.delta) + R(ln.mu) * s.rho * xc * (R(1) + R(pb.b_ref) * wo) + wo) * R(ln.inv_s);
+    } else {
+      const R mu = s.kin[0] * ko[0] + s.kin[1] * ko[1] + s.kin[2] * ko[2];
+      weight = p_hg(mu, R(pb.g_hg)) * R(1.0 / (2.0 * PI_D));
+      const R wo = ko[0] * s.ux + ko[1] * s.uy + ko[2] * s.uz;
+      const R b = R(pb.b_ref);
+      xo = (s.x + wo + b * s.x * wo - s.w) / (R(1) + b * s.w);
+    }
+    const int pix = pixel_of(ob, p);
+    const int bin = bin_of(ob, (double)xo);
+    if (pix < 0 || bin < 0) {
+      ++cnt.peel_drop;
+      continue;
+    }
+    ++cnt.peel_rays;
+    uint32_t nc = 0;
+    const double tau = ray_tau<R>(pb, p, ob.k, (double)xo, TauCut<R>::v, stk, stride, &nc);
+    cnt.peel_cross += nc;
+    if (tau >= TauCut<R>::v) continue;
+    const R wgt = weight * M<R>::exp((R)(-tau));
+    atomic_add_real((R *)ob.cube + ((size_t)pix * ob.nbins + bin), wgt);
+  }
+}
+
+// ------------------------------------------------------------- transport
+template <class R> struct Lane {
+  int64_t pid;
+  double p[3];
+  R k[3];
+  double kd[3];    // direction used for geometry (unit in double)
+  R x;
+  double tau, path;
+  uint32_t event, upar_iters;
+  int32_t nscat;
+  Cell c;
+  LeafRec<R> lf;
+  LaneCount cnt;
+};
+
+// Geometry direction: the float direction of the bulk path is renormalised
+// in double so that a packet's displacement equals its path length.
+template <class R> __device__ __forceinline__ void set_geom_dir(Lane<R> &s) {
+  if constexpr (sizeof(R) == 4) {
+    const double a = s.k[0], b = s.k[1], c = s.k[2];
+    const double inv = 1.0 / sqrt(a * a + b * b + c * c);
+    s.kd[0] = a * inv; s.kd[1] = b * inv; s.kd[2] = c * inv;
+  } else {
+    s.kd[0] = s.k[0]; s.kd[1] = s.k[1]; s.kd[2] = s.k[2];
+  }
+}
+
+template <class R>
+__device__ void finish(const ProblemK &pb, Lane<R> &s, int status) {
+  const int64_t i = s.pid - pb.first;
+  pb.status[i] = status;
+  pb.x_out[i] = (double)s.x;
+  pb.k_out[3 * i] = (double)s.k[0];
+  pb.k_out[3 * i + 1] = (double)s.k[1];
+  pb.k_out[3 * i + 2] = (double)s.k[2];
+  pb.pos_out[3 * i] = s.p[0];
+  pb.pos_out[3 * i + 1] = s.p[1];
+  pb.pos_out[3 * i + 2] = s.p[2];
+  pb.nscat[i] = s.nscat;
+  pb.path_out[i] = s.path;
+  unsigned long long *st = pb.stats;
+  atomicAdd(st + S_EMITTED, 1ull);
+  atomicAdd(st + (status == ST_ESCAPED ? S_ESCAPED : (status == ST_ABSORBED ? S_ABSORBED : S_STUCK)), 1ull);
+  atomicAdd(st + S_SCAT, (unsigned long long)s.nscat);
+  if (s.cnt.dust_scat) atomicAdd(st + S_DUST_SCAT, (unsigned long long)s.cnt.dust_scat);
+  atomicAdd(st + S_CROSS, (unsigned long long)s.cnt.cross);
+  if (s.cnt.peel_rays) atomicAdd(st + S_PEEL_RAYS, (unsigned long long)s.cnt.peel_rays);
+  if (s.cnt.peel_cross) atomicAdd(st + S_PEEL_CROSS, (unsigned long long)s.cnt.peel_cross);
+  if (s.cnt.peel_drop) atomicAdd(st + S_PEEL_DROPPED, (unsigned long long)s.cnt.peel_drop);
+}
+
+// Emission (Sect. 2): position and frequency from the source list,
+// isotropic direction unless given, tau_event = -ln r.
+template <class R>
+__device__ void emit(const ProblemK &pb, int64_t pid, Lane<R> &s, int *stk, int *pstk, int stride) {
+  s.pid = pid;
+  s.p[0] = pb.src_pos[3 * pid];
+  s.p[1] = pb.src_pos[3 * pid + 1];
+  s.p[2] = pb.src_pos[3 * pid + 2];
+  EventRng<R> rng(pb.seed, (uint64_t)pid, 0u);
+  if (pb.src_dir) {
+    s.k[0] = (R)pb.src_dir[3 * pid];
+    s.k[1] = (R)pb.src_dir[3 * pid + 1];
+    s.k[2] = (R)pb.src_dir[3 * pid + 2];
+  } else {
+    const R mu = R(2) * rng.u(J_MU) - R(1);
+    R sp, cp;
+    M<R>::sincos2pi(rng.u(J_PHI), &sp, &cp);
+    const R st = M<R>::sqrt(R(1) - mu * mu);
+    s.k[0] = st * cp;
+    s.k[1] = st * sp;
+    s.k[2] = mu;
+  }
+  set_geom_dir(s);
+  s.x = (R)pb.src_x[pid];
+  s.tau = -(double)M<R>::log(rng.u(J_TAU));
+  s.path = 0.0;
+  s.event = 0;
+  s.nscat = 0;
+  s.upar_iters = 0;
+  s.cnt = LaneCount{0, 0, 0, 0, 0};
+  if (pb.n_obs) {
+    PeelSrc<R> ps;
+    ps.kind = 0;
+    ps.x = s.x;
+    peel_all<R>(pb, s.p, ps, pstk, stride, s.cnt);
+  }
+}
+
+// Interaction at the current position (Sect. 3.2).  Returns the packet's
+// status (ST_NONE while it lives).
+template <class R>
+__device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R> &o, int *pstk, int stride) {
+  ++s.event;
+  if (pb.max_events > 0 && (int64_t)s.event >= pb.max_events) return ST_STUCK;
+  EventRng<R> rng(pb.seed, (uint64_t)s.pid, s.event);
+  R r = rng.u(J_CHANNEL) * o.ktot;
+  const R kin[3] = {s.k[0], s.k[1], s.k[2]};
+  R e1[3], e2[3];
+  perp_basis(kin, e1, e2);
+  PeelSrc<R> ps;
+  ps.kin[0] = kin[0]; ps.kin[1] = kin[1]; ps.kin[2] = kin[2];
+  ps.ux = s.lf.ux; ps.uy = s.lf.uy; ps.uz = s.lf.uz;
+  ps.w = o.w;
+  if (r < o.kd) {
+    // dust (Sect. 3.2.2): absorbed with probability 1 - albedo, else HG
+    if (rng.u(J_ALBEDO) >= R(pb.albedo)) return ST_ABSORBED;
+    ++s.cnt.dust_scat;
+    if (pb.n_obs) {
+      ps.kind = 2;
+      ps.x = s.x;
+      peel_all<R>(pb, s.p, ps, pstk, stride, s.cnt);
+    }
+    if (!pb.forward_only) {
+      const R mu = mu_hg(rng.u(J_MU), R(pb.g_hg));
+      R sp, cp;
+      M<R>::sincos2pi(rng.u(J_PHI), &sp, &cp);
+      const R st = M<R>::sqrt(fmax(R(0), R(1) - mu * mu));
+#pragma unroll
+      for (int d = 0; d < 3; ++d) s.k[d] = mu * kin[d] + st * (cp * e1[d] + sp * e2[d]);
+      set_geom_dir(s);
+      // coherent in the cell frame
+      const R wn = s.k[0] * s.lf.ux + s.k[1] * s.lf.uy + s.k[2] * s.lf.uz;
+      const R b = R(pb.b_ref);
+      s.x = (s.x + wn + b * s.x * wn - o.w) / (R(1) + b * o.w);
+    }
+  } else {
+    // resonant scattering in line i (Sect. 3.2.1)
+    r -= o.kd;
+    // first line whose cumulative opacity exceeds r (the last line takes
+    // any rounding remainder)
+    int i = 0;
+    R x = o.x[0];
+    bool found = false;
+#pragma unroll
+    for (int q = 0; q < MAX_LINES; ++q) {
+      if (!found && q < pb.n_lines) {
+        if (r < o.kl[q] || q == pb.n_lines - 1) {
+          i = q;
+          x = o.x[q];
+          found = true;
+        } else {
+          r -= o.kl[q];
+        }
+      }
+    }
+    const LineK &ln = pb.lines[i];
+    const R a = R(ln.alpha) * s.lf.irho;
+    R upar;
+    if (!sample_upar<R>(x, a, rng, &s.upar_iters, &upar)) return ST_STUCK;
+    R sp, cp;
+    M<R>::sincos2pi(rng.u(J_PERP2), &sp, &cp);
+    const R rr = M<R>::sqrt(-M<R>::log(rng.u(J_PERP1)));
+    const R up1 = rr * cp, up2 = rr * sp;
+    R U[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) U[d] = upar * kin[d] + up1 * e1[d] + up2 * e2[d];
+    const R rho = R(1) / s.lf.irho;
+    const R bc = R(pb.b_ref) * R(ln.mu) * rho;
+    // frequency seen by the atom, nu_in (1 - k_in.v/c), within 0.2 dnu_D
+    const R g1 = R(1) + bc * x;
+    const int core = fabs(x - g1 * upar) < R(0.2);
+    ++s.nscat;
+    if (pb.n_obs) {
+      ps.kind = 1;
+      ps.x = x;
+      ps.U[0] = U[0]; ps.U[1] = U[1]; ps.U[2] = U[2];
+      ps.bc = bc;
+      ps.rho = rho;
+      ps.line = i;
+      ps.core = core;
+      peel_all<R>(pb, s.p, ps, pstk, stride, s.cnt);
+    }
+    if (!pb.forward_only) {
+      const R ru = rng.u(J_MU);
+      const R mu = ln.phase == PHASE_ISO ? R(2) * ru - R(1) : (core ? mu_core(ru) : mu_wing(ru));
+      M<R>::sincos2pi(rng.u(J_PHI), &sp, &cp);
+      const R st = M<R>::sqrt(fmax(R(0), R(1) - mu * mu));
+#pragma unroll
+      for (int d = 0; d < 3; ++d) s.k[d] = mu * kin[d] + st * (cp * e1[d] + sp * e2[d]);
+      set_geom_dir(s);
+      // outgoing frequency, coherent in the atom frame, recoil in the
+      // denominator (Eq. for nu_out), then back to the external frame
+      const R dkU = (s.k[0] - kin[0]) * U[0] + (s.k[1] - kin[1]) * U[1] + (s.k[2] - kin[2]) * U[2];
+      const R Rr = ln.recoil ? (R(1) - mu) * R(ln.rec) * g1 : R(0);
+      const R xc = (x + g1 * dkU - Rr / bc) / (R(1) + Rr);
+      const R wn = s.k[0] * s.lf.ux + s.k[1] * s.lf.uy + s.k[2] * s.lf.uz;
+      s.x = (R(-ln.delta) + R(ln.mu) * rho * xc * (R(1) + R(pb.b_ref) * wn) + wn) * R(ln.inv_s);
+    }
+  }
+  s.tau = -(double)M<R>::log(rng.u(J_TAU));
+  return ST_NONE;
+}
+
+template <class R, bool BATCH>
+__global__ void __launch_bounds__(256) k_transport(const ProblemK *__restrict__ probs,
+                                                   const int64_t *__restrict__ starts, int n_probs,
+                                                   unsigned long long *__restrict__ next,
+                                                   int refill_min, int stack_levels) {
+  extern __shared__ int lds[];
+  const int stride = blockDim.x;
+  int *stk = lds + threadIdx.x;
+  int *pstk = lds + stack_levels * stride + threadIdx.x;
+  const int64_t total = starts[n_probs];
+  const int lane = __lane_id();
+
+  Lane<R> s;
+  int prob = 0;
+  bool active = false;
+  bool drained = false;
+  while (true) {
+    // ---- refill idle lanes: one atomic per wave, ranks from mbcnt
+    if (!drained) {
+      const unsigned long long idle = __ballot(!active);
+      const int n_idle = __popcll(idle);
+      const bool any_active = idle != ~0ull >> (64 - warpSize);
+      if (n_idle > 0 && (n_idle >= refill_min || !any_active)) {
+        unsigned long long base = 0;
+        if (lane == __ffsll((long long)idle) - 1) base = atomicAdd(next, (unsigned long long)n_idle);
+        base = __shfl(base, __ffsll((long long)idle) - 1);
+        if (base >= (unsigned long long)total) drained = true;
+        if (!active) {
+          const unsigned long long below = idle & ((1ull << lane) - 1ull);
+          const int64_t g = (int64_t)(base + __popcll(below));
+          if (g < total) {
+            if (BATCH) {
+              int lo = 0, hi = n_probs - 1;
+              while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (starts[mid] <= g) lo = mid; else hi = mid - 1;
+              }
+              prob = lo;
+            }
+            const ProblemK &pb = probs[BATCH ? prob : 0];
+            const int64_t pid = pb.first + (g - starts[BATCH ? prob : 0]);
+            emit<R>(pb, pid, s, stk, pstk, stride);
+            int X[3];
+            if (int_coords(pb.L, s.p, s.kd, X)) {
+              descend(pb.nodes, pb.L, 0, 0, X, stk, stride, s.c);
+              s.lf = load_leaf<R>(pb.leaves, s.c.leaf);
+              active = true;
+            } else {
+              finish<R>(pb, s, ST_ESCAPED);
+            }
+          }
+        }
+      }
+    }
+    if (__ballot(active) == 0ull) {
+      if (drained) break;
+      continue;
+    }
+    if (!active) continue;
+
+    const ProblemK &pb = probs[BATCH ? prob : 0];
+    const double kd[3] = {s.kd[0], s.kd[1], s.kd[2]};
+    Opac<R> o;
+    opacity(pb, s.lf, (double)s.x, s.k, o);
+    double face[3], lo[3], hi[3];
+    int em;
+    const double te = exit_dist(s.c, pb.L, s.p, kd, face, lo, hi, &em);
+    const double td = domain_dist(pb.domain, pb.dom, s.p, kd);
+    const double lmax = te < td ? te : td;
+    const double tseg = (double)o.ktot * lmax;
+    int st = ST_NONE;
+    if (s.tau < tseg) {
+      // the event happens inside this leaf
+      const double dist = s.tau / (double)o.ktot;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) s.p[d] = fmin(fmax(fma(dist, kd[d], s.p[d]), lo[d]), hi[d]);
+      s.path += dist;
+      st = interact<R>(pb, s, o, pstk, stride);
+    } else {
+      s.tau -= tseg;
+      s.path += lmax;
+      ++s.cnt.cross;
+      if (s.cnt.cross >= MAX_CROSS) {
+        st = ST_STUCK;
+      } else if (td <= te) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) s.p[d] = fma(td, kd[d], s.p[d]);
+        st = ST_ESCAPED;
+      } else {
+        double pn[3];
+        exit_point(te, em, s.p, kd, face, lo, hi, pn);
+        s.p[0] = pn[0]; s.p[1] = pn[1]; s.p[2] = pn[2];
+        wrap_slab(pb.domain, s.p, kd);
+        int X[3];
+        if (!int_coords(pb.L, s.p, kd, X)) {
+          st = ST_ESCAPED;
+        } else {
+          relocate(pb.nodes, pb.L, X, stk, stride, s.c);
+          s.lf = load_leaf<R>(pb.leaves, s.c.leaf);
+        }
+      }
+    }
+    if (st != ST_NONE) {
+      finish<R>(pb, s, st);
+      active = false;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ probes
+__global__ void k_trace(ProblemK pb, int64_t n, const double *__restrict__ orig,
+                        const double *__restrict__ dir, int max_cells, int32_t *__restrict__ leaf_out,
+                        double *__restrict__ seg_out, int32_t *__restrict__ n_out) {
+  extern __shared__ int lds[];
+  int *stk = lds + threadIdx.x;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double p[3] = {orig[3 * r], orig[3 * r + 1], orig[3 * r + 2]};
+  const double k[3] = {dir[3 * r], dir[3 * r + 1], dir[3 * r + 2]};
+  int X[3];
+  int cnt = 0;
+  if (int_coords(pb.L, p, k, X)) {
+    Cell c;
+    descend(pb.nodes, pb.L, 0, 0, X, stk, blockDim.x, c);
+    while (cnt < max_cells) {
+      double face[3], lo[3], hi[3];
+      int em;
+      const double te = exit_dist(c, pb.L, p, k, face, lo, hi, &em);
+      const double td = domain_dist(pb.domain, pb.dom, p, k);
+      leaf_out[r * max_cells + cnt] = c.leaf;
+      if (td <= te) {
+        seg_out[r * max_cells + cnt] = td;
+        ++cnt;
+        break;
+      }
+      seg_out[r * max_cells + cnt] = te;
+      ++cnt;
+      double pn[3];
+      exit_point(te, em, p, k, face, lo, hi, pn);
+      p[0] = pn[0]; p[1] = pn[1]; p[2] = pn[2];
+      wrap_slab(pb.domain, p, k);
+      if (!int_coords(pb.L, p, k, X)) break;
+      relocate(pb.nodes, pb.L, X, stk, blockDim.x, c);
+    }
+  }
+  n_out[r] = cnt;
+}
+
+template <class R>
+__global__ void k_tau(ProblemK pb, int64_t n, const double *__restrict__ orig,
+                      const double *__restrict__ dir, const double *__restrict__ x_ext,
+                      double *__restrict__ tau_out) {
+  extern __shared__ int lds[];
+  int *stk = lds + threadIdx.x;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const double p[3] = {orig[3 * r], orig[3 * r + 1], orig[3 * r + 2]};
+  const double k[3] = {dir[3 * r], dir[3 * r + 1], dir[3 * r + 2]};
+  uint32_t nc = 0;
+  tau_out[r] = ray_tau<R>(pb, p, k, x_ext[r], __builtin_inf(), stk, blockDim.x, &nc);
+}
+
+// ------------------------------------------------- peel-off image, adjoint
+template <class R>
+__global__ void k_image_fwd(ProblemK pb, int obs, int64_t n, const double *__restrict__ orig,
+                            const double *__restrict__ x_ext, const double *__restrict__ w,
+                            double *__restrict__ image, unsigned long long *__restrict__ ncross) {
+  extern __shared__ int lds[];
+  int *stk = lds + threadIdx.x;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t nc = 0;
+  if (r < n) {
+    const ObsK &ob = pb.obs[obs];
+    const double p[3] = {orig[3 * r], orig[3 * r + 1], orig[3 * r + 2]};
+    const int pix = pixel_of(ob, p);
+    if (pix >= 0) {
+      const double tau = ray_tau<R>(pb, p, ob.k, x_ext[r], TauCut<double>::v, stk, blockDim.x, &nc);
+      if (tau < TauCut<double>::v) unsafeAtomicAdd(image + pix, w[r] * exp(-tau));
+    }
+  }
+  // one atomic per wave for the crossing count
+  unsigned long long v = nc;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+  if (__lane_id() == 0 && v) atomicAdd(ncross, v);
+}
+
+// dL/dtheta_c = -G_p w exp(-tau) sum over the ray's crossings of c of
+// dtau/dtheta_c, with tau_c = (nl sum_i kfac_i H_i + kd) seg:
+//   dtau/dn_HI   = seg box irho sum_i kfac_i H_i
+//   dtau/dkappa_d = seg box
+//   dtau/dv_los  = seg nl sum_i kfac_i H'_i dx_i/dw / v_th,ref,
+//   dx_i/dw = -irho inv_mu_i s_i (1 + b x_ext) / (1 + b w)^2.
+template <class R>
+__global__ void k_image_bwd(ProblemK pb, int obs, int64_t n, const double *__restrict__ orig,
+                            const double *__restrict__ x_ext, const double *__restrict__ w,
+                            const double *__restrict__ G, double inv_vth_ref,
+                            double *__restrict__ g_n, double *__restrict__ g_k,
+                            double *__restrict__ g_v, unsigned long long *__restrict__ ncross) {
+  extern __shared__ int lds[];
+  int *stk = lds + threadIdx.x;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t nc = 0;
+  if (r < n) {
+    const ObsK &ob = pb.obs[obs];
+    const double p0[3] = {orig[3 * r], orig[3 * r + 1], orig[3 * r + 2]};
+    const int pix = pixel_of(ob, p0);
+    const double xr = x_ext[r];
+    double tau = TauCut<double>::v;
+    if (pix >= 0) tau = ray_tau<R>(pb, p0, ob.k, xr, TauCut<double>::v, stk, blockDim.x, &nc);
+    const double g = (pix >= 0 && tau < TauCut<double>::v) ? -G[pix] * w[r] * exp(-tau) : 0.0;
+    if (g != 0.0) {
+      // replay the ray (same traversal as the forward pass)
+      const double *k = ob.k;
+      const R kr[3] = {(R)k[0], (R)k[1], (R)k[2]};
+      double p[3] = {p0[0], p0[1], p0[2]};
+      int X[3];
+      Cell c;
+      if (int_coords(pb.L, p, k, X)) {
+        descend(pb.nodes, pb.L, 0, 0, X, stk, blockDim.x, c);
+        for (uint32_t steps = 0; steps < MAX_CROSS; ++steps) {
+          const LeafRec<R> lf = load_leaf<R>(pb.leaves, c.leaf);
+          Opac<R> o;
+          opacity(pb, lf, xr, kr, o);
+          double face[3], lo[3], hi[3];
+          int em;
+          const double te = exit_dist(c, pb.L, p, k, face, lo, hi, &em);
+          const double td = domain_dist(pb.domain, pb.dom, p, k);
+          const double seg = td <= te ? td : te;
+          const R b = R(pb.b_ref);
+          const R den = R(1) + b * o.w;
+          R sn = R(0), sv = R(0);
+#pragma unroll
+          for (int i = 0; i < MAX_LINES; ++i) {
+            if (i < pb.n_lines) {
+              const LineK &ln = pb.lines[i];
+              const R a = R(ln.alpha) * lf.irho;
+              sn += R(ln.kfac) * voigt_h<R>(a, o.x[i]);
+              const R dxdw = -lf.irho * R(ln.inv_mu) * R(ln.s) * (R(1) + b * (R)xr) / (den * den);
+              sv += R(ln.kfac) * voigt_dhdx<R>(a, o.x[i]) * dxdw;
+            }
+          }
+          unsafeAtomicAdd(g_n + c.leaf, g * seg * pb.box_cm * (double)lf.irho * (double)sn);
+          unsafeAtomicAdd(g_k + c.leaf, g * seg * pb.box_cm);
+          unsafeAtomicAdd(g_v + c.leaf, g * seg * (double)lf.nl * (double)sv * inv_vth_ref);
+          if (td <= te) break;
+          double pn[3];
+          exit_point(te, em, p, k, face, lo, hi, pn);
+          p[0] = pn[0]; p[1] = pn[1]; p[2] = pn[2];
+          wrap_slab(pb.domain, p, k);
+          if (!int_coords(pb.L, p, k, X)) break;
+          relocate(pb.nodes, pb.L, X, stk, blockDim.x, c);
+        }
+      }
+    }
+  }
+  unsigned long long v = nc;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+  if (__lane_id() == 0 && v) atomicAdd(ncross, v);
+}
+
+// --------------------------------------------------------------- helpers
+__global__ void k_hist(int64_t n, const int32_t *__restrict__ status, const double *__restrict__ x,
+                       int nbins, double x_min, double span, unsigned long long *__restrict__ h) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || status[i] != ST_ESCAPED) return;
+  const double fb = (x[i] - x_min) / span * nbins;
+  if (!(fb >= 0.0 && fb < nbins)) return;
+  const int b = (int)floor(fb);
+  if (b < nbins) atomicAdd(h + b, 1ull);
+}
+
+// Zero the counters of every problem of a launch and the work queue (a
+// kernel rather than a memset so that it can sit in a captured graph).
+__global__ void k_batch_reset(const ProblemK *__restrict__ probs, int n, unsigned long long *next) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n * N_STATS) probs[i / N_STATS].stats[i % N_STATS] = 0ull;
+  if (i == 0) *next = 0ull;
+}
+
+__global__ void k_fill_u64(unsigned long long *p, int64_t n, unsigned long long v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_u64_to_f64(const unsigned long long *a, double *b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (double)a[i];
+}
+
+__global__ void k_f32_to_f64(const float *a, double *b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (double)a[i];
+}
+
+__global__ void k_f64_to_f32(const double *a, float *b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+
+// ------------------------------------------------------------- launchers
+static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t launch_transport(bool fp32, bool batch, const ProblemK *d_probs, const int64_t *d_starts,
+                            int n_probs, unsigned long long *d_next, int refill_min, int stack_levels,
+                            int grid, int block, hipStream_t st) {
+  const size_t lds = (size_t)2 * stack_levels * block * sizeof(int);
+  if (fp32) {
+    if (batch)
+      hipLaunchKernelGGL((k_transport<float, true>), dim3(grid), dim3(block), lds, st, d_probs, d_starts,
+                         n_probs, d_next, refill_min, stack_levels);
+    else
+      hipLaunchKernelGGL((k_transport<float, false>), dim3(grid), dim3(block), lds, st, d_probs, d_starts,
+                         n_probs, d_next, refill_min, stack_levels);
+  } else {
+    if (batch)
+      hipLaunchKernelGGL((k_transport<double, true>), dim3(grid), dim3(block), lds, st, d_probs, d_starts,
+                         n_probs, d_next, refill_min, stack_levels);
+    else
+      hipLaunchKernelGGL((k_transport<double, false>), dim3(grid), dim3(block), lds, st, d_probs, d_starts,
+                         n_probs, d_next, refill_min, stack_levels);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_trace(const ProblemK &pb, int64_t n, const double *orig, const double *dir,
+                        int max_cells, int32_t *leaf, double *seg, int32_t *cnt, hipStream_t st) {
+  const int b = 256;
+  const size_t lds = (size_t)(pb.L > 0 ? pb.L : 1) * b * sizeof(int);
+  hipLaunchKernelGGL(k_trace, dim3(blocks_for(n, b)), dim3(b), lds, st, pb, n, orig, dir, max_cells, leaf,
+                     seg, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_tau(bool fp32, const ProblemK &pb, int64_t n, const double *orig, const double *dir,
+                      const double *x, double *tau, hipStream_t st) {
+  const int b = 256;
+  const size_t lds = (size_t)(pb.L > 0 ? pb.L : 1) * b * sizeof(int);
+  if (fp32)
+    hipLaunchKernelGGL(k_tau<float>, dim3(blocks_for(n, b)), dim3(b), lds, st, pb, n, orig, dir, x, tau);
+  else
+    hipLaunchKernelGGL(k_tau<double>, dim3(blocks_for(n, b)), dim3(b), lds, st, pb, n, orig, dir, x, tau);
+  return hipGetLastError();
+}
+
+hipError_t launch_image_fwd(bool fp32, const ProblemK &pb, int obs, int64_t n, const double *orig,
+                            const double *x, const double *w, double *image, unsigned long long *ncross,
+                            hipStream_t st) {
+  const int b = 256;
+  const size_t lds = (size_t)(pb.L > 0 ? pb.L : 1) * b * sizeof(int);
+  if (fp32)
+    hipLaunchKernelGGL(k_image_fwd<float>, dim3(blocks_for(n, b)), dim3(b), lds, st, pb, obs, n, orig, x, w,
+                       image, ncross);
+  else
+    hipLaunchKernelGGL(k_image_fwd<double>, dim3(blocks_for(n, b)), dim3(b), lds, st, pb, obs, n, orig, x, w,
+                       image, ncross);
+  return hipGetLastError();
+}
+
+hipError_t launch_image_bwd(bool fp32, const ProblemK &pb, int obs, int64_t n, const double *orig,
+                            const double *x, const double *w, const double *G, double inv_vth_ref,
+                            double *gn, double *gk, double *gv, unsigned long long *ncross, hipStream_t st) {
+  const int b = 256;
+  const size_t lds = (size_t)(pb.L > 0 ? pb.L : 1) * b * sizeof(int);
+  if (fp32)
+    hipLaunchKernelGGL(k_image_bwd<float>, dim3(blocks_for(n, b)), dim3(b), lds, st, pb, obs, n, orig, x, w, G,
+                       inv_vth_ref, gn, gk, gv, ncross);
+  else
+    hipLaunchKernelGGL(k_image_bwd<double>, dim3(blocks_for(n, b)), dim3(b), lds, st, pb, obs, n, orig, x, w, G,
+                       inv_vth_ref, gn, gk, gv, ncross);
+  return hipGetLastError();
+}
+
+hipError_t launch_hist(int64_t n, const int32_t *status, const double *x, int nbins, double x_min, double span,
+                       unsigned long long *h, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hist, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, status, x, nbins, x_min, span, h);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_reset(const ProblemK *d_probs, int n, unsigned long long *d_next, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_reset, dim3(blocks_for((int64_t)n * N_STATS, 256)), dim3(256), 0, st, d_probs, n,
+                     d_next);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_u64_to_f64(const unsigned long long *a, double *b, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_u64_to_f64, dim3(blocks_for(n, 256)), dim3(256), 0, st, a, b, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_f32_to_f64(const float *a, double *b, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_f32_to_f64, dim3(blocks_for(n, 256)), dim3(256), 0, st, a, b, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_f64_to_f32(const double *a, float *b, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_f64_to_f32, dim3(blocks_for(n, 256)), dim3(256), 0, st, a, b, n);
+  return hipGetLastError();
+}
+
+}  // namespace rmc

@@ -1,0 +1,31 @@
+// rmc_launch.h -- host-callable launchers of the kernels in rmc_kernels.hip.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rmc_device.h"
+
+namespace rmc {
+
+hipError_t launch_transport(bool fp32, bool batch, const ProblemK *d_probs, const int64_t *d_starts,
+                            int n_probs, unsigned long long *d_next, int refill_min, int stack_levels,
+                            int grid, int block, hipStream_t st);
+hipError_t launch_trace(const ProblemK &pb, int64_t n, const double *orig, const double *dir,
+                        int max_cells, int32_t *leaf, double *seg, int32_t *cnt, hipStream_t st);
+hipError_t launch_tau(bool fp32, const ProblemK &pb, int64_t n, const double *orig, const double *dir,
+                      const double *x, double *tau, hipStream_t st);
+hipError_t launch_image_fwd(bool fp32, const ProblemK &pb, int obs, int64_t n, const double *orig,
+                            const double *x, const double *w, double *image, unsigned long long *ncross,
+                            hipStream_t st);
+hipError_t launch_image_bwd(bool fp32, const ProblemK &pb, int obs, int64_t n, const double *orig,
+                            const double *x, const double *w, const double *G, double inv_vth_ref,
+                            double *gn, double *gk, double *gv, unsigned long long *ncross, hipStream_t st);
+hipError_t launch_hist(int64_t n, const int32_t *status, const double *x, int nbins, double x_min, double span,
+                       unsigned long long *h, hipStream_t st);
+hipError_t launch_batch_reset(const ProblemK *d_probs, int n, unsigned long long *d_next, hipStream_t st);
+hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t st);
+hipError_t launch_u64_to_f64(const unsigned long long *a, double *b, int64_t n, hipStream_t st);
+hipError_t launch_f32_to_f64(const float *a, double *b, int64_t n, hipStream_t st);
+hipError_t launch_f64_to_f32(const double *a, float *b, int64_t n, hipStream_t st);
+
+}  // namespace rmc

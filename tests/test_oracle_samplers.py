@@ -9,6 +9,7 @@ from scipy import integrate, stats
 from scipy.special import wofz
 
 from paper_2001_11252_amd import workloads as W
+from tests.analytic import r2a_expected_counts
 
 N = 100_000
 
@@ -96,17 +97,6 @@ def test_isotropic(orc):
 
 
 # ----------------------------------------------- frequency redistribution
-def _hummer_r2a(x, xp, a):
-    """Hummer's R_II-A (signed form), normalised over x' for fixed x:
-    R(x,x') = pi^-3/2 int_{|xbar-xlow|/2}^inf exp(-u^2) [atan((xlow+u)/a) - atan((xbar-u)/a)] du
-    with xlow = min(x,x'), xbar = max(x,x')."""
-    lo, hi = min(x, xp), max(x, xp)
-    f = lambda u: np.exp(-u * u) * (np.arctan((lo + u) / a) - np.arctan((hi - u) / a))
-    u0 = abs(hi - lo) / 2.0
-    v, _ = integrate.quad(f, u0, u0 + 8.0, limit=400, points=[abs(hi + lo) / 2.0] if abs(hi + lo) / 2.0 < u0 + 8 else None)
-    return v / np.pi ** 1.5
-
-
 @pytest.mark.parametrize("x_in", [0.0, 1.0, 2.0, 3.0, 4.0, 5.0])
 def test_single_scattering_matches_hummer_r2a(orc, x_in):
     # T = 100 K, isotropic angular redistribution, no recoil (Fig. of Sect. 3.4.1)
@@ -117,13 +107,7 @@ def test_single_scattering_matches_hummer_r2a(orc, x_in):
     xs = orc.single_scatter(n, line, T, x_in, seed=77 + int(x_in))
     edges = np.linspace(-6.0, 6.0 + x_in, 121)
     counts, _ = np.histogram(xs, bins=edges)
-    phi = wofz(x_in + 1j * a).real / np.sqrt(np.pi)
-    exp = []
-    for lo, hi in zip(edges[:-1], edges[1:]):
-        xm = np.linspace(lo, hi, 5)
-        vals = np.array([_hummer_r2a(x_in, xp, a) for xp in xm])
-        exp.append(integrate.simpson(vals, x=xm) / phi * n)
-    exp = np.array(exp)
+    exp = r2a_expected_counts(x_in, a, edges, n)
     sel = exp >= 20
     z = (counts[sel] - exp[sel]) / np.sqrt(exp[sel])
     chi2dof = (z ** 2).sum() / sel.sum()
