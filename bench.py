@@ -4,10 +4,15 @@ Workload (the configuration the metric is quoted on): static uniform HI
 sphere, tau0 = 1e6 at line centre along the radius, T = 1e4 K, dust with
 tau_dust = 1 (albedo 0.32, g = 0.73), octree refined from level 3 to 7
 toward the centre (287,064 leaves), packets emitted at x = 0 from the
-centre, one observer along +z with a 128x128x100 peel-off cube.  A step is
-one transport launch over a fresh range of packets (emission, propagation,
-scattering, dust, peel-off of every event, termination); the FP32 bulk path
-is the headline, the FP64 path runs beside it on the same packets.
+centre, one observer along +z with a 128x128x100 peel-off cube, 1e6
+packets queued.  A step is one transport launch: every lane of the grid
+advances the packet it holds by up to --slice loop iterations (emission,
+propagation, scattering, dust, peel-off of every event, termination) and
+lanes whose packet finished take the next one from the queue; packets that
+are still alive are parked in device memory for the next step.  Timed steps
+follow warm-up steps, so they measure the steady state of the resident
+packet pool.  The FP32 bulk path is the headline; the FP64 path runs beside
+it on the same packets.
 
 Prints one JSON line.  Inputs are synthetic and seeded.
 """
@@ -36,10 +41,11 @@ PEAK = {"fp32": 157.3, "fp64": 78.6}       # TFLOP/s, MI355X vector
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--packets", type=int, default=65536, help="packets per step")
-    ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--slice", type=int, default=2048, help="loop iterations per lane per step")
+    ap.add_argument("--packets", type=int, default=1_000_000, help="packets queued")
+    ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--tau0", type=float, default=1e6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-packets", type=int, default=0, help="oracle packets (0: one per core)")
@@ -60,30 +66,31 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     steps, warm, P = a.steps, a.warmup, a.packets
-    n_total = max(1_000_000, (warm + max(steps, a.fp64_steps) + 1) * P)
-    pb = W.c2_dusty_sphere(rmc.sigma0, n_packets=n_total, tau0=a.tau0)
-    print(f"# workload: {pb.mesh.n} leaves, n_HI={pb.meta['n_hi']:.4e}, {P} packets/step", file=sys.stderr, flush=True)
+    pb = W.c2_dusty_sphere(rmc.sigma0, n_packets=P, tau0=a.tau0)
+    print(f"# workload: {pb.mesh.n} leaves, n_HI={pb.meta['n_hi']:.4e}, {P} packets queued, "
+          f"{a.slice} iterations/lane/step", file=sys.stderr, flush=True)
 
     def measure(prec, nsteps):
         ctx = rmc.Context.from_problem(pb, prec)
         ctx.set_stream(torch.cuda.current_stream())
-        first = 0
+        ctx.set_option(rmc.OPT_SLICE_ITERS, a.slice)
+        ctx.stream_begin(pb.seed, 0, P)
         for _ in range(warm):
-            ctx.run(pb.seed, first, P)
-            first += P
+            ctx.stream_step()
         torch.cuda.synchronize()
         tot = {}
         kms = []
         t0 = time.perf_counter()
         for _ in range(nsteps):
-            st = ctx.run(pb.seed, first, P)
-            first += P
+            st, rem = ctx.stream_step()
             kms.append(st["kernel_ms"])
             for k, v in st.items():
                 tot[k] = tot.get(k, 0) + v
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        print(f"# {prec}: {nsteps} steps in {wall:.3f} s, kernel ms {kms}, stats {tot}", file=sys.stderr, flush=True)
+        print(f"# {prec}: {nsteps} steps in {wall:.3f} s, kernel ms {[round(k, 1) for k in kms]}, "
+              f"remaining {rem}, stats {tot}", file=sys.stderr, flush=True)
+        ctx.close()
         return wall, tot, kms
 
     res = {}
@@ -110,8 +117,7 @@ def main():
                       "kernel_ms_avg": sum(k) / len(k),
                       "hbm_GBps_algorithmic": (t["crossings"] + t["peel_crossings"]) * BYTES_PER_CROSSING[prec]
                       / (sum(k) * 1e-3) / 1e9,
-                      "escaped_fraction": t["escaped"] / max(1, t["emitted"]),
-                      "scatterings_per_packet": t["scatterings"] / max(1, t["emitted"])}
+                      "packets_finished": t["emitted"]}
     line = {
         "metric": "scatterings/s + ray-cell crossings/s (1 GPU), FP32 vs FP64 at matched spectra",
         "value": scat_s,
@@ -127,8 +133,8 @@ def main():
         "dtype": "f32" if head == "fp32" else "f64",
         "data": "synthetic",
         "config": {"workload": "dusty_sphere_tau1e6_T1e4_287k_leaves_peel_128x128x100",
-                   "tau0": a.tau0, "packets_per_step": P, "leaves": int(pb.mesh.n),
-                   "observer": "+z 128x128x100", "parallelism": "none"},
+                   "tau0": a.tau0, "packets_queued": P, "iterations_per_lane_per_step": a.slice,
+                   "leaves": int(pb.mesh.n), "observer": "+z 128x128x100", "parallelism": "none"},
         "precisions": side,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK[head], "unit": "TFLOP/s",
                      "frac": achieved / PEAK[head], "traffic": None,

@@ -65,8 +65,10 @@ enum {
   RMC_OPT_WAVES_PER_CU = 4,  /* resident waves per CU the grid is sized for  */
   RMC_OPT_REFILL = 5,        /* idle lanes a wave gathers before it takes new
                                 packets (1..64)                              */
-  RMC_OPT_PEEL_DEFER = 6     /* 1: peel-off rays go through a queue to a
+  RMC_OPT_PEEL_DEFER = 6,    /* 1: peel-off rays go through a queue to a
                                 separate ray-cast kernel                     */
+  RMC_OPT_SLICE_ITERS = 7    /* loop iterations (events or cell crossings)
+                                per lane in one transport launch            */
 };
 
 /* One transition (Table 1 of the paper). */
@@ -145,6 +147,17 @@ rmc_status rmc_reset_cubes(rmc_ctx *ctx);
  * generator, so any split of a packet range gives the same packets. */
 rmc_status rmc_run(rmc_ctx *ctx, uint64_t seed, int64_t first, int64_t n,
                    rmc_run_stats *stats);
+/* Streaming form of rmc_run.  begin queues packets [first, first+n) and
+ * parks nothing; each step is one bounded launch (RMC_OPT_SLICE_ITERS loop
+ * iterations per lane) in which every lane advances the packet it holds,
+ * parks it in device memory if it is still alive, and idle lanes take new
+ * packets from the queue.  step reports the work of that launch (emitted =
+ * packets finished in it) and the packets not finished yet; end runs the
+ * remaining launches and reports the totals of the range.  rmc_run is
+ * begin + steps + end.  Results do not depend on how a run is sliced. */
+rmc_status rmc_stream_begin(rmc_ctx *ctx, uint64_t seed, int64_t first, int64_t n);
+rmc_status rmc_stream_step(rmc_ctx *ctx, rmc_run_stats *slice, int64_t *remaining);
+rmc_status rmc_stream_end(rmc_ctx *ctx, rmc_run_stats *total);
 /* Per-packet results of the last run (any pointer may be NULL): status,
  * escaped x_ext, final direction k[3n], final position pos[3n], line
  * scattering count, path length in box units. */

@@ -84,6 +84,7 @@ struct rmc_ctx {
   int waves_per_cu = 8;
   int refill = 1;
   int peel_defer = 0;
+  int slice_iters = 2048;
   // mesh
   bool has_mesh = false;
   int64_t n_leaves = 0;
@@ -122,6 +123,17 @@ struct rmc_ctx {
   std::vector<int64_t> b_starts_host;
   hipGraphExec_t b_graph = nullptr;
   std::string b_key;
+  // streaming state (single problem or a batch led by this context)
+  DevBuf slots, d_slice;
+  int64_t s_total = 0, s_done = 0;
+  int s_grid = 0, s_levels = 1, s_nprobs = 0;
+  bool s_open = false, s_batch = false;
+  const ProblemK *s_probs = nullptr;
+  const int64_t *s_starts = nullptr;
+  std::vector<rmc_ctx *> s_members;
+  rmc_run_stats s_acc;
+  hipGraphExec_t s_graph = nullptr;
+  std::string s_key;
 };
 
 namespace {
@@ -477,9 +489,11 @@ void rmc_destroy(rmc_ctx *c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
   if (c->b_graph) (void)hipGraphExecDestroy(c->b_graph);
+  if (c->s_graph) (void)hipGraphExecDestroy(c->s_graph);
   DevBuf *bufs[] = {&c->nodes, &c->leaves, &c->spos, &c->sdir, &c->sx, &c->o_status, &c->o_x, &c->o_k,
                     &c->o_pos, &c->o_nscat, &c->o_path, &c->d_stats, &c->d_next, &c->d_prob, &c->d_starts,
-                    &c->tmp1, &c->tmp2, &c->tmp3, &c->tmp4, &c->tmp5, &c->b_probs, &c->b_starts};
+                    &c->tmp1, &c->tmp2, &c->tmp3, &c->tmp4, &c->tmp5, &c->b_probs, &c->b_starts,
+                    &c->slots, &c->d_slice};
   for (DevBuf *b : bufs) b->release();
   for (auto &o : c->obs) o.cube.release();
   if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -520,6 +534,10 @@ rmc_status rmc_set_option(rmc_ctx *c, int opt, int64_t v) {
     case RMC_OPT_PEEL_DEFER:
       if (v) return fail(c, RMC_EUNSUPPORTED, "deferred peel-off queue not built");
       c->peel_defer = 0;
+      break;
+    case RMC_OPT_SLICE_ITERS:
+      if (v < 1 || v > (1 << 30)) return fail(c, RMC_EINVAL, "slice iterations in [1, 2^30]");
+      c->slice_iters = (int)v;
       break;
     default: return fail(c, RMC_EINVAL, "unknown option %d", opt);
   }
@@ -704,10 +722,94 @@ rmc_status rmc_reset_cubes(rmc_ctx *c) {
   return RMC_OK;
 }
 
-rmc_status rmc_run(rmc_ctx *c, uint64_t seed, int64_t first, int64_t n, rmc_run_stats *stats) {
-  rmc_status r = enter(c);
-  if (r) return r;
-  r = ready(c, true);
+// ------------------------------------------------------------ streaming
+namespace {
+
+void add_run_stats(rmc_run_stats &a, const rmc_run_stats &b) {
+  a.emitted += b.emitted; a.escaped += b.escaped; a.absorbed += b.absorbed; a.stuck += b.stuck;
+  a.scatterings += b.scatterings; a.dust_scatterings += b.dust_scatterings; a.crossings += b.crossings;
+  a.peel_rays += b.peel_rays; a.peel_crossings += b.peel_crossings; a.peel_dropped += b.peel_dropped;
+  a.kernel_ms += b.kernel_ms;
+}
+
+// Prepare slots and counters for a stream over the problems already
+// uploaded at s_probs / s_starts.
+rmc_status stream_open(rmc_ctx *c, int64_t total, int n_probs, int levels, bool batch) {
+  c->s_total = total;
+  c->s_done = 0;
+  c->s_nprobs = n_probs;
+  c->s_levels = std::max(levels, 1);
+  c->s_batch = batch;
+  c->s_grid = grid_for(c, total);
+  const int64_t n_slots = (int64_t)c->s_grid * c->block;
+  HIPCHK(c, c->slots.ensure((size_t)n_slots * slot_bytes()));
+  HIPCHK(c, c->d_slice.ensure(N_STATS * 8));
+  HIPCHK(c, c->d_next.ensure(8));
+  HIPCHK(c, launch_clear_slots(c->slots.p, n_slots, c->stream));
+  HIPCHK(c, launch_batch_reset(c->s_probs, n_probs, c->d_next.as<unsigned long long>(), c->stream));
+  std::memset(&c->s_acc, 0, sizeof c->s_acc);
+  c->s_open = true;
+  // one slice = zero the slice counters, one transport launch; captured
+  // once per shape and replayed
+  char key[256];
+  snprintf(key, sizeof key, "%p/%p/%p/%p/%d/%d/%d/%d/%d/%d/%d/%d", (void *)c->s_probs, (void *)c->s_starts,
+           c->slots.p, c->d_slice.p, n_probs, c->s_grid, c->block, c->refill, c->s_levels, c->precision,
+           c->slice_iters, (int)batch);
+  if (c->s_key != key || !c->s_graph) {
+    if (c->s_graph) {
+      (void)hipGraphExecDestroy(c->s_graph);
+      c->s_graph = nullptr;
+    }
+    hipStream_t cap = nullptr;
+    HIPCHK(c, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) e = launch_fill_u64(c->d_slice.as<unsigned long long>(), N_STATS, 0ull, cap);
+    if (e == hipSuccess)
+      e = launch_transport(c->precision == RMC_FP32_BULK, batch, c->s_probs, c->s_starts, n_probs,
+                           c->d_next.as<unsigned long long>(), c->refill, c->s_levels, c->s_grid, c->block,
+                           c->slots.p, c->slice_iters, c->d_slice.as<unsigned long long>(), cap);
+    hipError_t e2 = hipStreamEndCapture(cap, &g);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&c->s_graph, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) {
+      c->s_open = false;
+      return fail(c, RMC_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+    }
+    c->s_key = key;
+  }
+  return RMC_OK;
+}
+
+rmc_status stream_step(rmc_ctx *c, rmc_run_stats *slice, int64_t *remaining) {
+  if (!c->s_open) return fail(c, RMC_ESTATE, "no open stream (rmc_stream_begin)");
+  rmc_run_stats z;
+  std::memset(&z, 0, sizeof z);
+  if (c->s_done >= c->s_total) {
+    if (slice) *slice = z;
+    if (remaining) *remaining = 0;
+    return RMC_OK;
+  }
+  HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+  HIPCHK(c, hipGraphLaunch(c->s_graph, c->stream));
+  HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+  unsigned long long h[N_STATS];
+  HIPCHK(c, hipMemcpyAsync(h, c->d_slice.p, sizeof h, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  float ms = 0.f;
+  HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  fill_stats(&z, h, ms);
+  c->s_done += (int64_t)h[S_EMITTED];
+  add_run_stats(c->s_acc, z);
+  if (slice) *slice = z;
+  if (remaining) *remaining = c->s_total - c->s_done;
+  return RMC_OK;
+}
+
+rmc_status stream_begin_single(rmc_ctx *c, uint64_t seed, int64_t first, int64_t n) {
+  rmc_status r = ready(c, true);
   if (r) return r;
   if (first < 0 || n < 0 || first + n > c->n_src) return fail(c, RMC_EINVAL, "packet range outside the sources");
   r = ensure_outputs(c, n);
@@ -720,23 +822,64 @@ rmc_status rmc_run(rmc_ctx *c, uint64_t seed, int64_t first, int64_t n, rmc_run_
   HIPCHK(c, c->d_starts.ensure(16));
   HIPCHK(c, hipMemcpyAsync(c->d_prob.p, &c->pb_host, sizeof(ProblemK), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->d_starts.p, c->starts_host, 16, hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, launch_batch_reset(c->d_prob.as<ProblemK>(), 1, c->d_next.as<unsigned long long>(), c->stream));
-  const int levels = std::max(c->L, 1);
-  HIPCHK(c, hipEventRecord(c->ev0, c->stream));
-  if (n > 0)
-    HIPCHK(c, launch_transport(c->precision == RMC_FP32_BULK, false, c->d_prob.as<ProblemK>(),
-                               c->d_starts.as<int64_t>(), 1, c->d_next.as<unsigned long long>(), c->refill, levels,
-                               grid_for(c, n), c->block, c->stream));
-  HIPCHK(c, hipEventRecord(c->ev1, c->stream));
-  unsigned long long h[N_STATS];
-  HIPCHK(c, hipMemcpyAsync(h, c->d_stats.p, sizeof h, hipMemcpyDeviceToHost, c->stream));
+  c->s_probs = c->d_prob.as<ProblemK>();
+  c->s_starts = c->d_starts.as<int64_t>();
+  c->s_members.assign(1, c);
+  return stream_open(c, n, 1, c->L, false);
+}
+
+// Totals of a finished stream: per-problem counters and the summed
+// launch times.
+rmc_status stream_finish(rmc_ctx *c, rmc_run_stats *per, rmc_run_stats *total) {
+  while (c->s_done < c->s_total) {
+    rmc_status r = stream_step(c, nullptr, nullptr);
+    if (r) return r;
+  }
+  c->s_open = false;
+  const int np = (int)c->s_members.size();
+  std::vector<unsigned long long> h((size_t)np * N_STATS);
+  for (int i = 0; i < np; ++i)
+    HIPCHK(c, hipMemcpyAsync(h.data() + (size_t)i * N_STATS, c->s_members[i]->d_stats.p, N_STATS * 8,
+                             hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  float ms = 0.f;
-  HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
-  if (stats) fill_stats(stats, h, ms);
-  if ((int64_t)h[S_EMITTED] != n)
-    return fail(c, RMC_EDEVICE, "transport finished %llu of %lld packets", h[S_EMITTED], (long long)n);
+  unsigned long long t[N_STATS] = {0};
+  for (int i = 0; i < np; ++i) {
+    if (per) fill_stats(per + i, h.data() + (size_t)i * N_STATS, c->s_acc.kernel_ms);
+    for (int q = 0; q < N_STATS; ++q) t[q] += h[(size_t)i * N_STATS + q];
+  }
+  if (total) fill_stats(total, t, c->s_acc.kernel_ms);
+  if ((int64_t)t[S_EMITTED] != c->s_total)
+    return fail(c, RMC_EDEVICE, "transport finished %llu of %lld packets", t[S_EMITTED], (long long)c->s_total);
   return RMC_OK;
+}
+
+}  // namespace
+
+rmc_status rmc_stream_begin(rmc_ctx *c, uint64_t seed, int64_t first, int64_t n) {
+  rmc_status r = enter(c);
+  if (r) return r;
+  return stream_begin_single(c, seed, first, n);
+}
+
+rmc_status rmc_stream_step(rmc_ctx *c, rmc_run_stats *slice, int64_t *remaining) {
+  rmc_status r = enter(c);
+  if (r) return r;
+  return stream_step(c, slice, remaining);
+}
+
+rmc_status rmc_stream_end(rmc_ctx *c, rmc_run_stats *total) {
+  rmc_status r = enter(c);
+  if (r) return r;
+  if (!c->s_open) return fail(c, RMC_ESTATE, "no open stream (rmc_stream_begin)");
+  return stream_finish(c, nullptr, total);
+}
+
+rmc_status rmc_run(rmc_ctx *c, uint64_t seed, int64_t first, int64_t n, rmc_run_stats *stats) {
+  rmc_status r = enter(c);
+  if (r) return r;
+  r = stream_begin_single(c, seed, first, n);
+  if (r) return r;
+  return stream_finish(c, nullptr, stats);
 }
 
 rmc_status rmc_get_packets(rmc_ctx *c, int32_t *status, double *x, double *k, double *pos, int32_t *nscat,
@@ -977,55 +1120,14 @@ rmc_status rmc_batch_run(rmc_ctx *const *P, int np, const uint64_t *seeds, const
   const int64_t tot = c0->b_starts_host[np];
   HIPCHK(c0, c0->b_probs.ensure(sizeof(ProblemK) * np));
   HIPCHK(c0, c0->b_starts.ensure(8 * (np + 1)));
-  HIPCHK(c0, c0->d_next.ensure(8));
   HIPCHK(c0, hipMemcpyAsync(c0->b_probs.p, c0->b_host.data(), sizeof(ProblemK) * np, hipMemcpyHostToDevice, c0->stream));
   HIPCHK(c0, hipMemcpyAsync(c0->b_starts.p, c0->b_starts_host.data(), 8 * (np + 1), hipMemcpyHostToDevice, c0->stream));
-  const int grid = grid_for(c0, tot);
-  // the launch sequence is captured once per shape and replayed
-  char key[256];
-  snprintf(key, sizeof key, "%p/%p/%d/%d/%d/%d/%d/%d", c0->b_probs.p, c0->b_starts.p, np, grid, c0->block, c0->refill,
-           maxL, c0->precision);
-  if (c0->b_key != key || !c0->b_graph) {
-    if (c0->b_graph) {
-      (void)hipGraphExecDestroy(c0->b_graph);
-      c0->b_graph = nullptr;
-    }
-    hipStream_t cap = nullptr;
-    HIPCHK(c0, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) e = launch_batch_reset(c0->b_probs.as<ProblemK>(), np, c0->d_next.as<unsigned long long>(), cap);
-    if (e == hipSuccess)
-      e = launch_transport(c0->precision == RMC_FP32_BULK, true, c0->b_probs.as<ProblemK>(), c0->b_starts.as<int64_t>(),
-                           np, c0->d_next.as<unsigned long long>(), c0->refill, maxL, grid, c0->block, cap);
-    hipError_t e2 = hipStreamEndCapture(cap, &g);
-    if (e == hipSuccess) e = e2;
-    if (e == hipSuccess) e = hipGraphInstantiate(&c0->b_graph, g, nullptr, nullptr, 0);
-    if (g) (void)hipGraphDestroy(g);
-    (void)hipStreamDestroy(cap);
-    if (e != hipSuccess) return fail(c0, RMC_EDEVICE, "graph capture: %s", hipGetErrorString(e));
-    c0->b_key = key;
-  }
-  HIPCHK(c0, hipEventRecord(c0->ev0, c0->stream));
-  HIPCHK(c0, hipGraphLaunch(c0->b_graph, c0->stream));
-  HIPCHK(c0, hipEventRecord(c0->ev1, c0->stream));
-  std::vector<unsigned long long> h((size_t)np * N_STATS);
-  for (int i = 0; i < np; ++i)
-    HIPCHK(c0, hipMemcpyAsync(h.data() + (size_t)i * N_STATS, P[i]->d_stats.p, N_STATS * 8, hipMemcpyDeviceToHost,
-                              c0->stream));
-  HIPCHK(c0, hipStreamSynchronize(c0->stream));
-  float ms = 0.f;
-  HIPCHK(c0, hipEventElapsedTime(&ms, c0->ev0, c0->ev1));
-  unsigned long long t[N_STATS] = {0};
-  for (int i = 0; i < np; ++i) {
-    if (per) fill_stats(per + i, h.data() + (size_t)i * N_STATS, ms);
-    for (int s = 0; s < N_STATS; ++s) t[s] += h[(size_t)i * N_STATS + s];
-    if ((int64_t)h[(size_t)i * N_STATS + S_EMITTED] != npk[i])
-      return fail(c0, RMC_EDEVICE, "problem %d finished %llu of %lld packets", i, h[(size_t)i * N_STATS + S_EMITTED],
-                  (long long)npk[i]);
-  }
-  if (total) fill_stats(total, t, ms);
-  return RMC_OK;
+  c0->s_probs = c0->b_probs.as<ProblemK>();
+  c0->s_starts = c0->b_starts.as<int64_t>();
+  c0->s_members.assign(P, P + np);
+  r = stream_open(c0, tot, np, maxL, true);
+  if (r) return r;
+  return stream_finish(c0, per, total);
 }
 
 rmc_status rmc_mesh_check(int64_t n, const int8_t *level, const int32_t *ijk, char *msg, int msg_len) {

@@ -25,20 +25,46 @@ __device__ __forceinline__ void atomic_add_real(float *p, float v) { unsafeAtomi
 __device__ __forceinline__ void atomic_add_real(double *p, double v) { unsafeAtomicAdd(p, v); }
 
 // --------------------------------------------------------------- ray cast
+// A point strictly inside a cell is located in that cell whatever the
+// direction, so a ray starting there needs no descent from the root.
+__device__ __forceinline__ bool strictly_inside(const Cell &c, int L, const double p[3]) {
+  const double inv = ldexp(1.0, -L);
+  const int s = 1 << (L - c.level);
+  const int o[3] = {c.ox, c.oy, c.oz};
+  bool in = true;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) in = in && (p[d] > (double)o[d] * inv) && (p[d] < (double)(o[d] + s) * inv);
+  return in;
+}
+
+// Where a peel-off ray may start: the packet's current cell, its leaf
+// record and the LDS stack of its ancestors.
+template <class R> struct StartCell {
+  const Cell *c;
+  const LeafRec<R> *lf;
+  const int *stk;
+};
+
 // Optical depth from p along k to the domain border at fixed x_ext (the
 // peel-off integral); stops once tau >= tau_cut.  Uses its own LDS stack.
 template <class R>
 __device__ double ray_tau(const ProblemK &pb, const double p0[3], const double k[3], double x_ext,
-                          double tau_cut, int *stk, int stride, uint32_t *ncross) {
+                          double tau_cut, int *stk, int stride, uint32_t *ncross,
+                          const StartCell<R> *sc = nullptr) {
   double p[3] = {p0[0], p0[1], p0[2]};
   int X[3];
-  if (!int_coords(pb.L, p, k, X)) return 0.0;
   const R kr[3] = {(R)k[0], (R)k[1], (R)k[2]};
   Cell c;
-  descend(pb.nodes, pb.L, 0, 0, X, stk, stride, c);
+  bool reuse = sc && strictly_inside(*sc->c, pb.L, p);
+  if (reuse) {
+    c = *sc->c;
+  } else {
+    if (!int_coords(pb.L, p, k, X)) return 0.0;
+    descend(pb.nodes, pb.L, 0, 0, X, stk, stride, c);
+  }
   double tau = 0.0;
   for (uint32_t steps = 0; steps < MAX_CROSS; ++steps) {
-    const LeafRec<R> lf = load_leaf<R>(pb.leaves, c.leaf);
+    const LeafRec<R> lf = (reuse && steps == 0) ? *sc->lf : load_leaf<R>(pb.leaves, c.leaf);
     Opac<R> o;
     opacity(pb, lf, x_ext, kr, o);
     double face[3], lo[3], hi[3];
@@ -57,6 +83,10 @@ __device__ double ray_tau(const ProblemK &pb, const double p0[3], const double k
     p[0] = pn[0]; p[1] = pn[1]; p[2] = pn[2];
     wrap_slab(pb.domain, p, k);
     if (!int_coords(pb.L, p, k, X)) break;
+    if (reuse && steps == 0) {
+      // first move out of the borrowed cell: copy its ancestors
+      for (int l = 0; l < c.level; ++l) stk[l * stride] = sc->stk[l * stride];
+    }
     relocate(pb.nodes, pb.L, X, stk, stride, c);
   }
   return tau;
@@ -103,7 +133,7 @@ template <class R> struct PeelSrc {
 
 template <class R>
 __device__ void peel_all(const ProblemK &pb, const double p[3], const PeelSrc<R> &s, int *stk,
-                         int stride, LaneCount &cnt) {
+                         int stride, LaneCount &cnt, const StartCell<R> *sc = nullptr) {
   for (int oi = 0; oi < pb.n_obs; ++oi) {
     const ObsK &ob = pb.obs[oi];
     const R ko[3] = {(R)ob.k[0], (R)ob.k[1], (R)ob.k[2]};
@@ -137,7 +167,7 @@ __device__ void peel_all(const ProblemK &pb, const double p[3], const PeelSrc<R>
     }
     ++cnt.peel_rays;
     uint32_t nc = 0;
-    const double tau = ray_tau<R>(pb, p, ob.k, (double)xo, TauCut<R>::v, stk, stride, &nc);
+    const double tau = ray_tau<R>(pb, p, ob.k, (double)xo, TauCut<R>::v, stk, stride, &nc, sc);
     cnt.peel_cross += nc;
     if (tau >= TauCut<R>::v) continue;
     const R wgt = weight * M<R>::exp((R)(-tau));
@@ -237,7 +267,9 @@ __device__ void emit(const ProblemK &pb, int64_t pid, Lane<R> &s, int *stk, int 
 // Interaction at the current position (Sect. 3.2).  Returns the packet's
 // status (ST_NONE while it lives).
 template <class R>
-__device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R> &o, int *pstk, int stride) {
+__device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R> &o, int *pstk, const int *stk,
+                        int stride) {
+  const StartCell<R> sc{&s.c, &s.lf, stk};
   ++s.event;
   if (pb.max_events > 0 && (int64_t)s.event >= pb.max_events) return ST_STUCK;
   EventRng<R> rng(pb.seed, (uint64_t)s.pid, s.event);
@@ -256,7 +288,7 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R> &o, int *p
     if (pb.n_obs) {
       ps.kind = 2;
       ps.x = s.x;
-      peel_all<R>(pb, s.p, ps, pstk, stride, s.cnt);
+      peel_all<R>(pb, s.p, ps, pstk, stride, s.cnt, &sc);
     }
     if (!pb.forward_only) {
       const R mu = mu_hg(rng.u(J_MU), R(pb.g_hg));
@@ -316,7 +348,7 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R> &o, int *p
       ps.rho = rho;
       ps.line = i;
       ps.core = core;
-      peel_all<R>(pb, s.p, ps, pstk, stride, s.cnt);
+      peel_all<R>(pb, s.p, ps, pstk, stride, s.cnt, &sc);
     }
     if (!pb.forward_only) {
       const R ru = rng.u(J_MU);
@@ -339,23 +371,89 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R> &o, int *p
   return ST_NONE;
 }
 
+// Packet state kept in HBM between launches (one slot per lane of the
+// grid): a run is a sequence of bounded launches, each lane resuming the
+// packet it held, so no launch waits for the longest random walk and each
+// launch can be replayed from a captured graph.
+struct SlotState {
+  double p[3], k[3];
+  double x, tau, path;
+  int64_t pid;
+  int32_t prob, active, event, nscat;
+  int32_t leaf, level, ox, oy, oz;
+  uint32_t dust, cross, peel_rays, peel_cross, peel_drop, iters;
+  int32_t pad;
+};
+
+template <class R>
+__device__ __forceinline__ void save_slot(SlotState &q, const Lane<R> &s, int prob) {
+  for (int d = 0; d < 3; ++d) { q.p[d] = s.p[d]; q.k[d] = (double)s.k[d]; }
+  q.x = (double)s.x; q.tau = s.tau; q.path = s.path; q.pid = s.pid;
+  q.prob = prob; q.active = 1; q.event = (int32_t)s.event; q.nscat = s.nscat;
+  q.leaf = s.c.leaf; q.level = s.c.level; q.ox = s.c.ox; q.oy = s.c.oy; q.oz = s.c.oz;
+  q.dust = s.cnt.dust_scat; q.cross = s.cnt.cross; q.peel_rays = s.cnt.peel_rays;
+  q.peel_cross = s.cnt.peel_cross; q.peel_drop = s.cnt.peel_drop; q.iters = s.upar_iters;
+}
+
+template <class R>
+__device__ __forceinline__ void load_slot(const SlotState &q, Lane<R> &s, int *prob) {
+  for (int d = 0; d < 3; ++d) { s.p[d] = q.p[d]; s.k[d] = (R)q.k[d]; }
+  s.x = (R)q.x; s.tau = q.tau; s.path = q.path; s.pid = q.pid;
+  *prob = q.prob; s.event = (uint32_t)q.event; s.nscat = q.nscat;
+  s.c.leaf = q.leaf; s.c.level = q.level; s.c.ox = q.ox; s.c.oy = q.oy; s.c.oz = q.oz;
+  s.cnt.dust_scat = q.dust; s.cnt.cross = q.cross; s.cnt.peel_rays = q.peel_rays;
+  s.cnt.peel_cross = q.peel_cross; s.cnt.peel_drop = q.peel_drop; s.upar_iters = q.iters;
+  set_geom_dir(s);
+}
+
+// Counters of work done inside one launch.
+struct SliceCount {
+  uint32_t scat, dust, cross, peel_rays, peel_cross, finished;
+};
+
+template <class R>
+__device__ __forceinline__ void add_delta(SliceCount &a, const Lane<R> &s, const Lane<R> &z) {
+  a.scat += (uint32_t)(s.nscat - z.nscat);
+  a.dust += s.cnt.dust_scat - z.cnt.dust_scat;
+  a.cross += s.cnt.cross - z.cnt.cross;
+  a.peel_rays += s.cnt.peel_rays - z.cnt.peel_rays;
+  a.peel_cross += s.cnt.peel_cross - z.cnt.peel_cross;
+}
+
 template <class R, bool BATCH>
 __global__ void __launch_bounds__(256) k_transport(const ProblemK *__restrict__ probs,
                                                    const int64_t *__restrict__ starts, int n_probs,
                                                    unsigned long long *__restrict__ next,
-                                                   int refill_min, int stack_levels) {
+                                                   int refill_min, int stack_levels,
+                                                   SlotState *__restrict__ slots, int budget,
+                                                   unsigned long long *__restrict__ slice) {
   extern __shared__ int lds[];
   const int stride = blockDim.x;
   int *stk = lds + threadIdx.x;
   int *pstk = lds + stack_levels * stride + threadIdx.x;
   const int64_t total = starts[n_probs];
   const int lane = __lane_id();
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
 
   Lane<R> s;
+  Lane<R> z;            // counters when this slice took the packet over
+  SliceCount acc{0, 0, 0, 0, 0, 0};
   int prob = 0;
   bool active = false;
   bool drained = false;
-  while (true) {
+  {
+    const SlotState &q = slots[gid];
+    if (q.active) {
+      load_slot<R>(q, s, &prob);
+      const ProblemK &pb = probs[BATCH ? prob : 0];
+      const int X[3] = {s.c.ox, s.c.oy, s.c.oz};
+      descend(pb.nodes, pb.L, 0, 0, X, stk, stride, s.c);
+      s.lf = load_leaf<R>(pb.leaves, s.c.leaf);
+      active = true;
+      z = s;
+    }
+  }
+  for (int it = 0; it < budget; ++it) {
     // ---- refill idle lanes: one atomic per wave, ranks from mbcnt
     if (!drained) {
       const unsigned long long idle = __ballot(!active);
@@ -381,12 +479,17 @@ __global__ void __launch_bounds__(256) k_transport(const ProblemK *__restrict__ 
             const ProblemK &pb = probs[BATCH ? prob : 0];
             const int64_t pid = pb.first + (g - starts[BATCH ? prob : 0]);
             emit<R>(pb, pid, s, stk, pstk, stride);
+            z = s;
+            z.nscat = 0;
+            z.cnt = LaneCount{0, 0, 0, 0, 0};
             int X[3];
             if (int_coords(pb.L, s.p, s.kd, X)) {
               descend(pb.nodes, pb.L, 0, 0, X, stk, stride, s.c);
               s.lf = load_leaf<R>(pb.leaves, s.c.leaf);
               active = true;
             } else {
+              add_delta(acc, s, z);
+              ++acc.finished;
               finish<R>(pb, s, ST_ESCAPED);
             }
           }
@@ -416,7 +519,7 @@ __global__ void __launch_bounds__(256) k_transport(const ProblemK *__restrict__ 
 #pragma unroll
       for (int d = 0; d < 3; ++d) s.p[d] = fmin(fmax(fma(dist, kd[d], s.p[d]), lo[d]), hi[d]);
       s.path += dist;
-      st = interact<R>(pb, s, o, pstk, stride);
+      st = interact<R>(pb, s, o, pstk, stk, stride);
     } else {
       s.tau -= tseg;
       s.path += lmax;
@@ -442,10 +545,41 @@ __global__ void __launch_bounds__(256) k_transport(const ProblemK *__restrict__ 
       }
     }
     if (st != ST_NONE) {
+      add_delta(acc, s, z);
+      ++acc.finished;
       finish<R>(pb, s, st);
       active = false;
     }
   }
+  // ---- park the packet (if any) for the next launch, publish the counts
+  SlotState &q = slots[gid];
+  if (active) {
+    save_slot<R>(q, s, prob);
+    add_delta(acc, s, z);
+  } else {
+    q.active = 0;
+  }
+  unsigned long long v[6] = {acc.scat, acc.dust, acc.cross, acc.peel_rays, acc.peel_cross, acc.finished};
+  const int idx[6] = {S_SCAT, S_DUST_SCAT, S_CROSS, S_PEEL_RAYS, S_PEEL_CROSS, S_EMITTED};
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    unsigned long long x = v[j];
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off);
+    if (lane == 0 && x) atomicAdd(slice + idx[j], x);
+  }
+}
+
+// Number of slots (lanes) holding a packet after a launch.
+__global__ void k_count_live(const SlotState *__restrict__ slots, int64_t n, unsigned long long *out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long v = (i < n && slots[i].active) ? 1ull : 0ull;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+  if (__lane_id() == 0 && v) atomicAdd(out, v);
+}
+
+__global__ void k_clear_slots(SlotState *__restrict__ slots, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) slots[i].active = 0;
 }
 
 // ------------------------------------------------------------------ probes
@@ -643,23 +777,37 @@ static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b -
 
 hipError_t launch_transport(bool fp32, bool batch, const ProblemK *d_probs, const int64_t *d_starts,
                             int n_probs, unsigned long long *d_next, int refill_min, int stack_levels,
-                            int grid, int block, hipStream_t st) {
+                            int grid, int block, void *slots, int budget, unsigned long long *slice,
+                            hipStream_t st) {
   const size_t lds = (size_t)2 * stack_levels * block * sizeof(int);
+  SlotState *sl = (SlotState *)slots;
   if (fp32) {
     if (batch)
       hipLaunchKernelGGL((k_transport<float, true>), dim3(grid), dim3(block), lds, st, d_probs, d_starts,
-                         n_probs, d_next, refill_min, stack_levels);
+                         n_probs, d_next, refill_min, stack_levels, sl, budget, slice);
     else
       hipLaunchKernelGGL((k_transport<float, false>), dim3(grid), dim3(block), lds, st, d_probs, d_starts,
-                         n_probs, d_next, refill_min, stack_levels);
+                         n_probs, d_next, refill_min, stack_levels, sl, budget, slice);
   } else {
     if (batch)
       hipLaunchKernelGGL((k_transport<double, true>), dim3(grid), dim3(block), lds, st, d_probs, d_starts,
-                         n_probs, d_next, refill_min, stack_levels);
+                         n_probs, d_next, refill_min, stack_levels, sl, budget, slice);
     else
       hipLaunchKernelGGL((k_transport<double, false>), dim3(grid), dim3(block), lds, st, d_probs, d_starts,
-                         n_probs, d_next, refill_min, stack_levels);
+                         n_probs, d_next, refill_min, stack_levels, sl, budget, slice);
   }
+  return hipGetLastError();
+}
+
+size_t slot_bytes() { return sizeof(SlotState); }
+
+hipError_t launch_clear_slots(void *slots, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_clear_slots, dim3(blocks_for(n, 256)), dim3(256), 0, st, (SlotState *)slots, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_live(const void *slots, int64_t n, unsigned long long *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_count_live, dim3(blocks_for(n, 256)), dim3(256), 0, st, (const SlotState *)slots, n, out);
   return hipGetLastError();
 }
 

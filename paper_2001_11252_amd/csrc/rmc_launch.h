@@ -9,7 +9,11 @@ namespace rmc {
 
 hipError_t launch_transport(bool fp32, bool batch, const ProblemK *d_probs, const int64_t *d_starts,
                             int n_probs, unsigned long long *d_next, int refill_min, int stack_levels,
-                            int grid, int block, hipStream_t st);
+                            int grid, int block, void *slots, int budget, unsigned long long *slice,
+                            hipStream_t st);
+size_t slot_bytes();
+hipError_t launch_clear_slots(void *slots, int64_t n, hipStream_t st);
+hipError_t launch_count_live(const void *slots, int64_t n, unsigned long long *out, hipStream_t st);
 hipError_t launch_trace(const ProblemK &pb, int64_t n, const double *orig, const double *dir,
                         int max_cells, int32_t *leaf, double *seg, int32_t *cnt, hipStream_t st);
 hipError_t launch_tau(bool fp32, const ProblemK &pb, int64_t n, const double *orig, const double *dir,

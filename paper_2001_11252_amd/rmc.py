@@ -20,6 +20,7 @@ FP64, FP32_BULK = 0, 1
 HOST, DEVICE = 0, 1
 F32, F64 = 0, 1
 OPT_FORWARD_ONLY, OPT_MAX_EVENTS, OPT_BLOCK, OPT_WAVES_PER_CU, OPT_REFILL, OPT_PEEL_DEFER = 1, 2, 3, 4, 5, 6
+OPT_SLICE_ITERS = 7
 ST_NONE, ST_ESCAPED, ST_ABSORBED, ST_STUCK = 0, 1, 2, 3
 _NAMES = {EINVAL: "RMC_EINVAL", ENOMEM: "RMC_ENOMEM", EDEVICE: "RMC_EDEVICE", EMESH: "RMC_EMESH",
           ESTATE: "RMC_ESTATE", EUNSUPPORTED: "RMC_EUNSUPPORTED"}
@@ -67,6 +68,9 @@ _sig = {
                                    C.POINTER(C.c_int)]),
     "rmc_reset_cubes": (C.c_int, [_P]),
     "rmc_run": (C.c_int, [_P, C.c_uint64, _i64, _i64, C.POINTER(RmcRunStats)]),
+    "rmc_stream_begin": (C.c_int, [_P, C.c_uint64, _i64, _i64]),
+    "rmc_stream_step": (C.c_int, [_P, C.POINTER(RmcRunStats), C.POINTER(_i64)]),
+    "rmc_stream_end": (C.c_int, [_P, C.POINTER(RmcRunStats)]),
     "rmc_get_packets": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, C.c_int]),
     "rmc_get_spectrum": (C.c_int, [_P, C.c_int, C.c_double, C.c_double, _P, C.c_int]),
     "rmc_get_cube": (C.c_int, [_P, C.c_int, _P, C.c_int, C.c_int]),
@@ -222,6 +226,21 @@ class Context:
         st = RmcRunStats()
         self._chk(_L.rmc_run(self._h, C.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), first, n, C.byref(st)), "run")
         self.last_n = n
+        return st.as_dict()
+
+    def stream_begin(self, seed, first, n):
+        self._chk(_L.rmc_stream_begin(self._h, C.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), first, n), "stream_begin")
+        self.last_n = n
+
+    def stream_step(self):
+        st = RmcRunStats()
+        rem = _i64(0)
+        self._chk(_L.rmc_stream_step(self._h, C.byref(st), C.byref(rem)), "stream_step")
+        return st.as_dict(), rem.value
+
+    def stream_end(self):
+        st = RmcRunStats()
+        self._chk(_L.rmc_stream_end(self._h, C.byref(st)), "stream_end")
         return st.as_dict()
 
     def get_packets(self, n=None):

@@ -223,6 +223,38 @@ def test_determinism_and_packet_ranges(rmc, orc):
         assert np.array_equal(a[k], np.concatenate([c[k], d[k]])), k
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_slicing_does_not_change_results(rmc, orc, prec):
+    # packets parked between launches resume exactly where they stopped
+    pb = W.static_sphere(s0(orc), 2e3, 1e3, 5000, level=4, tau_dust=0.3)
+    pb.gas.v[:] = np.random.default_rng(2).standard_normal((pb.mesh.n, 3)) * 10e5
+    pb.observers = [W.Observer((0.0, 0.6, 0.8), 8, 8, 10, (-0.5, 0.5, -0.5, 0.5), -20, 20)]
+    a = rmc.Context.from_problem(pb, prec)
+    sa = a.run(9, 0, 5000)
+    pa = a.get_packets()
+    b = rmc.Context.from_problem(pb, prec)
+    b.set_option(rmc.OPT_SLICE_ITERS, 7)
+    b.stream_begin(9, 0, 5000)
+    steps, work = 0, 0
+    while True:
+        sl, rem = b.stream_step()
+        steps += 1
+        work += sl["scatterings"]
+        if rem == 0:
+            break
+    sb = b.stream_end()
+    pbk = b.get_packets()
+    assert steps > 20
+    for k in pa:
+        assert np.array_equal(pa[k], pbk[k]), k
+    for k in ("emitted", "escaped", "absorbed", "scatterings", "crossings", "peel_rays", "peel_crossings"):
+        assert sa[k] == sb[k], k
+    assert work == sb["scatterings"]
+    # cubes agree up to the order of the atomic additions
+    ca, cb = a.get_cube(0), b.get_cube(0)
+    assert np.allclose(ca, cb, rtol=1e-5 if prec == "fp32" else 1e-12, atol=0)
+
+
 def test_error_paths(rmc, orc):
     ctx = rmc.Context("fp64")
     with pytest.raises(rmc.RmcError) as e:
