@@ -13,27 +13,27 @@ LIB = os.path.join(PKG, "librmc.so")
 SOURCES = ["csrc/rmc_kernels.hip", "csrc/rmc_api.cpp"]
 
 
-def hipcc_cmd(out=LIB):
+def hipcc_cmd(out=LIB, defines=()):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    return [hipcc, "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    return [hipcc, "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared"] + list(defines) + [
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-I" + os.path.join(ROOT, "include"), "-I" + os.path.join(PKG, "csrc"),
             "-o", out] + [os.path.join(PKG, s) for s in SOURCES]
 
 
-def build(verbose=False):
-    tmp = LIB + ".tmp"
-    cmd = hipcc_cmd(tmp)
+def build(verbose=False, out=LIB, defines=()):
+    tmp = out + ".tmp"
+    cmd = hipcc_cmd(tmp, defines)
     if verbose:
         print(" ".join(cmd), flush=True)
     p = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
-    out = "\n".join(l for l in p.stdout.splitlines() if "packed-fp32-ops" not in l)
+    log = "\n".join(l for l in p.stdout.splitlines() if "packed-fp32-ops" not in l)
     if p.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + out)
-    if verbose and out.strip():
-        print(out)
-    os.replace(tmp, LIB)
-    return LIB
+        raise RuntimeError("hipcc failed:\n" + log)
+    if verbose and log.strip():
+        print(log)
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -81,7 +81,7 @@ struct rmc_ctx {
   int forward_only = 0;
   int64_t max_events = 0;
   int block = 256;
-  int waves_per_cu = 8;
+  int waves_per_cu = 0;   // 0: as many as the transport kernel's occupancy allows
   int refill = 1;
   int peel_defer = 0;
   int slice_iters = 2048;
@@ -99,7 +99,10 @@ struct rmc_ctx {
   double T_ref = 0.0;
   // gas
   bool has_gas = false;
+  bool leaves_dirty = false;
   std::vector<double> gn, gT, gv, gk;
+  std::vector<int8_t> lev_h;
+  std::vector<int32_t> ijk_h;
   DevBuf leaves;
   double albedo = 0.32, g_hg = 0.73;
   int domain = RMC_DOM_BOX;
@@ -342,6 +345,31 @@ rmc_status download(rmc_ctx *c, void *dst, const void *src, size_t bytes, int me
   return RMC_OK;
 }
 
+// Does leaf (level l, integer coords ijk at its level) reach the border of
+// the domain (or lie outside it)?  Leaves strictly inside never need the
+// domain distance.  Sphere: all corners inside R(1 - 1e-9).
+bool leaf_on_border(const rmc_ctx *c, int l, const int32_t *ijk) {
+  const double h = std::ldexp(1.0, -l);
+  double lo[3], hi[3];
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = ijk[d] * h;
+    hi[d] = (ijk[d] + 1) * h;
+  }
+  if (c->domain == RMC_DOM_BOX) {
+    for (int d = 0; d < 3; ++d)
+      if (lo[d] <= 0.0 || hi[d] >= 1.0) return true;
+    return false;
+  }
+  if (c->domain == RMC_DOM_SLAB_Z) return !(lo[2] > c->dom[0] - c->dom[1] && hi[2] < c->dom[0] + c->dom[1]);
+  const double R = c->dom[3] * (1.0 - 1e-9);
+  double far2 = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    const double a = std::fabs(lo[d] - c->dom[d]), b = std::fabs(hi[d] - c->dom[d]);
+    far2 += std::max(a, b) * std::max(a, b);
+  }
+  return !(far2 < R * R);
+}
+
 // Per-leaf records relative to T_ref (see rmc_device.h).
 rmc_status build_leaves(rmc_ctx *c) {
   const LineQ q0 = line_q(c->lines[0], c->T_ref);
@@ -352,15 +380,17 @@ rmc_status build_leaves(rmc_ctx *c) {
   std::vector<unsigned char> host((size_t)n * LEAF_STRIDE * esz, 0);
   for (int64_t i = 0; i < n; ++i) {
     const double irho = std::sqrt(c->T_ref / c->gT[i]);
-    const double rec[6] = {c->gn[i] * c->box_cm * irho, irho, c->gk[i] * c->box_cm,
-                           c->gv[3 * i] / vth_ref, c->gv[3 * i + 1] / vth_ref, c->gv[3 * i + 2] / vth_ref};
-    for (int q = 0; q < 6; ++q) {
+    const double rec[7] = {c->gn[i] * c->box_cm * irho, irho, c->gk[i] * c->box_cm,
+                           c->gv[3 * i] / vth_ref, c->gv[3 * i + 1] / vth_ref, c->gv[3 * i + 2] / vth_ref,
+                           leaf_on_border(c, c->lev_h[i], &c->ijk_h[3 * i]) ? 1.0 : 0.0};
+    for (int q = 0; q < 7; ++q) {
       if (f32) ((float *)host.data())[(size_t)i * LEAF_STRIDE + q] = (float)rec[q];
       else ((double *)host.data())[(size_t)i * LEAF_STRIDE + q] = rec[q];
     }
   }
   HIPCHK(c, c->leaves.ensure(host.size()));
   HIPCHK(c, hipMemcpy(c->leaves.p, host.data(), host.size(), hipMemcpyHostToDevice));
+  c->leaves_dirty = false;
   return RMC_OK;
 }
 
@@ -415,6 +445,10 @@ rmc_status ready(rmc_ctx *c, bool need_sources) {
   if (!c->has_mesh) return fail(c, RMC_ESTATE, "no mesh (rmc_set_mesh)");
   if (!c->has_lines) return fail(c, RMC_ESTATE, "no lines (rmc_set_lines)");
   if (!c->has_gas) return fail(c, RMC_ESTATE, "no gas (rmc_set_gas)");
+  if (c->leaves_dirty) {
+    rmc_status r = build_leaves(c);
+    if (r) return r;
+  }
   if (need_sources && c->n_src <= 0) return fail(c, RMC_ESTATE, "no sources (rmc_set_sources)");
   if (c->domain == RMC_DOM_SLAB_Z)
     for (auto &o : c->obs)
@@ -435,9 +469,14 @@ rmc_status ensure_outputs(rmc_ctx *c, int64_t n) {
   return RMC_OK;
 }
 
-int grid_for(rmc_ctx *c, int64_t n) {
-  const int64_t lanes = (int64_t)c->num_cus * c->waves_per_cu * 64;
-  int64_t g = lanes / c->block;
+int grid_for(rmc_ctx *c, int64_t n, bool batch, int levels) {
+  int64_t g;
+  if (c->waves_per_cu > 0) {
+    g = (int64_t)c->num_cus * c->waves_per_cu * 64 / c->block;
+  } else {
+    const int bpc = transport_blocks_per_cu(c->precision == RMC_FP32_BULK, batch, c->block, std::max(levels, 1));
+    g = (int64_t)c->num_cus * bpc;
+  }
   const int64_t need = (n + c->block - 1) / c->block;
   g = std::min(g, need);
   return (int)std::max<int64_t>(g, 1);
@@ -524,7 +563,7 @@ rmc_status rmc_set_option(rmc_ctx *c, int opt, int64_t v) {
       c->block = (int)v;
       break;
     case RMC_OPT_WAVES_PER_CU:
-      if (v < 1 || v > 32) return fail(c, RMC_EINVAL, "waves per CU in [1,32]");
+      if (v < 0 || v > 32) return fail(c, RMC_EINVAL, "waves per CU in [0,32] (0: occupancy limit)");
       c->waves_per_cu = (int)v;
       break;
     case RMC_OPT_REFILL:
@@ -556,6 +595,8 @@ rmc_status rmc_set_mesh(rmc_ctx *c, int64_t n, const int8_t *level, const int32_
   HIPCHK(c, c->nodes.ensure(std::max<size_t>(nodes.size() * 4, 32)));
   if (!nodes.empty()) HIPCHK(c, hipMemcpy(c->nodes.p, nodes.data(), nodes.size() * 4, hipMemcpyHostToDevice));
   c->n_leaves = n;
+  c->lev_h.assign(level, level + n);
+  c->ijk_h.assign(ijk, ijk + 3 * n);
   c->n_nodes = (int64_t)nodes.size() / 8;
   c->L = L;
   c->box_cm = box_cm;
@@ -636,6 +677,7 @@ rmc_status rmc_set_domain(rmc_ctx *c, int kind, const double p[4]) {
   }
   c->domain = kind;
   for (int d = 0; d < 4; ++d) c->dom[d] = q[d];
+  if (c->has_gas) c->leaves_dirty = true;
   return RMC_OK;
 }
 
@@ -740,7 +782,7 @@ rmc_status stream_open(rmc_ctx *c, int64_t total, int n_probs, int levels, bool 
   c->s_nprobs = n_probs;
   c->s_levels = std::max(levels, 1);
   c->s_batch = batch;
-  c->s_grid = grid_for(c, total);
+  c->s_grid = grid_for(c, total, batch, levels);
   const int64_t n_slots = (int64_t)c->s_grid * c->block;
   HIPCHK(c, c->slots.ensure((size_t)n_slots * slot_bytes()));
   HIPCHK(c, c->d_slice.ensure(N_STATS * 8));

@@ -460,8 +460,11 @@ __device__ __forceinline__ void relocate(const int32_t *__restrict__ nodes, int 
 #pragma clang fp contract(fast)
 
 // ------------------------------------------------------------- leaf data
+// bnd != 0 marks a leaf that reaches the domain border (or lies outside
+// the domain); from a leaf strictly inside, every ray leaves the leaf
+// before the domain, so its domain distance is never the smaller one.
 template <class R> struct LeafRec {
-  R nl, irho, kd, ux, uy, uz;
+  R nl, irho, kd, ux, uy, uz, bnd;
 };
 
 template <class R>
@@ -470,15 +473,23 @@ __device__ __forceinline__ LeafRec<R> load_leaf(const void *leaves, int i) {
   const R *p = (const R *)leaves + (size_t)i * LEAF_STRIDE;
   if constexpr (sizeof(R) == 4) {
     const float4 a = *(const float4 *)p;
-    const float2 b = *(const float2 *)(p + 4);
-    r.nl = a.x; r.irho = a.y; r.kd = a.z; r.ux = a.w; r.uy = b.x; r.uz = b.y;
+    const float4 b = *(const float4 *)(p + 4);
+    r.nl = a.x; r.irho = a.y; r.kd = a.z; r.ux = a.w; r.uy = b.x; r.uz = b.y; r.bnd = b.z;
   } else {
     const double2 a = *(const double2 *)p;
     const double2 b = *(const double2 *)(p + 2);
     const double2 c = *(const double2 *)(p + 4);
-    r.nl = a.x; r.irho = a.y; r.kd = b.x; r.ux = b.y; r.uy = c.x; r.uz = c.y;
+    const double2 d = *(const double2 *)(p + 6);
+    r.nl = a.x; r.irho = a.y; r.kd = b.x; r.ux = b.y; r.uy = c.x; r.uz = c.y; r.bnd = d.x;
   }
   return r;
+}
+
+// Domain distance where it can matter (see LeafRec::bnd).
+template <class R>
+__device__ __forceinline__ double domain_dist_leaf(const LeafRec<R> &lf, int kind, const double dom[4],
+                                                   const double p[3], const double k[3]) {
+  return lf.bnd != R(0) ? domain_dist(kind, dom, p, k) : __builtin_inf();
 }
 
 // Opacity (times box size) of a leaf for a packet at x_ext along k.

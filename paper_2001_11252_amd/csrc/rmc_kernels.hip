@@ -70,7 +70,7 @@ __device__ double ray_tau(const ProblemK &pb, const double p0[3], const double k
     double face[3], lo[3], hi[3];
     int em;
     const double te = exit_dist(c, pb.L, p, k, face, lo, hi, &em);
-    const double td = domain_dist(pb.domain, pb.dom, p, k);
+    const double td = domain_dist_leaf(lf, pb.domain, pb.dom, p, k);
     ++*ncross;
     if (td <= te) {
       tau += (double)o.ktot * td;
@@ -420,8 +420,21 @@ __device__ __forceinline__ void add_delta(SliceCount &a, const Lane<R> &s, const
   a.peel_cross += s.cnt.peel_cross - z.cnt.peel_cross;
 }
 
+// Waves per SIMD the transport kernel is compiled for (register budget).
+#ifndef RMC_WAVES_F32
+#define RMC_WAVES_F32 3
+#endif
+#ifndef RMC_WAVES_F64
+#define RMC_WAVES_F64 1
+#endif
+template <class R> struct WavesPerEU;
+template <> struct WavesPerEU<float> { static constexpr int v = RMC_WAVES_F32; };
+template <> struct WavesPerEU<double> { static constexpr int v = RMC_WAVES_F64; };
+
 template <class R, bool BATCH>
-__global__ void __launch_bounds__(256) k_transport(const ProblemK *__restrict__ probs,
+__global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(WavesPerEU<R>::v, WavesPerEU<R>::v)))
+    k_transport(const ProblemK *__restrict__ probs,
                                                    const int64_t *__restrict__ starts, int n_probs,
                                                    unsigned long long *__restrict__ next,
                                                    int refill_min, int stack_levels,
@@ -509,7 +522,7 @@ __global__ void __launch_bounds__(256) k_transport(const ProblemK *__restrict__ 
     double face[3], lo[3], hi[3];
     int em;
     const double te = exit_dist(s.c, pb.L, s.p, kd, face, lo, hi, &em);
-    const double td = domain_dist(pb.domain, pb.dom, s.p, kd);
+    const double td = domain_dist_leaf(s.lf, pb.domain, pb.dom, s.p, kd);
     const double lmax = te < td ? te : td;
     const double tseg = (double)o.ktot * lmax;
     int st = ST_NONE;
@@ -699,7 +712,7 @@ __global__ void k_image_bwd(ProblemK pb, int obs, int64_t n, const double *__res
           double face[3], lo[3], hi[3];
           int em;
           const double te = exit_dist(c, pb.L, p, k, face, lo, hi, &em);
-          const double td = domain_dist(pb.domain, pb.dom, p, k);
+          const double td = domain_dist_leaf(lf, pb.domain, pb.dom, p, k);
           const double seg = td <= te ? td : te;
           const R b = R(pb.b_ref);
           const R den = R(1) + b * o.w;
@@ -800,6 +813,19 @@ hipError_t launch_transport(bool fp32, bool batch, const ProblemK *d_probs, cons
 }
 
 size_t slot_bytes() { return sizeof(SlotState); }
+
+int transport_blocks_per_cu(bool fp32, bool batch, int block, int stack_levels) {
+  const size_t lds = (size_t)2 * stack_levels * block * sizeof(int);
+  int nb = 0;
+  hipError_t e;
+  if (fp32)
+    e = batch ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_transport<float, true>, block, lds)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_transport<float, false>, block, lds);
+  else
+    e = batch ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_transport<double, true>, block, lds)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_transport<double, false>, block, lds);
+  return (e == hipSuccess && nb > 0) ? nb : 1;
+}
 
 hipError_t launch_clear_slots(void *slots, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_clear_slots, dim3(blocks_for(n, 256)), dim3(256), 0, st, (SlotState *)slots, n);

@@ -12,6 +12,7 @@ hipError_t launch_transport(bool fp32, bool batch, const ProblemK *d_probs, cons
                             int grid, int block, void *slots, int budget, unsigned long long *slice,
                             hipStream_t st);
 size_t slot_bytes();
+int transport_blocks_per_cu(bool fp32, bool batch, int block, int stack_levels);
 hipError_t launch_clear_slots(void *slots, int64_t n, hipStream_t st);
 hipError_t launch_count_live(const void *slots, int64_t n, unsigned long long *out, hipStream_t st);
 hipError_t launch_trace(const ProblemK &pb, int64_t n, const double *orig, const double *dir,

@@ -13,7 +13,9 @@ import numpy as np
 from . import workloads as W
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "librmc.so")
+# RMC_LIBRARY selects another build of the library (e.g. one compiled for
+# a different register budget); default: the in-tree librmc.so
+LIB_PATH = os.environ.get("RMC_LIBRARY") or os.path.join(_HERE, "librmc.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EMESH, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 FP64, FP32_BULK = 0, 1
