@@ -205,6 +205,16 @@ rmc_status rmc_batch_run(rmc_ctx *const *problems, int n_problems, const uint64_
                          const int64_t *n_packets, rmc_run_stats *per_problem,
                          rmc_run_stats *total);
 
+/* Pick the transport launch shape for a batch by measurement: every
+ * candidate (threads per block x idle lanes a wave gathers before refilling
+ * x loop iterations per launch) runs `trial_slices` launches of this batch
+ * (their results are discarded) and the one with the most scatterings plus
+ * ray-cell crossings per second is kept as the options of problems[0] for
+ * later rmc_batch_run calls.  best[3] (may be NULL) receives the chosen
+ * {block, refill, slice_iters}. */
+rmc_status rmc_batch_autotune(rmc_ctx *const *problems, int n_problems, const uint64_t *seeds,
+                              const int64_t *n_packets, int trial_slices, int best[3]);
+
 /* ------------------------------------------------ host-only helpers */
 /* Mesh check without a device: RMC_OK or RMC_EMESH/RMC_EINVAL with a
  * message in msg (may be NULL). */

@@ -15,7 +15,8 @@ SOURCES = ["csrc/rmc_kernels.hip", "csrc/rmc_api.cpp"]
 
 def hipcc_cmd(out=LIB, defines=()):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    return [hipcc, "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared"] + list(defines) + [
+    return [hipcc, "--offload-arch=gfx950", "-mcode-object-version=5", "-O3", "-std=c++17", "-fPIC",
+            "-shared"] + list(defines) + [
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-I" + os.path.join(ROOT, "include"), "-I" + os.path.join(PKG, "csrc"),
             "-o", out] + [os.path.join(PKG, s) for s in SOURCES]

@@ -124,8 +124,6 @@ struct rmc_ctx {
   DevBuf b_probs, b_starts;
   std::vector<ProblemK> b_host;
   std::vector<int64_t> b_starts_host;
-  hipGraphExec_t b_graph = nullptr;
-  std::string b_key;
   // streaming state (single problem or a batch led by this context)
   DevBuf slots, d_slice;
   int64_t s_total = 0, s_done = 0;
@@ -527,7 +525,6 @@ void rmc_destroy(rmc_ctx *c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
-  if (c->b_graph) (void)hipGraphExecDestroy(c->b_graph);
   if (c->s_graph) (void)hipGraphExecDestroy(c->s_graph);
   DevBuf *bufs[] = {&c->nodes, &c->leaves, &c->spos, &c->sdir, &c->sx, &c->o_status, &c->o_x, &c->o_k,
                     &c->o_pos, &c->o_nscat, &c->o_path, &c->d_stats, &c->d_next, &c->d_prob, &c->d_starts,
@@ -1134,12 +1131,12 @@ rmc_status rmc_raycast_image_backward(rmc_ctx *c, int id, int64_t n, const doubl
   return RMC_OK;
 }
 
-rmc_status rmc_batch_run(rmc_ctx *const *P, int np, const uint64_t *seeds, const int64_t *npk,
-                         rmc_run_stats *per, rmc_run_stats *total) {
-  if (!P || np <= 0 || !seeds || !npk) return RMC_EINVAL;
+namespace {
+
+// Upload the problem descriptors of a batch and open a stream over them.
+rmc_status batch_open(rmc_ctx *const *P, int np, const uint64_t *seeds, const int64_t *npk) {
   rmc_ctx *c0 = P[0];
-  rmc_status r = enter(c0);
-  if (r) return r;
+  rmc_status r;
   int maxL = 1;
   for (int i = 0; i < np; ++i) {
     rmc_ctx *c = P[i];
@@ -1167,9 +1164,69 @@ rmc_status rmc_batch_run(rmc_ctx *const *P, int np, const uint64_t *seeds, const
   c0->s_probs = c0->b_probs.as<ProblemK>();
   c0->s_starts = c0->b_starts.as<int64_t>();
   c0->s_members.assign(P, P + np);
-  r = stream_open(c0, tot, np, maxL, true);
+  return stream_open(c0, tot, np, maxL, true);
+}
+
+}  // namespace
+
+rmc_status rmc_batch_run(rmc_ctx *const *P, int np, const uint64_t *seeds, const int64_t *npk,
+                         rmc_run_stats *per, rmc_run_stats *total) {
+  if (!P || np <= 0 || !seeds || !npk) return RMC_EINVAL;
+  rmc_ctx *c0 = P[0];
+  rmc_status r = enter(c0);
+  if (r) return r;
+  r = batch_open(P, np, seeds, npk);
   if (r) return r;
   return stream_finish(c0, per, total);
+}
+
+rmc_status rmc_batch_autotune(rmc_ctx *const *P, int np, const uint64_t *seeds, const int64_t *npk, int trials,
+                              int best[3]) {
+  if (!P || np <= 0 || !seeds || !npk || trials <= 0) return RMC_EINVAL;
+  rmc_ctx *c0 = P[0];
+  rmc_status r = enter(c0);
+  if (r) return r;
+  const int blocks[] = {64, 128, 256};
+  const int refills[] = {1, 8, 32};
+  const int slices[] = {256, 2048};
+  double best_rate = -1.0;
+  int bb = c0->block, br = c0->refill, bs = c0->slice_iters;
+  for (int b : blocks)
+    for (int f : refills)
+      for (int sl : slices) {
+        c0->block = b;
+        c0->refill = f;
+        c0->slice_iters = sl;
+        r = batch_open(P, np, seeds, npk);
+        if (r) return r;
+        double work = 0.0, ms = 0.0;
+        for (int t = 0; t < trials; ++t) {
+          rmc_run_stats st;
+          int64_t rem = 0;
+          r = stream_step(c0, &st, &rem);
+          if (r) return r;
+          work += (double)st.scatterings + (double)st.crossings + (double)st.peel_crossings;
+          ms += st.kernel_ms;
+          if (rem == 0) break;
+        }
+        c0->s_open = false;
+        const double rate = ms > 0.0 ? work / ms : 0.0;
+        if (rate > best_rate) {
+          best_rate = rate;
+          bb = b;
+          br = f;
+          bs = sl;
+        }
+      }
+  c0->block = bb;
+  c0->refill = br;
+  c0->slice_iters = bs;
+  if (best) {
+    best[0] = bb;
+    best[1] = br;
+    best[2] = bs;
+  }
+  return RMC_OK;
 }
 
 rmc_status rmc_mesh_check(int64_t n, const int8_t *level, const int32_t *ijk, char *msg, int msg_len) {

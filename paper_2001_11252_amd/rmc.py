@@ -50,6 +50,15 @@ class RmcRunStats(C.Structure):
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+# PyTorch provides the device memory and streams; it carries its own HIP
+# runtime.  Loading it first makes librmc bind to that same runtime (the
+# library's libamdhip64.so.7 dependency resolves to the one already loaded),
+# so a process holds a single HIP runtime and torch streams and pointers
+# are valid in the library.
+try:
+    import torch as _torch  # noqa: F401
+except ImportError:
+    _torch = None
 _L = C.CDLL(LIB_PATH)
 _P = C.c_void_p
 _i64 = C.c_int64
@@ -81,6 +90,7 @@ _sig = {
     "rmc_raycast_image": (C.c_int, [_P, C.c_int, _i64, _P, _P, _P, _P, C.c_int]),
     "rmc_raycast_image_backward": (C.c_int, [_P, C.c_int, _i64, _P, _P, _P, _P, _P, _P, _P, C.c_int]),
     "rmc_batch_run": (C.c_int, [_P, C.c_int, _P, _P, C.POINTER(RmcRunStats), C.POINTER(RmcRunStats)]),
+    "rmc_batch_autotune": (C.c_int, [_P, C.c_int, _P, _P, C.c_int, _P]),
     "rmc_mesh_check": (C.c_int, [_i64, _P, _P, C.c_char_p, C.c_int]),
     "rmc_line_quantities": (C.c_int, [_P, C.c_double, _P]),
 }
@@ -348,6 +358,20 @@ def batch_run(contexts, seeds, n_packets):
     for c, k in zip(contexts, npk):
         c.last_n = int(k)
     return [p.as_dict() for p in per], tot.as_dict()
+
+
+def batch_autotune(contexts, seeds, n_packets, trial_slices=3):
+    """Measure launch shapes on this batch; returns {block, refill,
+    slice_iters} now set on contexts[0] for later batch_run calls."""
+    n = len(contexts)
+    hs = (C.c_void_p * n)(*[c.handle.value for c in contexts])
+    sd = np.ascontiguousarray([int(s) & 0xFFFFFFFFFFFFFFFF for s in seeds], dtype=np.uint64)
+    npk = np.ascontiguousarray(n_packets, dtype=np.int64)
+    best = np.zeros(3, dtype=np.int32)
+    rc = _L.rmc_batch_autotune(hs, n, _ptr(sd), _ptr(npk), int(trial_slices), _ptr(best))
+    if rc:
+        raise RmcError(rc, "batch_autotune: " + _L.rmc_last_error(contexts[0].handle).decode())
+    return dict(block=int(best[0]), refill=int(best[1]), slice_iters=int(best[2]))
 
 
 def _make_raycast_fn():

@@ -312,7 +312,7 @@ def c3_shell(sigma0_fn, vmax_kms=200.0, n_packets=10_000_000, tau0=1e7, mesh=Non
 
 
 def c4_batch(sigma0_fn, n_problems=64, seed=0x5EED0004, work_cap=1e10, packet_scale=1.0,
-             max_level=7):
+             max_level=7, log_tau_range=(3.0, 7.0)):
     """Many uneven problems: slab or sphere, tau0 log-uniform in [1e3,1e7],
     T log-uniform in [1e2,1e5] K, Lya or the MgII 2796/2804 doublet,
     uniform grids 8^3..128^3 with lognormal n_HI (sigma_ln = 1, mean
@@ -323,7 +323,7 @@ def c4_batch(sigma0_fn, n_problems=64, seed=0x5EED0004, work_cap=1e10, packet_sc
     for pid in range(n_problems):
         while True:
             geom = rng.integers(2)
-            ltau = rng.uniform(3, 7)
+            ltau = rng.uniform(*log_tau_range)
             lT = rng.uniform(2, 5)
             mg = rng.integers(2)
             lev = int(rng.integers(3, max_level + 1))

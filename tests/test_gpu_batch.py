@@ -1,0 +1,80 @@
+"""GPU batched launch (many uneven problems in one persistent, graph-
+replayed launch): per-packet results equal to running each problem on its
+own, parity of each problem with the oracle, and the autotuner."""
+import numpy as np
+import pytest
+from scipy import stats
+
+from paper_2001_11252_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _small_batch(orc, n=12, seed=0x5EED0004, packet_scale=0.02, work_cap=2e7):
+    # C4's mix (slab/sphere, Lya/MgII doublet, lognormal n_HI, uneven grids
+    # and packet counts) at tau0 <= 1e4 so that each packet's walk stays short
+    s0 = lambda ln, T: orc.line_quantities(ln, T)["sigma0"]
+    return W.c4_batch(s0, n_problems=n, seed=seed, work_cap=work_cap, packet_scale=packet_scale, max_level=5,
+                      log_tau_range=(3.0, 4.0))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_equals_single_runs(orc, prec):
+    from paper_2001_11252_amd import rmc
+    probs = _small_batch(orc)
+    ctxs = [rmc.Context.from_problem(p, prec) for p in probs]
+    npk = [len(p.sources.x) for p in probs]
+    seeds = [p.seed for p in probs]
+    per, tot = rmc.batch_run(ctxs, seeds, npk)
+    assert tot["emitted"] == sum(npk)
+    outs = [c.get_packets() for c in ctxs]
+    for p, c, o, st, n in zip(probs, ctxs, outs, per, npk):
+        assert st["emitted"] == n and st["escaped"] + st["absorbed"] + st["stuck"] == n
+        single = rmc.Context.from_problem(p, prec)
+        s1 = single.run(p.seed, 0, n)
+        o1 = single.get_packets()
+        for k in o:
+            assert np.array_equal(o[k], o1[k]), (p.name, k)
+        for k in ("scatterings", "crossings", "escaped", "absorbed"):
+            assert st[k] == s1[k], (p.name, k)
+    # the captured launch replays with the same results
+    per2, _ = rmc.batch_run(ctxs, seeds, npk)
+    for c, o in zip(ctxs, outs):
+        o2 = c.get_packets()
+        for k in o:
+            assert np.array_equal(o[k], o2[k])
+
+
+def test_batch_matches_oracle(orc):
+    from paper_2001_11252_amd import rmc
+    probs = _small_batch(orc, n=6, seed=77, packet_scale=1.0, work_cap=5e6)
+    ctxs = [rmc.Context.from_problem(p, "fp32") for p in probs]
+    npk = [len(p.sources.x) for p in probs]
+    rmc.batch_run(ctxs, [p.seed for p in probs], npk)
+    for p, c, n in zip(probs, ctxs, npk):
+        g = c.get_packets()
+        o = orc.run(p, p.seed)
+        xg = g["x"][g["status"] == 1]
+        xo = o["x"][o["status"] == 1]
+        assert stats.ks_2samp(xg, xo).pvalue > 1e-3, (p.name, p.meta)
+        se = np.sqrt(g["n_scat"].var() / n + o["n_scat"].var() / n)
+        assert abs(g["n_scat"].mean() - o["n_scat"].mean()) < 4 * se + 1e-9, p.name
+
+
+def test_batch_autotune_picks_a_valid_shape(orc):
+    from paper_2001_11252_amd import rmc
+    probs = _small_batch(orc, n=8, seed=3)
+    ctxs = [rmc.Context.from_problem(p, "fp32") for p in probs]
+    npk = [len(p.sources.x) for p in probs]
+    seeds = [p.seed for p in probs]
+    best = rmc.batch_autotune(ctxs, seeds, npk, trial_slices=2)
+    assert best["block"] in (64, 128, 256) and best["refill"] in (1, 8, 32) and best["slice_iters"] in (256, 2048)
+    # the tuned run gives the same packets as an untuned one
+    rmc.batch_run(ctxs, seeds, npk)
+    tuned = [c.get_packets() for c in ctxs]
+    ref = [rmc.Context.from_problem(p, "fp32") for p in probs]
+    rmc.batch_run(ref, seeds, npk)
+    for a, b in zip(tuned, ref):
+        bb = b.get_packets()
+        for k in a:
+            assert np.array_equal(a[k], bb[k])
