@@ -38,6 +38,31 @@ BYTES_PER_CROSSING = {"fp32": 28.0, "fp64": 52.0}
 PEAK = {"fp32": 157.3, "fp64": 78.6}       # TFLOP/s, MI355X vector
 
 
+def kernel_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    src = os.path.join(ROOT, "paper_2001_11252_amd", "csrc")
+    for f in sorted(os.listdir(src)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(open(os.path.join(src, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(prec):
+    """HBM bytes per transport launch from the profiler's FETCH_SIZE and
+    WRITE_SIZE counters (profiles/transport_traffic.json), or None if the
+    kernel sources changed since they were taken."""
+    import json as _j
+    f = os.path.join(ROOT, "profiles", "transport_traffic.json")
+    if not os.path.exists(f):
+        return None
+    d = _j.load(open(f))
+    e = d.get(prec)
+    if not e or d.get("source_digest") != kernel_source_digest():
+        return None
+    return e["bytes_per_launch"]
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -50,6 +75,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-packets", type=int, default=0, help="oracle packets (0: one per core)")
     ap.add_argument("--only", choices=["fp32", "fp64", "both"], default="both")
+    ap.add_argument("--copy-gib", type=float, default=1.0, help="size of the copy used to measure HBM bandwidth")
     return ap.parse_args()
 
 
@@ -92,6 +118,24 @@ def main():
               f"remaining {rem}, stats {tot}", file=sys.stderr, flush=True)
         ctx.close()
         return wall, tot, kms
+
+    # achievable HBM bandwidth: a plain device copy (read + write) of known
+    # size; the same kernel calibrates the profiler's traffic counters
+    n_el = int(a.copy_gib * (1 << 30)) // 4
+    src = torch.ones(n_el, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_GBps = 5 * 2 * n_el * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    print(f"# copy: {copy_GBps:.1f} GB/s (read+write of {a.copy_gib} GiB)", file=sys.stderr, flush=True)
 
     res = {}
     if a.only in ("fp32", "both"):
@@ -137,8 +181,9 @@ def main():
                    "leaves": int(pb.mesh.n), "observer": "+z 128x128x100", "parallelism": "none"},
         "precisions": side,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK[head], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK[head], "traffic": None,
+                     "frac": achieved / PEAK[head], "traffic": measured_traffic(head),
                      "kernel": "k_transport<float,false>" if head == "fp32" else "k_transport<double,false>"},
+        "hbm_copy_GBps": copy_GBps,
     }
     if not a.no_cpu_baseline:
         from oracle import oracle as O
