@@ -5,14 +5,16 @@ sphere, tau0 = 1e6 at line centre along the radius, T = 1e4 K, dust with
 tau_dust = 1 (albedo 0.32, g = 0.73), octree refined from level 3 to 7
 toward the centre (287,064 leaves), packets emitted at x = 0 from the
 centre, one observer along +z with a 128x128x100 peel-off cube, 1e6
-packets queued.  A step is one transport launch: every lane of the grid
-advances the packet it holds by up to --slice loop iterations (emission,
-propagation, scattering, dust, peel-off of every event, termination) and
-lanes whose packet finished take the next one from the queue; packets that
-are still alive are parked in device memory for the next step.  Timed steps
-follow warm-up steps, so they measure the steady state of the resident
-packet pool.  The FP32 bulk path is the headline; the FP64 path runs beside
-it on the same packets.
+packets queued.  A step is one transport launch and the ray-cast pass that
+follows it: every lane of the grid advances the packet it holds by up to
+--slice loop iterations (emission, propagation, scattering, dust, peel-off
+of every event through the scattering's own leaf, termination) and lanes
+whose packet finished take the next one from the queue; packets that are
+still alive are parked in device memory for the next step, and peel-off
+rays that leave their first leaf are walked to the border by the ray-cast
+pass.  Timed steps follow warm-up steps, so they measure the steady state
+of the resident packet pool.  The FP32 bulk path is the headline; the FP64
+path runs beside it on the same packets.
 
 Prints one JSON line.  Inputs are synthetic and seeded.
 """
@@ -39,12 +41,12 @@ PEAK = {"fp32": 157.3, "fp64": 78.6}       # TFLOP/s, MI355X vector
 
 
 def kernel_source_digest():
+    """Digest of the device code (kernels and the header they include)."""
     import hashlib
     h = hashlib.sha256()
     src = os.path.join(ROOT, "paper_2001_11252_amd", "csrc")
-    for f in sorted(os.listdir(src)):
-        if f.endswith((".hip", ".h", ".cpp")):
-            h.update(open(os.path.join(src, f), "rb").read())
+    for f in ("rmc_device.h", "rmc_kernels.hip"):
+        h.update(open(os.path.join(src, f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -114,7 +116,7 @@ def main():
                 tot[k] = tot.get(k, 0) + v
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        print(f"# {prec}: {nsteps} steps in {wall:.3f} s, kernel ms {[round(k, 1) for k in kms]}, "
+        print(f"# {prec}: {nsteps} steps in {wall:.3f} s, transport ms {[round(k, 1) for k in kms]}, "
               f"remaining {rem}, stats {tot}", file=sys.stderr, flush=True)
         ctx.close()
         return wall, tot, kms
@@ -148,19 +150,26 @@ def main():
     scat_s = tot["scatterings"] / wall
     cross = tot["crossings"] + tot["peel_crossings"]
     cross_s = cross / wall
-    # roofline of the dominant kernel (the transport launch): algorithmic
-    # work per launch over its average device duration
+    # roofline of the dominant kernel (the transport launch): its
+    # algorithmic work per launch (every scattering, every transport
+    # segment, and the first leaf of every peel-off ray) over its average
+    # device duration; the rest of the peel-off rays is the ray-cast pass
     avg_ms = sum(kms) / nsteps
-    flops_per_launch = (FLOP_PER_SCATTERING * tot["scatterings"] + FLOP_PER_CROSSING * cross) / nsteps
+    transport_cross = tot["crossings"] + tot["peel_rays"]
+    flops_per_launch = (FLOP_PER_SCATTERING * tot["scatterings"] + FLOP_PER_CROSSING * transport_cross) / nsteps
     achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
     side = {}
     for prec, (w, t, k) in res.items():
+        pass_cross = t["peel_crossings"] - t["peel_rays"]
         side[prec] = {"scatterings_per_s": t["scatterings"] / w,
                       "crossings_per_s": (t["crossings"] + t["peel_crossings"]) / w,
                       "ms_per_step": 1e3 * w / len(k),
-                      "kernel_ms_avg": sum(k) / len(k),
+                      "transport_ms_avg": sum(k) / len(k),
+                      "peel_pass_ms_avg": t["peel_pass_ms"] / len(k),
+                      "peel_rays_deferred_per_step": t["peel_deferred"] / len(k),
+                      "peel_pass_crossings_per_s": pass_cross / max(t["peel_pass_ms"] * 1e-3, 1e-30),
                       "hbm_GBps_algorithmic": (t["crossings"] + t["peel_crossings"]) * BYTES_PER_CROSSING[prec]
-                      / (sum(k) * 1e-3) / 1e9,
+                      / ((sum(k) + t["peel_pass_ms"]) * 1e-3) / 1e9,
                       "packets_finished": t["emitted"]}
     line = {
         "metric": "scatterings/s + ray-cell crossings/s (1 GPU), FP32 vs FP64 at matched spectra",
@@ -182,7 +191,7 @@ def main():
         "precisions": side,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK[head], "unit": "TFLOP/s",
                      "frac": achieved / PEAK[head], "traffic": measured_traffic(head),
-                     "kernel": "k_transport<float,false>" if head == "fp32" else "k_transport<double,false>"},
+                     "kernel": "k_transport<float,false,true>" if head == "fp32" else "k_transport<double,false,true>"},
         "hbm_copy_GBps": copy_GBps,
     }
     if not a.no_cpu_baseline:

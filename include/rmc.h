@@ -65,8 +65,12 @@ enum {
   RMC_OPT_WAVES_PER_CU = 4,  /* resident waves per CU the grid is sized for  */
   RMC_OPT_REFILL = 5,        /* idle lanes a wave gathers before it takes new
                                 packets (1..64)                              */
-  RMC_OPT_PEEL_DEFER = 6,    /* 1: peel-off rays go through a queue to a
-                                separate ray-cast kernel                     */
+  RMC_OPT_PEEL_DEFER = 6,    /* 1 (default): a peel-off ray that leaves the
+                                leaf of its scattering is queued and walked
+                                on by a ray-cast pass after each transport
+                                launch; 0: walked inline by the transport
+                                kernel.  Results agree up to the order of
+                                the cube additions.                          */
   RMC_OPT_SLICE_ITERS = 7    /* loop iterations (events or cell crossings)
                                 per lane in one transport launch            */
 };
@@ -90,7 +94,12 @@ typedef struct {
   uint64_t peel_rays;
   uint64_t peel_crossings;    /* ray-cell segments of peel-off rays           */
   uint64_t peel_dropped;      /* peel-off deposits outside a cube             */
+  uint64_t peel_deferred;     /* peel-off rays handed from the transport
+                                 launch to the ray-cast pass (whole launch;
+                                 0 in per-problem reports)                    */
   double kernel_ms;           /* device time of the transport launch(es)      */
+  double peel_pass_ms;        /* device time of the ray-cast passes over the
+                                 deferred peel-off rays                       */
 } rmc_run_stats;
 
 /* ------------------------------------------------------------- lifetime */
@@ -183,8 +192,8 @@ rmc_status rmc_tau(rmc_ctx *ctx, int64_t n, const double *orig, const double *di
                    const double *x_ext, double *tau_out, int mem);
 
 /* ---------------------------------------- peel-off image and its adjoint */
-/* Image (ny*nx, frequency-integrated over the observer's spectral range) of
- * fixed rays toward observer `id`: image[p] = sum_r w_r exp(-tau_r) for the
+/* Image (ny*nx) of fixed rays toward observer `id`, each ray at its own
+ * x_ext (no spectral binning): image[p] = sum_r w_r exp(-tau_r) over the
  * rays whose origin projects onto pixel p. */
 rmc_status rmc_raycast_image(rmc_ctx *ctx, int id, int64_t n_rays, const double *orig,
                              const double *x_ext, const double *w, double *image, int mem);

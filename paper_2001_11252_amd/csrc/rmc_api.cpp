@@ -83,7 +83,7 @@ struct rmc_ctx {
   int block = 256;
   int waves_per_cu = 0;   // 0: as many as the transport kernel's occupancy allows
   int refill = 1;
-  int peel_defer = 0;
+  int peel_defer = 1;      // peel-off rays past their first leaf go to the ray-cast pass
   int slice_iters = 2048;
   // mesh
   bool has_mesh = false;
@@ -119,7 +119,7 @@ struct rmc_ctx {
   ProblemK pb_host;
   int64_t starts_host[2];
   int num_cus = 0;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
   // batch launches
   DevBuf b_probs, b_starts;
   std::vector<ProblemK> b_host;
@@ -133,8 +133,13 @@ struct rmc_ctx {
   const int64_t *s_starts = nullptr;
   std::vector<rmc_ctx *> s_members;
   rmc_run_stats s_acc;
-  hipGraphExec_t s_graph = nullptr;
+  hipGraphExec_t s_graph = nullptr;   // slice counters + transport launch
+  hipGraphExec_t s_graph2 = nullptr;  // ray-cast pass over the peel-off queue
   std::string s_key;
+  PeelQueue *s_pq = nullptr;
+  // deferred peel-off rays: control block (PeelQueue) and job buffer
+  DevBuf pq_ctl, pq_jobs, pq_counts;
+  unsigned long long pq_cap = 0, pq_regions = 0;
 };
 
 namespace {
@@ -472,7 +477,8 @@ int grid_for(rmc_ctx *c, int64_t n, bool batch, int levels) {
   if (c->waves_per_cu > 0) {
     g = (int64_t)c->num_cus * c->waves_per_cu * 64 / c->block;
   } else {
-    const int bpc = transport_blocks_per_cu(c->precision == RMC_FP32_BULK, batch, c->block, std::max(levels, 1));
+    const int bpc = transport_blocks_per_cu(c->precision == RMC_FP32_BULK, batch, c->s_pq != nullptr, c->block,
+                                            std::max(levels, 1));
     g = (int64_t)c->num_cus * bpc;
   }
   const int64_t need = (n + c->block - 1) / c->block;
@@ -491,14 +497,16 @@ void fill_stats(rmc_run_stats *s, const unsigned long long *h, double ms) {
   s->peel_rays = h[S_PEEL_RAYS];
   s->peel_crossings = h[S_PEEL_CROSS];
   s->peel_dropped = h[S_PEEL_DROPPED];
+  s->peel_deferred = 0;
   s->kernel_ms = ms;
+  s->peel_pass_ms = 0.0;
 }
 
 }  // namespace
 
 extern "C" {
 
-int rmc_abi_version(void) { return 1; }
+int rmc_abi_version(void) { return 2; }
 
 rmc_status rmc_create(rmc_ctx **out, int device, int precision) {
   if (!out) return RMC_EINVAL;
@@ -512,7 +520,8 @@ rmc_status rmc_create(rmc_ctx **out, int device, int precision) {
   c->precision = precision;
   if (hipSetDevice(device) != hipSuccess ||
       hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
-      hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+      hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+      hipEventCreate(&c->ev2) != hipSuccess) {
     delete c;
     return RMC_EDEVICE;
   }
@@ -526,14 +535,16 @@ void rmc_destroy(rmc_ctx *c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
   if (c->s_graph) (void)hipGraphExecDestroy(c->s_graph);
+  if (c->s_graph2) (void)hipGraphExecDestroy(c->s_graph2);
   DevBuf *bufs[] = {&c->nodes, &c->leaves, &c->spos, &c->sdir, &c->sx, &c->o_status, &c->o_x, &c->o_k,
                     &c->o_pos, &c->o_nscat, &c->o_path, &c->d_stats, &c->d_next, &c->d_prob, &c->d_starts,
                     &c->tmp1, &c->tmp2, &c->tmp3, &c->tmp4, &c->tmp5, &c->b_probs, &c->b_starts,
-                    &c->slots, &c->d_slice};
+                    &c->slots, &c->d_slice, &c->pq_ctl, &c->pq_jobs, &c->pq_counts};
   for (DevBuf *b : bufs) b->release();
   for (auto &o : c->obs) o.cube.release();
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
+  if (c->ev2) (void)hipEventDestroy(c->ev2);
   delete c;
 }
 
@@ -568,8 +579,8 @@ rmc_status rmc_set_option(rmc_ctx *c, int opt, int64_t v) {
       c->refill = (int)v;
       break;
     case RMC_OPT_PEEL_DEFER:
-      if (v) return fail(c, RMC_EUNSUPPORTED, "deferred peel-off queue not built");
-      c->peel_defer = 0;
+      if (v != 0 && v != 1) return fail(c, RMC_EINVAL, "peel defer is 0 or 1");
+      c->peel_defer = (int)v;
       break;
     case RMC_OPT_SLICE_ITERS:
       if (v < 1 || v > (1 << 30)) return fail(c, RMC_EINVAL, "slice iterations in [1, 2^30]");
@@ -768,7 +779,75 @@ void add_run_stats(rmc_run_stats &a, const rmc_run_stats &b) {
   a.emitted += b.emitted; a.escaped += b.escaped; a.absorbed += b.absorbed; a.stuck += b.stuck;
   a.scatterings += b.scatterings; a.dust_scatterings += b.dust_scatterings; a.crossings += b.crossings;
   a.peel_rays += b.peel_rays; a.peel_crossings += b.peel_crossings; a.peel_dropped += b.peel_dropped;
+  a.peel_deferred += b.peel_deferred;
+  a.peel_pass_ms += b.peel_pass_ms;
   a.kernel_ms += b.kernel_ms;
+}
+
+constexpr unsigned long long PQ_FIRST_CAP = 1024;          // jobs per region (one region per wave)
+constexpr unsigned long long PQ_MAX_BYTES = 8ull << 30;     // job buffer limit
+static_assert(PQ_FIRST_CAP > 2 * 64 * MAX_OBS, "a region must hold one wave iteration of pushes");
+
+// Control block of the deferred peel-off queue, or null when peel-off rays
+// are walked inline (option off).  Its regions are laid out per transport
+// wave by stream_open.
+rmc_status peel_queue(rmc_ctx *c, PeelQueue **out) {
+  *out = nullptr;
+  if (!c->peel_defer) return RMC_OK;
+  HIPCHK(c, c->pq_ctl.ensure(peel_queue_bytes()));
+  if (!c->pq_cap) {
+    // first guess: a sixteenth of a wave's peel-off rays in one launch
+    const unsigned long long rays = 64ull * (unsigned long long)c->slice_iters * std::max<size_t>(c->obs.size(), 1);
+    c->pq_cap = PQ_FIRST_CAP;
+    while (c->pq_cap < rays / 16 && c->pq_cap < (1ull << 16)) c->pq_cap <<= 1;
+  }
+  *out = c->pq_ctl.as<PeelQueue>();
+  return RMC_OK;
+}
+
+// Lay out n_regions regions of c->pq_cap jobs and upload the control
+// block (totals zero).
+rmc_status layout_queue(rmc_ctx *c, unsigned long long n_regions) {
+  // at least PQ_FIRST_CAP, so that a region always has room for a wave
+  // iteration's pushes
+  const unsigned long long max_cap =
+      std::max<unsigned long long>(PQ_MAX_BYTES / peel_job_bytes() / n_regions, PQ_FIRST_CAP);
+  c->pq_cap = std::min(c->pq_cap, max_cap);
+  HIPCHK(c, c->pq_counts.ensure(n_regions * 4));
+  HIPCHK(c, c->pq_jobs.ensure(n_regions * c->pq_cap * peel_job_bytes()));
+  PeelQueue q;
+  q.jobs = c->pq_jobs.as<PeelJob>();
+  q.counts = c->pq_counts.as<uint32_t>();
+  q.cap = c->pq_cap;
+  q.n_regions = n_regions;
+  q.pushes = 0;
+  q.max_region = 0;
+  q.take = 0;
+  q.lost = 0;
+  HIPCHK(c, hipMemcpyAsync(c->pq_ctl.p, &q, sizeof q, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->pq_regions = n_regions;
+  return RMC_OK;
+}
+
+// After a launch in which a wave ended its slice early because its region
+// was nearly full, enlarge the regions eightfold (up to PQ_MAX_BYTES) for
+// the next launches.
+rmc_status grow_queue(rmc_ctx *c, unsigned long long max_region) {
+  const unsigned long long per_iter = 2ull * 64 * MAX_OBS;   // pushes one wave iteration can make
+  if (max_region + per_iter <= c->pq_cap) return RMC_OK;
+  const unsigned long long max_cap =
+      std::max<unsigned long long>(PQ_MAX_BYTES / peel_job_bytes() / c->pq_regions, PQ_FIRST_CAP);
+  if (c->pq_cap >= max_cap) return RMC_OK;
+  const unsigned long long cap = c->pq_cap * 8;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const unsigned long long old = c->pq_cap;
+  c->pq_cap = std::min(cap, max_cap);
+  if (c->pq_jobs.ensure(c->pq_regions * c->pq_cap * peel_job_bytes()) != hipSuccess) {
+    (void)hipGetLastError();
+    c->pq_cap = old;    // keep the old size (waves go on ending slices early)
+  }
+  return layout_queue(c, c->pq_regions);
 }
 
 // Prepare slots and counters for a stream over the problems already
@@ -782,36 +861,53 @@ rmc_status stream_open(rmc_ctx *c, int64_t total, int n_probs, int levels, bool 
   c->s_grid = grid_for(c, total, batch, levels);
   const int64_t n_slots = (int64_t)c->s_grid * c->block;
   HIPCHK(c, c->slots.ensure((size_t)n_slots * slot_bytes()));
-  HIPCHK(c, c->d_slice.ensure(N_STATS * 8));
+  HIPCHK(c, c->d_slice.ensure((N_STATS + 3) * 8));
   HIPCHK(c, c->d_next.ensure(8));
   HIPCHK(c, launch_clear_slots(c->slots.p, n_slots, c->stream));
+  if (c->s_pq) {
+    rmc_status r = layout_queue(c, (unsigned long long)n_slots / 64);
+    if (r) return r;
+  }
   HIPCHK(c, launch_batch_reset(c->s_probs, n_probs, c->d_next.as<unsigned long long>(), c->stream));
   std::memset(&c->s_acc, 0, sizeof c->s_acc);
   c->s_open = true;
   // one slice = zero the slice counters, one transport launch; captured
   // once per shape and replayed
   char key[256];
-  snprintf(key, sizeof key, "%p/%p/%p/%p/%d/%d/%d/%d/%d/%d/%d/%d", (void *)c->s_probs, (void *)c->s_starts,
-           c->slots.p, c->d_slice.p, n_probs, c->s_grid, c->block, c->refill, c->s_levels, c->precision,
-           c->slice_iters, (int)batch);
+  PeelQueue *pq = c->s_pq;
+  snprintf(key, sizeof key, "%p/%p/%p/%p/%p/%d/%d/%d/%d/%d/%d/%d/%d", (void *)c->s_probs, (void *)c->s_starts,
+           c->slots.p, c->d_slice.p, (void *)pq, n_probs, c->s_grid, c->block, c->refill, c->s_levels,
+           c->precision, c->slice_iters, (int)batch);
   if (c->s_key != key || !c->s_graph) {
-    if (c->s_graph) {
-      (void)hipGraphExecDestroy(c->s_graph);
-      c->s_graph = nullptr;
-    }
+    for (hipGraphExec_t *ge : {&c->s_graph, &c->s_graph2})
+      if (*ge) {
+        (void)hipGraphExecDestroy(*ge);
+        *ge = nullptr;
+      }
+    const bool f32 = c->precision == RMC_FP32_BULK;
     hipStream_t cap = nullptr;
     HIPCHK(c, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) e = launch_fill_u64(c->d_slice.as<unsigned long long>(), N_STATS, 0ull, cap);
-    if (e == hipSuccess)
-      e = launch_transport(c->precision == RMC_FP32_BULK, batch, c->s_probs, c->s_starts, n_probs,
-                           c->d_next.as<unsigned long long>(), c->refill, c->s_levels, c->s_grid, c->block,
-                           c->slots.p, c->slice_iters, c->d_slice.as<unsigned long long>(), cap);
-    hipError_t e2 = hipStreamEndCapture(cap, &g);
-    if (e == hipSuccess) e = e2;
-    if (e == hipSuccess) e = hipGraphInstantiate(&c->s_graph, g, nullptr, nullptr, 0);
-    if (g) (void)hipGraphDestroy(g);
+    hipError_t e = hipSuccess;
+    for (int part = 0; part < (pq ? 2 : 1) && e == hipSuccess; ++part) {
+      hipGraph_t g = nullptr;
+      e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+      if (part == 0) {
+        if (e == hipSuccess) e = launch_fill_u64(c->d_slice.as<unsigned long long>(), N_STATS + 3, 0ull, cap);
+        if (e == hipSuccess)
+          e = launch_transport(f32, batch, pq != nullptr, c->s_probs, c->s_starts, n_probs,
+                               c->d_next.as<unsigned long long>(), c->refill, c->s_levels, c->s_grid, c->block,
+                               c->slots.p, c->slice_iters, c->d_slice.as<unsigned long long>(), cap);
+      } else {
+        const int grid = c->num_cus * peel_drain_blocks_per_cu(f32, batch, c->s_levels);
+        if (e == hipSuccess)
+          e = launch_peel_drain(f32, batch, c->s_probs, pq, c->s_levels, grid, c->d_slice.as<unsigned long long>(),
+                                cap);
+      }
+      hipError_t e2 = hipStreamEndCapture(cap, &g);
+      if (e == hipSuccess) e = e2;
+      if (e == hipSuccess) e = hipGraphInstantiate(part == 0 ? &c->s_graph : &c->s_graph2, g, nullptr, nullptr, 0);
+      if (g) (void)hipGraphDestroy(g);
+    }
     (void)hipStreamDestroy(cap);
     if (e != hipSuccess) {
       c->s_open = false;
@@ -834,12 +930,25 @@ rmc_status stream_step(rmc_ctx *c, rmc_run_stats *slice, int64_t *remaining) {
   HIPCHK(c, hipEventRecord(c->ev0, c->stream));
   HIPCHK(c, hipGraphLaunch(c->s_graph, c->stream));
   HIPCHK(c, hipEventRecord(c->ev1, c->stream));
-  unsigned long long h[N_STATS];
+  if (c->s_pq) HIPCHK(c, hipGraphLaunch(c->s_graph2, c->stream));
+  HIPCHK(c, hipEventRecord(c->ev2, c->stream));
+  unsigned long long h[N_STATS + 3];
   HIPCHK(c, hipMemcpyAsync(h, c->d_slice.p, sizeof h, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  float ms = 0.f;
+  float ms = 0.f, ms2 = 0.f;
   HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  HIPCHK(c, hipEventElapsedTime(&ms2, c->ev1, c->ev2));
   fill_stats(&z, h, ms);
+  z.peel_deferred = h[N_STATS];
+  z.peel_pass_ms = c->s_pq ? ms2 : 0.0;
+  if (c->s_pq) {
+    if (h[N_STATS + 2]) {
+      c->s_open = false;
+      return fail(c, RMC_EDEVICE, "peel-off queue: %llu rays found their region full", h[N_STATS + 2]);
+    }
+    rmc_status r = grow_queue(c, h[N_STATS + 1]);
+    if (r) return r;
+  }
   c->s_done += (int64_t)h[S_EMITTED];
   add_run_stats(c->s_acc, z);
   if (slice) *slice = z;
@@ -855,6 +964,11 @@ rmc_status stream_begin_single(rmc_ctx *c, uint64_t seed, int64_t first, int64_t
   if (r) return r;
   c->last_n = n;
   make_problem(c, first, n, seed, c->pb_host);
+  r = peel_queue(c, &c->s_pq);
+  if (r) return r;
+  if (c->obs.empty()) c->s_pq = nullptr;
+  c->pb_host.pq = c->s_pq;
+  c->pb_host.index = 0;
   c->starts_host[0] = 0;
   c->starts_host[1] = n;
   HIPCHK(c, c->d_prob.ensure(sizeof(ProblemK)));
@@ -883,10 +997,17 @@ rmc_status stream_finish(rmc_ctx *c, rmc_run_stats *per, rmc_run_stats *total) {
   HIPCHK(c, hipStreamSynchronize(c->stream));
   unsigned long long t[N_STATS] = {0};
   for (int i = 0; i < np; ++i) {
-    if (per) fill_stats(per + i, h.data() + (size_t)i * N_STATS, c->s_acc.kernel_ms);
+    if (per) {
+      fill_stats(per + i, h.data() + (size_t)i * N_STATS, c->s_acc.kernel_ms);
+      per[i].peel_pass_ms = c->s_acc.peel_pass_ms;
+    }
     for (int q = 0; q < N_STATS; ++q) t[q] += h[(size_t)i * N_STATS + q];
   }
-  if (total) fill_stats(total, t, c->s_acc.kernel_ms);
+  if (total) {
+    fill_stats(total, t, c->s_acc.kernel_ms);
+    total->peel_deferred = c->s_acc.peel_deferred;
+    total->peel_pass_ms = c->s_acc.peel_pass_ms;
+  }
   if ((int64_t)t[S_EMITTED] != c->s_total)
     return fail(c, RMC_EDEVICE, "transport finished %llu of %lld packets", t[S_EMITTED], (long long)c->s_total);
   return RMC_OK;
@@ -1149,11 +1270,19 @@ rmc_status batch_open(rmc_ctx *const *P, int np, const uint64_t *seeds, const in
     if (r) return fail(c0, r, "problem %d: %s", i, c->err.c_str());
     maxL = std::max(maxL, c->L);
   }
+  if (np > (1 << 19)) return fail(c0, RMC_EINVAL, "at most 2^19 problems per batch");
+  bool any_obs = false;
+  for (int i = 0; i < np; ++i) any_obs = any_obs || !P[i]->obs.empty();
+  r = peel_queue(c0, &c0->s_pq);
+  if (r) return r;
+  if (!any_obs) c0->s_pq = nullptr;
   c0->b_host.resize(np);
   c0->b_starts_host.assign(np + 1, 0);
   for (int i = 0; i < np; ++i) {
     P[i]->last_n = npk[i];
     make_problem(P[i], 0, npk[i], seeds[i], c0->b_host[i]);
+    c0->b_host[i].pq = c0->s_pq;
+    c0->b_host[i].index = i;
     c0->b_starts_host[i + 1] = c0->b_starts_host[i] + npk[i];
   }
   const int64_t tot = c0->b_starts_host[np];
@@ -1206,7 +1335,7 @@ rmc_status rmc_batch_autotune(rmc_ctx *const *P, int np, const uint64_t *seeds, 
           r = stream_step(c0, &st, &rem);
           if (r) return r;
           work += (double)st.scatterings + (double)st.crossings + (double)st.peel_crossings;
-          ms += st.kernel_ms;
+          ms += st.kernel_ms + st.peel_pass_ms;
           if (rem == 0) break;
         }
         c0->s_open = false;

@@ -49,6 +49,30 @@ struct ObsK {
   void *cube;      // [ny][nx][nbins], float or double by precision
 };
 
+// A peel-off ray stopped where it leaves its first leaf, queued for the
+// ray-cast pass that follows each transport launch.
+struct PeelJob {
+  double p[3];              // point where the ray enters its next leaf
+  double tau;               // optical depth accumulated so far
+  double x;                 // x_ext of the ray (frequency toward the observer)
+  double weight;            // phase-function weight of the deposit
+  unsigned long long dst;   // cube element | observer << 40 | problem << 44
+  uint32_t steps, pad;      // leaves crossed so far
+};
+constexpr int PQ_OBS_SHIFT = 40, PQ_PROB_SHIFT = 44;
+constexpr unsigned long long PQ_ELEM_MASK = (1ull << PQ_OBS_SHIFT) - 1ull;
+
+struct PeelQueue {
+  PeelJob *jobs;                  // [n_regions][cap]: one region per transport wave
+  uint32_t *counts;               // [n_regions]: pushes of each region in the last launch
+  unsigned long long cap;         // jobs per region (pushes beyond it are traced inline)
+  unsigned long long n_regions;
+  unsigned long long pushes;      // pushes of the launch
+  unsigned long long max_region;  // largest region push count of the launch
+  unsigned long long take;        // regions handed out by the ray-cast pass
+  unsigned long long lost;        // pushes that found their region full (an error)
+};
+
 struct ProblemK {
   const int32_t *nodes;     // [n_nodes][8]: >=0 child node, <0: -(leaf+1)
   const void *leaves;       // [n_leaves][LEAF_STRIDE] float or double
@@ -72,6 +96,8 @@ struct ProblemK {
   int n_obs;
   ObsK obs[MAX_OBS];
   unsigned long long *stats; // [N_STATS]
+  PeelQueue *pq;            // deferred peel-off rays (null: traced inline)
+  int index;                // position in the launch's problem array
 };
 
 // ------------------------------------------------------------------ Philox

@@ -45,26 +45,28 @@ template <class R> struct StartCell {
   const int *stk;
 };
 
-// Optical depth from p along k to the domain border at fixed x_ext (the
-// peel-off integral); stops once tau >= tau_cut.  Uses its own LDS stack.
+// Where a ray walk stopped early: the point where it enters its next leaf.
+struct RayStop {
+  double p[3];
+  double tau;
+  uint32_t steps;
+  bool stopped;
+};
+
+// Walks a ray at fixed x_ext from p (inside cell c) leaf by leaf, adding
+// kappa * segment to tau, until it reaches the domain border or tau >=
+// tau_cut.  steps counts the leaves crossed so far (at most MAX_CROSS).  With
+// borrowed, sc lends the first leaf's record and ancestor stack; with
+// may_stop, the walk ends where the ray leaves its first leaf and stop
+// records the state to resume from.
 template <class R>
-__device__ double ray_tau(const ProblemK &pb, const double p0[3], const double k[3], double x_ext,
-                          double tau_cut, int *stk, int stride, uint32_t *ncross,
-                          const StartCell<R> *sc = nullptr) {
-  double p[3] = {p0[0], p0[1], p0[2]};
-  int X[3];
+__device__ double ray_walk(const ProblemK &pb, double p[3], const double k[3], double x_ext, double tau,
+                           uint32_t steps, double tau_cut, int *stk, int stride, uint32_t *ncross, Cell &c,
+                           const StartCell<R> *sc, bool borrowed, RayStop &stop, bool may_stop) {
   const R kr[3] = {(R)k[0], (R)k[1], (R)k[2]};
-  Cell c;
-  bool reuse = sc && strictly_inside(*sc->c, pb.L, p);
-  if (reuse) {
-    c = *sc->c;
-  } else {
-    if (!int_coords(pb.L, p, k, X)) return 0.0;
-    descend(pb.nodes, pb.L, 0, 0, X, stk, stride, c);
-  }
-  double tau = 0.0;
-  for (uint32_t steps = 0; steps < MAX_CROSS; ++steps) {
-    const LeafRec<R> lf = (reuse && steps == 0) ? *sc->lf : load_leaf<R>(pb.leaves, c.leaf);
+  bool first = borrowed;
+  for (; steps < MAX_CROSS; ++steps) {
+    const LeafRec<R> lf = first ? *sc->lf : load_leaf<R>(pb.leaves, c.leaf);
     Opac<R> o;
     opacity(pb, lf, x_ext, kr, o);
     double face[3], lo[3], hi[3];
@@ -82,14 +84,42 @@ __device__ double ray_tau(const ProblemK &pb, const double p0[3], const double k
     exit_point(te, em, p, k, face, lo, hi, pn);
     p[0] = pn[0]; p[1] = pn[1]; p[2] = pn[2];
     wrap_slab(pb.domain, p, k);
+    int X[3];
     if (!int_coords(pb.L, p, k, X)) break;
-    if (reuse && steps == 0) {
+    if (may_stop) {
+      stop.p[0] = p[0]; stop.p[1] = p[1]; stop.p[2] = p[2];
+      stop.tau = tau;
+      stop.steps = steps + 1;
+      stop.stopped = true;
+      break;
+    }
+    if (first) {
       // first move out of the borrowed cell: copy its ancestors
       for (int l = 0; l < c.level; ++l) stk[l * stride] = sc->stk[l * stride];
     }
+    first = false;
     relocate(pb.nodes, pb.L, X, stk, stride, c);
   }
   return tau;
+}
+
+// Optical depth from p along k to the domain border at fixed x_ext (the
+// peel-off integral); stops once tau >= tau_cut.  Uses its own LDS stack.
+template <class R>
+__device__ double ray_tau(const ProblemK &pb, const double p0[3], const double k[3], double x_ext,
+                          double tau_cut, int *stk, int stride, uint32_t *ncross,
+                          const StartCell<R> *sc, RayStop &stop, bool may_stop) {
+  double p[3] = {p0[0], p0[1], p0[2]};
+  Cell c;
+  const bool reuse = sc && strictly_inside(*sc->c, pb.L, p);
+  if (reuse) {
+    c = *sc->c;
+  } else {
+    int X[3];
+    if (!int_coords(pb.L, p, k, X)) return 0.0;
+    descend(pb.nodes, pb.L, 0, 0, X, stk, stride, c);
+  }
+  return ray_walk<R>(pb, p, k, x_ext, 0.0, 0u, tau_cut, stk, stride, ncross, c, sc, reuse, stop, may_stop);
 }
 
 // Pixel of position p in observer ob's image, -1 outside.
@@ -131,9 +161,24 @@ template <class R> struct PeelSrc {
   R ux, uy, uz;    // cell bulk velocity / v_th,ref
 };
 
-template <class R>
+// Where a transport wave queues its deferred peel-off rays: its own region
+// of the queue and the region's fill count, kept in LDS (one per wave, so
+// no global atomics).  The wave stops taking events before the region
+// could overflow, so a push always finds room.
+struct PeelSink {
+  PeelJob *region;
+  int *count;
+  uint32_t cap;
+  unsigned long long *lost;   // pushes that found no room (never expected)
+};
+
+// Peel-off of one event toward every observer (Sect. 3.4).  DEFER: each ray
+// is walked through its first leaf only (the scattering's own leaf, whose
+// record the lane already holds); a ray that goes on is queued for the
+// ray-cast pass.  Otherwise the whole ray is walked here.
+template <class R, bool DEFER>
 __device__ void peel_all(const ProblemK &pb, const double p[3], const PeelSrc<R> &s, int *stk,
-                         int stride, LaneCount &cnt, const StartCell<R> *sc = nullptr) {
+                         int stride, LaneCount &cnt, const PeelSink &snk, const StartCell<R> *sc = nullptr) {
   for (int oi = 0; oi < pb.n_obs; ++oi) {
     const ObsK &ob = pb.obs[oi];
     const R ko[3] = {(R)ob.k[0], (R)ob.k[1], (R)ob.k[2]};
@@ -167,11 +212,43 @@ __device__ void peel_all(const ProblemK &pb, const double p[3], const PeelSrc<R>
     }
     ++cnt.peel_rays;
     uint32_t nc = 0;
-    const double tau = ray_tau<R>(pb, p, ob.k, (double)xo, TauCut<R>::v, stk, stride, &nc, sc);
+    const size_t elem = (size_t)pix * ob.nbins + bin;
+    RayStop rs;
+    rs.stopped = false;
+    const double tau = ray_tau<R>(pb, p, ob.k, (double)xo, TauCut<R>::v, stk, stride, &nc, sc, rs, DEFER);
+    if (DEFER) {
+      // a ray that goes on past its first leaf is queued instead of
+      // holding the wave here
+      const unsigned long long m = __ballot(rs.stopped);
+      if (m) {
+        const int lane = __lane_id();
+        const int leader = __ffsll((long long)m) - 1;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(snk.count, __popcll(m));
+        base = __shfl(base, leader);
+        if (rs.stopped) {
+          const uint32_t slot = (uint32_t)base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+          if (slot < snk.cap) {
+            PeelJob &j = snk.region[slot];
+            j.p[0] = rs.p[0]; j.p[1] = rs.p[1]; j.p[2] = rs.p[2];
+            j.tau = rs.tau;
+            j.x = (double)xo;
+            j.weight = (double)weight;
+            j.dst = (unsigned long long)elem | ((unsigned long long)oi << PQ_OBS_SHIFT) |
+                    ((unsigned long long)pb.index << PQ_PROB_SHIFT);
+            j.steps = rs.steps;
+          } else {
+            atomicAdd(snk.lost, 1ull);
+          }
+          cnt.peel_cross += nc;
+          continue;
+        }
+      }
+    }
     cnt.peel_cross += nc;
     if (tau >= TauCut<R>::v) continue;
     const R wgt = weight * M<R>::exp((R)(-tau));
-    atomic_add_real((R *)ob.cube + ((size_t)pix * ob.nbins + bin), wgt);
+    atomic_add_real((R *)ob.cube + elem, wgt);
   }
 }
 
@@ -228,8 +305,9 @@ __device__ void finish(const ProblemK &pb, Lane<R> &s, int status) {
 
 // Emission (Sect. 2): position and frequency from the source list,
 // isotropic direction unless given, tau_event = -ln r.
-template <class R>
-__device__ void emit(const ProblemK &pb, int64_t pid, Lane<R> &s, int *stk, int *pstk, int stride) {
+template <class R, bool DEFER>
+__device__ void emit(const ProblemK &pb, int64_t pid, Lane<R> &s, int *stk, int *pstk, int stride,
+                     const PeelSink &snk) {
   s.pid = pid;
   s.p[0] = pb.src_pos[3 * pid];
   s.p[1] = pb.src_pos[3 * pid + 1];
@@ -260,15 +338,15 @@ __device__ void emit(const ProblemK &pb, int64_t pid, Lane<R> &s, int *stk, int 
     PeelSrc<R> ps;
     ps.kind = 0;
     ps.x = s.x;
-    peel_all<R>(pb, s.p, ps, pstk, stride, s.cnt);
+    peel_all<R, DEFER>(pb, s.p, ps, pstk, stride, s.cnt, snk);
   }
 }
 
 // Interaction at the current position (Sect. 3.2).  Returns the packet's
 // status (ST_NONE while it lives).
-template <class R>
+template <class R, bool DEFER>
 __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R> &o, int *pstk, const int *stk,
-                        int stride) {
+                        const PeelSink &snk, int stride) {
   const StartCell<R> sc{&s.c, &s.lf, stk};
   ++s.event;
   if (pb.max_events > 0 && (int64_t)s.event >= pb.max_events) return ST_STUCK;
@@ -288,7 +366,7 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R> &o, int *p
     if (pb.n_obs) {
       ps.kind = 2;
       ps.x = s.x;
-      peel_all<R>(pb, s.p, ps, pstk, stride, s.cnt, &sc);
+      peel_all<R, DEFER>(pb, s.p, ps, pstk, stride, s.cnt, snk, &sc);
     }
     if (!pb.forward_only) {
       const R mu = mu_hg(rng.u(J_MU), R(pb.g_hg));
@@ -348,7 +426,7 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R> &o, int *p
       ps.rho = rho;
       ps.line = i;
       ps.core = core;
-      peel_all<R>(pb, s.p, ps, pstk, stride, s.cnt, &sc);
+      peel_all<R, DEFER>(pb, s.p, ps, pstk, stride, s.cnt, snk, &sc);
     }
     if (!pb.forward_only) {
       const R ru = rng.u(J_MU);
@@ -431,7 +509,7 @@ template <class R> struct WavesPerEU;
 template <> struct WavesPerEU<float> { static constexpr int v = RMC_WAVES_F32; };
 template <> struct WavesPerEU<double> { static constexpr int v = RMC_WAVES_F64; };
 
-template <class R, bool BATCH>
+template <class R, bool BATCH, bool DEFER>
 __global__ void __launch_bounds__(256)
     __attribute__((amdgpu_waves_per_eu(WavesPerEU<R>::v, WavesPerEU<R>::v)))
     k_transport(const ProblemK *__restrict__ probs,
@@ -447,6 +525,18 @@ __global__ void __launch_bounds__(256)
   const int64_t total = starts[n_probs];
   const int lane = __lane_id();
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // this wave's region of the deferred peel-off queue; the wave ends its
+  // slice early once one more iteration (an emission and an event, each
+  // peeled toward every observer) could overflow it
+  PeelQueue *const pq = DEFER ? probs[0].pq : nullptr;
+  const int64_t wave = gid >> 6;
+  PeelSink snk;
+  snk.count = lds + 2 * stack_levels * stride + (threadIdx.x >> 6);
+  snk.region = DEFER ? pq->jobs + (size_t)wave * pq->cap : nullptr;
+  snk.cap = DEFER ? (uint32_t)pq->cap : 0u;
+  snk.lost = DEFER ? &pq->lost : nullptr;
+  const int room = DEFER ? (int)pq->cap - 2 * 64 * MAX_OBS : 0;
+  if (lane == 0) *snk.count = 0;
 
   Lane<R> s;
   Lane<R> z;            // counters when this slice took the packet over
@@ -467,6 +557,7 @@ __global__ void __launch_bounds__(256)
     }
   }
   for (int it = 0; it < budget; ++it) {
+    if (DEFER && *snk.count > room) break;
     // ---- refill idle lanes: one atomic per wave, ranks from mbcnt
     if (!drained) {
       const unsigned long long idle = __ballot(!active);
@@ -491,7 +582,7 @@ __global__ void __launch_bounds__(256)
             }
             const ProblemK &pb = probs[BATCH ? prob : 0];
             const int64_t pid = pb.first + (g - starts[BATCH ? prob : 0]);
-            emit<R>(pb, pid, s, stk, pstk, stride);
+            emit<R, DEFER>(pb, pid, s, stk, pstk, stride, snk);
             z = s;
             z.nscat = 0;
             z.cnt = LaneCount{0, 0, 0, 0, 0};
@@ -532,7 +623,7 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
       for (int d = 0; d < 3; ++d) s.p[d] = fmin(fmax(fma(dist, kd[d], s.p[d]), lo[d]), hi[d]);
       s.path += dist;
-      st = interact<R>(pb, s, o, pstk, stk, stride);
+      st = interact<R, DEFER>(pb, s, o, pstk, stk, snk, stride);
     } else {
       s.tau -= tseg;
       s.path += lmax;
@@ -572,6 +663,14 @@ __global__ void __launch_bounds__(256)
   } else {
     q.active = 0;
   }
+  if (DEFER && lane == 0) {
+    const int nq = *snk.count;
+    pq->counts[wave] = (uint32_t)nq;
+    if (nq) {
+      atomicAdd(&pq->pushes, (unsigned long long)nq);
+      atomicMax(&pq->max_region, (unsigned long long)nq);
+    }
+  }
   unsigned long long v[6] = {acc.scat, acc.dust, acc.cross, acc.peel_rays, acc.peel_cross, acc.finished};
   const int idx[6] = {S_SCAT, S_DUST_SCAT, S_CROSS, S_PEEL_RAYS, S_PEEL_CROSS, S_EMITTED};
 #pragma unroll
@@ -593,6 +692,156 @@ __global__ void k_count_live(const SlotState *__restrict__ slots, int64_t n, uns
 __global__ void k_clear_slots(SlotState *__restrict__ slots, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) slots[i].active = 0;
+}
+
+// Ray-cast pass over the peel-off rays queued by a transport launch.  A
+// wave takes the queue regions one at a time; each lane walks one ray a
+// leaf per iteration and takes the region's next ray as soon as its own is
+// done, so the waves stay full while ray lengths vary.  The walk is the one
+// of ray_walk, resumed from the queued state.
+template <class R, bool BATCH>
+__global__ void __launch_bounds__(256) k_peel_drain(const ProblemK *__restrict__ probs, PeelQueue *pq,
+                                                    unsigned long long *__restrict__ slice) {
+  extern __shared__ int lds[];
+  const int stride = blockDim.x;
+  int *stk = lds + threadIdx.x;
+  const int lane = __lane_id();
+  const unsigned long long n_regions = pq->n_regions, cap = pq->cap;
+  const PeelJob *__restrict__ jobs = pq->jobs;
+  const uint32_t *__restrict__ counts = pq->counts;
+  const double cut = TauCut<R>::v;
+  // wave-uniform: current region, next job in it, jobs in it
+  unsigned long long reg = 0;
+  uint32_t r_next = 0, r_n = 0;
+  bool drained = false;
+  bool active = false;
+  int prob = 0, acc_prob = 0;
+  double p[3], k[3], tau = 0.0, x = 0.0;
+  R weight = R(0), kr[3];
+  unsigned long long elem = 0;
+  int oi = 0;
+  uint32_t steps = 0;
+  Cell c;
+  unsigned long long nc_prob = 0, nc_all = 0;
+  while (true) {
+    unsigned long long idle = __ballot(!active);
+    while (idle && !drained) {
+      if (r_next >= r_n) {
+        unsigned long long t = 0;
+        if (lane == 0) t = atomicAdd(&pq->take, 1ull);
+        reg = __shfl(t, 0);
+        if (reg >= n_regions) {
+          drained = true;
+          break;
+        }
+        const uint32_t cnt = counts[reg];
+        r_n = cnt < cap ? cnt : (uint32_t)cap;
+        r_next = 0;
+        continue;
+      }
+      const uint32_t avail = r_n - r_next;
+      const uint32_t rank = (uint32_t)__popcll(idle & ((1ull << lane) - 1ull));
+      const bool mine = ((idle >> lane) & 1ull) && rank < avail;
+      if (mine) {
+        const PeelJob j = jobs[reg * cap + r_next + rank];
+        const int jp = BATCH ? (int)(j.dst >> PQ_PROB_SHIFT) : 0;
+        if (BATCH && jp != acc_prob) {
+          if (nc_prob) atomicAdd(probs[acc_prob].stats + S_PEEL_CROSS, nc_prob);
+          nc_prob = 0;
+          acc_prob = jp;
+        }
+        prob = jp;
+        const ProblemK &pb = probs[prob];
+        oi = (int)((j.dst >> PQ_OBS_SHIFT) & 15ull);
+        elem = j.dst & PQ_ELEM_MASK;
+        const ObsK &ob = pb.obs[oi];
+        k[0] = ob.k[0]; k[1] = ob.k[1]; k[2] = ob.k[2];
+        kr[0] = (R)k[0]; kr[1] = (R)k[1]; kr[2] = (R)k[2];
+        p[0] = j.p[0]; p[1] = j.p[1]; p[2] = j.p[2];
+        tau = j.tau;
+        x = j.x;
+        weight = (R)j.weight;
+        steps = j.steps;
+        int X[3];
+        if (steps < MAX_CROSS && int_coords(pb.L, p, k, X)) {
+          descend(pb.nodes, pb.L, 0, 0, X, stk, stride, c);
+          active = true;
+        } else if (tau < cut) {
+          atomic_add_real((R *)ob.cube + elem, weight * M<R>::exp((R)(-tau)));
+        }
+      }
+      const uint32_t n_idle = (uint32_t)__popcll(idle);
+      r_next += avail < n_idle ? avail : n_idle;
+      // lanes given a job that ended at once stay idle until the next pass
+      idle &= ~__ballot(mine);
+    }
+    if (__ballot(active) == 0ull) {
+      if (drained) break;
+      continue;
+    }
+    if (!active) continue;
+    const ProblemK &pb = probs[BATCH ? prob : 0];
+    const LeafRec<R> lf = load_leaf<R>(pb.leaves, c.leaf);
+    Opac<R> o;
+    opacity(pb, lf, x, kr, o);
+    double face[3], lo[3], hi[3];
+    int em;
+    const double te = exit_dist(c, pb.L, p, k, face, lo, hi, &em);
+    const double td = domain_dist_leaf(lf, pb.domain, pb.dom, p, k);
+    ++nc_prob;
+    ++nc_all;
+    bool done = false;
+    if (td <= te) {
+      tau += (double)o.ktot * td;
+      done = true;
+    } else {
+      tau += (double)o.ktot * te;
+      if (tau >= cut) {
+        done = true;
+      } else {
+        double pn[3];
+        exit_point(te, em, p, k, face, lo, hi, pn);
+        p[0] = pn[0]; p[1] = pn[1]; p[2] = pn[2];
+        wrap_slab(pb.domain, p, k);
+        int X[3];
+        if (!int_coords(pb.L, p, k, X)) {
+          done = true;
+        } else {
+          relocate(pb.nodes, pb.L, X, stk, stride, c);
+          if (++steps >= MAX_CROSS) done = true;
+        }
+      }
+    }
+    if (done) {
+      if (tau < cut) atomic_add_real((R *)pb.obs[oi].cube + elem, weight * M<R>::exp((R)(-tau)));
+      active = false;
+    }
+  }
+  // crossings: per problem, and for the launch's slice counters
+  if (BATCH) {
+    if (nc_prob) atomicAdd(probs[acc_prob].stats + S_PEEL_CROSS, nc_prob);
+  } else {
+    unsigned long long v = nc_prob;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+    if (lane == 0 && v) atomicAdd(probs[0].stats + S_PEEL_CROSS, v);
+  }
+  unsigned long long v = nc_all;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+  if (lane == 0 && v) atomicAdd(slice + S_PEEL_CROSS, v);
+}
+
+// After the ray-cast pass: report the launch's pushes, largest region and
+// lost pushes (slice counters N_STATS .. N_STATS+2) and reset the totals.
+__global__ void k_peel_reset(PeelQueue *pq, unsigned long long *slice) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    slice[N_STATS] = pq->pushes;
+    slice[N_STATS + 1] = pq->max_region;
+    slice[N_STATS + 2] = pq->lost;
+    pq->lost = 0ull;
+    pq->pushes = 0ull;
+    pq->max_region = 0ull;
+    pq->take = 0ull;
+  }
 }
 
 // ------------------------------------------------------------------ probes
@@ -645,7 +894,8 @@ __global__ void k_tau(ProblemK pb, int64_t n, const double *__restrict__ orig,
   const double p[3] = {orig[3 * r], orig[3 * r + 1], orig[3 * r + 2]};
   const double k[3] = {dir[3 * r], dir[3 * r + 1], dir[3 * r + 2]};
   uint32_t nc = 0;
-  tau_out[r] = ray_tau<R>(pb, p, k, x_ext[r], __builtin_inf(), stk, blockDim.x, &nc);
+  RayStop rs;
+  tau_out[r] = ray_tau<R>(pb, p, k, x_ext[r], __builtin_inf(), stk, blockDim.x, &nc, nullptr, rs, false);
 }
 
 // ------------------------------------------------- peel-off image, adjoint
@@ -662,7 +912,9 @@ __global__ void k_image_fwd(ProblemK pb, int obs, int64_t n, const double *__res
     const double p[3] = {orig[3 * r], orig[3 * r + 1], orig[3 * r + 2]};
     const int pix = pixel_of(ob, p);
     if (pix >= 0) {
-      const double tau = ray_tau<R>(pb, p, ob.k, x_ext[r], TauCut<double>::v, stk, blockDim.x, &nc);
+      RayStop rs;
+      const double tau = ray_tau<R>(pb, p, ob.k, x_ext[r], TauCut<double>::v, stk, blockDim.x, &nc, nullptr, rs,
+                                    false);
       if (tau < TauCut<double>::v) unsafeAtomicAdd(image + pix, w[r] * exp(-tau));
     }
   }
@@ -694,7 +946,8 @@ __global__ void k_image_bwd(ProblemK pb, int obs, int64_t n, const double *__res
     const int pix = pixel_of(ob, p0);
     const double xr = x_ext[r];
     double tau = TauCut<double>::v;
-    if (pix >= 0) tau = ray_tau<R>(pb, p0, ob.k, xr, TauCut<double>::v, stk, blockDim.x, &nc);
+    RayStop rs;
+    if (pix >= 0) tau = ray_tau<R>(pb, p0, ob.k, xr, TauCut<double>::v, stk, blockDim.x, &nc, nullptr, rs, false);
     const double g = (pix >= 0 && tau < TauCut<double>::v) ? -G[pix] * w[r] * exp(-tau) : 0.0;
     if (g != 0.0) {
       // replay the ray (same traversal as the forward pass)
@@ -788,42 +1041,75 @@ __global__ void k_f64_to_f32(const double *a, float *b, int64_t n) {
 // ------------------------------------------------------------- launchers
 static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-hipError_t launch_transport(bool fp32, bool batch, const ProblemK *d_probs, const int64_t *d_starts,
+using TransportFn = void (*)(const ProblemK *, const int64_t *, int, unsigned long long *, int, int, SlotState *,
+                            int, unsigned long long *);
+
+template <class R>
+static TransportFn transport_fn(bool batch, bool defer) {
+  if (batch) return defer ? k_transport<R, true, true> : k_transport<R, true, false>;
+  return defer ? k_transport<R, false, true> : k_transport<R, false, false>;
+}
+
+static TransportFn transport_fn(bool fp32, bool batch, bool defer) {
+  return fp32 ? transport_fn<float>(batch, defer) : transport_fn<double>(batch, defer);
+}
+
+static size_t transport_lds(int stack_levels, int block) {
+  return ((size_t)2 * stack_levels * block + block / 64) * sizeof(int);
+}
+
+hipError_t launch_transport(bool fp32, bool batch, bool defer, const ProblemK *d_probs, const int64_t *d_starts,
                             int n_probs, unsigned long long *d_next, int refill_min, int stack_levels,
                             int grid, int block, void *slots, int budget, unsigned long long *slice,
                             hipStream_t st) {
-  const size_t lds = (size_t)2 * stack_levels * block * sizeof(int);
-  SlotState *sl = (SlotState *)slots;
-  if (fp32) {
-    if (batch)
-      hipLaunchKernelGGL((k_transport<float, true>), dim3(grid), dim3(block), lds, st, d_probs, d_starts,
-                         n_probs, d_next, refill_min, stack_levels, sl, budget, slice);
-    else
-      hipLaunchKernelGGL((k_transport<float, false>), dim3(grid), dim3(block), lds, st, d_probs, d_starts,
-                         n_probs, d_next, refill_min, stack_levels, sl, budget, slice);
-  } else {
-    if (batch)
-      hipLaunchKernelGGL((k_transport<double, true>), dim3(grid), dim3(block), lds, st, d_probs, d_starts,
-                         n_probs, d_next, refill_min, stack_levels, sl, budget, slice);
-    else
-      hipLaunchKernelGGL((k_transport<double, false>), dim3(grid), dim3(block), lds, st, d_probs, d_starts,
-                         n_probs, d_next, refill_min, stack_levels, sl, budget, slice);
-  }
+  hipLaunchKernelGGL(transport_fn(fp32, batch, defer), dim3(grid), dim3(block), transport_lds(stack_levels, block), st,
+                     d_probs, d_starts, n_probs, d_next, refill_min, stack_levels, (SlotState *)slots, budget, slice);
   return hipGetLastError();
 }
 
-size_t slot_bytes() { return sizeof(SlotState); }
+hipError_t launch_peel_drain(bool fp32, bool batch, const ProblemK *d_probs, void *pq, int stack_levels, int grid,
+                             unsigned long long *slice, hipStream_t st) {
+  const int b = 256;
+  const size_t lds = (size_t)stack_levels * b * sizeof(int);
+  PeelQueue *q = (PeelQueue *)pq;
+  if (fp32) {
+    if (batch)
+      hipLaunchKernelGGL((k_peel_drain<float, true>), dim3(grid), dim3(b), lds, st, d_probs, q, slice);
+    else
+      hipLaunchKernelGGL((k_peel_drain<float, false>), dim3(grid), dim3(b), lds, st, d_probs, q, slice);
+  } else {
+    if (batch)
+      hipLaunchKernelGGL((k_peel_drain<double, true>), dim3(grid), dim3(b), lds, st, d_probs, q, slice);
+    else
+      hipLaunchKernelGGL((k_peel_drain<double, false>), dim3(grid), dim3(b), lds, st, d_probs, q, slice);
+  }
+  if (hipError_t e = hipGetLastError()) return e;
+  hipLaunchKernelGGL(k_peel_reset, dim3(1), dim3(64), 0, st, q, slice);
+  return hipGetLastError();
+}
 
-int transport_blocks_per_cu(bool fp32, bool batch, int block, int stack_levels) {
-  const size_t lds = (size_t)2 * stack_levels * block * sizeof(int);
+int peel_drain_blocks_per_cu(bool fp32, bool batch, int stack_levels) {
+  const size_t lds = (size_t)stack_levels * 256 * sizeof(int);
   int nb = 0;
   hipError_t e;
   if (fp32)
-    e = batch ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_transport<float, true>, block, lds)
-              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_transport<float, false>, block, lds);
+    e = batch ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_peel_drain<float, true>, 256, lds)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_peel_drain<float, false>, 256, lds);
   else
-    e = batch ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_transport<double, true>, block, lds)
-              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_transport<double, false>, block, lds);
+    e = batch ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_peel_drain<double, true>, 256, lds)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_peel_drain<double, false>, 256, lds);
+  return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
+size_t peel_job_bytes() { return sizeof(PeelJob); }
+size_t peel_queue_bytes() { return sizeof(PeelQueue); }
+
+size_t slot_bytes() { return sizeof(SlotState); }
+
+int transport_blocks_per_cu(bool fp32, bool batch, bool defer, int block, int stack_levels) {
+  int nb = 0;
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, transport_fn(fp32, batch, defer), block,
+                                                                    transport_lds(stack_levels, block));
   return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 

@@ -42,10 +42,11 @@ class RmcLine(C.Structure):
 class RmcRunStats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in ("emitted", "escaped", "absorbed", "stuck", "scatterings",
                                           "dust_scatterings", "crossings", "peel_rays", "peel_crossings",
-                                          "peel_dropped")] + [("kernel_ms", C.c_double)]
+                                          "peel_dropped", "peel_deferred")] + [("kernel_ms", C.c_double),
+                                                                             ("peel_pass_ms", C.c_double)]
 
     def as_dict(self):
-        return {n: (float(getattr(self, n)) if n == "kernel_ms" else int(getattr(self, n))) for n, _ in self._fields_}
+        return {n: (float(getattr(self, n)) if t is C.c_double else int(getattr(self, n))) for n, t in self._fields_}
 
 
 if not os.path.exists(LIB_PATH):
@@ -162,7 +163,7 @@ class Context:
         self.stream = None
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _L is not None:
             _L.rmc_destroy(self._h)
             self._h = None
 

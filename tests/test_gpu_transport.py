@@ -255,6 +255,45 @@ def test_slicing_does_not_change_results(rmc, orc, prec):
     assert np.allclose(ca, cb, rtol=1e-5 if prec == "fp32" else 1e-12, atol=0)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_deferred_peel_off_matches_inline(rmc, orc, prec):
+    # peel-off rays walked by the ray-cast pass after each launch give the
+    # cubes of rays walked inline, up to the order of the additions; an
+    # optically thick case with many rays leaving their first leaf, sliced
+    # finely so that every launch fills and drains the queue
+    pb = W.static_sphere(s0(orc), 1e4, 1e4, 4000, level=4, tau_dust=0.5)
+    pb.gas.v[:] = np.random.default_rng(5).standard_normal((pb.mesh.n, 3)) * 20e5
+    pb.observers = [W.Observer((0.0, 0.0, 1.0), 8, 8, 12, (-0.5, 0.5, -0.5, 0.5), -30, 30),
+                    W.Observer((0.6, 0.0, 0.8), 8, 8, 12, (-0.5, 0.5, -0.5, 0.5), -30, 30)]
+    a = rmc.Context.from_problem(pb, prec)
+    a.set_option(rmc.OPT_PEEL_DEFER, 0)
+    sa = a.run(21, 0, 4000)
+    pa = a.get_packets()
+    b = rmc.Context.from_problem(pb, prec)
+    b.set_option(rmc.OPT_SLICE_ITERS, 64)
+    b.stream_begin(21, 0, 4000)
+    deferred = 0
+    while True:
+        sl, rem = b.stream_step()
+        deferred += sl["peel_deferred"]
+        if rem == 0:
+            break
+    sb = b.stream_end()
+    pbk = b.get_packets()
+    assert sa["peel_deferred"] == 0
+    assert deferred > 0.01 * sb["peel_rays"]
+    assert sb["peel_deferred"] == deferred
+    for k in pa:
+        assert np.array_equal(pa[k], pbk[k]), k
+    for k in ("emitted", "escaped", "absorbed", "scatterings", "crossings", "peel_rays", "peel_crossings",
+              "peel_dropped"):
+        assert sa[k] == sb[k], k
+    for o in range(2):
+        ca, cb = a.get_cube(o), b.get_cube(o)
+        assert ca.sum() > 0
+        assert np.allclose(ca, cb, rtol=1e-5 if prec == "fp32" else 1e-12, atol=0)
+
+
 def test_error_paths(rmc, orc):
     ctx = rmc.Context("fp64")
     with pytest.raises(rmc.RmcError) as e:
