@@ -191,7 +191,7 @@ def main():
         "precisions": side,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK[head], "unit": "TFLOP/s",
                      "frac": achieved / PEAK[head], "traffic": measured_traffic(head),
-                     "kernel": "k_transport<float,false,true>" if head == "fp32" else "k_transport<double,false,true>"},
+                     "kernel": "k_transport<float,false,true,1>" if head == "fp32" else "k_transport<double,false,true,1>"},
         "hbm_copy_GBps": copy_GBps,
     }
     if not a.no_cpu_baseline:

@@ -518,27 +518,28 @@ __device__ __forceinline__ double domain_dist_leaf(const LeafRec<R> &lf, int kin
   return lf.bnd != R(0) ? domain_dist(kind, dom, p, k) : __builtin_inf();
 }
 
-// Opacity (times box size) of a leaf for a packet at x_ext along k.
-template <class R> struct Opac {
-  R kd, kl[MAX_LINES], x[MAX_LINES], ktot, w;
+// Opacity (times box size) of a leaf for a packet at x_ext along k; NL
+// bounds the number of lines (1 for single-line problems, MAX_LINES else).
+template <class R, int NL = MAX_LINES> struct Opac {
+  R kd, kl[NL], x[NL], ktot, w;
 };
 
 // The numerator delta + s x_ext - w is formed in double in both precisions:
 // for gas moving many thermal widths it is a small difference of large
 // terms, and float would lose the core of the profile.
-template <class R>
+template <class R, int NL>
 __device__ __forceinline__ void opacity(const ProblemK &pb, const LeafRec<R> &lf, double x_ext, const R k[3],
-                                        Opac<R> &o) {
+                                        Opac<R, NL> &o) {
   const double wd = (double)k[0] * (double)lf.ux + (double)k[1] * (double)lf.uy + (double)k[2] * (double)lf.uz;
   o.w = (R)wd;
   const R inv_den = R(1) / (R(1) + R(pb.b_ref) * o.w);
   o.kd = lf.kd;
   o.ktot = lf.kd;
 #pragma unroll
-  for (int i = 0; i < MAX_LINES; ++i) {
+  for (int i = 0; i < NL; ++i) {
     o.x[i] = R(0);
     o.kl[i] = R(0);
-    if (i < pb.n_lines) {
+    if (NL == 1 || i < pb.n_lines) {
       const LineK &ln = pb.lines[i];
       o.x[i] = (R)(ln.delta + ln.s * x_ext - wd) * lf.irho * R(ln.inv_mu) * inv_den;
       o.kl[i] = lf.nl * R(ln.kfac) * voigt_h<R>(R(ln.alpha) * lf.irho, o.x[i]);

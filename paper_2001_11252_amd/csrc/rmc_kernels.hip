@@ -59,7 +59,7 @@ struct RayStop {
 // borrowed, sc lends the first leaf's record and ancestor stack; with
 // may_stop, the walk ends where the ray leaves its first leaf and stop
 // records the state to resume from.
-template <class R>
+template <class R, int NL>
 __device__ double ray_walk(const ProblemK &pb, double p[3], const double k[3], double x_ext, double tau,
                            uint32_t steps, double tau_cut, int *stk, int stride, uint32_t *ncross, Cell &c,
                            const StartCell<R> *sc, bool borrowed, RayStop &stop, bool may_stop) {
@@ -67,7 +67,7 @@ __device__ double ray_walk(const ProblemK &pb, double p[3], const double k[3], d
   bool first = borrowed;
   for (; steps < MAX_CROSS; ++steps) {
     const LeafRec<R> lf = first ? *sc->lf : load_leaf<R>(pb.leaves, c.leaf);
-    Opac<R> o;
+    Opac<R, NL> o;
     opacity(pb, lf, x_ext, kr, o);
     double face[3], lo[3], hi[3];
     int em;
@@ -105,7 +105,7 @@ __device__ double ray_walk(const ProblemK &pb, double p[3], const double k[3], d
 
 // Optical depth from p along k to the domain border at fixed x_ext (the
 // peel-off integral); stops once tau >= tau_cut.  Uses its own LDS stack.
-template <class R>
+template <class R, int NL = MAX_LINES>
 __device__ double ray_tau(const ProblemK &pb, const double p0[3], const double k[3], double x_ext,
                           double tau_cut, int *stk, int stride, uint32_t *ncross,
                           const StartCell<R> *sc, RayStop &stop, bool may_stop) {
@@ -119,7 +119,7 @@ __device__ double ray_tau(const ProblemK &pb, const double p0[3], const double k
     if (!int_coords(pb.L, p, k, X)) return 0.0;
     descend(pb.nodes, pb.L, 0, 0, X, stk, stride, c);
   }
-  return ray_walk<R>(pb, p, k, x_ext, 0.0, 0u, tau_cut, stk, stride, ncross, c, sc, reuse, stop, may_stop);
+  return ray_walk<R, NL>(pb, p, k, x_ext, 0.0, 0u, tau_cut, stk, stride, ncross, c, sc, reuse, stop, may_stop);
 }
 
 // Pixel of position p in observer ob's image, -1 outside.
@@ -176,7 +176,7 @@ struct PeelSink {
 // is walked through its first leaf only (the scattering's own leaf, whose
 // record the lane already holds); a ray that goes on is queued for the
 // ray-cast pass.  Otherwise the whole ray is walked here.
-template <class R, bool DEFER>
+template <class R, bool DEFER, int NL>
 __device__ void peel_all(const ProblemK &pb, const double p[3], const PeelSrc<R> &s, int *stk,
                          int stride, LaneCount &cnt, const PeelSink &snk, const StartCell<R> *sc = nullptr) {
   for (int oi = 0; oi < pb.n_obs; ++oi) {
@@ -215,7 +215,7 @@ __device__ void peel_all(const ProblemK &pb, const double p[3], const PeelSrc<R>
     const size_t elem = (size_t)pix * ob.nbins + bin;
     RayStop rs;
     rs.stopped = false;
-    const double tau = ray_tau<R>(pb, p, ob.k, (double)xo, TauCut<R>::v, stk, stride, &nc, sc, rs, DEFER);
+    const double tau = ray_tau<R, NL>(pb, p, ob.k, (double)xo, TauCut<R>::v, stk, stride, &nc, sc, rs, DEFER);
     if (DEFER) {
       // a ray that goes on past its first leaf is queued instead of
       // holding the wave here
@@ -305,7 +305,7 @@ __device__ void finish(const ProblemK &pb, Lane<R> &s, int status) {
 
 // Emission (Sect. 2): position and frequency from the source list,
 // isotropic direction unless given, tau_event = -ln r.
-template <class R, bool DEFER>
+template <class R, bool DEFER, int NL>
 __device__ void emit(const ProblemK &pb, int64_t pid, Lane<R> &s, int *stk, int *pstk, int stride,
                      const PeelSink &snk) {
   s.pid = pid;
@@ -338,14 +338,14 @@ __device__ void emit(const ProblemK &pb, int64_t pid, Lane<R> &s, int *stk, int 
     PeelSrc<R> ps;
     ps.kind = 0;
     ps.x = s.x;
-    peel_all<R, DEFER>(pb, s.p, ps, pstk, stride, s.cnt, snk);
+    peel_all<R, DEFER, NL>(pb, s.p, ps, pstk, stride, s.cnt, snk);
   }
 }
 
 // Interaction at the current position (Sect. 3.2).  Returns the packet's
 // status (ST_NONE while it lives).
-template <class R, bool DEFER>
-__device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R> &o, int *pstk, const int *stk,
+template <class R, bool DEFER, int NL>
+__device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R, NL> &o, int *pstk, const int *stk,
                         const PeelSink &snk, int stride) {
   const StartCell<R> sc{&s.c, &s.lf, stk};
   ++s.event;
@@ -366,7 +366,7 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R> &o, int *p
     if (pb.n_obs) {
       ps.kind = 2;
       ps.x = s.x;
-      peel_all<R, DEFER>(pb, s.p, ps, pstk, stride, s.cnt, snk, &sc);
+      peel_all<R, DEFER, NL>(pb, s.p, ps, pstk, stride, s.cnt, snk, &sc);
     }
     if (!pb.forward_only) {
       const R mu = mu_hg(rng.u(J_MU), R(pb.g_hg));
@@ -390,7 +390,7 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R> &o, int *p
     R x = o.x[0];
     bool found = false;
 #pragma unroll
-    for (int q = 0; q < MAX_LINES; ++q) {
+    for (int q = 0; q < NL; ++q) {
       if (!found && q < pb.n_lines) {
         if (r < o.kl[q] || q == pb.n_lines - 1) {
           i = q;
@@ -426,7 +426,7 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R> &o, int *p
       ps.rho = rho;
       ps.line = i;
       ps.core = core;
-      peel_all<R, DEFER>(pb, s.p, ps, pstk, stride, s.cnt, snk, &sc);
+      peel_all<R, DEFER, NL>(pb, s.p, ps, pstk, stride, s.cnt, snk, &sc);
     }
     if (!pb.forward_only) {
       const R ru = rng.u(J_MU);
@@ -509,7 +509,7 @@ template <class R> struct WavesPerEU;
 template <> struct WavesPerEU<float> { static constexpr int v = RMC_WAVES_F32; };
 template <> struct WavesPerEU<double> { static constexpr int v = RMC_WAVES_F64; };
 
-template <class R, bool BATCH, bool DEFER>
+template <class R, bool BATCH, bool DEFER, int NL>
 __global__ void __launch_bounds__(256)
     __attribute__((amdgpu_waves_per_eu(WavesPerEU<R>::v, WavesPerEU<R>::v)))
     k_transport(const ProblemK *__restrict__ probs,
@@ -582,7 +582,7 @@ __global__ void __launch_bounds__(256)
             }
             const ProblemK &pb = probs[BATCH ? prob : 0];
             const int64_t pid = pb.first + (g - starts[BATCH ? prob : 0]);
-            emit<R, DEFER>(pb, pid, s, stk, pstk, stride, snk);
+            emit<R, DEFER, NL>(pb, pid, s, stk, pstk, stride, snk);
             z = s;
             z.nscat = 0;
             z.cnt = LaneCount{0, 0, 0, 0, 0};
@@ -608,7 +608,7 @@ __global__ void __launch_bounds__(256)
 
     const ProblemK &pb = probs[BATCH ? prob : 0];
     const double kd[3] = {s.kd[0], s.kd[1], s.kd[2]};
-    Opac<R> o;
+    Opac<R, NL> o;
     opacity(pb, s.lf, (double)s.x, s.k, o);
     double face[3], lo[3], hi[3];
     int em;
@@ -623,7 +623,7 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
       for (int d = 0; d < 3; ++d) s.p[d] = fmin(fmax(fma(dist, kd[d], s.p[d]), lo[d]), hi[d]);
       s.path += dist;
-      st = interact<R, DEFER>(pb, s, o, pstk, stk, snk, stride);
+      st = interact<R, DEFER, NL>(pb, s, o, pstk, stk, snk, stride);
     } else {
       s.tau -= tseg;
       s.path += lmax;
@@ -699,8 +699,19 @@ __global__ void k_clear_slots(SlotState *__restrict__ slots, int64_t n) {
 // leaf per iteration and takes the region's next ray as soon as its own is
 // done, so the waves stay full while ray lengths vary.  The walk is the one
 // of ray_walk, resumed from the queued state.
-template <class R, bool BATCH>
-__global__ void __launch_bounds__(256) k_peel_drain(const ProblemK *__restrict__ probs, PeelQueue *pq,
+#ifndef RMC_DRAIN_WAVES_F32
+#define RMC_DRAIN_WAVES_F32 4
+#endif
+#ifndef RMC_DRAIN_WAVES_F64
+#define RMC_DRAIN_WAVES_F64 3
+#endif
+template <class R> struct DrainWaves;
+template <> struct DrainWaves<float> { static constexpr int v = RMC_DRAIN_WAVES_F32; };
+template <> struct DrainWaves<double> { static constexpr int v = RMC_DRAIN_WAVES_F64; };
+
+template <class R, bool BATCH, int NL>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DrainWaves<R>::v)))
+    k_peel_drain(const ProblemK *__restrict__ probs, PeelQueue *pq,
                                                     unsigned long long *__restrict__ slice) {
   extern __shared__ int lds[];
   const int stride = blockDim.x;
@@ -782,7 +793,7 @@ __global__ void __launch_bounds__(256) k_peel_drain(const ProblemK *__restrict__
     if (!active) continue;
     const ProblemK &pb = probs[BATCH ? prob : 0];
     const LeafRec<R> lf = load_leaf<R>(pb.leaves, c.leaf);
-    Opac<R> o;
+    Opac<R, NL> o;
     opacity(pb, lf, x, kr, o);
     double face[3], lo[3], hi[3];
     int em;
@@ -1044,60 +1055,57 @@ static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b -
 using TransportFn = void (*)(const ProblemK *, const int64_t *, int, unsigned long long *, int, int, SlotState *,
                             int, unsigned long long *);
 
-template <class R>
+template <class R, int NL>
 static TransportFn transport_fn(bool batch, bool defer) {
-  if (batch) return defer ? k_transport<R, true, true> : k_transport<R, true, false>;
-  return defer ? k_transport<R, false, true> : k_transport<R, false, false>;
+  if (batch) return defer ? k_transport<R, true, true, NL> : k_transport<R, true, false, NL>;
+  return defer ? k_transport<R, false, true, NL> : k_transport<R, false, false, NL>;
 }
 
-static TransportFn transport_fn(bool fp32, bool batch, bool defer) {
-  return fp32 ? transport_fn<float>(batch, defer) : transport_fn<double>(batch, defer);
+static TransportFn transport_fn(bool fp32, bool batch, bool defer, bool one_line) {
+  if (fp32) return one_line ? transport_fn<float, 1>(batch, defer) : transport_fn<float, MAX_LINES>(batch, defer);
+  return one_line ? transport_fn<double, 1>(batch, defer) : transport_fn<double, MAX_LINES>(batch, defer);
 }
 
 static size_t transport_lds(int stack_levels, int block) {
   return ((size_t)2 * stack_levels * block + block / 64) * sizeof(int);
 }
 
-hipError_t launch_transport(bool fp32, bool batch, bool defer, const ProblemK *d_probs, const int64_t *d_starts,
-                            int n_probs, unsigned long long *d_next, int refill_min, int stack_levels,
-                            int grid, int block, void *slots, int budget, unsigned long long *slice,
-                            hipStream_t st) {
-  hipLaunchKernelGGL(transport_fn(fp32, batch, defer), dim3(grid), dim3(block), transport_lds(stack_levels, block), st,
+hipError_t launch_transport(bool fp32, bool batch, bool defer, bool one_line, const ProblemK *d_probs,
+                            const int64_t *d_starts, int n_probs, unsigned long long *d_next, int refill_min,
+                            int stack_levels, int grid, int block, void *slots, int budget,
+                            unsigned long long *slice, hipStream_t st) {
+  hipLaunchKernelGGL(transport_fn(fp32, batch, defer, one_line), dim3(grid), dim3(block), transport_lds(stack_levels, block), st,
                      d_probs, d_starts, n_probs, d_next, refill_min, stack_levels, (SlotState *)slots, budget, slice);
   return hipGetLastError();
 }
 
-hipError_t launch_peel_drain(bool fp32, bool batch, const ProblemK *d_probs, void *pq, int stack_levels, int grid,
-                             unsigned long long *slice, hipStream_t st) {
+using DrainFn = void (*)(const ProblemK *, PeelQueue *, unsigned long long *);
+
+template <class R>
+static DrainFn drain_fn(bool batch, bool one_line) {
+  if (batch) return one_line ? k_peel_drain<R, true, 1> : k_peel_drain<R, true, MAX_LINES>;
+  return one_line ? k_peel_drain<R, false, 1> : k_peel_drain<R, false, MAX_LINES>;
+}
+
+static DrainFn drain_fn(bool fp32, bool batch, bool one_line) {
+  return fp32 ? drain_fn<float>(batch, one_line) : drain_fn<double>(batch, one_line);
+}
+
+hipError_t launch_peel_drain(bool fp32, bool batch, bool one_line, const ProblemK *d_probs, void *pq,
+                             int stack_levels, int grid, unsigned long long *slice, hipStream_t st) {
   const int b = 256;
   const size_t lds = (size_t)stack_levels * b * sizeof(int);
   PeelQueue *q = (PeelQueue *)pq;
-  if (fp32) {
-    if (batch)
-      hipLaunchKernelGGL((k_peel_drain<float, true>), dim3(grid), dim3(b), lds, st, d_probs, q, slice);
-    else
-      hipLaunchKernelGGL((k_peel_drain<float, false>), dim3(grid), dim3(b), lds, st, d_probs, q, slice);
-  } else {
-    if (batch)
-      hipLaunchKernelGGL((k_peel_drain<double, true>), dim3(grid), dim3(b), lds, st, d_probs, q, slice);
-    else
-      hipLaunchKernelGGL((k_peel_drain<double, false>), dim3(grid), dim3(b), lds, st, d_probs, q, slice);
-  }
+  hipLaunchKernelGGL(drain_fn(fp32, batch, one_line), dim3(grid), dim3(b), lds, st, d_probs, q, slice);
   if (hipError_t e = hipGetLastError()) return e;
   hipLaunchKernelGGL(k_peel_reset, dim3(1), dim3(64), 0, st, q, slice);
   return hipGetLastError();
 }
 
-int peel_drain_blocks_per_cu(bool fp32, bool batch, int stack_levels) {
+int peel_drain_blocks_per_cu(bool fp32, bool batch, bool one_line, int stack_levels) {
   const size_t lds = (size_t)stack_levels * 256 * sizeof(int);
   int nb = 0;
-  hipError_t e;
-  if (fp32)
-    e = batch ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_peel_drain<float, true>, 256, lds)
-              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_peel_drain<float, false>, 256, lds);
-  else
-    e = batch ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_peel_drain<double, true>, 256, lds)
-              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_peel_drain<double, false>, 256, lds);
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, drain_fn(fp32, batch, one_line), 256, lds);
   return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
@@ -1106,9 +1114,10 @@ size_t peel_queue_bytes() { return sizeof(PeelQueue); }
 
 size_t slot_bytes() { return sizeof(SlotState); }
 
-int transport_blocks_per_cu(bool fp32, bool batch, bool defer, int block, int stack_levels) {
+int transport_blocks_per_cu(bool fp32, bool batch, bool defer, bool one_line, int block, int stack_levels) {
   int nb = 0;
-  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, transport_fn(fp32, batch, defer), block,
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, transport_fn(fp32, batch, defer, one_line),
+                                                                    block,
                                                                     transport_lds(stack_levels, block));
   return (e == hipSuccess && nb > 0) ? nb : 1;
 }

@@ -8,20 +8,21 @@
 namespace rmc {
 
 // defer: peel-off rays past their first leaf go to the queue of
-// d_probs[0].pq (then launch_peel_drain must follow).
-hipError_t launch_transport(bool fp32, bool batch, bool defer, const ProblemK *d_probs, const int64_t *d_starts,
-                            int n_probs, unsigned long long *d_next, int refill_min, int stack_levels,
-                            int grid, int block, void *slots, int budget, unsigned long long *slice,
-                            hipStream_t st);
+// d_probs[0].pq (then launch_peel_drain must follow).  one_line: every
+// problem of the launch has a single line (a kernel specialised for it).
+hipError_t launch_transport(bool fp32, bool batch, bool defer, bool one_line, const ProblemK *d_probs,
+                            const int64_t *d_starts, int n_probs, unsigned long long *d_next, int refill_min,
+                            int stack_levels, int grid, int block, void *slots, int budget,
+                            unsigned long long *slice, hipStream_t st);
 size_t slot_bytes();
 // Ray-cast pass over the peel-off queue pq (a device PeelQueue), then the
 // queue reset; grid blocks of 256 threads.
-hipError_t launch_peel_drain(bool fp32, bool batch, const ProblemK *d_probs, void *pq, int stack_levels, int grid,
-                             unsigned long long *slice, hipStream_t st);
-int peel_drain_blocks_per_cu(bool fp32, bool batch, int stack_levels);
+hipError_t launch_peel_drain(bool fp32, bool batch, bool one_line, const ProblemK *d_probs, void *pq,
+                             int stack_levels, int grid, unsigned long long *slice, hipStream_t st);
+int peel_drain_blocks_per_cu(bool fp32, bool batch, bool one_line, int stack_levels);
 size_t peel_job_bytes();
 size_t peel_queue_bytes();
-int transport_blocks_per_cu(bool fp32, bool batch, bool defer, int block, int stack_levels);
+int transport_blocks_per_cu(bool fp32, bool batch, bool defer, bool one_line, int block, int stack_levels);
 hipError_t launch_clear_slots(void *slots, int64_t n, hipStream_t st);
 hipError_t launch_count_live(const void *slots, int64_t n, unsigned long long *out, hipStream_t st);
 hipError_t launch_trace(const ProblemK &pb, int64_t n, const double *orig, const double *dir,
