@@ -378,6 +378,36 @@ __device__ __forceinline__ double exit_dist(const Cell &c, int L, const double p
   return t;
 }
 
+// Bounds of cell c, as exit_dist computes them.
+__device__ __forceinline__ void cell_bounds(const Cell &c, int L, double lo[3], double hi[3]) {
+  const double inv = ldexp(1.0, -L);
+  const int s = 1 << (L - c.level);
+  const int o[3] = {c.ox, c.oy, c.oz};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = (double)o[d] * inv;
+    hi[d] = (double)(o[d] + s) * inv;
+  }
+}
+
+// Distance from p (inside cell c) to the nearest face of the cell, shrunk by
+// 2^-40: no ray from p leaves the cell sooner than this, whatever its
+// direction, with exit_dist's rounding (which divides the same face - p
+// differences by |k_d| <= 1 + 2^-52) included.
+__device__ __forceinline__ double inner_dist(const Cell &c, int L, const double p[3]) {
+  const double inv = ldexp(1.0, -L);
+  const int s = 1 << (L - c.level);
+  const int o[3] = {c.ox, c.oy, c.oz};
+  double m = __builtin_inf();
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double lo = (double)o[d] * inv;
+    const double hi = (double)(o[d] + s) * inv;
+    m = fmin(m, fmin(p[d] - lo, hi - p[d]));
+  }
+  return fmax(m, 0.0) * (1.0 - 0x1p-40);
+}
+
 // The point where the packet leaves: exit axes snapped onto the face, the
 // others advanced by one fma and clamped into the cell.
 __device__ __forceinline__ void exit_point(double t, int emask, const double p[3], const double k[3],

@@ -69,6 +69,12 @@ __device__ double ray_walk(const ProblemK &pb, double p[3], const double k[3], d
     const LeafRec<R> lf = first ? *sc->lf : load_leaf<R>(pb.leaves, c.leaf);
     Opac<R, NL> o;
     opacity(pb, lf, x_ext, kr, o);
+    if (lf.bnd == R(0) && tau + (double)o.ktot * inner_dist(c, pb.L, p) >= tau_cut) {
+      // the cut is reached inside this leaf whatever the exit distance
+      ++*ncross;
+      tau = tau_cut;
+      break;
+    }
     double face[3], lo[3], hi[3];
     int em;
     const double te = exit_dist(c, pb.L, p, k, face, lo, hi, &em);
@@ -611,13 +617,23 @@ __global__ void __launch_bounds__(256)
     Opac<R, NL> o;
     opacity(pb, s.lf, (double)s.x, s.k, o);
     double face[3], lo[3], hi[3];
-    int em;
-    const double te = exit_dist(s.c, pb.L, s.p, kd, face, lo, hi, &em);
-    const double td = domain_dist_leaf(s.lf, pb.domain, pb.dom, s.p, kd);
-    const double lmax = te < td ? te : td;
-    const double tseg = (double)o.ktot * lmax;
+    int em = 0;
+    double te = 0.0, td = 0.0, lmax = 0.0, tseg = 0.0;
+    // An event closer than the nearest face of a leaf inside the domain
+    // happens in this leaf whatever the exit distance; only a packet that
+    // may leave needs it (the decision is the one tau < tseg would take).
+    bool here = s.lf.bnd == R(0) && s.tau < (double)o.ktot * inner_dist(s.c, pb.L, s.p);
+    if (here) {
+      cell_bounds(s.c, pb.L, lo, hi);
+    } else {
+      te = exit_dist(s.c, pb.L, s.p, kd, face, lo, hi, &em);
+      td = domain_dist_leaf(s.lf, pb.domain, pb.dom, s.p, kd);
+      lmax = te < td ? te : td;
+      tseg = (double)o.ktot * lmax;
+      here = s.tau < tseg;
+    }
     int st = ST_NONE;
-    if (s.tau < tseg) {
+    if (here) {
       // the event happens inside this leaf
       const double dist = s.tau / (double)o.ktot;
 #pragma unroll
