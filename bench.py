@@ -78,7 +78,149 @@ def parse():
     ap.add_argument("--cpu-packets", type=int, default=0, help="oracle packets (0: one per core)")
     ap.add_argument("--only", choices=["fp32", "fp64", "both"], default="both")
     ap.add_argument("--copy-gib", type=float, default=1.0, help="size of the copy used to measure HBM bandwidth")
+    ap.add_argument("--workload", choices=["dusty_sphere", "shell", "batch", "adjoint"], default="dusty_sphere",
+                    help="dusty_sphere: the headline; shell, batch, adjoint: the other configurations")
+    ap.add_argument("--vmax", type=float, default=200.0, help="shell: outflow speed at R (km/s)")
+    ap.add_argument("--leaves", type=float, default=2e7, help="adjoint: target leaf count")
+    ap.add_argument("--sources", type=int, default=100_000, help="adjoint: sources (100 rays each)")
     return ap.parse_args()
+
+
+def _line(metric, value, unit, steps, warm, ms_per_step, dtype, config, roofline, **extra):
+    d = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warm,
+         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+         "dtype": dtype, "data": "synthetic", "config": config, "roofline": roofline}
+    d.update(extra)
+    return d
+
+
+def stream_rate(ctx, steps, warm, tag):
+    """Warm-up then timed stream steps of an open stream; totals and wall."""
+    import torch
+    for _ in range(warm):
+        ctx.stream_step()
+    torch.cuda.synchronize()
+    tot, kms = {}, []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st, rem = ctx.stream_step()
+        kms.append(st["kernel_ms"])
+        for k, v in st.items():
+            tot[k] = tot.get(k, 0) + v
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    print(f"# {tag}: {steps} steps in {wall:.3f} s, transport ms {[round(k, 1) for k in kms]}, remaining {rem}, "
+          f"stats {tot}", file=sys.stderr, flush=True)
+    return wall, tot, kms
+
+
+def transport_roofline(tot, kms, prec, kernel):
+    n = len(kms)
+    avg_ms = sum(kms) / n
+    fl = (FLOP_PER_SCATTERING * tot["scatterings"] + FLOP_PER_CROSSING * (tot["crossings"] + tot["peel_rays"])) / n
+    ach = fl / (avg_ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": ach, "peak": PEAK[prec], "unit": "TFLOP/s", "frac": ach / PEAK[prec],
+            "traffic": None, "kernel": kernel}
+
+
+def bench_shell(a, rmc, W):
+    """C3: outflowing shell, 2.36e6 leaves, tau0 = 1e7 across the shell,
+    tau_dust = 1, three observers with 256x256x200 cubes, 1e7 packets
+    queued; FP32, streaming steps as the headline."""
+    pb = W.c3_shell(rmc.sigma0, vmax_kms=a.vmax, n_packets=10_000_000)
+    print(f"# shell: {pb.mesh.n} leaves, vmax {a.vmax} km/s", file=sys.stderr, flush=True)
+    ctx = rmc.Context.from_problem(pb, "fp32")
+    import torch
+    ctx.set_stream(torch.cuda.current_stream())
+    ctx.set_option(rmc.OPT_SLICE_ITERS, a.slice)
+    ctx.stream_begin(pb.seed, 0, 10_000_000)
+    wall, tot, kms = stream_rate(ctx, a.steps, a.warmup, "shell fp32")
+    ctx.close()
+    return _line("scatterings/s + ray-cell crossings/s (1 GPU), FP32", tot["scatterings"] / wall, "scatterings/s",
+                 a.steps, a.warmup, 1e3 * wall / a.steps, "f32",
+                 {"workload": f"outflowing_shell_vmax{int(a.vmax)}_tau1e7_{pb.mesh.n}_leaves_3x256x256x200",
+                  "packets_queued": 10_000_000, "iterations_per_lane_per_step": a.slice, "parallelism": "none"},
+                 transport_roofline(tot, kms, "fp32", "k_transport<float,false,true,1>"),
+                 crossings_per_s=(tot["crossings"] + tot["peel_crossings"]) / wall,
+                 transport_ms_avg=sum(kms) / len(kms), peel_pass_ms_avg=tot["peel_pass_ms"] / len(kms))
+
+
+def bench_batch(a, rmc, W):
+    """C4: 64 uneven problems (slab/sphere, Lya or the MgII doublet, tau0 in
+    [1e3, 1e7], T in [1e2, 1e5] K, 8^3-128^3 lognormal grids, 1e3-1e6
+    packets) in one persistent launch; launch shape from the autotuner;
+    FP32, streaming steps over the whole batch."""
+    probs = W.c4_batch(rmc.sigma0)
+    ctxs = [rmc.Context.from_problem(p, "fp32") for p in probs]
+    import torch
+    for c in ctxs:
+        c.set_stream(torch.cuda.current_stream())
+    seeds = [p.seed for p in probs]
+    npk = [len(p.sources.x) for p in probs]
+    best = rmc.batch_autotune(ctxs, seeds, npk)
+    print(f"# batch: {len(probs)} problems, {sum(npk)} packets, tuned {best}", file=sys.stderr, flush=True)
+    rmc.batch_begin(ctxs, seeds, npk)
+    wall, tot, kms = stream_rate(ctxs[0], a.steps, a.warmup, "batch fp32")
+    for c in ctxs:
+        c.close()
+    return _line("scatterings/s + ray-cell crossings/s (1 GPU), FP32", tot["scatterings"] / wall, "scatterings/s",
+                 a.steps, a.warmup, 1e3 * wall / a.steps, "f32",
+                 {"workload": "batch_64_problems_slab_sphere_lya_mgii", "problems": len(probs),
+                  "packets": int(sum(npk)), "tuned": best, "parallelism": "none"},
+                 transport_roofline(tot, kms, "fp32", "k_transport<float,true,false,4>"),
+                 crossings_per_s=(tot["crossings"] + tot["peel_crossings"]) / wall)
+
+
+def bench_adjoint(a, rmc, W):
+    """C5: galaxy-like adaptive mesh (~2e7 leaves), 1e7 fixed rays toward
+    +z, 512^2 image; one forward image and one backward (gradients per
+    leaf) per step, FP32 leaf records."""
+    import torch
+    t0 = time.perf_counter()
+    pb = W.c5_galaxy(rmc.sigma0, target_leaves=a.leaves, n_sources=a.sources,
+                     log=lambda m: print("# " + m, file=sys.stderr, flush=True))
+    r = pb.meta["rays"]
+    print(f"# adjoint: {pb.mesh.n} leaves, {len(r['x_ext'])} rays, generated in {time.perf_counter() - t0:.0f} s",
+          file=sys.stderr, flush=True)
+    ctx = rmc.Context.from_problem(pb, "fp32", sources=False)
+    ctx.set_stream(torch.cuda.current_stream())
+    dev = torch.device("cuda:0")
+    o = torch.tensor(r["orig"], dtype=torch.float64, device=dev)
+    x = torch.tensor(r["x_ext"], dtype=torch.float64, device=dev)
+    w = torch.tensor(r["w"], dtype=torch.float64, device=dev)
+    G = torch.tensor(pb.meta["grad_image"], dtype=torch.float64, device=dev)
+    fwd, bwd = [], []
+    t_all = 0.0
+    for i in range(a.warmup + a.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.raycast_image(0, o, x, w)
+        f = ctx.image_stats()
+        ctx.raycast_image_backward(0, o, x, w, G)
+        b = ctx.image_stats()
+        torch.cuda.synchronize()
+        if i >= a.warmup:
+            fwd.append(f)
+            bwd.append(b)
+            t_all += time.perf_counter() - t0
+    cf = sum(c for c, _ in fwd)
+    cb = sum(c for c, _ in bwd)
+    mf = sum(m for _, m in fwd)
+    mb = sum(m for _, m in bwd)
+    n = a.steps
+    # gather roofline of the forward ray cast: one FP32 leaf record (24 B)
+    # and one node entry (4 B) per crossing; the backward adds three 8-B
+    # gradient read-modify-writes
+    gbs_f = cf * 28.0 / (mf * 1e-3) / 1e9
+    gbs_b = cb * (28.0 + 48.0) / (mb * 1e-3) / 1e9
+    ctx.close()
+    return _line("adjoint ray-cell crossings/s (forward image + backward gradients, 1 GPU), FP32 records",
+                 (cf + cb) / t_all, "crossings/s", n, a.warmup, 1e3 * t_all / n, "f32",
+                 {"workload": f"galaxy_{pb.mesh.n}_leaves_{len(r['x_ext'])}_rays_512x512", "parallelism": "none"},
+                 {"bound": "hbm", "achieved": gbs_f, "peak": 8000.0, "unit": "GB/s", "frac": gbs_f / 8000.0,
+                  "traffic": None, "kernel": "k_image_fwd<float>"},
+                 forward={"crossings_per_launch": cf / n, "ms": mf / n, "GBps_algorithmic": gbs_f},
+                 backward={"crossings_per_launch": cb / n, "ms": mb / n, "GBps_algorithmic": gbs_b})
 
 
 def main():
@@ -93,6 +235,10 @@ def main():
     from paper_2001_11252_amd import rmc, workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if a.workload != "dusty_sphere":
+        fn = {"shell": bench_shell, "batch": bench_batch, "adjoint": bench_adjoint}[a.workload]
+        print(json.dumps(fn(a, rmc, W)), flush=True)
+        return
     steps, warm, P = a.steps, a.warmup, a.packets
     pb = W.c2_dusty_sphere(rmc.sigma0, n_packets=P, tau0=a.tau0)
     print(f"# workload: {pb.mesh.n} leaves, n_HI={pb.meta['n_hi']:.4e}, {P} packets queued, "

@@ -204,6 +204,10 @@ rmc_status rmc_raycast_image_backward(rmc_ctx *ctx, int id, int64_t n_rays, cons
                                       const double *x_ext, const double *w,
                                       const double *grad_image, double *g_nhi, double *g_kd,
                                       double *g_vlos, int mem);
+/* Ray-cell crossings and device time (ms) of the last rmc_raycast_image or
+ * rmc_raycast_image_backward call of this context (RMC_ESTATE if none
+ * since the last transport run). */
+rmc_status rmc_image_stats(rmc_ctx *ctx, uint64_t *crossings, double *kernel_ms);
 
 /* ---------------------------------------------------------------- batches */
 /* Run many independent problems (contexts on one device with the same
@@ -213,6 +217,13 @@ rmc_status rmc_raycast_image_backward(rmc_ctx *ctx, int id, int64_t n_rays, cons
 rmc_status rmc_batch_run(rmc_ctx *const *problems, int n_problems, const uint64_t *seeds,
                          const int64_t *n_packets, rmc_run_stats *per_problem,
                          rmc_run_stats *total);
+/* Streaming form of rmc_batch_run: opens the batch's stream on
+ * problems[0]; rmc_stream_step(problems[0]) advances every problem of the
+ * batch by one launch and rmc_stream_end(problems[0]) runs the rest and
+ * reports the totals.  Per-packet results land in each problem's context
+ * as with rmc_batch_run. */
+rmc_status rmc_batch_begin(rmc_ctx *const *problems, int n_problems, const uint64_t *seeds,
+                           const int64_t *n_packets);
 
 /* Pick the transport launch shape for a batch by measurement: every
  * candidate (threads per block x idle lanes a wave gathers before refilling

@@ -137,6 +137,7 @@ struct rmc_ctx {
   hipGraphExec_t s_graph2 = nullptr;  // ray-cast pass over the peel-off queue
   std::string s_key;
   PeelQueue *s_pq = nullptr;
+  bool image_done = false;           // an image call has filled d_stats and ev0/ev1
   bool s_one_line = false;           // every problem of the stream has one line
   // deferred peel-off rays: control block (PeelQueue) and job buffer
   DevBuf pq_ctl, pq_jobs, pq_counts;
@@ -855,6 +856,7 @@ rmc_status grow_queue(rmc_ctx *c, unsigned long long max_region) {
 // Prepare slots and counters for a stream over the problems already
 // uploaded at s_probs / s_starts.
 rmc_status stream_open(rmc_ctx *c, int64_t total, int n_probs, int levels, bool batch) {
+  c->image_done = false;
   c->s_total = total;
   c->s_done = 0;
   c->s_nprobs = n_probs;
@@ -1213,8 +1215,24 @@ rmc_status rmc_raycast_image(rmc_ctx *c, int id, int64_t n, const double *orig, 
   HIPCHK(c, launch_image_fwd(c->precision == RMC_FP32_BULK, pb, id, n, o, x, ww, img,
                              c->d_stats.as<unsigned long long>() + S_PEEL_CROSS, c->stream));
   HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+  c->image_done = true;
   if (mem != RMC_DEVICE) HIPCHK(c, hipMemcpyAsync(image, img, npix * 8, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  return RMC_OK;
+}
+
+rmc_status rmc_image_stats(rmc_ctx *c, uint64_t *crossings, double *kernel_ms) {
+  rmc_status r = enter(c);
+  if (r) return r;
+  if (!c->image_done) return fail(c, RMC_ESTATE, "no image call yet");
+  unsigned long long h = 0;
+  HIPCHK(c, hipMemcpyAsync(&h, c->d_stats.as<unsigned long long>() + S_PEEL_CROSS, 8, hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  float ms = 0.f;
+  HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  if (crossings) *crossings = h;
+  if (kernel_ms) *kernel_ms = ms;
   return RMC_OK;
 }
 
@@ -1247,6 +1265,7 @@ rmc_status rmc_raycast_image_backward(rmc_ctx *c, int id, int64_t n, const doubl
   HIPCHK(c, launch_image_bwd(c->precision == RMC_FP32_BULK, pb, id, n, o, x, ww, Gd, inv_vth_ref, a, b, d,
                              c->d_stats.as<unsigned long long>() + S_PEEL_CROSS, c->stream));
   HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+  c->image_done = true;
   if (mem != RMC_DEVICE) {
     HIPCHK(c, hipMemcpyAsync(gn, a, nl * 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(gk, b, nl * 8, hipMemcpyDeviceToHost, c->stream));
@@ -1303,6 +1322,13 @@ rmc_status batch_open(rmc_ctx *const *P, int np, const uint64_t *seeds, const in
 }
 
 }  // namespace
+
+rmc_status rmc_batch_begin(rmc_ctx *const *P, int np, const uint64_t *seeds, const int64_t *npk) {
+  if (!P || np <= 0 || !P[0] || !seeds || !npk) return RMC_EINVAL;
+  rmc_status r = enter(P[0]);
+  if (r) return r;
+  return batch_open(P, np, seeds, npk);
+}
 
 rmc_status rmc_batch_run(rmc_ctx *const *P, int np, const uint64_t *seeds, const int64_t *npk,
                          rmc_run_stats *per, rmc_run_stats *total) {

@@ -958,7 +958,7 @@ __global__ void k_image_fwd(ProblemK pb, int obs, int64_t n, const double *__res
 //   dtau/dv_los  = seg nl sum_i kfac_i H'_i dx_i/dw / v_th,ref,
 //   dx_i/dw = -irho inv_mu_i s_i (1 + b x_ext) / (1 + b w)^2.
 template <class R>
-__global__ void k_image_bwd(ProblemK pb, int obs, int64_t n, const double *__restrict__ orig,
+__global__ void __launch_bounds__(256) k_image_bwd(ProblemK pb, int obs, int64_t n, const double *__restrict__ orig,
                             const double *__restrict__ x_ext, const double *__restrict__ w,
                             const double *__restrict__ G, double inv_vth_ref,
                             double *__restrict__ g_n, double *__restrict__ g_k,
@@ -966,64 +966,115 @@ __global__ void k_image_bwd(ProblemK pb, int obs, int64_t n, const double *__res
   extern __shared__ int lds[];
   int *stk = lds + threadIdx.x;
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = __lane_id();
   uint32_t nc = 0;
+  const double *k = pb.obs[obs].k;
+  const R kr[3] = {(R)k[0], (R)k[1], (R)k[2]};
+  bool walking = false;
+  double g = 0.0, xr = 0.0;
+  double p[3] = {0.0, 0.0, 0.0};
+  Cell c;
+  uint32_t steps = 0;
   if (r < n) {
     const ObsK &ob = pb.obs[obs];
     const double p0[3] = {orig[3 * r], orig[3 * r + 1], orig[3 * r + 2]};
     const int pix = pixel_of(ob, p0);
-    const double xr = x_ext[r];
+    xr = x_ext[r];
     double tau = TauCut<double>::v;
     RayStop rs;
     if (pix >= 0) tau = ray_tau<R>(pb, p0, ob.k, xr, TauCut<double>::v, stk, blockDim.x, &nc, nullptr, rs, false);
-    const double g = (pix >= 0 && tau < TauCut<double>::v) ? -G[pix] * w[r] * exp(-tau) : 0.0;
+    g = (pix >= 0 && tau < TauCut<double>::v) ? -G[pix] * w[r] * exp(-tau) : 0.0;
     if (g != 0.0) {
       // replay the ray (same traversal as the forward pass)
-      const double *k = ob.k;
-      const R kr[3] = {(R)k[0], (R)k[1], (R)k[2]};
-      double p[3] = {p0[0], p0[1], p0[2]};
+      p[0] = p0[0]; p[1] = p0[1]; p[2] = p0[2];
       int X[3];
-      Cell c;
       if (int_coords(pb.L, p, k, X)) {
         descend(pb.nodes, pb.L, 0, 0, X, stk, blockDim.x, c);
-        for (uint32_t steps = 0; steps < MAX_CROSS; ++steps) {
-          const LeafRec<R> lf = load_leaf<R>(pb.leaves, c.leaf);
-          Opac<R> o;
-          opacity(pb, lf, xr, kr, o);
-          double face[3], lo[3], hi[3];
-          int em;
-          const double te = exit_dist(c, pb.L, p, k, face, lo, hi, &em);
-          const double td = domain_dist_leaf(lf, pb.domain, pb.dom, p, k);
-          const double seg = td <= te ? td : te;
-          const R b = R(pb.b_ref);
-          const R den = R(1) + b * o.w;
-          R sn = R(0), sv = R(0);
+        walking = true;
+      }
+    }
+  }
+  // The wave walks its rays in step (every lane runs every iteration) so
+  // that the gradient contributions of lanes in the same leaf are summed
+  // across the wave first: rays from one source share their cells, and
+  // one atomic per leaf replaces up to 64.  Every lane reaches the
+  // shuffles below (no lane has left the loop), so their sources are live.
+  while (__ballot(walking)) {
+    int leaf = -1;
+    double an = 0.0, ak = 0.0, av = 0.0;
+    if (walking) {
+      const LeafRec<R> lf = load_leaf<R>(pb.leaves, c.leaf);
+      Opac<R> o;
+      opacity(pb, lf, xr, kr, o);
+      double face[3], lo[3], hi[3];
+      int em;
+      const double te = exit_dist(c, pb.L, p, k, face, lo, hi, &em);
+      const double td = domain_dist_leaf(lf, pb.domain, pb.dom, p, k);
+      const double seg = td <= te ? td : te;
+      const R b = R(pb.b_ref);
+      const R den = R(1) + b * o.w;
+      R sn = R(0), sv = R(0);
 #pragma unroll
-          for (int i = 0; i < MAX_LINES; ++i) {
-            if (i < pb.n_lines) {
-              const LineK &ln = pb.lines[i];
-              const R a = R(ln.alpha) * lf.irho;
-              sn += R(ln.kfac) * voigt_h<R>(a, o.x[i]);
-              const R dxdw = -lf.irho * R(ln.inv_mu) * R(ln.s) * (R(1) + b * (R)xr) / (den * den);
-              sv += R(ln.kfac) * voigt_dhdx<R>(a, o.x[i]) * dxdw;
-            }
-          }
-          unsafeAtomicAdd(g_n + c.leaf, g * seg * pb.box_cm * (double)lf.irho * (double)sn);
-          unsafeAtomicAdd(g_k + c.leaf, g * seg * pb.box_cm);
-          unsafeAtomicAdd(g_v + c.leaf, g * seg * (double)lf.nl * (double)sv * inv_vth_ref);
-          if (td <= te) break;
-          double pn[3];
-          exit_point(te, em, p, k, face, lo, hi, pn);
-          p[0] = pn[0]; p[1] = pn[1]; p[2] = pn[2];
-          wrap_slab(pb.domain, p, k);
-          if (!int_coords(pb.L, p, k, X)) break;
-          relocate(pb.nodes, pb.L, X, stk, blockDim.x, c);
+      for (int i = 0; i < MAX_LINES; ++i) {
+        if (i < pb.n_lines) {
+          const LineK &ln = pb.lines[i];
+          const R a = R(ln.alpha) * lf.irho;
+          sn += R(ln.kfac) * voigt_h<R>(a, o.x[i]);
+          const R dxdw = -lf.irho * R(ln.inv_mu) * R(ln.s) * (R(1) + b * (R)xr) / (den * den);
+          sv += R(ln.kfac) * voigt_dhdx<R>(a, o.x[i]) * dxdw;
         }
       }
+      leaf = c.leaf;
+      an = g * seg * pb.box_cm * (double)lf.irho * (double)sn;
+      ak = g * seg * pb.box_cm;
+      av = g * seg * (double)lf.nl * (double)sv * inv_vth_ref;
+      if (td <= te) {
+        walking = false;
+      } else {
+        double pn[3];
+        exit_point(te, em, p, k, face, lo, hi, pn);
+        p[0] = pn[0]; p[1] = pn[1]; p[2] = pn[2];
+        wrap_slab(pb.domain, p, k);
+        int X[3];
+        if (!int_coords(pb.L, p, k, X)) {
+          walking = false;
+        } else {
+          relocate(pb.nodes, pb.L, X, stk, blockDim.x, c);
+          if (++steps >= MAX_CROSS) walking = false;
+        }
+      }
+    }
+    // one sum and one atomic per distinct leaf of the wave (a few when a
+    // wave holds rays of two sources); lanes with many distinct leaves
+    // fall back to their own atomics after four rounds
+    unsigned long long m = __ballot(leaf >= 0);
+    for (int round = 0; m && round < 4; ++round) {
+      const int lead = __ffsll((long long)m) - 1;
+      const int l0 = __shfl(leaf, lead);
+      const bool mine = leaf == l0;
+      double sn = mine ? an : 0.0, sk = mine ? ak : 0.0, sv2 = mine ? av : 0.0;
+      for (int off = 32; off > 0; off >>= 1) {
+        sn += __shfl_xor(sn, off);
+        sk += __shfl_xor(sk, off);
+        sv2 += __shfl_xor(sv2, off);
+      }
+      if (lane == lead) {
+        unsafeAtomicAdd(g_n + l0, sn);
+        unsafeAtomicAdd(g_k + l0, sk);
+        unsafeAtomicAdd(g_v + l0, sv2);
+      }
+      if (mine) leaf = -1;
+      m = __ballot(leaf >= 0);
+    }
+    if (leaf >= 0) {
+      unsafeAtomicAdd(g_n + leaf, an);
+      unsafeAtomicAdd(g_k + leaf, ak);
+      unsafeAtomicAdd(g_v + leaf, av);
     }
   }
   unsigned long long v = nc;
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
-  if (__lane_id() == 0 && v) atomicAdd(ncross, v);
+  if (lane == 0 && v) atomicAdd(ncross, v);
 }
 
 // --------------------------------------------------------------- helpers

@@ -90,7 +90,9 @@ _sig = {
     "rmc_tau": (C.c_int, [_P, _i64, _P, _P, _P, _P, C.c_int]),
     "rmc_raycast_image": (C.c_int, [_P, C.c_int, _i64, _P, _P, _P, _P, C.c_int]),
     "rmc_raycast_image_backward": (C.c_int, [_P, C.c_int, _i64, _P, _P, _P, _P, _P, _P, _P, C.c_int]),
+    "rmc_image_stats": (C.c_int, [_P, C.POINTER(C.c_uint64), C.POINTER(C.c_double)]),
     "rmc_batch_run": (C.c_int, [_P, C.c_int, _P, _P, C.POINTER(RmcRunStats), C.POINTER(RmcRunStats)]),
+    "rmc_batch_begin": (C.c_int, [_P, C.c_int, _P, _P]),
     "rmc_batch_autotune": (C.c_int, [_P, C.c_int, _P, _P, C.c_int, _P]),
     "rmc_mesh_check": (C.c_int, [_i64, _P, _P, C.c_char_p, C.c_int]),
     "rmc_line_quantities": (C.c_int, [_P, C.c_double, _P]),
@@ -327,6 +329,13 @@ class Context:
                                                 _ptr(gk), _ptr(gv), HOST), "raycast_image_backward")
         return gn, gk, gv
 
+    def image_stats(self):
+        """(ray-cell crossings, device ms) of the last image call."""
+        n = C.c_uint64(0)
+        ms = C.c_double(0.0)
+        self._chk(_L.rmc_image_stats(self._h, C.byref(n), C.byref(ms)), "image_stats")
+        return int(n.value), float(ms.value)
+
     # ------------------------------------------------------ convenience
     @classmethod
     def from_problem(cls, pb, precision="fp64", device=0, observers=True, sources=True):
@@ -359,6 +368,20 @@ def batch_run(contexts, seeds, n_packets):
     for c, k in zip(contexts, npk):
         c.last_n = int(k)
     return [p.as_dict() for p in per], tot.as_dict()
+
+
+def batch_begin(contexts, seeds, n_packets):
+    """Open the batch's stream on contexts[0]: advance it with
+    contexts[0].stream_step(), finish with contexts[0].stream_end()."""
+    n = len(contexts)
+    hs = (C.c_void_p * n)(*[c.handle.value for c in contexts])
+    sd = np.ascontiguousarray([int(s) & 0xFFFFFFFFFFFFFFFF for s in seeds], dtype=np.uint64)
+    npk = np.ascontiguousarray(n_packets, dtype=np.int64)
+    rc = _L.rmc_batch_begin(hs, n, _ptr(sd), _ptr(npk))
+    if rc:
+        raise RmcError(rc, "batch_begin: " + _L.rmc_last_error(contexts[0].handle).decode())
+    for c, k in zip(contexts, npk):
+        c.last_n = int(k)
 
 
 def batch_autotune(contexts, seeds, n_packets, trial_slices=3):

@@ -169,10 +169,11 @@ def balance_2to1(level, ijk, max_iter=64):
     raise RuntimeError("2:1 balancing did not converge")
 
 
-def refined_mesh(base_level, max_level, rule, box_cm=KPC_CM, balance=True):
+def refined_mesh(base_level, max_level, rule, box_cm=KPC_CM, balance=True, max_leaves=None):
     """Start from a uniform grid at base_level and split every leaf for
     which rule(level, lo, hi) is true (lo, hi: [n,3] cell bounds in box
-    units), level by level up to max_level; then enforce 2:1 grading."""
+    units), level by level up to max_level; then enforce 2:1 grading.
+    With max_leaves, returns None as soon as the unbalanced mesh exceeds it."""
     m = uniform_mesh(base_level, box_cm)
     level, ijk = m.level, m.ijk
     for lev in range(base_level, max_level):
@@ -183,6 +184,8 @@ def refined_mesh(base_level, max_level, rule, box_cm=KPC_CM, balance=True):
         mask[np.nonzero(cand)[0]] = rule(lev, lo, lo + h)
         if not mask.any():
             continue
+        if max_leaves is not None and len(level) + 7 * int(mask.sum()) > max_leaves:
+            return None
         level, ijk = _split(level, ijk, mask)
     if balance:
         level, ijk = balance_2to1(level, ijk)
@@ -392,12 +395,15 @@ def _trilinear_periodic(field, pos):
 
 def c5_galaxy(sigma0_fn, grid=256, min_level=6, max_level=12, target_leaves=2.0e7, n_sources=100_000,
               rays_per_source=100, seed=0x5EED0005, tau_mean=1e4, tau_dust=1.0, vrms_kms=30.0,
-              nx=512):
+              nx=512, log=None):
     """Galaxy-like adaptive mesh: lognormal n_HI (sigma_ln = 2) from a k^-3
     Gaussian field, dust proportional to n_HI, three k^-3 velocity fields
     with 30 km/s rms per component, T = 1e4 K; levels min..max refined where
     the cell's n_HI h^3 exceeds a threshold chosen for ~target_leaves;
-    sources at leaves drawn proportionally to n_HI h^3, rays toward +z."""
+    sources at leaves drawn proportionally to n_HI h^3, rays toward +z.
+    log (optional) receives a line per stage (a full-size build takes
+    minutes)."""
+    log = log or (lambda msg: None)
     g = gaussian_field(grid, -3.0, seed)
     vf = [gaussian_field(grid, -3.0, seed + 1 + i) for i in range(3)]
     dens = np.exp(2.0 * g - 2.0)                     # mean 1 (sigma_ln = 2)
@@ -410,29 +416,54 @@ def c5_galaxy(sigma0_fn, grid=256, min_level=6, max_level=12, target_leaves=2.0e
         h = np.ldexp(1.0, -lev)
         return _trilinear_periodic(dens, c) * h ** 3
 
-    # choose the threshold from the cell masses so the leaf count lands near
-    # the target: each split adds 7 leaves
-    def build(thr):
-        return refined_mesh(min_level, max_level, lambda lev, lo, hi: mass_of(lev, lo, hi) > thr,
-                            balance=True)
+    # choose the threshold so that the leaf count lands near the target:
+    # trial builds skip the balancing (which adds ~15% leaves) and stop once
+    # they exceed twice the goal; the threshold is found by bracketing and
+    # regula falsi on log N against log threshold
+    def rule_for(thr):
+        return lambda lev, lo, hi: mass_of(lev, lo, hi) > thr
 
-    lo_t, hi_t = 1e-12, 1e-3
-    mesh = None
-    for _ in range(14):
-        mid = np.sqrt(lo_t * hi_t)
-        mesh = build(mid)
-        if mesh.n > target_leaves * 1.05:
-            lo_t = mid
-        elif mesh.n < target_leaves * 0.95:
-            hi_t = mid
-        else:
+    goal = target_leaves / 1.15
+
+    def count(thr):
+        m = refined_mesh(min_level, max_level, rule_for(thr), balance=False, max_leaves=2 * goal)
+        n = np.inf if m is None else m.n
+        log(f"c5 trial threshold {thr:.3e}: {n} leaves before balancing")
+        return n
+
+    t_a, n_a = 1e-6, count(1e-6)
+    step = 10.0 if n_a > goal else 0.1
+    t_b, n_b = t_a * step, count(t_a * step)
+    for _ in range(12):
+        if (n_a > goal) != (n_b > goal) or (n_b == n_a and np.isfinite(n_b)):
+            break                       # bracketed, or the count no longer moves
+        t_a, n_a = t_b, n_b
+        t_b *= step
+        n_b = count(t_b)
+    thr = t_b
+    for _ in range(10 if (n_a > goal) != (n_b > goal) else 0):
+        la, lb = np.log(t_a), np.log(t_b)
+        fa = np.log(min(n_a, 4 * goal) / goal)
+        fb = np.log(min(n_b, 4 * goal) / goal)
+        lt = lb - fb * (lb - la) / (fb - fa) if fb != fa else 0.5 * (la + lb)
+        lt = min(max(lt, min(la, lb) + 0.05 * abs(lb - la)), max(la, lb) - 0.05 * abs(lb - la))
+        thr = float(np.exp(lt))
+        n_t = count(thr)
+        if abs(n_t / goal - 1.0) < 0.1:
             break
+        if (n_t > goal) == (n_a > goal):
+            t_a, n_a = thr, n_t
+        else:
+            t_b, n_b = thr, n_t
+    mesh = refined_mesh(min_level, max_level, rule_for(thr), balance=True)
+    log(f"c5 mesh: {mesh.n} leaves")
     cen, h = mesh.centres()
     rho = _trilinear_periodic(dens, cen).astype(np.float64)
     n_hi = nbar * rho
     kd = rho * (tau_dust / box)
     v = np.stack([_trilinear_periodic(f, cen) for f in vf], axis=1).astype(np.float64) * (vrms_kms * KMS)
     gas = Gas(n_hi, np.full(mesh.n, T), v, kd)
+    log("c5 gas fields done")
     rng = np.random.default_rng(seed + 7)
     wts = rho * h ** 3
     wts /= wts.sum()

@@ -36,6 +36,10 @@ def test_image_and_gradient_match_oracle(orc, galaxy, prec):
     img = ctx.raycast_image(0, orig, x, w)
     gn, gk, gv = ctx.raycast_image_backward(0, orig, x, w, G)
     assert img_o.sum() > 0 and np.count_nonzero(gn_o) > 100
+    nb, mb = ctx.image_stats()
+    img = ctx.raycast_image(0, orig, x, w)
+    nf, mf = ctx.image_stats()
+    assert nf > len(x) and nb >= nf and mf > 0 and mb > 0
     if prec == "fp64":
         assert np.allclose(img, img_o, rtol=1e-12, atol=1e-300)
         for a, b in ((gn, gn_o), (gk, gk_o), (gv, gv_o)):

@@ -78,3 +78,33 @@ def test_batch_autotune_picks_a_valid_shape(orc):
         bb = b.get_packets()
         for k in a:
             assert np.array_equal(a[k], bb[k])
+
+
+def test_batch_stream_equals_batch_run(orc):
+    # the streaming form (begin, steps, end on the first context) gives the
+    # packets and totals of one rmc_batch_run call
+    from paper_2001_11252_amd import rmc
+    probs = _small_batch(orc, n=10, seed=11)
+    npk = [len(p.sources.x) for p in probs]
+    seeds = [p.seed for p in probs]
+    a = [rmc.Context.from_problem(p, "fp32") for p in probs]
+    _, ta = rmc.batch_run(a, seeds, npk)
+    b = [rmc.Context.from_problem(p, "fp32") for p in probs]
+    b[0].set_option(rmc.OPT_SLICE_ITERS, 16)
+    rmc.batch_begin(b, seeds, npk)
+    steps, work = 0, 0
+    while True:
+        sl, rem = b[0].stream_step()
+        steps += 1
+        work += sl["scatterings"]
+        if rem == 0:
+            break
+    tb = b[0].stream_end()
+    assert steps > 2
+    for k in ("emitted", "escaped", "absorbed", "scatterings", "crossings"):
+        assert ta[k] == tb[k], k
+    assert work == tb["scatterings"]
+    for ca, cb in zip(a, b):
+        pa, pb_ = ca.get_packets(), cb.get_packets()
+        for k in pa:
+            assert np.array_equal(pa[k], pb_[k]), k
