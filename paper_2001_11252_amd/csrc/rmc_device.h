@@ -189,23 +189,40 @@ template <> struct M<double> {
     ::sincospi(2.0 * r, s, c);
   }
   static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+  static __device__ __forceinline__ double div(double a, double b) { return a / b; }
+  static __device__ __forceinline__ double cbrt_pos(double x) { return ::cbrt(x); }
 };
+// The float path uses the hardware transcendental instructions (log2,
+// exp2, sqrt, rcp, sin and cos in turns, each within a few ulp); its
+// arguments here are normal numbers (uniforms >= 2^-24, positive sums).
 template <> struct M<float> {
   static __device__ __forceinline__ float exp(float x) { return __expf(x); }
-  static __device__ __forceinline__ float log(float x) { return __logf(x); }
-  static __device__ __forceinline__ float log10(float x) { return __log10f(x); }
-  static __device__ __forceinline__ float sqrt(float x) { return __fsqrt_rn(x); }
+  static __device__ __forceinline__ float log(float x) {
+    return __builtin_amdgcn_logf(x) * 0.69314718055994531f;
+  }
+  static __device__ __forceinline__ float log10(float x) {
+    return __builtin_amdgcn_logf(x) * 0.30102999566398120f;
+  }
+  static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
   static __device__ __forceinline__ float cbrt(float x) { return ::cbrtf(x); }
   static __device__ __forceinline__ float atan(float x) { return ::atanf(x); }
   static __device__ __forceinline__ float tan(float x) {
     float s, c;
     __sincosf(x, &s, &c);
-    return __fdividef(s, c);
+    return s * __builtin_amdgcn_rcpf(c);
   }
+  // the hardware sine and cosine take their argument in turns
   static __device__ __forceinline__ void sincos2pi(float r, float *s, float *c) {
-    ::sincospif(2.0f * r, s, c);
+    *s = __builtin_amdgcn_sinf(r);
+    *c = __builtin_amdgcn_cosf(r);
   }
   static __device__ __forceinline__ float rcp(float x) { return __frcp_rn(x); }
+  // a times the hardware reciprocal of b (about 1 ulp)
+  static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+  // cube root of a positive normal number from the hardware log2 and exp2
+  static __device__ __forceinline__ float cbrt_pos(float x) {
+    return __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(x) * (1.0f / 3.0f));
+  }
 };
 
 // ---------------------------------------------------------------- Voigt H
@@ -215,11 +232,11 @@ template <> struct M<float> {
 //   H = sqrt(pi) q + exp(-x^2)
 template <class R> __device__ __forceinline__ R voigt_h(R a, R x) {
   const R x2 = x * x;
-  const R z = (x2 - R(0.855)) / (x2 + R(3.42));
+  const R z = M<R>::div(x2 - R(0.855), x2 + R(3.42));
   R h = M<R>::exp(-x2);
   if (z > R(0)) {
     const R P = ((R(5.674) * z - R(9.207)) * z + R(4.421)) * z + R(0.1117);
-    const R q = z * (R(1) + R(21) / x2) * (a * R(1.0 / PI_D)) / (x2 + R(1)) * P;
+    const R q = M<R>::div(z * (R(1) + M<R>::div(R(21), x2)) * (a * R(1.0 / PI_D)), x2 + R(1)) * P;
     h += R(1.7724538509055160273) * q;
   }
   return h;
@@ -268,17 +285,17 @@ __device__ __forceinline__ bool sample_upar(R x, R a, EventRng<R> &rng, uint32_t
   if (fabs(x) >= R(8)) {
     R s, c;
     M<R>::sincos2pi(rng.u(J_GAUSS2), &s, &c);
-    *out = R(1) / x + M<R>::sqrt(-M<R>::log(rng.u(J_GAUSS1))) * c;
+    *out = M<R>::div(R(1), x) + M<R>::sqrt(-M<R>::log(rng.u(J_GAUSS1))) * c;
     return true;
   }
   const R sg = x < R(0) ? R(-1) : R(1);
   const R xa = fabs(x);
   R u0 = u0_fit(xa, M<R>::log10(a));
   u0 = u0 < R(0) ? R(0) : u0;
-  const R th0 = M<R>::atan((u0 - xa) / a);
+  const R th0 = M<R>::atan(M<R>::div(u0 - xa, a));
   const R e0 = M<R>::exp(-u0 * u0);
   const R hp = R(0.5 * PI_D);
-  const R p1 = (th0 + hp) / ((R(1) - e0) * th0 + (R(1) + e0) * hp);
+  const R p1 = M<R>::div(th0 + hp, (R(1) - e0) * th0 + (R(1) + e0) * hp);
   const R u02 = u0 * u0;
   for (uint32_t it = 0; it < MAX_REJECT; ++it) {
     const R r1 = rng.u(J_REJ + 3 * it);
@@ -307,24 +324,24 @@ __device__ __forceinline__ bool sample_upar(R x, R a, EventRng<R> &rng, uint32_t
 template <class R> __device__ __forceinline__ R mu_core(R r) {
   const R B = R(6) * (R(2) * r - R(1));
   const R A = M<R>::sqrt(B * B + R(11.0 * 11.0 * 11.0 / 27.0));
-  return M<R>::cbrt(A + B) - M<R>::cbrt(A - B);
+  return M<R>::cbrt_pos(A + B) - M<R>::cbrt_pos(A - B);
 }
 template <class R> __device__ __forceinline__ R mu_wing(R r) {
   const R B = R(4) * r - R(2);
   const R A = M<R>::sqrt(B * B + R(1));
-  return M<R>::cbrt(A + B) - M<R>::cbrt(A - B);
+  return M<R>::cbrt_pos(A + B) - M<R>::cbrt_pos(A - B);
 }
 // Henyey-Greenstein inverse, with the square of the exact inverse.
 template <class R> __device__ __forceinline__ R mu_hg(R r, R g) {
   if (g == R(0)) return R(2) * r - R(1);
-  const R t = (R(1) - g * g) / (R(1) - g + R(2) * g * r);
-  return (R(1) + g * g - t * t) / (R(2) * g);
+  const R t = M<R>::div(R(1) - g * g, R(1) - g + R(2) * g * r);
+  return M<R>::div(R(1) + g * g - t * t, R(2) * g);
 }
 template <class R> __device__ __forceinline__ R p_core(R mu) { return R(11.0 / 24.0) + R(3.0 / 24.0) * mu * mu; }
 template <class R> __device__ __forceinline__ R p_wing(R mu) { return R(3.0 / 8.0) * (R(1) + mu * mu); }
 template <class R> __device__ __forceinline__ R p_hg(R mu, R g) {
   const R d = R(1) + g * g - R(2) * g * mu;
-  return R(0.5) * (R(1) - g * g) / (d * M<R>::sqrt(d));
+  return M<R>::div(R(0.5) * (R(1) - g * g), d * M<R>::sqrt(d));
 }
 
 // Orthonormal pair perpendicular to k: e1 = normalize(k x z) (k x x when
@@ -333,7 +350,7 @@ template <class R> __device__ __forceinline__ void perp_basis(const R k[3], R e1
   R c0, c1, c2;
   if (fabs(k[2]) > R(0.9)) { c0 = R(0); c1 = k[2]; c2 = -k[1]; }
   else { c0 = k[1]; c1 = -k[0]; c2 = R(0); }
-  const R n = R(1) / M<R>::sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+  const R n = M<R>::div(R(1), M<R>::sqrt(c0 * c0 + c1 * c1 + c2 * c2));
   e1[0] = c0 * n; e1[1] = c1 * n; e1[2] = c2 * n;
   e2[0] = k[1] * e1[2] - k[2] * e1[1];
   e2[1] = k[2] * e1[0] - k[0] * e1[2];
@@ -562,7 +579,7 @@ __device__ __forceinline__ void opacity(const ProblemK &pb, const LeafRec<R> &lf
                                         Opac<R, NL> &o) {
   const double wd = (double)k[0] * (double)lf.ux + (double)k[1] * (double)lf.uy + (double)k[2] * (double)lf.uz;
   o.w = (R)wd;
-  const R inv_den = R(1) / (R(1) + R(pb.b_ref) * o.w);
+  const R inv_den = M<R>::div(R(1), R(1) + R(pb.b_ref) * o.w);
   o.kd = lf.kd;
   o.ktot = lf.kd;
 #pragma unroll

@@ -200,7 +200,7 @@ __device__ void peel_all(const ProblemK &pb, const double p[3], const PeelSrc<R>
       const R dkU = (ko[0] - s.kin[0]) * s.U[0] + (ko[1] - s.kin[1]) * s.U[1] + (ko[2] - s.kin[2]) * s.U[2];
       const R g1 = R(1) + s.bc * s.x;
       const R Rr = ln.recoil ? (R(1) - mu) * R(ln.rec) * g1 : R(0);
-      const R xc = (s.x + g1 * dkU - Rr / s.bc) / (R(1) + Rr);
+      const R xc = M<R>::div(s.x + g1 * dkU - M<R>::div(Rr, s.bc), R(1) + Rr);
       const R wo = ko[0] * s.ux + ko[1] * s.uy + ko[2] * s.uz;
       xo = (R(-ln.delta) + R(ln.mu) * s.rho * xc * (R(1) + R(pb.b_ref) * wo) + wo) * R(ln.inv_s);
     } else {
@@ -208,7 +208,7 @@ __device__ void peel_all(const ProblemK &pb, const double p[3], const PeelSrc<R>
       weight = p_hg(mu, R(pb.g_hg)) * R(1.0 / (2.0 * PI_D));
       const R wo = ko[0] * s.ux + ko[1] * s.uy + ko[2] * s.uz;
       const R b = R(pb.b_ref);
-      xo = (s.x + wo + b * s.x * wo - s.w) / (R(1) + b * s.w);
+      xo = M<R>::div(s.x + wo + b * s.x * wo - s.w, R(1) + b * s.w);
     }
     const int pix = pixel_of(ob, p);
     const int bin = bin_of(ob, (double)xo);
@@ -385,7 +385,7 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R, NL> &o, in
       // coherent in the cell frame
       const R wn = s.k[0] * s.lf.ux + s.k[1] * s.lf.uy + s.k[2] * s.lf.uz;
       const R b = R(pb.b_ref);
-      s.x = (s.x + wn + b * s.x * wn - o.w) / (R(1) + b * o.w);
+      s.x = M<R>::div(s.x + wn + b * s.x * wn - o.w, R(1) + b * o.w);
     }
   } else {
     // resonant scattering in line i (Sect. 3.2.1)
@@ -418,7 +418,7 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R, NL> &o, in
     R U[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) U[d] = upar * kin[d] + up1 * e1[d] + up2 * e2[d];
-    const R rho = R(1) / s.lf.irho;
+    const R rho = M<R>::div(R(1), s.lf.irho);
     const R bc = R(pb.b_ref) * R(ln.mu) * rho;
     // frequency seen by the atom, nu_in (1 - k_in.v/c), within 0.2 dnu_D
     const R g1 = R(1) + bc * x;
@@ -446,7 +446,7 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R, NL> &o, in
       // denominator (Eq. for nu_out), then back to the external frame
       const R dkU = (s.k[0] - kin[0]) * U[0] + (s.k[1] - kin[1]) * U[1] + (s.k[2] - kin[2]) * U[2];
       const R Rr = ln.recoil ? (R(1) - mu) * R(ln.rec) * g1 : R(0);
-      const R xc = (x + g1 * dkU - Rr / bc) / (R(1) + Rr);
+      const R xc = M<R>::div(x + g1 * dkU - M<R>::div(Rr, bc), R(1) + Rr);
       const R wn = s.k[0] * s.lf.ux + s.k[1] * s.lf.uy + s.k[2] * s.lf.uz;
       s.x = (R(-ln.delta) + R(ln.mu) * rho * xc * (R(1) + R(pb.b_ref) * wn) + wn) * R(ln.inv_s);
     }
