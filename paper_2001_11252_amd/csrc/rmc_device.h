@@ -126,6 +126,7 @@ enum {
   J_GAUSS1 = 6,   // line, |x| >= 8: Box-Muller pair for the Gaussian
   J_GAUSS2 = 7,
   J_REJ = 6       // line, |x| < 8: rejection round i uses J_REJ+3i .. +2
+                  // (double) or J_REJ+2i, +1 (float)
 };
 
 // Uniforms of one event.  Double: draw j uses the word pair (2(j%2),
@@ -297,17 +298,34 @@ __device__ __forceinline__ bool sample_upar(R x, R a, EventRng<R> &rng, uint32_t
   const R hp = R(0.5 * PI_D);
   const R p1 = M<R>::div(th0 + hp, (R(1) - e0) * th0 + (R(1) + e0) * hp);
   const R u02 = u0 * u0;
+  // float: one uniform picks the piece and, rescaled within it, the angle
+  // (the same distribution with two uniforms per round, so that an event
+  // with one round fits in two Philox blocks); double: three per round
+  const R s1 = p1 > R(0) ? M<R>::div(th0 + hp, p1) : R(0);
+  const R s2 = p1 < R(1) ? M<R>::div(hp - th0, R(1) - p1) : R(0);
   for (uint32_t it = 0; it < MAX_REJECT; ++it) {
-    const R r1 = rng.u(J_REJ + 3 * it);
-    const R r2 = rng.u(J_REJ + 3 * it + 1);
-    const R r3 = rng.u(J_REJ + 3 * it + 2);
-    R th, lim;
-    if (r1 < p1) {
-      th = -hp + r2 * (th0 + hp);
-      lim = R(0);
+    R th, lim, r3;
+    if constexpr (sizeof(R) == 4) {
+      const R r1 = rng.u(J_REJ + 2 * it);
+      r3 = rng.u(J_REJ + 2 * it + 1);
+      if (r1 < p1) {
+        th = -hp + r1 * s1;
+        lim = R(0);
+      } else {
+        th = th0 + (r1 - p1) * s2;
+        lim = u02;
+      }
     } else {
-      th = th0 + r2 * (hp - th0);
-      lim = u02;
+      const R r1 = rng.u(J_REJ + 3 * it);
+      const R r2 = rng.u(J_REJ + 3 * it + 1);
+      r3 = rng.u(J_REJ + 3 * it + 2);
+      if (r1 < p1) {
+        th = -hp + r2 * (th0 + hp);
+        lim = R(0);
+      } else {
+        th = th0 + r2 * (hp - th0);
+        lim = u02;
+      }
     }
     const R u = xa + a * M<R>::tan(th);
     if (r3 < M<R>::exp(lim - u * u)) {
