@@ -278,7 +278,10 @@ template <class R> struct Lane {
 template <class R> __device__ __forceinline__ void set_geom_dir(Lane<R> &s) {
   if constexpr (sizeof(R) == 4) {
     const double a = s.k[0], b = s.k[1], c = s.k[2];
-    const double inv = 1.0 / sqrt(a * a + b * b + c * c);
+    // |k|^2 = 1 + e with |e| of order the float rounding: 1/sqrt(1+e) by its
+    // series to e^3 (remainder below 2^-53 for |e| < 2^-16), else exactly
+    const double e = fma(a, a, fma(b, b, fma(c, c, -1.0)));
+    const double inv = fabs(e) < 0x1p-16 ? 1.0 + e * (-0.5 + e * (0.375 - 0.3125 * e)) : 1.0 / sqrt(1.0 + e);
     s.kd[0] = a * inv; s.kd[1] = b * inv; s.kd[2] = c * inv;
   } else {
     s.kd[0] = s.k[0]; s.kd[1] = s.k[1]; s.kd[2] = s.k[2];
