@@ -104,8 +104,10 @@ typedef struct {
 
 /* ------------------------------------------------------------- lifetime */
 /* Create a context on HIP device `device`; precision RMC_FP64 (all
- * physics in double) or RMC_FP32_BULK (frequency, direction and cross-
- * section work in float; position, path length and optical depths double). */
+ * physics in double, correctly rounded operations) or RMC_FP32_BULK
+ * (frequency, direction and cross-section work in float with the hardware
+ * transcendental and reciprocal instructions, a few ulp each; position,
+ * path length, optical depths and leaf traversal in double). */
 rmc_status rmc_create(rmc_ctx **out, int device, int precision);
 void rmc_destroy(rmc_ctx *ctx);
 const char *rmc_last_error(const rmc_ctx *ctx);

@@ -755,6 +755,9 @@ rmc_status rmc_add_observer(rmc_ctx *c, const double k[3], int nx, int ny, int n
   o.k.nx = nx;
   o.k.ny = ny;
   o.k.nbins = nbins;
+  o.k.su = nx / o.k.uspan;
+  o.k.sv = ny / o.k.vspan;
+  o.k.sx = nbins / o.k.xspan;
   o.n_elems = (size_t)nx * ny * nbins;
   const size_t esz = c->precision == RMC_FP32_BULK ? 4 : 8;
   HIPCHK(c, o.cube.ensure(o.n_elems * esz));

@@ -45,6 +45,7 @@ struct LineK {
 struct ObsK {
   double k[3], e1[3], e2[3];
   double u0, uspan, v0, vspan, x_min, xspan;
+  double su, sv, sx;   // nx/uspan, ny/vspan, nbins/xspan (float path binning)
   int nx, ny, nbins, pad;
   void *cube;      // [ny][nx][nbins], float or double by precision
 };

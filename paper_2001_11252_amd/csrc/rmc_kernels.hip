@@ -128,23 +128,28 @@ __device__ double ray_tau(const ProblemK &pb, const double p0[3], const double k
   return ray_walk<R, NL>(pb, p, k, x_ext, 0.0, 0u, tau_cut, stk, stride, ncross, c, sc, reuse, stop, may_stop);
 }
 
-// Pixel of position p in observer ob's image, -1 outside.
+// Pixel of position p in observer ob's image, -1 outside.  The double path
+// bins exactly as the oracle does (divide by the span); the float path
+// multiplies by the precomputed cells per unit (a point within an ulp of a
+// pixel edge may fall on the other side).
+template <bool FAST = false>
 __device__ __forceinline__ int pixel_of(const ObsK &ob, const double p[3]) {
 #pragma clang fp contract(off)
   const double q0 = p[0] - 0.5, q1 = p[1] - 0.5, q2 = p[2] - 0.5;
   const double u = q0 * ob.e1[0] + q1 * ob.e1[1] + q2 * ob.e1[2];
   const double v = q0 * ob.e2[0] + q1 * ob.e2[1] + q2 * ob.e2[2];
-  const double fu = (u - ob.u0) / ob.uspan * ob.nx;
-  const double fv = (v - ob.v0) / ob.vspan * ob.ny;
+  const double fu = FAST ? (u - ob.u0) * ob.su : (u - ob.u0) / ob.uspan * ob.nx;
+  const double fv = FAST ? (v - ob.v0) * ob.sv : (v - ob.v0) / ob.vspan * ob.ny;
   if (!(fu >= 0.0 && fu < ob.nx && fv >= 0.0 && fv < ob.ny)) return -1;
   const int ix = (int)floor(fu), iy = (int)floor(fv);
   if (ix >= ob.nx || iy >= ob.ny) return -1;
   return iy * ob.nx + ix;
 }
 
+template <bool FAST = false>
 __device__ __forceinline__ int bin_of(const ObsK &ob, double x) {
 #pragma clang fp contract(off)
-  const double fb = (x - ob.x_min) / ob.xspan * ob.nbins;
+  const double fb = FAST ? (x - ob.x_min) * ob.sx : (x - ob.x_min) / ob.xspan * ob.nbins;
   if (!(fb >= 0.0 && fb < ob.nbins)) return -1;
   const int b = (int)floor(fb);
   return b >= ob.nbins ? -1 : b;
@@ -210,8 +215,8 @@ __device__ void peel_all(const ProblemK &pb, const double p[3], const PeelSrc<R>
       const R b = R(pb.b_ref);
       xo = M<R>::div(s.x + wo + b * s.x * wo - s.w, R(1) + b * s.w);
     }
-    const int pix = pixel_of(ob, p);
-    const int bin = bin_of(ob, (double)xo);
+    const int pix = pixel_of<sizeof(R) == 4>(ob, p);
+    const int bin = bin_of<sizeof(R) == 4>(ob, (double)xo);
     if (pix < 0 || bin < 0) {
       ++cnt.peel_drop;
       continue;
