@@ -4,7 +4,13 @@
 //               with peel-off toward observers at each emission and
 //               scattering (Sect. 5.1); one packet per lane, lanes of a
 //               wave refilled from a global queue with one atomic per wave
-//               (ballot + mbcnt compaction of the idle lanes).
+//               (ballot + mbcnt compaction of the idle lanes).  Peel-off
+//               rays are walked through their first leaf here; the ones
+//               that go on are queued in the wave's region of the peel-off
+//               queue.
+// k_peel_drain  ray-cast pass over the queued peel-off rays after each
+//               transport launch (lanes refilled per ray), k_peel_reset
+//               its bookkeeping
 // k_trace       deterministic cell sequence of rays (probe)
 // k_tau         optical depth of rays to the domain border (probe)
 // k_image_fwd   peel-off image of fixed rays
@@ -183,7 +189,7 @@ struct PeelSink {
   unsigned long long *lost;   // pushes that found no room (never expected)
 };
 
-// Peel-off of one event toward every observer (Sect. 3.4).  DEFER: each ray
+// Peel-off of one event toward every observer (Sect. 5.1).  DEFER: each ray
 // is walked through its first leaf only (the scattering's own leaf, whose
 // record the lane already holds); a ray that goes on is queued for the
 // ray-cast pass.  Otherwise the whole ray is walked here.
