@@ -41,12 +41,18 @@ PEAK = {"fp32": 157.3, "fp64": 78.6}       # TFLOP/s, MI355X vector
 
 
 def kernel_source_digest():
-    """Digest of the device code (kernels and the header they include)."""
+    """Digest of the device code (kernels and the header they include),
+    comments and layout removed, so that only a change of the code itself
+    invalidates a traffic measurement."""
     import hashlib
+    import re
     h = hashlib.sha256()
     src = os.path.join(ROOT, "paper_2001_11252_amd", "csrc")
     for f in ("rmc_device.h", "rmc_kernels.hip"):
-        h.update(open(os.path.join(src, f), "rb").read())
+        text = open(os.path.join(src, f)).read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
