@@ -76,7 +76,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--slice", type=int, default=2048, help="loop iterations per lane per step")
+    ap.add_argument("--slice", type=int, default=8192, help="loop iterations per lane per step")
     ap.add_argument("--packets", type=int, default=1_000_000, help="packets queued")
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--tau0", type=float, default=1e6)

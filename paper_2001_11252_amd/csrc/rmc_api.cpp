@@ -1352,7 +1352,7 @@ rmc_status rmc_batch_autotune(rmc_ctx *const *P, int np, const uint64_t *seeds, 
   if (r) return r;
   const int blocks[] = {64, 128, 256};
   const int refills[] = {1, 8, 32};
-  const int slices[] = {256, 2048};
+  const int slices[] = {256, 2048, 8192};
   double best_rate = -1.0;
   int bb = c0->block, br = c0->refill, bs = c0->slice_iters;
   for (int b : blocks)

@@ -68,7 +68,7 @@ def test_batch_autotune_picks_a_valid_shape(orc):
     npk = [len(p.sources.x) for p in probs]
     seeds = [p.seed for p in probs]
     best = rmc.batch_autotune(ctxs, seeds, npk, trial_slices=2)
-    assert best["block"] in (64, 128, 256) and best["refill"] in (1, 8, 32) and best["slice_iters"] in (256, 2048)
+    assert best["block"] in (64, 128, 256) and best["refill"] in (1, 8, 32) and best["slice_iters"] in (256, 2048, 8192)
     # the tuned run gives the same packets as an untuned one
     rmc.batch_run(ctxs, seeds, npk)
     tuned = [c.get_packets() for c in ctxs]
