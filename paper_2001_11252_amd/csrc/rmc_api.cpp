@@ -755,6 +755,7 @@ rmc_status rmc_add_observer(rmc_ctx *c, const double k[3], int nx, int ny, int n
   o.k.nx = nx;
   o.k.ny = ny;
   o.k.nbins = nbins;
+  for (int d = 0; d < 3; ++d) o.k.kinv[d] = k[d] != 0.0 ? 1.0 / k[d] : 0.0;
   o.k.su = nx / o.k.uspan;
   o.k.sv = ny / o.k.vspan;
   o.k.sx = nbins / o.k.xspan;

@@ -46,6 +46,7 @@ struct ObsK {
   double k[3], e1[3], e2[3];
   double u0, uspan, v0, vspan, x_min, xspan;
   double su, sv, sx;   // nx/uspan, ny/vspan, nbins/xspan (float path binning)
+  double kinv[3];      // 1/k (0 where k is 0; float path ray walks)
   int nx, ny, nbins, pad;
   void *cube;      // [ny][nx][nbins], float or double by precision
 };
@@ -388,10 +389,12 @@ struct Cell {
 };
 
 // Distance along k from p to the face through which the packet leaves the
-// cell; exit axes are flagged in *emask.
+// cell; exit axes are flagged in *emask.  With kinv (1/k, float path only)
+// the per-axis distances are products instead of correctly rounded
+// quotients.
 __device__ __forceinline__ double exit_dist(const Cell &c, int L, const double p[3],
                                             const double k[3], double face[3], double lo[3],
-                                            double hi[3], int *emask) {
+                                            double hi[3], int *emask, const double *kinv = nullptr) {
   const double inv = ldexp(1.0, -L);
   const int s = 1 << (L - c.level);
   const int o[3] = {c.ox, c.oy, c.oz};
@@ -401,8 +404,8 @@ __device__ __forceinline__ double exit_dist(const Cell &c, int L, const double p
   for (int d = 0; d < 3; ++d) {
     lo[d] = (double)o[d] * inv;
     hi[d] = (double)(o[d] + s) * inv;
-    if (k[d] > 0.0) { face[d] = hi[d]; td[d] = (face[d] - p[d]) / k[d]; }
-    else if (k[d] < 0.0) { face[d] = lo[d]; td[d] = (face[d] - p[d]) / k[d]; }
+    if (k[d] > 0.0) { face[d] = hi[d]; td[d] = kinv ? (face[d] - p[d]) * kinv[d] : (face[d] - p[d]) / k[d]; }
+    else if (k[d] < 0.0) { face[d] = lo[d]; td[d] = kinv ? (face[d] - p[d]) * kinv[d] : (face[d] - p[d]) / k[d]; }
     else { face[d] = 0.0; td[d] = __builtin_inf(); }
     t = td[d] < t ? td[d] : t;
   }

@@ -68,7 +68,8 @@ struct RayStop {
 template <class R, int NL>
 __device__ double ray_walk(const ProblemK &pb, double p[3], const double k[3], double x_ext, double tau,
                            uint32_t steps, double tau_cut, int *stk, int stride, uint32_t *ncross, Cell &c,
-                           const StartCell<R> *sc, bool borrowed, RayStop &stop, bool may_stop) {
+                           const StartCell<R> *sc, bool borrowed, RayStop &stop, bool may_stop,
+                           const double *kinv = nullptr) {
   const R kr[3] = {(R)k[0], (R)k[1], (R)k[2]};
   bool first = borrowed;
   for (; steps < MAX_CROSS; ++steps) {
@@ -83,7 +84,7 @@ __device__ double ray_walk(const ProblemK &pb, double p[3], const double k[3], d
     }
     double face[3], lo[3], hi[3];
     int em;
-    const double te = exit_dist(c, pb.L, p, k, face, lo, hi, &em);
+    const double te = exit_dist(c, pb.L, p, k, face, lo, hi, &em, kinv);
     const double td = domain_dist_leaf(lf, pb.domain, pb.dom, p, k);
     ++*ncross;
     if (td <= te) {
@@ -120,7 +121,8 @@ __device__ double ray_walk(const ProblemK &pb, double p[3], const double k[3], d
 template <class R, int NL = MAX_LINES>
 __device__ double ray_tau(const ProblemK &pb, const double p0[3], const double k[3], double x_ext,
                           double tau_cut, int *stk, int stride, uint32_t *ncross,
-                          const StartCell<R> *sc, RayStop &stop, bool may_stop) {
+                          const StartCell<R> *sc, RayStop &stop, bool may_stop,
+                          const double *kinv = nullptr) {
   double p[3] = {p0[0], p0[1], p0[2]};
   Cell c;
   const bool reuse = sc && strictly_inside(*sc->c, pb.L, p);
@@ -131,7 +133,8 @@ __device__ double ray_tau(const ProblemK &pb, const double p0[3], const double k
     if (!int_coords(pb.L, p, k, X)) return 0.0;
     descend(pb.nodes, pb.L, 0, 0, X, stk, stride, c);
   }
-  return ray_walk<R, NL>(pb, p, k, x_ext, 0.0, 0u, tau_cut, stk, stride, ncross, c, sc, reuse, stop, may_stop);
+  return ray_walk<R, NL>(pb, p, k, x_ext, 0.0, 0u, tau_cut, stk, stride, ncross, c, sc, reuse, stop, may_stop,
+                         kinv);
 }
 
 // Pixel of position p in observer ob's image, -1 outside.  The double path
@@ -232,7 +235,8 @@ __device__ void peel_all(const ProblemK &pb, const double p[3], const PeelSrc<R>
     const size_t elem = (size_t)pix * ob.nbins + bin;
     RayStop rs;
     rs.stopped = false;
-    const double tau = ray_tau<R, NL>(pb, p, ob.k, (double)xo, TauCut<R>::v, stk, stride, &nc, sc, rs, DEFER);
+    const double tau = ray_tau<R, NL>(pb, p, ob.k, (double)xo, TauCut<R>::v, stk, stride, &nc, sc, rs, DEFER,
+                                      sizeof(R) == 4 ? ob.kinv : nullptr);
     if (DEFER) {
       // a ray that goes on past its first leaf is queued instead of
       // holding the wave here
@@ -827,7 +831,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DrainW
     opacity(pb, lf, x, kr, o);
     double face[3], lo[3], hi[3];
     int em;
-    const double te = exit_dist(c, pb.L, p, k, face, lo, hi, &em);
+    const double te = exit_dist(c, pb.L, p, k, face, lo, hi, &em, sizeof(R) == 4 ? pb.obs[oi].kinv : nullptr);
     const double td = domain_dist_leaf(lf, pb.domain, pb.dom, p, k);
     ++nc_prob;
     ++nc_all;
