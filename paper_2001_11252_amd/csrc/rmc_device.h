@@ -248,16 +248,16 @@ template <class R> __device__ __forceinline__ R voigt_h(R a, R x) {
 // dH/dx of the same form.
 template <class R> __device__ __forceinline__ R voigt_dhdx(R a, R x) {
   const R x2 = x * x;
-  const R z = (x2 - R(0.855)) / (x2 + R(3.42));
+  const R z = M<R>::div(x2 - R(0.855), x2 + R(3.42));
   R d = R(-2) * x * M<R>::exp(-x2);
   if (z > R(0)) {
     const R den = x2 + R(3.42);
-    const R dz = R(2) * x * R(4.275) / (den * den);
+    const R dz = M<R>::div(R(2) * x * R(4.275), den * den);
     const R P = ((R(5.674) * z - R(9.207)) * z + R(4.421)) * z + R(0.1117);
     const R dP = (R(17.022) * z - R(18.414)) * z + R(4.421);
-    const R f2 = R(1) + R(21) / x2, df2 = R(-42) / (x2 * x);
-    const R f3 = (a * R(1.0 / PI_D)) / (x2 + R(1));
-    const R df3 = -f3 * R(2) * x / (x2 + R(1));
+    const R f2 = R(1) + M<R>::div(R(21), x2), df2 = M<R>::div(R(-42), x2 * x);
+    const R f3 = M<R>::div(a * R(1.0 / PI_D), x2 + R(1));
+    const R df3 = M<R>::div(-f3 * R(2) * x, x2 + R(1));
     const R dq = dz * f2 * f3 * P + z * df2 * f3 * P + z * f2 * df3 * P + z * f2 * f3 * dP * dz;
     d += R(1.7724538509055160273) * dq;
   }

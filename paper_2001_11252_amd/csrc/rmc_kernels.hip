@@ -959,7 +959,7 @@ __global__ void k_image_fwd(ProblemK pb, int obs, int64_t n, const double *__res
     if (pix >= 0) {
       RayStop rs;
       const double tau = ray_tau<R>(pb, p, ob.k, x_ext[r], TauCut<double>::v, stk, blockDim.x, &nc, nullptr, rs,
-                                    false);
+                                    false, sizeof(R) == 4 ? ob.kinv : nullptr);
       if (tau < TauCut<double>::v) unsafeAtomicAdd(image + pix, w[r] * exp(-tau));
     }
   }
@@ -1000,7 +1000,9 @@ __global__ void __launch_bounds__(256) k_image_bwd(ProblemK pb, int obs, int64_t
     xr = x_ext[r];
     double tau = TauCut<double>::v;
     RayStop rs;
-    if (pix >= 0) tau = ray_tau<R>(pb, p0, ob.k, xr, TauCut<double>::v, stk, blockDim.x, &nc, nullptr, rs, false);
+    if (pix >= 0)
+      tau = ray_tau<R>(pb, p0, ob.k, xr, TauCut<double>::v, stk, blockDim.x, &nc, nullptr, rs, false,
+                       sizeof(R) == 4 ? ob.kinv : nullptr);
     g = (pix >= 0 && tau < TauCut<double>::v) ? -G[pix] * w[r] * exp(-tau) : 0.0;
     if (g != 0.0) {
       // replay the ray (same traversal as the forward pass)
@@ -1026,7 +1028,7 @@ __global__ void __launch_bounds__(256) k_image_bwd(ProblemK pb, int obs, int64_t
       opacity(pb, lf, xr, kr, o);
       double face[3], lo[3], hi[3];
       int em;
-      const double te = exit_dist(c, pb.L, p, k, face, lo, hi, &em);
+      const double te = exit_dist(c, pb.L, p, k, face, lo, hi, &em, sizeof(R) == 4 ? pb.obs[obs].kinv : nullptr);
       const double td = domain_dist_leaf(lf, pb.domain, pb.dom, p, k);
       const double seg = td <= te ? td : te;
       const R b = R(pb.b_ref);
@@ -1038,7 +1040,7 @@ __global__ void __launch_bounds__(256) k_image_bwd(ProblemK pb, int obs, int64_t
           const LineK &ln = pb.lines[i];
           const R a = R(ln.alpha) * lf.irho;
           sn += R(ln.kfac) * voigt_h<R>(a, o.x[i]);
-          const R dxdw = -lf.irho * R(ln.inv_mu) * R(ln.s) * (R(1) + b * (R)xr) / (den * den);
+          const R dxdw = M<R>::div(-lf.irho * R(ln.inv_mu) * R(ln.s) * (R(1) + b * (R)xr), den * den);
           sv += R(ln.kfac) * voigt_dhdx<R>(a, o.x[i]) * dxdw;
         }
       }
