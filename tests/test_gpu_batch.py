@@ -108,3 +108,38 @@ def test_batch_stream_equals_batch_run(orc):
         pa, pb_ = ca.get_packets(), cb.get_packets()
         for k in pa:
             assert np.array_equal(pa[k], pb_[k]), k
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_with_observers_equals_single_runs(orc, prec):
+    # problems with different observer counts and line sets in one batch:
+    # the deferred peel-off rays of every problem land in that problem's
+    # cubes (queue entries carry their problem and observer)
+    from paper_2001_11252_amd import rmc
+    s0 = lambda ln, T: orc.line_quantities(ln, T)["sigma0"]
+    probs = []
+    for i, (tau0, nobs) in enumerate(((3e3, 1), (1e4, 2), (1e3, 3), (5e3, 2))):
+        pb = W.static_sphere(s0, tau0, 1e4, 1500 + 500 * i, level=3 + i % 2, tau_dust=0.3)
+        pb.gas.v[:] = np.random.default_rng(i).standard_normal((pb.mesh.n, 3)) * 10e5
+        dirs = [(0.0, 0.0, 1.0), (0.6, 0.0, 0.8), (0.0, -0.8, 0.6)][:nobs]
+        pb.observers = [W.Observer(d, 8, 8, 10, (-0.5, 0.5, -0.5, 0.5), -25, 25) for d in dirs]
+        pb.seed = 100 + i
+        probs.append(pb)
+    npk = [len(p.sources.x) for p in probs]
+    seeds = [p.seed for p in probs]
+    ctxs = [rmc.Context.from_problem(p, prec) for p in probs]
+    ctxs[0].set_option(rmc.OPT_SLICE_ITERS, 64)
+    per, tot = rmc.batch_run(ctxs, seeds, npk)
+    assert tot["peel_deferred"] > 0
+    for p, c, st, n in zip(probs, ctxs, per, npk):
+        single = rmc.Context.from_problem(p, prec)
+        s1 = single.run(p.seed, 0, n)
+        pa, pb_ = c.get_packets(), single.get_packets()
+        for k in pa:
+            assert np.array_equal(pa[k], pb_[k]), (p.name, k)
+        for k in ("scatterings", "crossings", "peel_rays", "peel_crossings", "peel_dropped"):
+            assert st[k] == s1[k], (p.name, k)
+        for o in range(len(p.observers)):
+            ca, cb = c.get_cube(o), single.get_cube(o)
+            assert ca.sum() > 0
+            assert np.allclose(ca, cb, rtol=1e-5 if prec == "fp32" else 1e-12, atol=0), (p.name, o)
