@@ -294,6 +294,33 @@ def test_deferred_peel_off_matches_inline(rmc, orc, prec):
         assert np.allclose(ca, cb, rtol=1e-5 if prec == "fp32" else 1e-12, atol=0)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_deferred_peel_off_in_a_periodic_slab(rmc, orc, prec):
+    # inclined observers see rays that wrap through the periodic x and y
+    # borders many times; the ray-cast pass wraps them as the inline walk
+    pb = W.static_slab(s0(orc), 1e3, 1e4, 3000, level=3, tau_dust=0.2)
+    pb.gas.v[:] = np.random.default_rng(8).standard_normal((pb.mesh.n, 3)) * 20e5
+    pb.observers = [W.Observer((0.6, 0.0, 0.8), 8, 8, 12, (-0.5, 0.5, -0.5, 0.5), -30, 30),
+                    W.Observer((0.48, 0.64, 0.6), 8, 8, 12, (-0.5, 0.5, -0.5, 0.5), -30, 30)]
+    a = rmc.Context.from_problem(pb, prec)
+    a.set_option(rmc.OPT_PEEL_DEFER, 0)
+    sa = a.run(31, 0, 3000)
+    b = rmc.Context.from_problem(pb, prec)
+    b.set_option(rmc.OPT_SLICE_ITERS, 32)
+    sb = b.run(31, 0, 3000)
+    assert sb["peel_deferred"] > 0.1 * sb["peel_rays"]
+    pa, pbk = a.get_packets(), b.get_packets()
+    for k in pa:
+        assert np.array_equal(pa[k], pbk[k]), k
+    for k in ("scatterings", "crossings", "peel_rays", "peel_crossings", "peel_dropped"):
+        assert sa[k] == sb[k], k
+    assert sa["peel_crossings"] > 3 * sa["peel_rays"]
+    for o in range(2):
+        ca, cb = a.get_cube(o), b.get_cube(o)
+        assert ca.sum() > 0
+        assert np.allclose(ca, cb, rtol=1e-5 if prec == "fp32" else 1e-12, atol=0)
+
+
 def test_error_paths(rmc, orc):
     ctx = rmc.Context("fp64")
     with pytest.raises(rmc.RmcError) as e:
