@@ -120,6 +120,32 @@ def stream_rate(ctx, steps, warm, tag):
     return wall, tot, kms
 
 
+def oracle_transport_baseline(a, probs, packets_each, max_events):
+    """The oracle on a bounded sample: packets_each packets of every problem,
+    each stopped after max_events interactions; FP64, full peel-off rays."""
+    if a.no_cpu_baseline:
+        return None
+    from oracle import oracle as O
+    cores = max(1, min(16, os.cpu_count() or 1))
+    scat, dt, setup = 0, 0.0, 0.0
+    for p in probs:
+        n = min(packets_each, len(p.sources.x))
+        # the oracle rebuilds its leaf hash map on every call: time that
+        # with a one-event call and subtract it
+        t0 = time.perf_counter()
+        O.run(p, p.seed, first=0, n=1, threads=1, max_events=1, with_cubes=False)
+        t_set = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        r = O.run(p, p.seed, first=0, n=n, threads=cores, max_events=max_events)
+        dt += max(time.perf_counter() - t0 - t_set, 1e-9)
+        setup += t_set
+        scat += r["stats"]["scatterings"]
+    return {"value": scat / dt, "unit": "scatterings/s", "cores": cores, "kind": "oracle",
+            "sample": f"{packets_each} packets of each of {len(probs)} problem(s), each stopped after "
+                      f"{max_events} interactions: {scat} scatterings in {dt:.1f} s (set-up {setup:.1f} s "
+                      f"subtracted)"}
+
+
 def transport_roofline(tot, kms, prec, kernel):
     n = len(kms)
     avg_ms = sum(kms) / n
@@ -142,13 +168,15 @@ def bench_shell(a, rmc, W):
     ctx.stream_begin(pb.seed, 0, 10_000_000)
     wall, tot, kms = stream_rate(ctx, a.steps, a.warmup, "shell fp32")
     ctx.close()
+    cpu = oracle_transport_baseline(a, [pb], 8 * max(1, min(16, os.cpu_count() or 1)), 20000)
     return _line("scatterings/s + ray-cell crossings/s (1 GPU), FP32", tot["scatterings"] / wall, "scatterings/s",
                  a.steps, a.warmup, 1e3 * wall / a.steps, "f32",
                  {"workload": f"outflowing_shell_vmax{int(a.vmax)}_tau1e7_{pb.mesh.n}_leaves_3x256x256x200",
                   "packets_queued": 10_000_000, "iterations_per_lane_per_step": a.slice, "parallelism": "none"},
                  transport_roofline(tot, kms, "fp32", "k_transport<float,false,true,1>"),
                  crossings_per_s=(tot["crossings"] + tot["peel_crossings"]) / wall,
-                 transport_ms_avg=sum(kms) / len(kms), peel_pass_ms_avg=tot["peel_pass_ms"] / len(kms))
+                 transport_ms_avg=sum(kms) / len(kms), peel_pass_ms_avg=tot["peel_pass_ms"] / len(kms),
+                 cpu_baseline=cpu)
 
 
 def bench_batch(a, rmc, W):
@@ -169,12 +197,13 @@ def bench_batch(a, rmc, W):
     wall, tot, kms = stream_rate(ctxs[0], a.steps, a.warmup, "batch fp32")
     for c in ctxs:
         c.close()
+    cpu = oracle_transport_baseline(a, probs, 4, 20000)
     return _line("scatterings/s + ray-cell crossings/s (1 GPU), FP32", tot["scatterings"] / wall, "scatterings/s",
                  a.steps, a.warmup, 1e3 * wall / a.steps, "f32",
                  {"workload": "batch_64_problems_slab_sphere_lya_mgii", "problems": len(probs),
                   "packets": int(sum(npk)), "tuned": best, "parallelism": "none"},
                  transport_roofline(tot, kms, "fp32", "k_transport<float,true,false,4>"),
-                 crossings_per_s=(tot["crossings"] + tot["peel_crossings"]) / wall)
+                 crossings_per_s=(tot["crossings"] + tot["peel_crossings"]) / wall, cpu_baseline=cpu)
 
 
 def bench_adjoint(a, rmc, W):
@@ -220,13 +249,37 @@ def bench_adjoint(a, rmc, W):
     gbs_f = cf * 28.0 / (mf * 1e-3) / 1e9
     gbs_b = cb * (28.0 + 48.0) / (mb * 1e-3) / 1e9
     ctx.close()
+    cpu = None
+    if not a.no_cpu_baseline:
+        # the oracle on a bounded sample of the same rays (image and exact
+        # gradient in one call: one walk per ray plus the gradient of each
+        # crossing, counted twice like the GPU's forward + backward); its
+        # set-up (hash map of the leaves), timed with a one-ray call, is
+        # subtracted
+        from oracle import oracle as O
+        import numpy as np
+        cores = max(1, min(16, os.cpu_count() or 1))
+        ns = 20000
+        ob = pb.observers[0]
+        t0 = time.perf_counter()
+        O.raycast_image(pb, ob, r["orig"][:1], r["x_ext"][:1], r["w"][:1], pb.meta["grad_image"], threads=cores)
+        t_setup = time.perf_counter() - t0
+        nc = np.zeros(1, dtype=np.int64)
+        t0 = time.perf_counter()
+        O.raycast_image(pb, ob, r["orig"][:ns], r["x_ext"][:ns], r["w"][:ns], pb.meta["grad_image"], threads=cores,
+                        crossings=nc)
+        dt = max(time.perf_counter() - t0 - t_setup, 1e-9)
+        cpu = {"value": 2 * int(nc[0]) / dt, "unit": "crossings/s", "cores": cores, "kind": "oracle",
+               "sample": f"first {ns} rays, image + exact gradient: {int(nc[0])} crossings walked (counted twice) "
+                         f"in {dt:.1f} s after a {t_setup:.1f} s set-up"}
     return _line("adjoint ray-cell crossings/s (forward image + backward gradients, 1 GPU), FP32 records",
                  (cf + cb) / t_all, "crossings/s", n, a.warmup, 1e3 * t_all / n, "f32",
                  {"workload": f"galaxy_{pb.mesh.n}_leaves_{len(r['x_ext'])}_rays_512x512", "parallelism": "none"},
                  {"bound": "hbm", "achieved": gbs_f, "peak": 8000.0, "unit": "GB/s", "frac": gbs_f / 8000.0,
                   "traffic": None, "kernel": "k_image_fwd<float>"},
                  forward={"crossings_per_launch": cf / n, "ms": mf / n, "GBps_algorithmic": gbs_f},
-                 backward={"crossings_per_launch": cb / n, "ms": mb / n, "GBps_algorithmic": gbs_b})
+                 backward={"crossings_per_launch": cb / n, "ms": mb / n, "GBps_algorithmic": gbs_b},
+                 cpu_baseline=cpu)
 
 
 def main():

@@ -972,7 +972,7 @@ int orc_run(const orc_problem *pb, int64_t n_src, const double *src_pos, const d
 int orc_raycast_image(const orc_problem *pb, const orc_observer *ob, int64_t n_rays,
                       const double *orig, const double *x_ext, const double *w, double *image,
                       const double *grad_image, double *g_nhi, double *g_kd, double *g_vlos,
-                      int n_threads) {
+                      int n_threads, int64_t *n_crossings) {
   Problem P;
   int rc = setup_problem(pb, P);
   if (rc) return rc;
@@ -982,6 +982,7 @@ int orc_raycast_image(const orc_problem *pb, const orc_observer *ob, int64_t n_r
   std::vector<std::vector<Rec>> recs(grad_image ? n_rays : 0);
   int nt = nthreads_of(n_threads);
   std::atomic<int64_t> next(0);
+  std::atomic<int64_t> total_cross(0);
   auto work = [&]() {
     while (true) {
       int64_t r = next.fetch_add(1);
@@ -994,6 +995,7 @@ int orc_raycast_image(const orc_problem *pb, const orc_observer *ob, int64_t n_r
       tau[r] = ray_tau(P, p, ob->k, dnu, &nc, [&](int64_t c, double seg, const Opac &) {
         cross.emplace_back(c, seg);
       });
+      total_cross += nc;
       if (!grad_image || pix[r] < 0) continue;
       /* dL/dtau_r = -G_p w_r exp(-tau_r); dtau_r/dtheta_c summed over
        * the crossings of c (one per visit) */
@@ -1032,6 +1034,7 @@ int orc_raycast_image(const orc_problem *pb, const orc_observer *ob, int64_t n_r
         g_vlos[e.c] += e.gv;
       }
   }
+  if (n_crossings) *n_crossings = total_cross.load();
   return 0;
 }
 

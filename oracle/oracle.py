@@ -85,7 +85,7 @@ def lib():
         L.orc_run.argtypes = [P, C.c_int64, P, P, P, C.c_uint64, C.c_int64, C.c_int64, C.c_int,
                               P, P, P, P, P, P, P, P, C.c_int, P]
         L.orc_raycast_image.restype = C.c_int
-        L.orc_raycast_image.argtypes = [P, P, C.c_int64, P, P, P, P, P, P, P, P, C.c_int]
+        L.orc_raycast_image.argtypes = [P, P, C.c_int64, P, P, P, P, P, P, P, P, C.c_int, P]
         _LIB = L
     return _LIB
 
@@ -263,10 +263,11 @@ def run(pb, seed, first=0, n=None, threads=0, forward_only=False, max_events=0, 
                 cubes=cubes, stats=st.as_dict())
 
 
-def raycast_image(pb, observer, orig, x_ext, w, grad_image=None, threads=0):
+def raycast_image(pb, observer, orig, x_ext, w, grad_image=None, threads=0, crossings=None):
     """Peel-off image of fixed rays toward `observer` and, if grad_image is
     given, the exact gradient of sum(grad_image * image) with respect to the
-    per-leaf n_HI, kappa_d and v_los = k_obs . v."""
+    per-leaf n_HI, kappa_d and v_los = k_obs . v.  crossings (optional, a
+    one-element int64 array) receives the ray-cell segments walked."""
     P = _Prob(pb)
     ob = _obs_struct(observer)
     o = np.ascontiguousarray(orig, dtype=np.float64).reshape(-1, 3)
@@ -279,7 +280,8 @@ def raycast_image(pb, observer, orig, x_ext, w, grad_image=None, threads=0):
     gk = np.zeros(nl) if G is not None else None
     gv = np.zeros(nl) if G is not None else None
     rc = lib().orc_raycast_image(C.byref(P.s), C.byref(ob), len(o), _ptr(o), _ptr(x), _ptr(ww),
-                                 _ptr(img), _ptr(G), _ptr(gn), _ptr(gk), _ptr(gv), _threads(threads))
+                                 _ptr(img), _ptr(G), _ptr(gn), _ptr(gk), _ptr(gv), _threads(threads),
+                                 None if crossings is None else _ptr(crossings))
     if rc:
         raise RuntimeError(f"orc_raycast_image failed: {rc}")
     if G is None:

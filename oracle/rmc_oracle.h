@@ -114,13 +114,15 @@ int orc_run(const orc_problem *pb, int64_t n_src, const double *src_pos,
             int32_t *n_scat, double *path_out, int n_threads, orc_stats *stats);
 
 /* peel-off image of fixed rays and its exact gradient.
- * image: [ny*nx] (frequency-integrated); grad_image may be NULL, else the
- * gradients of L = sum_p grad_image[p] * image[p] with respect to per-leaf
- * n_HI, kappa_d and v_los = k_obs . v are written to g_nhi, g_kd, g_vlos. */
+ * image: [ny*nx] (each ray at its own x_ext); grad_image may be NULL, else
+ * the gradients of L = sum_p grad_image[p] * image[p] with respect to
+ * per-leaf n_HI, kappa_d and v_los = k_obs . v are written to g_nhi, g_kd,
+ * g_vlos.  n_crossings (may be NULL) receives the ray-cell segments walked. */
 int orc_raycast_image(const orc_problem *pb, const orc_observer *ob, int64_t n_rays,
                       const double *orig, const double *x_ext, const double *w,
                       double *image, const double *grad_image,
-                      double *g_nhi, double *g_kd, double *g_vlos, int n_threads);
+                      double *g_nhi, double *g_kd, double *g_vlos, int n_threads,
+                      int64_t *n_crossings);
 
 #ifdef __cplusplus
 }
