@@ -259,7 +259,7 @@ def bench_adjoint(a, rmc, W):
         from oracle import oracle as O
         import numpy as np
         cores = max(1, min(16, os.cpu_count() or 1))
-        ns = 20000
+        ns = 2_000_000
         ob = pb.observers[0]
         t0 = time.perf_counter()
         O.raycast_image(pb, ob, r["orig"][:1], r["x_ext"][:1], r["w"][:1], pb.meta["grad_image"], threads=cores)

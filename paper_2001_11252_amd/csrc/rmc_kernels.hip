@@ -72,16 +72,23 @@ __device__ double ray_walk(const ProblemK &pb, double p[3], const double k[3], d
                            const double *kinv = nullptr) {
   const R kr[3] = {(R)k[0], (R)k[1], (R)k[2]};
   bool first = borrowed;
+  bool start = true;
   for (; steps < MAX_CROSS; ++steps) {
     const LeafRec<R> lf = first ? *sc->lf : load_leaf<R>(pb.leaves, c.leaf);
     Opac<R, NL> o;
     opacity(pb, lf, x_ext, kr, o);
-    if (lf.bnd == R(0) && tau + (double)o.ktot * inner_dist(c, pb.L, p) >= tau_cut) {
-      // the cut is reached inside this leaf whatever the exit distance
-      ++*ncross;
-      tau = tau_cut;
-      break;
+    // Only the start point can lie inside a leaf: later leaves are entered
+    // on a face (inner distance 0, where the test is tau >= tau_cut, which
+    // the previous leaf already ruled out).
+    if (start && lf.bnd == R(0)) {
+      if (tau + (double)o.ktot * inner_dist(c, pb.L, p) >= tau_cut) {
+        // the cut is reached inside this leaf whatever the exit distance
+        ++*ncross;
+        tau = tau_cut;
+        break;
+      }
     }
+    start = false;
     double face[3], lo[3], hi[3];
     int em;
     const double te = exit_dist(c, pb.L, p, k, face, lo, hi, &em, kinv);
