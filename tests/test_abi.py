@@ -75,3 +75,16 @@ def test_context_creation_fails_loudly_without_gpu():
     from paper_2001_11252_amd import rmc
     with pytest.raises(rmc.RmcError):
         rmc.Context("fp64")
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # the benchmark runs on one GPU; asking for more exits with a message
+    # before touching a device
+    import subprocess
+    import sys
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr
