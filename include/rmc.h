@@ -140,7 +140,8 @@ rmc_status rmc_set_dust(rmc_ctx *ctx, double albedo, double g_hg);
 rmc_status rmc_set_domain(rmc_ctx *ctx, int kind, const double params[4]);
 /* Packet initial conditions (the paper's PPIC lists, Sect. 2): pos[3n],
  * dir[3n] unit vectors or NULL for isotropic emission, x_ext[n].  Packet i
- * is identified by its index i, which keys its random numbers. */
+ * is identified by its index i, which keys its random numbers.  A
+ * position outside the unit cube is rejected with RMC_EINVAL. */
 rmc_status rmc_set_sources(rmc_ctx *ctx, int64_t n, const double *pos, const double *dir,
                            const double *x_ext, int mem);
 /* Peel-off observer (Sect. 5.1): direction k_obs (unit), image nx by ny

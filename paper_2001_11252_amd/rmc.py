@@ -341,17 +341,21 @@ class Context:
     def from_problem(cls, pb, precision="fp64", device=0, observers=True, sources=True):
         """Configure a context from a workloads.Problem."""
         c = cls(precision, device)
-        c.set_mesh(pb.mesh.level, pb.mesh.ijk, pb.mesh.box_cm)
-        c.set_lines(pb.lines, pb.T_ref)
-        c.set_gas(pb.gas.n_hi, pb.gas.T, pb.gas.v, pb.gas.kappa_d)
-        c.set_dust(pb.dust.albedo, pb.dust.g)
-        c.set_domain(pb.domain.kind, pb.domain.params)
-        if sources:
-            c.set_sources(pb.sources.pos, pb.sources.x, pb.sources.dir)
-            c.n_src = len(pb.sources.x)
-        if observers:
-            for o in pb.observers:
-                c.add_observer(o.k, o.nx, o.ny, o.nbins, o.fov, o.x_min, o.x_max)
+        try:
+            c.set_mesh(pb.mesh.level, pb.mesh.ijk, pb.mesh.box_cm)
+            c.set_lines(pb.lines, pb.T_ref)
+            c.set_gas(pb.gas.n_hi, pb.gas.T, pb.gas.v, pb.gas.kappa_d)
+            c.set_dust(pb.dust.albedo, pb.dust.g)
+            c.set_domain(pb.domain.kind, pb.domain.params)
+            if sources:
+                c.set_sources(pb.sources.pos, pb.sources.x, pb.sources.dir)
+                c.n_src = len(pb.sources.x)
+            if observers:
+                for o in pb.observers:
+                    c.add_observer(o.k, o.nx, o.ny, o.nbins, o.fov, o.x_min, o.x_max)
+        except BaseException:
+            c.close()
+            raise
         return c
 
 

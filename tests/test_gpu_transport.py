@@ -321,6 +321,42 @@ def test_deferred_peel_off_in_a_periodic_slab(rmc, orc, prec):
         assert np.allclose(ca, cb, rtol=1e-5 if prec == "fp32" else 1e-12, atol=0)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_degenerate_inputs(rmc, orc, prec):
+    # an empty range, a single packet, a one-leaf mesh, and sources outside
+    # the domain
+    pb = W.static_sphere(s0(orc), 3.0, 1e4, 300, level=0, tau_dust=0.3)
+    pb.observers = [W.Observer((0.0, 0.0, 1.0), 4, 4, 8, (-0.5, 0.5, -0.5, 0.5), -20, 20)]
+    ctx = rmc.Context.from_problem(pb, prec)
+    st = ctx.run(5, 0, 0)
+    assert st["emitted"] == 0 and st["scatterings"] == 0
+    st1 = ctx.run(5, 17, 1)
+    check_conservation(st1, 1)
+    # one leaf: the FP64 path follows the oracle packet by packet
+    ref = orc.run(pb, 5, threads=0)
+    st = ctx.run(5, 0, 300)
+    check_conservation(st, 300)
+    out = ctx.get_packets()
+    same = (out["status"] == ref["status"]) & (out["n_scat"] == ref["n_scat"])
+    assert same.mean() > (0.99 if prec == "fp64" else 0.0)
+    assert np.all(out["status"] > 0)
+    # a source outside the box is refused; one in a box corner outside the
+    # sphere is walked like the oracle walks it
+    pb2 = W.static_sphere(s0(orc), 3.0, 1e4, 2, level=2)
+    pb2.sources = W.Sources(np.array([[1.5, 0.5, 0.5], [0.02, 0.02, 0.02]]), np.zeros(2))
+    with pytest.raises(rmc.RmcError, match="outside the box"):
+        rmc.Context.from_problem(pb2, prec)
+    pb2.sources = W.Sources(np.array([[0.98, 0.5, 0.5], [0.02, 0.02, 0.02]]), np.zeros(2))
+    c2 = rmc.Context.from_problem(pb2, prec)
+    st2 = c2.run(3, 0, 2)
+    check_conservation(st2, 2)
+    o2 = c2.get_packets()
+    assert np.all(o2["status"] > 0)
+    if prec == "fp64":
+        r2 = orc.run(pb2, 3, threads=0)
+        assert np.array_equal(o2["status"], r2["status"]) and np.array_equal(o2["n_scat"], r2["n_scat"])
+
+
 def test_error_paths(rmc, orc):
     ctx = rmc.Context("fp64")
     with pytest.raises(rmc.RmcError) as e:
