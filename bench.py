@@ -37,6 +37,7 @@ FLOP_PER_CROSSING = 110.0
 # Algorithmic HBM bytes: one leaf record per segment (24 B float, 48 B
 # double) plus one 4 B node entry.
 BYTES_PER_CROSSING = {"fp32": 28.0, "fp64": 52.0}
+MATCH_SLICE = 1024          # loop iterations per launch of the FP32/FP64 comparison sample
 PEAK = {"fp32": 157.3, "fp64": 78.6}       # TFLOP/s, MI355X vector
 
 
@@ -79,6 +80,8 @@ def parse():
     ap.add_argument("--slice", type=int, default=8192, help="loop iterations per lane per step")
     ap.add_argument("--packets", type=int, default=1_000_000, help="packets queued")
     ap.add_argument("--fp64-steps", type=int, default=5)
+    ap.add_argument("--match-launches", type=int, default=32,
+                    help="launches of the untimed FP32/FP64 comparison sample (0: skip)")
     ap.add_argument("--tau0", type=float, default=1e6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-packets", type=int, default=0, help="oracle packets (0: eight per core)")
@@ -282,6 +285,34 @@ def bench_adjoint(a, rmc, W):
                  cpu_baseline=cpu)
 
 
+def matched_spectra(early, launches):
+    """FP32 against FP64 on the packets each finished within the same loop
+    iterations per lane: escape fraction (two-proportion z), mean line
+    scatterings (z of the difference) and the escaped x_ext distributions
+    (two-sample KS)."""
+    import numpy as np
+    from scipy import stats
+    out = {"sample": f"packets finished within {launches * MATCH_SLICE} loop iterations per lane "
+                     f"({launches} launches of {MATCH_SLICE}, untimed) in each precision"}
+    f, d = early["fp32"], early["fp64"]
+    n_f, n_d = len(f["status"]), len(d["status"])
+    out["finished"] = {"fp32": n_f, "fp64": n_d}
+    out["slices_cut"] = {"fp32": f["slices_cut"], "fp64": d["slices_cut"]}
+    if n_f < 20 or n_d < 20:
+        return out
+    e_f, e_d = f["status"] == 1, d["status"] == 1
+    p_f, p_d = e_f.mean(), e_d.mean()
+    p = (e_f.sum() + e_d.sum()) / (n_f + n_d)
+    se = np.sqrt(max(p * (1 - p), 1e-300) * (1 / n_f + 1 / n_d))
+    out["escape_fraction"] = {"fp32": float(p_f), "fp64": float(p_d), "z": float((p_f - p_d) / se)}
+    m_f, m_d = f["n_scat"].mean(), d["n_scat"].mean()
+    se = np.sqrt(f["n_scat"].var() / n_f + d["n_scat"].var() / n_d)
+    out["mean_line_scatterings"] = {"fp32": float(m_f), "fp64": float(m_d), "z": float((m_f - m_d) / max(se, 1e-300))}
+    if e_f.sum() >= 20 and e_d.sum() >= 20:
+        out["escaped_x_ks_p"] = float(stats.ks_2samp(f["x"][e_f], d["x"][e_d]).pvalue)
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -304,6 +335,7 @@ def main():
           f"{a.slice} iterations/lane/step", file=sys.stderr, flush=True)
 
     setup = {}
+    early = {}
 
     def measure(prec, nsteps):
         t0 = time.perf_counter()
@@ -312,6 +344,12 @@ def main():
         setup[prec] = time.perf_counter() - t0
         ctx.set_stream(torch.cuda.current_stream())
         ctx.set_option(rmc.OPT_SLICE_ITERS, a.slice)
+        # a first stream, abandoned after two launches, lets the peel-off
+        # queue grow to its working size (it grows after a launch in which
+        # a wave ended its slice early for room) before the measured stream
+        ctx.stream_begin(pb.seed, 0, P)
+        for _ in range(2):
+            ctx.stream_step()
         ctx.stream_begin(pb.seed, 0, P)
         for _ in range(warm):
             ctx.stream_step()
@@ -328,6 +366,21 @@ def main():
         wall = time.perf_counter() - t0
         print(f"# {prec}: {nsteps} steps in {wall:.3f} s, transport ms {[round(k, 1) for k in kms]}, "
               f"remaining {rem}, stats {tot}", file=sys.stderr, flush=True)
+        if a.match_launches:
+            # sample for the FP32/FP64 comparison (untimed): the packets
+            # finished within the same number of loop iterations per lane in
+            # either precision, so both samples are selected alike (short
+            # walks first); launches short enough that no wave runs out of
+            # queue room, which would end its slice early
+            ctx.set_option(rmc.OPT_SLICE_ITERS, MATCH_SLICE)
+            ctx.stream_begin(pb.seed, 0, P)
+            cut = 0
+            for _ in range(a.match_launches):
+                cut += ctx.stream_step()[0]["slices_cut"]
+            pk = ctx.get_packets()
+            fin = pk["status"] > 0
+            early[prec] = {"status": pk["status"][fin], "x": pk["x"][fin], "n_scat": pk["n_scat"][fin],
+                           "slices_cut": cut}
         ctx.close()
         return wall, tot, kms
 
@@ -377,6 +430,7 @@ def main():
                       "transport_ms_avg": sum(k) / len(k),
                       "peel_pass_ms_avg": t["peel_pass_ms"] / len(k),
                       "peel_rays_deferred_per_step": t["peel_deferred"] / len(k),
+                      "slices_cut": t["slices_cut"],
                       "peel_pass_crossings_per_s": pass_cross / max(t["peel_pass_ms"] * 1e-3, 1e-30),
                       "hbm_GBps_algorithmic": (t["crossings"] + t["peel_crossings"]) * BYTES_PER_CROSSING[prec]
                       / ((sum(k) + t["peel_pass_ms"]) * 1e-3) / 1e9,
@@ -407,6 +461,8 @@ def main():
         # validation, leaf records, uploads (seconds)
         "setup_s": setup,
     }
+    if len(early) == 2:
+        line["matched_spectra"] = matched_spectra(early, a.match_launches)
     if not a.no_cpu_baseline:
         from oracle import oracle as O
         cores = max(1, min(16, os.cpu_count() or 1))

@@ -100,6 +100,11 @@ typedef struct {
   double kernel_ms;           /* device time of the transport launch(es)      */
   double peel_pass_ms;        /* device time of the ray-cast passes over the
                                  deferred peel-off rays                       */
+  uint64_t slices_cut;        /* transport launches in which some wave ended
+                                 its slice early because its region of the
+                                 peel-off queue was nearly full (the queue
+                                 grows after such a launch; results do not
+                                 change, only the work per launch)           */
 } rmc_run_stats;
 
 /* ------------------------------------------------------------- lifetime */
@@ -166,13 +171,17 @@ rmc_status rmc_run(rmc_ctx *ctx, uint64_t seed, int64_t first, int64_t n,
  * packets from the queue.  step reports the work of that launch (emitted =
  * packets finished in it) and the packets not finished yet; end runs the
  * remaining launches and reports the totals of the range.  rmc_run is
- * begin + steps + end.  Results do not depend on how a run is sliced. */
+ * begin + steps + end.  Results do not depend on how a run is sliced.
+ * begin on a context whose stream is still open abandons that stream (its
+ * packets keep no results; cubes keep what it deposited). */
 rmc_status rmc_stream_begin(rmc_ctx *ctx, uint64_t seed, int64_t first, int64_t n);
 rmc_status rmc_stream_step(rmc_ctx *ctx, rmc_run_stats *slice, int64_t *remaining);
 rmc_status rmc_stream_end(rmc_ctx *ctx, rmc_run_stats *total);
 /* Per-packet results of the last run (any pointer may be NULL): status,
  * escaped x_ext, final direction k[3n], final position pos[3n], line
- * scattering count, path length in box units. */
+ * scattering count, path length in box units.  While a stream is open,
+ * packets not finished yet have status RMC_ST_NONE (their other fields are
+ * undefined). */
 rmc_status rmc_get_packets(rmc_ctx *ctx, int32_t *status, double *x_out, double *k_out,
                            double *pos_out, int32_t *n_scat, double *path_out, int mem);
 /* Histogram (counts) of x_ext of the escaped packets of the last run. */

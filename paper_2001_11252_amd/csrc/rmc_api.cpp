@@ -461,7 +461,10 @@ rmc_status ready(rmc_ctx *c, bool need_sources) {
   return RMC_OK;
 }
 
-rmc_status ensure_outputs(rmc_ctx *c, int64_t n) {
+// Output arrays for n packets; their statuses start at RMC_ST_NONE (set on
+// stream st, the one the transport runs on), so packets not finished yet
+// read as such.
+rmc_status ensure_outputs(rmc_ctx *c, int64_t n, hipStream_t st) {
   const size_t m = (size_t)std::max<int64_t>(n, 1);
   HIPCHK(c, c->o_status.ensure(m * 4));
   HIPCHK(c, c->o_nscat.ensure(m * 4));
@@ -471,6 +474,7 @@ rmc_status ensure_outputs(rmc_ctx *c, int64_t n) {
   HIPCHK(c, c->o_path.ensure(m * 8));
   HIPCHK(c, c->d_stats.ensure(N_STATS * 8));
   HIPCHK(c, c->d_next.ensure(8));
+  if (n > 0) HIPCHK(c, hipMemsetAsync(c->o_status.p, 0, (size_t)n * 4, st));
   return RMC_OK;
 }
 
@@ -503,13 +507,14 @@ void fill_stats(rmc_run_stats *s, const unsigned long long *h, double ms) {
   s->peel_deferred = 0;
   s->kernel_ms = ms;
   s->peel_pass_ms = 0.0;
+  s->slices_cut = 0;
 }
 
 }  // namespace
 
 extern "C" {
 
-int rmc_abi_version(void) { return 2; }
+int rmc_abi_version(void) { return 3; }
 
 rmc_status rmc_create(rmc_ctx **out, int device, int precision) {
   if (!out) return RMC_EINVAL;
@@ -787,6 +792,7 @@ void add_run_stats(rmc_run_stats &a, const rmc_run_stats &b) {
   a.scatterings += b.scatterings; a.dust_scatterings += b.dust_scatterings; a.crossings += b.crossings;
   a.peel_rays += b.peel_rays; a.peel_crossings += b.peel_crossings; a.peel_dropped += b.peel_dropped;
   a.peel_deferred += b.peel_deferred;
+  a.slices_cut += b.slices_cut;
   a.peel_pass_ms += b.peel_pass_ms;
   a.kernel_ms += b.kernel_ms;
 }
@@ -837,12 +843,18 @@ rmc_status layout_queue(rmc_ctx *c, unsigned long long n_regions) {
   return RMC_OK;
 }
 
+// Whether a wave may have ended its slice early for room: its region held
+// more than the capacity less one wave iteration's pushes.
+bool slice_cut(const rmc_ctx *c, unsigned long long max_region) {
+  const unsigned long long per_iter = 2ull * 64 * MAX_OBS;   // pushes one wave iteration can make
+  return max_region + per_iter > c->pq_cap;
+}
+
 // After a launch in which a wave ended its slice early because its region
 // was nearly full, enlarge the regions eightfold (up to PQ_MAX_BYTES) for
 // the next launches.
 rmc_status grow_queue(rmc_ctx *c, unsigned long long max_region) {
-  const unsigned long long per_iter = 2ull * 64 * MAX_OBS;   // pushes one wave iteration can make
-  if (max_region + per_iter <= c->pq_cap) return RMC_OK;
+  if (!slice_cut(c, max_region)) return RMC_OK;
   const unsigned long long max_cap =
       std::max<unsigned long long>(PQ_MAX_BYTES / peel_job_bytes() / c->pq_regions, PQ_FIRST_CAP);
   if (c->pq_cap >= max_cap) return RMC_OK;
@@ -955,6 +967,7 @@ rmc_status stream_step(rmc_ctx *c, rmc_run_stats *slice, int64_t *remaining) {
       c->s_open = false;
       return fail(c, RMC_EDEVICE, "peel-off queue: %llu rays found their region full", h[N_STATS + 2]);
     }
+    z.slices_cut = slice_cut(c, h[N_STATS + 1]) ? 1 : 0;
     rmc_status r = grow_queue(c, h[N_STATS + 1]);
     if (r) return r;
   }
@@ -969,7 +982,7 @@ rmc_status stream_begin_single(rmc_ctx *c, uint64_t seed, int64_t first, int64_t
   rmc_status r = ready(c, true);
   if (r) return r;
   if (first < 0 || n < 0 || first + n > c->n_src) return fail(c, RMC_EINVAL, "packet range outside the sources");
-  r = ensure_outputs(c, n);
+  r = ensure_outputs(c, n, c->stream);
   if (r) return r;
   c->last_n = n;
   make_problem(c, first, n, seed, c->pb_host);
@@ -1017,6 +1030,7 @@ rmc_status stream_finish(rmc_ctx *c, rmc_run_stats *per, rmc_run_stats *total) {
     fill_stats(total, t, c->s_acc.kernel_ms);
     total->peel_deferred = c->s_acc.peel_deferred;
     total->peel_pass_ms = c->s_acc.peel_pass_ms;
+    total->slices_cut = c->s_acc.slices_cut;
   }
   if ((int64_t)t[S_EMITTED] != c->s_total)
     return fail(c, RMC_EDEVICE, "transport finished %llu of %lld packets", t[S_EMITTED], (long long)c->s_total);
@@ -1293,7 +1307,7 @@ rmc_status batch_open(rmc_ctx *const *P, int np, const uint64_t *seeds, const in
     r = ready(c, true);
     if (r) return fail(c0, r, "problem %d: %s", i, c->err.c_str());
     if (npk[i] < 0 || npk[i] > c->n_src) return fail(c0, RMC_EINVAL, "problem %d: packet count outside the sources", i);
-    r = ensure_outputs(c, npk[i]);
+    r = ensure_outputs(c, npk[i], c0->stream);
     if (r) return fail(c0, r, "problem %d: %s", i, c->err.c_str());
     maxL = std::max(maxL, c->L);
   }

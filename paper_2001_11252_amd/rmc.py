@@ -43,7 +43,8 @@ class RmcRunStats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in ("emitted", "escaped", "absorbed", "stuck", "scatterings",
                                           "dust_scatterings", "crossings", "peel_rays", "peel_crossings",
                                           "peel_dropped", "peel_deferred")] + [("kernel_ms", C.c_double),
-                                                                             ("peel_pass_ms", C.c_double)]
+                                                                             ("peel_pass_ms", C.c_double),
+                                                                             ("slices_cut", C.c_uint64)]
 
     def as_dict(self):
         return {n: (float(getattr(self, n)) if t is C.c_double else int(getattr(self, n))) for n, t in self._fields_}

@@ -256,6 +256,34 @@ def test_slicing_does_not_change_results(rmc, orc, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_unfinished_packets_read_as_none(rmc, orc, prec):
+    # a stream clears the statuses of the previous run; while it is open,
+    # exactly the packets finished so far carry one
+    pb = W.static_sphere(s0(orc), 2e3, 1e3, 3000, level=3, tau_dust=0.3)
+    c = rmc.Context.from_problem(pb, prec, observers=False)
+    c.run(4, 0, 3000)
+    ref = c.get_packets()
+    assert np.all(ref["status"] > 0)
+    c.set_option(rmc.OPT_SLICE_ITERS, 5)
+    c.stream_begin(4, 0, 3000)
+    done = 0
+    for _ in range(3):
+        sl, rem = c.stream_step()
+        done += sl["emitted"]
+        st = c.get_packets()["status"]
+        assert (st > 0).sum() == done
+    assert done < 3000
+    # begin on an open stream starts over
+    c.stream_begin(4, 0, 3000)
+    assert np.all(c.get_packets()["status"] == rmc.ST_NONE)
+    tot = c.stream_end()
+    assert tot["emitted"] == 3000
+    out = c.get_packets()
+    for k in ref:
+        assert np.array_equal(out[k], ref[k]), k
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_deferred_peel_off_matches_inline(rmc, orc, prec):
     # peel-off rays walked by the ray-cast pass after each launch give the
     # cubes of rays walked inline, up to the order of the additions; an
@@ -272,17 +300,18 @@ def test_deferred_peel_off_matches_inline(rmc, orc, prec):
     b = rmc.Context.from_problem(pb, prec)
     b.set_option(rmc.OPT_SLICE_ITERS, 64)
     b.stream_begin(21, 0, 4000)
-    deferred = 0
+    deferred, cut = 0, 0
     while True:
         sl, rem = b.stream_step()
         deferred += sl["peel_deferred"]
+        cut += sl["slices_cut"]
         if rem == 0:
             break
     sb = b.stream_end()
     pbk = b.get_packets()
-    assert sa["peel_deferred"] == 0
+    assert sa["peel_deferred"] == 0 and sa["slices_cut"] == 0
     assert deferred > 0.01 * sb["peel_rays"]
-    assert sb["peel_deferred"] == deferred
+    assert sb["peel_deferred"] == deferred and sb["slices_cut"] == cut
     for k in pa:
         assert np.array_equal(pa[k], pbk[k]), k
     for k in ("emitted", "escaped", "absorbed", "scatterings", "crossings", "peel_rays", "peel_crossings",
