@@ -139,6 +139,8 @@ struct rmc_ctx {
   PeelQueue *s_pq = nullptr;
   bool image_done = false;           // an image call has filled d_stats and ev0/ev1
   bool s_one_line = false;           // every problem of the stream has one line
+  bool s_defer = true;               // transport kernel without the inline peel-off walker
+                                     // (deferred peel-off, or no observer in the stream)
   // deferred peel-off rays: control block (PeelQueue) and job buffer
   DevBuf pq_ctl, pq_jobs, pq_counts;
   unsigned long long pq_cap = 0, pq_regions = 0;
@@ -483,7 +485,7 @@ int grid_for(rmc_ctx *c, int64_t n, bool batch, int levels) {
   if (c->waves_per_cu > 0) {
     g = (int64_t)c->num_cus * c->waves_per_cu * 64 / c->block;
   } else {
-    const int bpc = transport_blocks_per_cu(c->precision == RMC_FP32_BULK, batch, c->s_pq != nullptr, c->s_one_line,
+    const int bpc = transport_blocks_per_cu(c->precision == RMC_FP32_BULK, batch, c->s_defer, c->s_one_line,
                                             c->block,
                                             std::max(levels, 1));
     g = (int64_t)c->num_cus * bpc;
@@ -897,7 +899,7 @@ rmc_status stream_open(rmc_ctx *c, int64_t total, int n_probs, int levels, bool 
   PeelQueue *pq = c->s_pq;
   snprintf(key, sizeof key, "%p/%p/%p/%p/%p/%d/%d/%d/%d/%d/%d/%d/%d/%d", (void *)c->s_probs, (void *)c->s_starts,
            c->slots.p, c->d_slice.p, (void *)pq, n_probs, c->s_grid, c->block, c->refill, c->s_levels,
-           c->precision, c->slice_iters, (int)batch, (int)c->s_one_line);
+           c->precision, c->slice_iters, (int)batch, (int)c->s_one_line * 2 + (int)c->s_defer);
   if (c->s_key != key || !c->s_graph) {
     for (hipGraphExec_t *ge : {&c->s_graph, &c->s_graph2})
       if (*ge) {
@@ -914,7 +916,7 @@ rmc_status stream_open(rmc_ctx *c, int64_t total, int n_probs, int levels, bool 
       if (part == 0) {
         if (e == hipSuccess) e = launch_fill_u64(c->d_slice.as<unsigned long long>(), N_STATS + 3, 0ull, cap);
         if (e == hipSuccess)
-          e = launch_transport(f32, batch, pq != nullptr, c->s_one_line, c->s_probs, c->s_starts, n_probs,
+          e = launch_transport(f32, batch, c->s_defer, c->s_one_line, c->s_probs, c->s_starts, n_probs,
                                c->d_next.as<unsigned long long>(), c->refill, c->s_levels, c->s_grid, c->block,
                                c->slots.p, c->slice_iters, c->d_slice.as<unsigned long long>(), cap);
       } else {
@@ -989,6 +991,7 @@ rmc_status stream_begin_single(rmc_ctx *c, uint64_t seed, int64_t first, int64_t
   r = peel_queue(c, &c->s_pq);
   if (r) return r;
   if (c->obs.empty()) c->s_pq = nullptr;
+  c->s_defer = c->s_pq != nullptr || c->obs.empty();
   c->pb_host.pq = c->s_pq;
   c->pb_host.index = 0;
   c->s_one_line = c->n_lines == 1;
@@ -1317,6 +1320,7 @@ rmc_status batch_open(rmc_ctx *const *P, int np, const uint64_t *seeds, const in
   r = peel_queue(c0, &c0->s_pq);
   if (r) return r;
   if (!any_obs) c0->s_pq = nullptr;
+  c0->s_defer = c0->s_pq != nullptr || !any_obs;
   c0->s_one_line = true;
   for (int i = 0; i < np; ++i) c0->s_one_line = c0->s_one_line && P[i]->n_lines == 1;
   c0->b_host.resize(np);

@@ -4,10 +4,9 @@
 //               with peel-off toward observers at each emission and
 //               scattering (Sect. 5.1); one packet per lane, lanes of a
 //               wave refilled from a global queue with one atomic per wave
-//               (ballot + mbcnt compaction of the idle lanes).  Peel-off
-//               rays are walked through their first leaf here; the ones
-//               that go on are queued in the wave's region of the peel-off
-//               queue.
+//               (ballot + mbcnt compaction of the idle lanes).  Each
+//               peel-off ray is decided in the scattering's own leaf or
+//               queued in the wave's region of the peel-off queue.
 // k_peel_drain  ray-cast pass over the queued peel-off rays after each
 //               transport launch (lanes refilled per ray), k_peel_reset
 //               its bookkeeping
@@ -51,25 +50,14 @@ template <class R> struct StartCell {
   const int *stk;
 };
 
-// Where a ray walk stopped early: the point where it enters its next leaf.
-struct RayStop {
-  double p[3];
-  double tau;
-  uint32_t steps;
-  bool stopped;
-};
-
 // Walks a ray at fixed x_ext from p (inside cell c) leaf by leaf, adding
 // kappa * segment to tau, until it reaches the domain border or tau >=
 // tau_cut.  steps counts the leaves crossed so far (at most MAX_CROSS).  With
-// borrowed, sc lends the first leaf's record and ancestor stack; with
-// may_stop, the walk ends where the ray leaves its first leaf and stop
-// records the state to resume from.
+// borrowed, sc lends the first leaf's record and ancestor stack.
 template <class R, int NL>
 __device__ double ray_walk(const ProblemK &pb, double p[3], const double k[3], double x_ext, double tau,
                            uint32_t steps, double tau_cut, int *stk, int stride, uint32_t *ncross, Cell &c,
-                           const StartCell<R> *sc, bool borrowed, RayStop &stop, bool may_stop,
-                           const double *kinv = nullptr) {
+                           const StartCell<R> *sc, bool borrowed, const double *kinv = nullptr) {
   const R kr[3] = {(R)k[0], (R)k[1], (R)k[2]};
   bool first = borrowed;
   bool start = true;
@@ -106,13 +94,6 @@ __device__ double ray_walk(const ProblemK &pb, double p[3], const double k[3], d
     wrap_slab(pb.domain, p, k);
     int X[3];
     if (!int_coords(pb.L, p, k, X)) break;
-    if (may_stop) {
-      stop.p[0] = p[0]; stop.p[1] = p[1]; stop.p[2] = p[2];
-      stop.tau = tau;
-      stop.steps = steps + 1;
-      stop.stopped = true;
-      break;
-    }
     if (first) {
       // first move out of the borrowed cell: copy its ancestors
       for (int l = 0; l < c.level; ++l) stk[l * stride] = sc->stk[l * stride];
@@ -128,8 +109,7 @@ __device__ double ray_walk(const ProblemK &pb, double p[3], const double k[3], d
 template <class R, int NL = MAX_LINES>
 __device__ double ray_tau(const ProblemK &pb, const double p0[3], const double k[3], double x_ext,
                           double tau_cut, int *stk, int stride, uint32_t *ncross,
-                          const StartCell<R> *sc, RayStop &stop, bool may_stop,
-                          const double *kinv = nullptr) {
+                          const StartCell<R> *sc, const double *kinv = nullptr) {
   double p[3] = {p0[0], p0[1], p0[2]};
   Cell c;
   const bool reuse = sc && strictly_inside(*sc->c, pb.L, p);
@@ -140,8 +120,7 @@ __device__ double ray_tau(const ProblemK &pb, const double p0[3], const double k
     if (!int_coords(pb.L, p, k, X)) return 0.0;
     descend(pb.nodes, pb.L, 0, 0, X, stk, stride, c);
   }
-  return ray_walk<R, NL>(pb, p, k, x_ext, 0.0, 0u, tau_cut, stk, stride, ncross, c, sc, reuse, stop, may_stop,
-                         kinv);
+  return ray_walk<R, NL>(pb, p, k, x_ext, 0.0, 0u, tau_cut, stk, stride, ncross, c, sc, reuse, kinv);
 }
 
 // Pixel of position p in observer ob's image, -1 outside.  The double path
@@ -199,10 +178,71 @@ struct PeelSink {
   unsigned long long *lost;   // pushes that found no room (never expected)
 };
 
+// Deferred peel-off ray toward observer oi from p: the scattering's own leaf
+// (its record is in the lane's registers) ends most rays, whose optical
+// depth to the nearest face, or to the exit face along k_obs, already
+// reaches the cut (exp(-tau) is zero, no deposit).  Any other ray is queued
+// for the ray-cast pass, which does every deposit: the float path queues it
+// from its start (the pass walks the first leaf again, which keeps this
+// kernel's registers low enough for four waves per SIMD), the double path
+// from the point where it leaves the first leaf, with the optical depth so
+// far.  Rays from a leaf the domain border may cut, and emission rays (sc
+// null: no leaf located yet), are queued from the start.
+template <class R, int NL>
+__device__ __forceinline__ void peel_defer(const ProblemK &pb, const double p[3], const ObsK &ob, const R ko[3],
+                                           R xo, R weight, size_t elem, int oi, LaneCount &cnt,
+                                           const PeelSink &snk, const StartCell<R> *sc) {
+  bool ends = false;
+  double q[3] = {p[0], p[1], p[2]}, qtau = 0.0;
+  uint32_t qsteps = 0;
+  if (sc && sc->lf->bnd == R(0)) {
+    Opac<R, NL> o;
+    opacity(pb, *sc->lf, (double)xo, ko, o);
+    const double kt = (double)o.ktot;
+    ends = kt * inner_dist(*sc->c, pb.L, p) >= TauCut<R>::v;
+    if (!ends) {
+      double face[3], lo[3], hi[3];
+      int em;
+      const double te = exit_dist(*sc->c, pb.L, p, ob.k, face, lo, hi, &em, sizeof(R) == 4 ? ob.kinv : nullptr);
+      const double t1 = kt * te;
+      ends = t1 >= TauCut<R>::v;
+      if constexpr (sizeof(R) == 8) {
+        if (!ends) {
+          exit_point(te, em, p, ob.k, face, lo, hi, q);
+          wrap_slab(pb.domain, q, ob.k);
+          qtau = t1;
+          qsteps = 1;
+        }
+      }
+    }
+  }
+  if (ends || qsteps) ++cnt.peel_cross;
+  if (ends) return;
+  // one LDS atomic per wave reserves the slots of the lanes pushing here
+  const unsigned long long m = __ballot(true);
+  const int lane = __lane_id();
+  const int leader = __ffsll((long long)m) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(snk.count, __popcll(m));
+  base = __shfl(base, leader);
+  const uint32_t slot = (uint32_t)base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+  if (slot < snk.cap) {
+    PeelJob &j = snk.region[slot];
+    j.p[0] = q[0]; j.p[1] = q[1]; j.p[2] = q[2];
+    j.tau = qtau;
+    j.x = (double)xo;
+    j.weight = (double)weight;
+    j.dst = (unsigned long long)elem | ((unsigned long long)oi << PQ_OBS_SHIFT) |
+            ((unsigned long long)pb.index << PQ_PROB_SHIFT);
+    j.steps = qsteps;
+  } else {
+    atomicAdd(snk.lost, 1ull);
+  }
+}
+
 // Peel-off of one event toward every observer (Sect. 5.1).  DEFER: each ray
-// is walked through its first leaf only (the scattering's own leaf, whose
-// record the lane already holds); a ray that goes on is queued for the
-// ray-cast pass.  Otherwise the whole ray is walked here.
+// is decided in the scattering's own leaf or queued for the ray-cast pass
+// (peel_defer).  Otherwise the whole ray is walked here.
 template <class R, bool DEFER, int NL>
 __device__ void peel_all(const ProblemK &pb, const double p[3], const PeelSrc<R> &s, int *stk,
                          int stride, LaneCount &cnt, const PeelSink &snk, const StartCell<R> *sc = nullptr) {
@@ -238,45 +278,16 @@ __device__ void peel_all(const ProblemK &pb, const double p[3], const PeelSrc<R>
       continue;
     }
     ++cnt.peel_rays;
-    uint32_t nc = 0;
     const size_t elem = (size_t)pix * ob.nbins + bin;
-    RayStop rs;
-    rs.stopped = false;
-    const double tau = ray_tau<R, NL>(pb, p, ob.k, (double)xo, TauCut<R>::v, stk, stride, &nc, sc, rs, DEFER,
-                                      sizeof(R) == 4 ? ob.kinv : nullptr);
-    if (DEFER) {
-      // a ray that goes on past its first leaf is queued instead of
-      // holding the wave here
-      const unsigned long long m = __ballot(rs.stopped);
-      if (m) {
-        const int lane = __lane_id();
-        const int leader = __ffsll((long long)m) - 1;
-        int base = 0;
-        if (lane == leader) base = atomicAdd(snk.count, __popcll(m));
-        base = __shfl(base, leader);
-        if (rs.stopped) {
-          const uint32_t slot = (uint32_t)base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-          if (slot < snk.cap) {
-            PeelJob &j = snk.region[slot];
-            j.p[0] = rs.p[0]; j.p[1] = rs.p[1]; j.p[2] = rs.p[2];
-            j.tau = rs.tau;
-            j.x = (double)xo;
-            j.weight = (double)weight;
-            j.dst = (unsigned long long)elem | ((unsigned long long)oi << PQ_OBS_SHIFT) |
-                    ((unsigned long long)pb.index << PQ_PROB_SHIFT);
-            j.steps = rs.steps;
-          } else {
-            atomicAdd(snk.lost, 1ull);
-          }
-          cnt.peel_cross += nc;
-          continue;
-        }
-      }
+    if constexpr (DEFER) {
+      peel_defer<R, NL>(pb, p, ob, ko, xo, weight, elem, oi, cnt, snk, sc);
+    } else {
+      uint32_t nc = 0;
+      const double tau = ray_tau<R, NL>(pb, p, ob.k, (double)xo, TauCut<R>::v, stk, stride, &nc, sc,
+                                        sizeof(R) == 4 ? ob.kinv : nullptr);
+      cnt.peel_cross += nc;
+      if (tau < TauCut<R>::v) atomic_add_real((R *)ob.cube + elem, weight * M<R>::exp((R)(-tau)));
     }
-    cnt.peel_cross += nc;
-    if (tau >= TauCut<R>::v) continue;
-    const R wgt = weight * M<R>::exp((R)(-tau));
-    atomic_add_real((R *)ob.cube + elem, wgt);
   }
 }
 
@@ -529,20 +540,32 @@ __device__ __forceinline__ void add_delta(SliceCount &a, const Lane<R> &s, const
   a.peel_cross += s.cnt.peel_cross - z.cnt.peel_cross;
 }
 
-// Waves per SIMD the transport kernel is compiled for (register budget).
+// Waves per SIMD the transport kernel is compiled for (register budget,
+// chosen by measurement): the float single-problem, single-line kernel with
+// deferred peel-off runs four (about 30 registers spill, and it is still
+// 8% faster than at three), the other float kernels three (no spills; at
+// four the batch and four-line kernels spill 40-70 registers and the batch
+// runs slower), the double kernels one.
+#ifndef RMC_WAVES_F32_LEAN
+#define RMC_WAVES_F32_LEAN 4
+#endif
 #ifndef RMC_WAVES_F32
 #define RMC_WAVES_F32 3
 #endif
 #ifndef RMC_WAVES_F64
 #define RMC_WAVES_F64 1
 #endif
-template <class R> struct WavesPerEU;
-template <> struct WavesPerEU<float> { static constexpr int v = RMC_WAVES_F32; };
-template <> struct WavesPerEU<double> { static constexpr int v = RMC_WAVES_F64; };
+template <class R, bool BATCH, bool DEFER, int NL> struct WavesPerEU;
+template <bool BATCH, bool DEFER, int NL> struct WavesPerEU<float, BATCH, DEFER, NL> {
+  static constexpr int v = (!BATCH && DEFER && NL == 1) ? RMC_WAVES_F32_LEAN : RMC_WAVES_F32;
+};
+template <bool BATCH, bool DEFER, int NL> struct WavesPerEU<double, BATCH, DEFER, NL> {
+  static constexpr int v = RMC_WAVES_F64;
+};
 
 template <class R, bool BATCH, bool DEFER, int NL>
 __global__ void __launch_bounds__(256)
-    __attribute__((amdgpu_waves_per_eu(WavesPerEU<R>::v, WavesPerEU<R>::v)))
+    __attribute__((amdgpu_waves_per_eu(WavesPerEU<R, BATCH, DEFER, NL>::v, WavesPerEU<R, BATCH, DEFER, NL>::v)))
     k_transport(const ProblemK *__restrict__ probs,
                                                    const int64_t *__restrict__ starts, int n_probs,
                                                    unsigned long long *__restrict__ next,
@@ -559,14 +582,16 @@ __global__ void __launch_bounds__(256)
   // this wave's region of the deferred peel-off queue; the wave ends its
   // slice early once one more iteration (an emission and an event, each
   // peeled toward every observer) could overflow it
+  // (no queue when no problem of the launch has an observer)
   PeelQueue *const pq = DEFER ? probs[0].pq : nullptr;
+  const bool queue = DEFER && pq != nullptr;
   const int64_t wave = gid >> 6;
   PeelSink snk;
   snk.count = lds + 2 * stack_levels * stride + (threadIdx.x >> 6);
-  snk.region = DEFER ? pq->jobs + (size_t)wave * pq->cap : nullptr;
-  snk.cap = DEFER ? (uint32_t)pq->cap : 0u;
-  snk.lost = DEFER ? &pq->lost : nullptr;
-  const int room = DEFER ? (int)pq->cap - 2 * 64 * MAX_OBS : 0;
+  snk.region = queue ? pq->jobs + (size_t)wave * pq->cap : nullptr;
+  snk.cap = queue ? (uint32_t)pq->cap : 0u;
+  snk.lost = queue ? &pq->lost : nullptr;
+  const int room = queue ? (int)pq->cap - 2 * 64 * MAX_OBS : 0x7fffffff;
   if (lane == 0) *snk.count = 0;
 
   Lane<R> s;
@@ -659,8 +684,11 @@ __global__ void __launch_bounds__(256)
     }
     int st = ST_NONE;
     if (here) {
-      // the event happens inside this leaf
-      const double dist = s.tau / (double)o.ktot;
+      // the event happens inside this leaf (float path: kappa is a float
+      // and tau_event came from a float logarithm, so a float reciprocal
+      // of kappa loses nothing the path keeps)
+      const double dist = sizeof(R) == 4 ? s.tau * (double)__builtin_amdgcn_rcpf((float)o.ktot)
+                                         : s.tau / (double)o.ktot;
 #pragma unroll
       for (int d = 0; d < 3; ++d) s.p[d] = fmin(fmax(fma(dist, kd[d], s.p[d]), lo[d]), hi[d]);
       s.path += dist;
@@ -704,7 +732,7 @@ __global__ void __launch_bounds__(256)
   } else {
     q.active = 0;
   }
-  if (DEFER && lane == 0) {
+  if (queue && lane == 0) {
     const int nq = *snk.count;
     pq->counts[wave] = (uint32_t)nq;
     if (nq) {
@@ -739,7 +767,8 @@ __global__ void k_clear_slots(SlotState *__restrict__ slots, int64_t n) {
 // wave takes the queue regions one at a time; each lane walks one ray a
 // leaf per iteration and takes the region's next ray as soon as its own is
 // done, so the waves stay full while ray lengths vary.  The walk is the one
-// of ray_walk, resumed from the queued state.
+// of ray_walk from the queued state (a ray's start, or where it left its
+// first leaf), and every deferred deposit is made here.
 #ifndef RMC_DRAIN_WAVES_F32
 #define RMC_DRAIN_WAVES_F32 4
 #endif
@@ -946,8 +975,7 @@ __global__ void k_tau(ProblemK pb, int64_t n, const double *__restrict__ orig,
   const double p[3] = {orig[3 * r], orig[3 * r + 1], orig[3 * r + 2]};
   const double k[3] = {dir[3 * r], dir[3 * r + 1], dir[3 * r + 2]};
   uint32_t nc = 0;
-  RayStop rs;
-  tau_out[r] = ray_tau<R>(pb, p, k, x_ext[r], __builtin_inf(), stk, blockDim.x, &nc, nullptr, rs, false);
+  tau_out[r] = ray_tau<R>(pb, p, k, x_ext[r], __builtin_inf(), stk, blockDim.x, &nc, nullptr);
 }
 
 // ------------------------------------------------- peel-off image, adjoint
@@ -964,9 +992,8 @@ __global__ void k_image_fwd(ProblemK pb, int obs, int64_t n, const double *__res
     const double p[3] = {orig[3 * r], orig[3 * r + 1], orig[3 * r + 2]};
     const int pix = pixel_of(ob, p);
     if (pix >= 0) {
-      RayStop rs;
-      const double tau = ray_tau<R>(pb, p, ob.k, x_ext[r], TauCut<double>::v, stk, blockDim.x, &nc, nullptr, rs,
-                                    false, sizeof(R) == 4 ? ob.kinv : nullptr);
+      const double tau = ray_tau<R>(pb, p, ob.k, x_ext[r], TauCut<double>::v, stk, blockDim.x, &nc, nullptr,
+                                    sizeof(R) == 4 ? ob.kinv : nullptr);
       if (tau < TauCut<double>::v) unsafeAtomicAdd(image + pix, w[r] * exp(-tau));
     }
   }
@@ -1006,9 +1033,8 @@ __global__ void __launch_bounds__(256) k_image_bwd(ProblemK pb, int obs, int64_t
     const int pix = pixel_of(ob, p0);
     xr = x_ext[r];
     double tau = TauCut<double>::v;
-    RayStop rs;
     if (pix >= 0)
-      tau = ray_tau<R>(pb, p0, ob.k, xr, TauCut<double>::v, stk, blockDim.x, &nc, nullptr, rs, false,
+      tau = ray_tau<R>(pb, p0, ob.k, xr, TauCut<double>::v, stk, blockDim.x, &nc, nullptr,
                        sizeof(R) == 4 ? ob.kinv : nullptr);
     g = (pix >= 0 && tau < TauCut<double>::v) ? -G[pix] * w[r] * exp(-tau) : 0.0;
     if (g != 0.0) {
