@@ -205,7 +205,7 @@ def bench_batch(a, rmc, W):
                  a.steps, a.warmup, 1e3 * wall / a.steps, "f32",
                  {"workload": "batch_64_problems_slab_sphere_lya_mgii", "problems": len(probs),
                   "packets": int(sum(npk)), "tuned": best, "parallelism": "none"},
-                 transport_roofline(tot, kms, "fp32", "k_transport<float,true,false,4>"),
+                 transport_roofline(tot, kms, "fp32", "k_transport<float,true,true,4>"),
                  crossings_per_s=(tot["crossings"] + tot["peel_crossings"]) / wall, cpu_baseline=cpu)
 
 

@@ -65,12 +65,14 @@ enum {
   RMC_OPT_WAVES_PER_CU = 4,  /* resident waves per CU the grid is sized for  */
   RMC_OPT_REFILL = 5,        /* idle lanes a wave gathers before it takes new
                                 packets (1..64)                              */
-  RMC_OPT_PEEL_DEFER = 6,    /* 1 (default): a peel-off ray that leaves the
-                                leaf of its scattering is queued and walked
-                                on by a ray-cast pass after each transport
-                                launch; 0: walked inline by the transport
-                                kernel.  Results agree up to the order of
-                                the cube additions.                          */
+  RMC_OPT_PEEL_DEFER = 6,    /* 1 (default): a peel-off ray whose optical
+                                depth does not reach the cut inside the leaf
+                                of its scattering is queued (device memory
+                                that grows on demand, at most 16 GiB) and
+                                walked by a ray-cast pass after each
+                                transport launch; 0: walked inline by the
+                                transport kernel.  Results agree up to the
+                                order of the cube additions.                 */
   RMC_OPT_SLICE_ITERS = 7    /* loop iterations (events or cell crossings)
                                 per lane in one transport launch            */
 };
