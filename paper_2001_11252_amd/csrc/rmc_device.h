@@ -156,6 +156,8 @@ template <> struct EventRng<double> {
     const uint64_t m = ((uint64_t)hi << 20) | (uint64_t)(lo >> 12);
     return (double)(2 * m + 1) * 0x1p-53;
   }
+  // 2^-52 spacing resolves any probability the path compares with
+  __device__ double u_small(uint32_t j) { return u(j); }
 };
 
 template <> struct EventRng<float> {
@@ -175,6 +177,20 @@ template <> struct EventRng<float> {
     const uint32_t q = j & 3;
     const uint32_t x = q == 0 ? w.x : (q == 1 ? w.y : (q == 2 ? w.z : w.w));
     return (float)(2u * (x >> 9) + 1u) * 0x1p-24f;
+  }
+  // Draw j for a comparison with a probability that may be far below the
+  // 2^-23 spacing of u (kappa_d / kappa in an optically thick line core):
+  // the whole 32-bit word, whose conversion is exact below 2^24, so near
+  // zero the draw is resolved to 2^-32.  Lies in [0, 1].
+  __device__ float u_small(uint32_t j) {
+    const uint32_t b = j >> 2;
+    if (b != cur) {
+      w = philox4x32_10(make_uint4(plo, phi, ev, b), key);
+      cur = b;
+    }
+    const uint32_t q = j & 3;
+    const uint32_t x = q == 0 ? w.x : (q == 1 ? w.y : (q == 2 ? w.z : w.w));
+    return (float)x * 0x1p-32f;
   }
 };
 

@@ -393,7 +393,8 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R, NL> &o, in
   ++s.event;
   if (pb.max_events > 0 && (int64_t)s.event >= pb.max_events) return ST_STUCK;
   EventRng<R> rng(pb.seed, (uint64_t)s.pid, s.event);
-  R r = rng.u(J_CHANNEL) * o.ktot;
+  // kappa_d / kappa reaches ~1e-8 in optically thick line cores
+  R r = rng.u_small(J_CHANNEL) * o.ktot;
   const R kin[3] = {s.k[0], s.k[1], s.k[2]};
   R e1[3], e2[3];
   perp_basis(kin, e1, e2);

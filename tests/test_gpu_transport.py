@@ -256,6 +256,23 @@ def test_slicing_does_not_change_results(rmc, orc, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_small_dust_probability_in_a_line_core(rmc, orc, prec):
+    # Forward-only scatterings keep x = 0, so every event compares with
+    # kappa_d / kappa = tau_d / tau0 = 3e-8 (below the 2^-23 spacing of a
+    # float uniform) and a packet flying out along the radius is absorbed
+    # with probability 1 - exp(-tau_d) exactly, whatever the line opacity.
+    n, tau_d = 100000, 0.006
+    pb = W.static_sphere(s0(orc), 2e5, 1e4, n, level=3, tau_dust=tau_d, albedo=0.0)
+    c = rmc.Context.from_problem(pb, prec, observers=False)
+    c.set_option(rmc.OPT_FORWARD_ONLY, 1)
+    st = c.run(78, 0, n)
+    check_conservation(st, n)
+    p = -np.expm1(-tau_d)
+    assert st["scatterings"] > 0.9 * n * 2e5
+    assert abs(st["absorbed"] - n * p) < 4.0 * np.sqrt(n * p * (1.0 - p)), (st["absorbed"], n * p)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_unfinished_packets_read_as_none(rmc, orc, prec):
     # a stream clears the statuses of the previous run; while it is open,
     # exactly the packets finished so far carry one

@@ -70,6 +70,20 @@ def test_dust_only_tau_and_transmission(orc, sigma0_oracle):
     assert r["stats"]["escaped"] + r["stats"]["absorbed"] + r["stats"]["stuck"] == n
 
 
+def test_dust_choice_beside_a_line(orc, sigma0_oracle):
+    # Sect. 3.2: an interaction is dust with probability kappa_d / kappa.
+    # Forward-only scatterings keep x = 0 and the direction, so a packet
+    # flying out along the radius is absorbed (albedo 0) with probability
+    # 1 - exp(-tau_d), whatever the line optical depth beside the dust.
+    n, tau_d = 8000, 0.5
+    pb = W.static_sphere(sigma0_oracle, 2e3, 1e4, n, level=3, tau_dust=tau_d, albedo=0.0)
+    r = orc.run(pb, 78, threads=8, forward_only=True)
+    p = -np.expm1(-tau_d)
+    assert abs(r["stats"]["absorbed"] - n * p) < 3.5 * np.sqrt(n * p * (1 - p))
+    # line events before absorption or escape: tau0 (1 - exp(-tau_d)) / tau_d on average
+    assert abs(r["stats"]["scatterings"] / n / (2e3 * p / tau_d) - 1) < 0.02
+
+
 def test_first_flight_distance_is_exponential(orc, sigma0_oracle):
     # App. B: the distance to the first scattering of x = 0 packets follows
     # an exponential law of mean lambda_MFP = 1/(n sigma0) (H(a,0) = 1)
