@@ -212,7 +212,8 @@ def bench_batch(a, rmc, W):
 def bench_adjoint(a, rmc, W):
     """C5: galaxy-like adaptive mesh (~2e7 leaves), 1e7 fixed rays toward
     +z, 512^2 image; one forward image and one backward (gradients per
-    leaf) per step, FP32 leaf records."""
+    leaf) per step, FP32 leaf records; the backward reads the forward's
+    crossing lists (the replaying backward is measured beside it)."""
     import torch
     t0 = time.perf_counter()
     pb = W.c5_galaxy(rmc.sigma0, target_leaves=a.leaves, n_sources=a.sources,
@@ -227,30 +228,52 @@ def bench_adjoint(a, rmc, W):
     x = torch.tensor(r["x_ext"], dtype=torch.float64, device=dev)
     w = torch.tensor(r["w"], dtype=torch.float64, device=dev)
     G = torch.tensor(pb.meta["grad_image"], dtype=torch.float64, device=dev)
-    fwd, bwd = [], []
-    t_all = 0.0
-    for i in range(a.warmup + a.steps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ctx.raycast_image(0, o, x, w)
-        f = ctx.image_stats()
-        ctx.raycast_image_backward(0, o, x, w, G)
-        b = ctx.image_stats()
-        torch.cuda.synchronize()
-        if i >= a.warmup:
-            fwd.append(f)
-            bwd.append(b)
-            t_all += time.perf_counter() - t0
-    cf = sum(c for c, _ in fwd)
-    cb = sum(c for c, _ in bwd)
-    mf = sum(m for _, m in fwd)
-    mb = sum(m for _, m in bwd)
+
+    def run(tape):
+        fwd, bwd = [], []
+        t_all = 0.0
+        for i in range(a.warmup + a.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if tape:
+                ctx.raycast_image_tape(0, o, x, w)
+            else:
+                ctx.raycast_image(0, o, x, w)
+            f = ctx.image_stats()
+            if tape:
+                ctx.raycast_image_backward_tape(G)
+            else:
+                ctx.raycast_image_backward(0, o, x, w, G)
+            b = ctx.image_stats()
+            torch.cuda.synchronize()
+            if i >= a.warmup:
+                fwd.append(f)
+                bwd.append(b)
+                t_all += time.perf_counter() - t0
+        n = a.steps
+        cf = sum(c for c, _ in fwd) / n
+        cb = sum(c for c, _ in bwd) / n
+        mf = sum(m for _, m in fwd) / n
+        mb = sum(m for _, m in bwd) / n
+        return cf, cb, mf, mb, t_all
+
+    # the tape path (forward records the crossing lists, backward reads
+    # them) and the replaying backward, on the same rays
+    tf, tb, tmf, tmb, t_tape = run(True)
+    rf, rb, rmf, rmb, t_rep = run(False)
     n = a.steps
-    # gather roofline of the forward ray cast: one FP32 leaf record (24 B)
-    # and one node entry (4 B) per crossing; the backward adds three 8-B
-    # gradient read-modify-writes
-    gbs_f = cf * 28.0 / (mf * 1e-3) / 1e9
-    gbs_b = cb * (28.0 + 48.0) / (mb * 1e-3) / 1e9
+    # algorithmic bytes per crossing, FP32 records: forward 24-B leaf record +
+    # 4-B node entry, plus the 8-B tape entry it writes; tape backward 8-B
+    # tape entry + 24-B leaf record + three 8-B gradient read-modify-writes
+    gbs_tf = tf * (28.0 + 8.0) / (tmf * 1e-3) / 1e9
+    gbs_tb = tb * (8.0 + 24.0 + 48.0) / (tmb * 1e-3) / 1e9
+    gbs_rf = rf * 28.0 / (rmf * 1e-3) / 1e9
+    if tmf >= tmb:
+        roof = {"bound": "hbm", "achieved": gbs_tf, "peak": 8000.0, "unit": "GB/s", "frac": gbs_tf / 8000.0,
+                "traffic": None, "kernel": "k_image_fwd_tape<float>"}
+    else:
+        roof = {"bound": "hbm", "achieved": gbs_tb, "peak": 8000.0, "unit": "GB/s", "frac": gbs_tb / 8000.0,
+                "traffic": None, "kernel": "k_image_bwd_tape<float>"}
     ctx.close()
     cpu = None
     if not a.no_cpu_baseline:
@@ -275,13 +298,16 @@ def bench_adjoint(a, rmc, W):
         cpu = {"value": 2 * int(nc[0]) / dt, "unit": "crossings/s", "cores": cores, "kind": "oracle",
                "sample": f"first {ns} rays, image + exact gradient: {int(nc[0])} crossings walked (counted twice) "
                          f"in {dt:.1f} s after a {t_setup:.1f} s set-up"}
+    # crossings of the forward walk, counted twice (image and its adjoint)
     return _line("adjoint ray-cell crossings/s (forward image + backward gradients, 1 GPU), FP32 records",
-                 (cf + cb) / t_all, "crossings/s", n, a.warmup, 1e3 * t_all / n, "f32",
-                 {"workload": f"galaxy_{pb.mesh.n}_leaves_{len(r['x_ext'])}_rays_512x512", "parallelism": "none"},
-                 {"bound": "hbm", "achieved": gbs_f, "peak": 8000.0, "unit": "GB/s", "frac": gbs_f / 8000.0,
-                  "traffic": None, "kernel": "k_image_fwd<float>"},
-                 forward={"crossings_per_launch": cf / n, "ms": mf / n, "GBps_algorithmic": gbs_f},
-                 backward={"crossings_per_launch": cb / n, "ms": mb / n, "GBps_algorithmic": gbs_b},
+                 2.0 * tf * n / t_tape, "crossings/s", n, a.warmup, 1e3 * t_tape / n, "f32",
+                 {"workload": f"galaxy_{pb.mesh.n}_leaves_{len(r['x_ext'])}_rays_512x512", "parallelism": "none",
+                  "backward": "tape"},
+                 roof,
+                 forward={"crossings_per_launch": tf, "ms": tmf, "GBps_algorithmic": gbs_tf},
+                 backward={"crossings_per_launch": tb, "ms": tmb, "GBps_algorithmic": gbs_tb},
+                 replay={"crossings_per_s": 2.0 * rf * n / t_rep, "ms_per_step": 1e3 * t_rep / n,
+                         "forward_ms": rmf, "backward_ms": rmb, "forward_GBps_algorithmic": gbs_rf},
                  cpu_baseline=cpu)
 
 

@@ -218,9 +218,28 @@ rmc_status rmc_raycast_image_backward(rmc_ctx *ctx, int id, int64_t n_rays, cons
                                       const double *x_ext, const double *w,
                                       const double *grad_image, double *g_nhi, double *g_kd,
                                       double *g_vlos, int mem);
-/* Ray-cell crossings and device time (ms) of the last rmc_raycast_image or
- * rmc_raycast_image_backward call of this context (RMC_ESTATE if none
- * since the last transport run). */
+/* rmc_raycast_image that also keeps each ray's crossing list (leaf and
+ * segment of every ray-cell crossing, in walk order; the tape) in device
+ * memory of the context, for rmc_raycast_image_backward_tape.  The tape
+ * takes 8 B (float path) or 12 B (double path) per crossing plus 24 B per
+ * ray, grows on demand (a pass that runs out is repeated with the size it
+ * needed) up to 32 GiB (RMC_ENOMEM beyond: use the replaying backward), and
+ * is kept until the next call of this function or a change of the mesh,
+ * lines, gas or domain.  The image equals rmc_raycast_image's up to the
+ * order of the additions. */
+rmc_status rmc_raycast_image_tape(rmc_ctx *ctx, int id, int64_t n_rays, const double *orig,
+                                  const double *x_ext, const double *w, double *image, int mem);
+/* Gradient of L = sum_p grad_image[p] image[p] (grad_image for the
+ * observer of the tape) for the rays of the last rmc_raycast_image_tape
+ * call, read from its tape instead of walking the rays again: the outputs
+ * of rmc_raycast_image_backward for the same rays, up to the order of the
+ * additions (and the float path's segments, kept as float).  RMC_ESTATE if
+ * there is no tape for the current model. */
+rmc_status rmc_raycast_image_backward_tape(rmc_ctx *ctx, const double *grad_image, double *g_nhi,
+                                           double *g_kd, double *g_vlos, int mem);
+/* Ray-cell crossings and device time (ms) of the last image or image
+ * adjoint call of this context (RMC_ESTATE if none since the last
+ * transport run). */
 rmc_status rmc_image_stats(rmc_ctx *ctx, uint64_t *crossings, double *kernel_ms);
 
 /* ---------------------------------------------------------------- batches */

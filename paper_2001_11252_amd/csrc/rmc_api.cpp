@@ -138,6 +138,15 @@ struct rmc_ctx {
   std::string s_key;
   PeelQueue *s_pq = nullptr;
   bool image_done = false;           // an image call has filled d_stats and ev0/ev1
+  // model generation: bumped by every change of the mesh, lines, gas or domain
+  uint64_t gen = 0;
+  // tape of the last rmc_raycast_image_tape call (crossing lists for the adjoint)
+  DevBuf tp_leaf, tp_seg, tp_next, tp_first, tp_count, tp_pix, tp_wt, tp_x, tp_ctl;
+  unsigned long long tp_cap = 0;     // chunks of TAPE_ENTRIES crossings
+  bool tp_valid = false;
+  int tp_obs = -1;
+  int64_t tp_n = 0;
+  uint64_t tp_gen = 0;
   bool s_one_line = false;           // every problem of the stream has one line
   bool s_defer = true;               // transport kernel without the inline peel-off walker
                                      // (deferred peel-off, or no observer in the stream)
@@ -620,6 +629,7 @@ rmc_status rmc_set_mesh(rmc_ctx *c, int64_t n, const int8_t *level, const int32_
   c->box_cm = box_cm;
   c->has_mesh = true;
   c->has_gas = false;
+  ++c->gen;
   return RMC_OK;
 }
 
@@ -639,6 +649,7 @@ rmc_status rmc_set_lines(rmc_ctx *c, int n, const rmc_line *lines, double T_ref)
   c->T_ref = T_ref;
   c->has_lines = true;
   if (c->has_gas) return build_leaves(c);
+  ++c->gen;
   return RMC_OK;
 }
 
@@ -664,6 +675,7 @@ rmc_status rmc_set_gas(rmc_ctx *c, const double *n_hi, const double *T, const do
   r = build_leaves(c);
   if (r) return r;
   c->has_gas = true;
+  ++c->gen;
   return RMC_OK;
 }
 
@@ -696,6 +708,7 @@ rmc_status rmc_set_domain(rmc_ctx *c, int kind, const double p[4]) {
   c->domain = kind;
   for (int d = 0; d < 4; ++d) c->dom[d] = q[d];
   if (c->has_gas) c->leaves_dirty = true;
+  ++c->gen;
   return RMC_OK;
 }
 
@@ -1285,6 +1298,128 @@ rmc_status rmc_raycast_image_backward(rmc_ctx *c, int id, int64_t n, const doubl
   HIPCHK(c, hipEventRecord(c->ev0, c->stream));
   HIPCHK(c, launch_image_bwd(c->precision == RMC_FP32_BULK, pb, id, n, o, x, ww, Gd, inv_vth_ref, a, b, d,
                              c->d_stats.as<unsigned long long>() + S_PEEL_CROSS, c->stream));
+  HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+  c->image_done = true;
+  if (mem != RMC_DEVICE) {
+    HIPCHK(c, hipMemcpyAsync(gn, a, nl * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(gk, b, nl * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(gv, d, nl * 8, hipMemcpyDeviceToHost, c->stream));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return RMC_OK;
+}
+
+constexpr unsigned long long TAPE_MAX_BYTES = 32ull << 30;   // crossing-list limit
+
+// Device view of the context's tape buffers.
+static TapeK tape_view(rmc_ctx *c) {
+  TapeK t;
+  t.leaf = c->tp_leaf.as<int32_t>();
+  t.seg = c->tp_seg.p;
+  t.next = c->tp_next.as<int64_t>();
+  t.first = c->tp_first.as<int64_t>();
+  t.count = c->tp_count.as<int32_t>();
+  t.pix = c->tp_pix.as<int32_t>();
+  t.wt = c->tp_wt.as<double>();
+  t.x = c->tp_x.as<double>();
+  t.ctl = c->tp_ctl.as<unsigned long long>();
+  t.cap = c->tp_cap;
+  return t;
+}
+
+rmc_status rmc_raycast_image_tape(rmc_ctx *c, int id, int64_t n, const double *orig, const double *x_ext,
+                                  const double *w, double *image, int mem) {
+  rmc_status r = enter(c);
+  if (r) return r;
+  const double *o, *x, *ww;
+  if ((r = image_common(c, id, n, orig, x_ext, w, mem, &o, &x, &ww))) return r;
+  if (!image) return fail(c, RMC_EINVAL, "null image");
+  c->tp_valid = false;
+  ProblemK pb;
+  make_problem(c, 0, 0, 0, pb);
+  const bool f32 = c->precision == RMC_FP32_BULK;
+  const size_t seg_bytes = f32 ? 4 : 8;
+  const size_t chunk_bytes = (size_t)TAPE_ENTRIES * (4 + seg_bytes) + 8;
+  const int64_t waves = tape_waves(n);
+  HIPCHK(c, c->tp_first.ensure((size_t)waves * 8));
+  HIPCHK(c, c->tp_count.ensure((size_t)n * 4));
+  HIPCHK(c, c->tp_pix.ensure((size_t)n * 4));
+  HIPCHK(c, c->tp_wt.ensure((size_t)n * 8));
+  HIPCHK(c, c->tp_x.ensure((size_t)n * 8));
+  HIPCHK(c, c->tp_ctl.ensure(8));
+  // first guess: four chunks (128 crossings per ray) per wave, or what the
+  // context used before; a pass that runs out is repeated with the exact
+  // number of chunks it asked for (the walks do not change)
+  if (c->tp_cap < (unsigned long long)waves * 4) c->tp_cap = (unsigned long long)waves * 4;
+  const size_t npix = (size_t)c->obs[id].k.nx * c->obs[id].k.ny;
+  double *img = image;
+  if (mem != RMC_DEVICE) {
+    HIPCHK(c, c->tmp4.ensure(npix * 8));
+    img = c->tmp4.as<double>();
+  }
+  for (int attempt = 0;; ++attempt) {
+    if ((double)c->tp_cap * (double)chunk_bytes > (double)TAPE_MAX_BYTES)
+      return fail(c, RMC_ENOMEM, "tape of %llu chunks exceeds %llu bytes (use rmc_raycast_image_backward)",
+                  c->tp_cap, TAPE_MAX_BYTES);
+    HIPCHK(c, c->tp_leaf.ensure((size_t)c->tp_cap * TAPE_ENTRIES * 4));
+    HIPCHK(c, c->tp_seg.ensure((size_t)c->tp_cap * TAPE_ENTRIES * seg_bytes));
+    HIPCHK(c, c->tp_next.ensure((size_t)c->tp_cap * 8));
+    HIPCHK(c, launch_fill_u64(c->tp_ctl.as<unsigned long long>(), 1, 0ull, c->stream));
+    HIPCHK(c, launch_fill_u64(c->d_stats.as<unsigned long long>(), N_STATS, 0ull, c->stream));
+    HIPCHK(c, hipMemsetAsync(img, 0, npix * 8, c->stream));
+    HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+    HIPCHK(c, launch_image_fwd_tape(f32, pb, id, n, o, x, ww, img, c->d_stats.as<unsigned long long>() + S_PEEL_CROSS,
+                                    tape_view(c), c->stream));
+    HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+    unsigned long long asked = 0;
+    HIPCHK(c, hipMemcpyAsync(&asked, c->tp_ctl.p, 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (asked <= c->tp_cap) break;
+    if (attempt >= 2) return fail(c, RMC_EDEVICE, "tape pass asked for %llu chunks again", asked);
+    c->tp_cap = asked;
+  }
+  c->image_done = true;
+  c->tp_valid = true;
+  c->tp_obs = id;
+  c->tp_n = n;
+  c->tp_gen = c->gen;
+  if (mem != RMC_DEVICE) HIPCHK(c, hipMemcpyAsync(image, img, npix * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return RMC_OK;
+}
+
+rmc_status rmc_raycast_image_backward_tape(rmc_ctx *c, const double *G, double *gn, double *gk, double *gv,
+                                           int mem) {
+  rmc_status r = enter(c);
+  if (r) return r;
+  if ((r = ready(c, false))) return r;
+  if (!c->tp_valid || c->tp_gen != c->gen || c->tp_obs >= (int)c->obs.size())
+    return fail(c, RMC_ESTATE, "no tape for the current model (rmc_raycast_image_tape)");
+  if (!G || !gn || !gk || !gv) return fail(c, RMC_EINVAL, "null gradient buffer");
+  ProblemK pb;
+  make_problem(c, 0, 0, 0, pb);
+  const int id = c->tp_obs;
+  const size_t npix = (size_t)c->obs[id].k.nx * c->obs[id].k.ny;
+  const size_t nl = (size_t)c->n_leaves;
+  const double *Gd = G;
+  double *a = gn, *b = gk, *d = gv;
+  if (mem != RMC_DEVICE) {
+    if ((r = upload(c, c->tmp4, G, npix * 8, RMC_HOST))) return r;
+    Gd = c->tmp4.as<double>();
+    HIPCHK(c, c->tmp5.ensure(nl * 24));
+    a = c->tmp5.as<double>();
+    b = a + nl;
+    d = b + nl;
+  }
+  HIPCHK(c, hipMemsetAsync(a, 0, nl * 8, c->stream));
+  HIPCHK(c, hipMemsetAsync(b, 0, nl * 8, c->stream));
+  HIPCHK(c, hipMemsetAsync(d, 0, nl * 8, c->stream));
+  HIPCHK(c, c->d_stats.ensure(N_STATS * 8));
+  HIPCHK(c, launch_fill_u64(c->d_stats.as<unsigned long long>(), N_STATS, 0ull, c->stream));
+  const double inv_vth_ref = 1.0 / line_q(c->lines[0], c->T_ref).vth;
+  HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+  HIPCHK(c, launch_image_bwd_tape(c->precision == RMC_FP32_BULK, pb, id, c->tp_n, tape_view(c), Gd, inv_vth_ref, a, b,
+                                  d, c->d_stats.as<unsigned long long>() + S_PEEL_CROSS, c->stream));
   HIPCHK(c, hipEventRecord(c->ev1, c->stream));
   c->image_done = true;
   if (mem != RMC_DEVICE) {

@@ -67,12 +67,32 @@ constexpr unsigned long long PQ_ELEM_MASK = (1ull << PQ_OBS_SHIFT) - 1ull;
 struct PeelQueue {
   PeelJob *jobs;                  // [n_regions][cap]: one region per transport wave
   uint32_t *counts;               // [n_regions]: pushes of each region in the last launch
-  unsigned long long cap;         // jobs per region (pushes beyond it are traced inline)
+  unsigned long long cap;         // jobs per region (a wave stops its slice before it)
   unsigned long long n_regions;
   unsigned long long pushes;      // pushes of the launch
   unsigned long long max_region;  // largest region push count of the launch
   unsigned long long take;        // regions handed out by the ray-cast pass
   unsigned long long lost;        // pushes that found their region full (an error)
+};
+
+// Crossing lists ("tape") of the rays of one image pass, for the adjoint.
+// The rays of a wave (64 consecutive rays) walk in step; the wave keeps a
+// linked list of chunks of TAPE_CHUNK wave iterations, each lane-
+// interleaved (entry of iteration i, lane l at (i % TAPE_CHUNK) * 64 + l),
+// so a wave stores and loads whole 256-B runs of leaf indices and segments.
+constexpr int TAPE_CHUNK = 32;
+constexpr int TAPE_ENTRIES = TAPE_CHUNK * 64;
+struct TapeK {
+  int32_t *leaf;             // [cap][TAPE_ENTRIES] leaf crossed
+  void *seg;                 // [cap][TAPE_ENTRIES] segment (box units), float or double
+  int64_t *next;             // [cap] next chunk of the same wave, -1 at its end
+  int64_t *first;            // [waves] first chunk of the wave, -1 none
+  int32_t *count;            // [rays] crossings recorded for the ray
+  int32_t *pix;              // [rays] image pixel, -1 outside
+  double *wt;                // [rays] w exp(-tau); 0 where exp(-tau) is zero
+  double *x;                 // [rays] x_ext
+  unsigned long long *ctl;   // [0]: chunks requested (beyond cap: none given)
+  unsigned long long cap;    // chunks
 };
 
 struct ProblemK {

@@ -1004,6 +1004,66 @@ __global__ void k_image_fwd(ProblemK pb, int obs, int64_t n, const double *__res
   if (__lane_id() == 0 && v) atomicAdd(ncross, v);
 }
 
+// Adds each lane's (an, ak, av) to leaf `leaf` (< 0: nothing) of the
+// gradients: one sum and one atomic per distinct leaf of the wave (a few
+// when a wave holds rays of two sources); lanes with many distinct leaves
+// fall back to their own atomics after four rounds.  Every lane of the
+// wave must call it (shuffles).
+__device__ __forceinline__ void wave_leaf_add(int leaf, double an, double ak, double av, double *g_n,
+                                              double *g_k, double *g_v, int lane) {
+  unsigned long long m = __ballot(leaf >= 0);
+  for (int round = 0; m && round < 4; ++round) {
+    const int lead = __ffsll((long long)m) - 1;
+    const int l0 = __shfl(leaf, lead);
+    const bool mine = leaf == l0;
+    double sn = mine ? an : 0.0, sk = mine ? ak : 0.0, sv = mine ? av : 0.0;
+    for (int off = 32; off > 0; off >>= 1) {
+      sn += __shfl_xor(sn, off);
+      sk += __shfl_xor(sk, off);
+      sv += __shfl_xor(sv, off);
+    }
+    if (lane == lead) {
+      unsafeAtomicAdd(g_n + l0, sn);
+      unsafeAtomicAdd(g_k + l0, sk);
+      unsafeAtomicAdd(g_v + l0, sv);
+    }
+    if (mine) leaf = -1;
+    m = __ballot(leaf >= 0);
+  }
+  if (leaf >= 0) {
+    unsafeAtomicAdd(g_n + leaf, an);
+    unsafeAtomicAdd(g_k + leaf, ak);
+    unsafeAtomicAdd(g_v + leaf, av);
+  }
+}
+
+// Gradient terms of one crossing (segment seg of leaf record lf) of a ray
+// at x_ext xr with weight g = -G_p w exp(-tau): d/dn_HI, d/dkappa_d and
+// d/dv_los of g tau_c (formulas below).
+template <class R>
+__device__ __forceinline__ void crossing_grad(const ProblemK &pb, const LeafRec<R> &lf, double xr, const R kr[3],
+                                              double seg, double g, double inv_vth_ref, double *an, double *ak,
+                                              double *av) {
+  Opac<R> o;
+  opacity(pb, lf, xr, kr, o);
+  const R b = R(pb.b_ref);
+  const R den = R(1) + b * o.w;
+  R sn = R(0), sv = R(0);
+#pragma unroll
+  for (int i = 0; i < MAX_LINES; ++i) {
+    if (i < pb.n_lines) {
+      const LineK &ln = pb.lines[i];
+      const R a = R(ln.alpha) * lf.irho;
+      sn += R(ln.kfac) * voigt_h<R>(a, o.x[i]);
+      const R dxdw = M<R>::div(-lf.irho * R(ln.inv_mu) * R(ln.s) * (R(1) + b * (R)xr), den * den);
+      sv += R(ln.kfac) * voigt_dhdx<R>(a, o.x[i]) * dxdw;
+    }
+  }
+  *an = g * seg * pb.box_cm * (double)lf.irho * (double)sn;
+  *ak = g * seg * pb.box_cm;
+  *av = g * seg * (double)lf.nl * (double)sv * inv_vth_ref;
+}
+
 // dL/dtheta_c = -G_p w exp(-tau) sum over the ray's crossings of c of
 // dtau/dtheta_c, with tau_c = (nl sum_i kfac_i H_i + kd) seg:
 //   dtau/dn_HI   = seg box irho sum_i kfac_i H_i
@@ -1058,30 +1118,13 @@ __global__ void __launch_bounds__(256) k_image_bwd(ProblemK pb, int obs, int64_t
     double an = 0.0, ak = 0.0, av = 0.0;
     if (walking) {
       const LeafRec<R> lf = load_leaf<R>(pb.leaves, c.leaf);
-      Opac<R> o;
-      opacity(pb, lf, xr, kr, o);
       double face[3], lo[3], hi[3];
       int em;
       const double te = exit_dist(c, pb.L, p, k, face, lo, hi, &em, sizeof(R) == 4 ? pb.obs[obs].kinv : nullptr);
       const double td = domain_dist_leaf(lf, pb.domain, pb.dom, p, k);
       const double seg = td <= te ? td : te;
-      const R b = R(pb.b_ref);
-      const R den = R(1) + b * o.w;
-      R sn = R(0), sv = R(0);
-#pragma unroll
-      for (int i = 0; i < MAX_LINES; ++i) {
-        if (i < pb.n_lines) {
-          const LineK &ln = pb.lines[i];
-          const R a = R(ln.alpha) * lf.irho;
-          sn += R(ln.kfac) * voigt_h<R>(a, o.x[i]);
-          const R dxdw = M<R>::div(-lf.irho * R(ln.inv_mu) * R(ln.s) * (R(1) + b * (R)xr), den * den);
-          sv += R(ln.kfac) * voigt_dhdx<R>(a, o.x[i]) * dxdw;
-        }
-      }
+      crossing_grad<R>(pb, lf, xr, kr, seg, g, inv_vth_ref, &an, &ak, &av);
       leaf = c.leaf;
-      an = g * seg * pb.box_cm * (double)lf.irho * (double)sn;
-      ak = g * seg * pb.box_cm;
-      av = g * seg * (double)lf.nl * (double)sv * inv_vth_ref;
       if (td <= te) {
         walking = false;
       } else {
@@ -1098,35 +1141,161 @@ __global__ void __launch_bounds__(256) k_image_bwd(ProblemK pb, int obs, int64_t
         }
       }
     }
-    // one sum and one atomic per distinct leaf of the wave (a few when a
-    // wave holds rays of two sources); lanes with many distinct leaves
-    // fall back to their own atomics after four rounds
-    unsigned long long m = __ballot(leaf >= 0);
-    for (int round = 0; m && round < 4; ++round) {
-      const int lead = __ffsll((long long)m) - 1;
-      const int l0 = __shfl(leaf, lead);
-      const bool mine = leaf == l0;
-      double sn = mine ? an : 0.0, sk = mine ? ak : 0.0, sv2 = mine ? av : 0.0;
-      for (int off = 32; off > 0; off >>= 1) {
-        sn += __shfl_xor(sn, off);
-        sk += __shfl_xor(sk, off);
-        sv2 += __shfl_xor(sv2, off);
-      }
-      if (lane == lead) {
-        unsafeAtomicAdd(g_n + l0, sn);
-        unsafeAtomicAdd(g_k + l0, sk);
-        unsafeAtomicAdd(g_v + l0, sv2);
-      }
-      if (mine) leaf = -1;
-      m = __ballot(leaf >= 0);
-    }
-    if (leaf >= 0) {
-      unsafeAtomicAdd(g_n + leaf, an);
-      unsafeAtomicAdd(g_k + leaf, ak);
-      unsafeAtomicAdd(g_v + leaf, av);
-    }
+    wave_leaf_add(leaf, an, ak, av, g_n, g_k, g_v, lane);
   }
   unsigned long long v = nc;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+  if (lane == 0 && v) atomicAdd(ncross, v);
+}
+
+// Peel-off image of fixed rays that also records each ray's crossings (the
+// tape read by k_image_bwd_tape).  The 64 rays of a wave walk in step, one
+// leaf per iteration; every TAPE_CHUNK iterations the wave takes a new
+// chunk (one atomic) and links it to its last one.  A wave that finds no
+// chunk left goes on without recording (the host sees the count of chunks
+// requested exceed the capacity and runs the pass again with more).  The
+// walk and the optical depth are those of ray_tau, so the image equals the
+// one k_image_fwd makes, up to the order of the additions.
+template <class R>
+__global__ void __launch_bounds__(256) k_image_fwd_tape(ProblemK pb, int obs, int64_t n,
+                                                        const double *__restrict__ orig,
+                                                        const double *__restrict__ x_ext,
+                                                        const double *__restrict__ w, double *__restrict__ image,
+                                                        unsigned long long *__restrict__ ncross, TapeK tp) {
+  extern __shared__ int lds[];
+  int *stk = lds + threadIdx.x;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t wave = r >> 6;
+  const int lane = __lane_id();
+  const ObsK &ob = pb.obs[obs];
+  const double *k = ob.k;
+  const R kr[3] = {(R)k[0], (R)k[1], (R)k[2]};
+  const double *kinv = sizeof(R) == 4 ? ob.kinv : nullptr;
+  const double cut = TauCut<double>::v;
+  bool walking = false;
+  int pix = -1;
+  double xr = 0.0, tau = 0.0;
+  double p[3] = {0.0, 0.0, 0.0};
+  Cell c;
+  uint32_t nc = 0;
+  if (r < n) {
+    p[0] = orig[3 * r]; p[1] = orig[3 * r + 1]; p[2] = orig[3 * r + 2];
+    pix = pixel_of(ob, p);
+    xr = x_ext[r];
+    int X[3];
+    if (pix >= 0 && int_coords(pb.L, p, k, X)) {
+      descend(pb.nodes, pb.L, 0, 0, X, stk, blockDim.x, c);
+      walking = true;
+    }
+  }
+  if (lane == 0) tp.first[wave] = -1;
+  int64_t chunk = -1;   // wave-uniform
+  for (uint32_t i = 0; __ballot(walking); ++i) {
+    if (i % TAPE_CHUNK == 0) {
+      unsigned long long q = 0;
+      if (lane == 0) q = atomicAdd(tp.ctl, 1ull);
+      q = __shfl(q, 0);
+      const int64_t nxt = q < tp.cap ? (int64_t)q : -1;
+      if (lane == 0) {
+        if (i == 0) tp.first[wave] = nxt;
+        else if (chunk >= 0) tp.next[chunk] = nxt;
+        if (nxt >= 0) tp.next[nxt] = -1;
+      }
+      chunk = nxt;
+    }
+    if (walking) {
+      const LeafRec<R> lf = load_leaf<R>(pb.leaves, c.leaf);
+      Opac<R> o;
+      opacity(pb, lf, xr, kr, o);
+      double face[3], lo[3], hi[3];
+      int em;
+      const double te = exit_dist(c, pb.L, p, k, face, lo, hi, &em, kinv);
+      const double td = domain_dist_leaf(lf, pb.domain, pb.dom, p, k);
+      const double seg = td <= te ? td : te;
+      ++nc;
+      if (chunk >= 0) {
+        const size_t e = (size_t)chunk * TAPE_ENTRIES + (size_t)(i % TAPE_CHUNK) * 64 + lane;
+        tp.leaf[e] = c.leaf;
+        ((R *)tp.seg)[e] = (R)seg;
+      }
+      tau += (double)o.ktot * seg;
+      if (td <= te || tau >= cut) {
+        walking = false;
+      } else {
+        double pn[3];
+        exit_point(te, em, p, k, face, lo, hi, pn);
+        p[0] = pn[0]; p[1] = pn[1]; p[2] = pn[2];
+        wrap_slab(pb.domain, p, k);
+        int X[3];
+        if (!int_coords(pb.L, p, k, X) || nc >= MAX_CROSS) {
+          walking = false;
+        } else {
+          relocate(pb.nodes, pb.L, X, stk, blockDim.x, c);
+        }
+      }
+    }
+  }
+  if (r < n) {
+    const double wt = (pix >= 0 && tau < cut) ? w[r] * exp(-tau) : 0.0;
+    if (wt != 0.0) unsafeAtomicAdd(image + pix, wt);
+    tp.count[r] = (int32_t)nc;
+    tp.pix[r] = pix;
+    tp.wt[r] = wt;
+    tp.x[r] = xr;
+  }
+  unsigned long long v = nc;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+  if (lane == 0 && v) atomicAdd(ncross, v);
+}
+
+// Adjoint of the image from the tape of the last k_image_fwd_tape pass (same
+// rays, same wave of 64 rays per 64 lanes): the crossings are read back in
+// the order they were walked, so no geometry and no optical depth are
+// computed again.  The gradient terms and their per-leaf wave sums are
+// those of k_image_bwd.
+template <class R>
+__global__ void __launch_bounds__(256) k_image_bwd_tape(ProblemK pb, int obs, int64_t n, TapeK tp,
+                                                        const double *__restrict__ G, double inv_vth_ref,
+                                                        double *__restrict__ g_n, double *__restrict__ g_k,
+                                                        double *__restrict__ g_v,
+                                                        unsigned long long *__restrict__ ncross) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t wave = r >> 6;
+  const int lane = __lane_id();
+  const double *k = pb.obs[obs].k;
+  const R kr[3] = {(R)k[0], (R)k[1], (R)k[2]};
+  double g = 0.0, xr = 0.0;
+  int cnt = 0;
+  if (r < n) {
+    const double wt = tp.wt[r];
+    if (wt != 0.0) {
+      g = -G[tp.pix[r]] * wt;
+      if (g != 0.0) {
+        cnt = tp.count[r];
+        xr = tp.x[r];
+      }
+    }
+  }
+  // wave iterations needed: the longest crossing list among lanes with a
+  // gradient (every lane's list starts at the wave's first iteration)
+  int m = cnt;
+  for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off));
+  int64_t chunk = m > 0 ? tp.first[wave] : -1;
+  for (int i = 0; i < m; ++i) {
+    if (i > 0 && i % TAPE_CHUNK == 0) chunk = tp.next[chunk];
+    if (chunk < 0) break;   // an incomplete tape (the host never passes one)
+    int leaf = -1;
+    double an = 0.0, ak = 0.0, av = 0.0;
+    if (i < cnt) {
+      const size_t e = (size_t)chunk * TAPE_ENTRIES + (size_t)(i % TAPE_CHUNK) * 64 + lane;
+      leaf = tp.leaf[e];
+      const double seg = (double)((const R *)tp.seg)[e];
+      const LeafRec<R> lf = load_leaf<R>(pb.leaves, leaf);
+      crossing_grad<R>(pb, lf, xr, kr, seg, g, inv_vth_ref, &an, &ak, &av);
+    }
+    wave_leaf_add(leaf, an, ak, av, g_n, g_k, g_v, lane);
+  }
+  unsigned long long v = (unsigned long long)cnt;
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
   if (lane == 0 && v) atomicAdd(ncross, v);
 }
@@ -1297,6 +1466,37 @@ hipError_t launch_image_bwd(bool fp32, const ProblemK &pb, int obs, int64_t n, c
                        inv_vth_ref, gn, gk, gv, ncross);
   else
     hipLaunchKernelGGL(k_image_bwd<double>, dim3(blocks_for(n, b)), dim3(b), lds, st, pb, obs, n, orig, x, w, G,
+                       inv_vth_ref, gn, gk, gv, ncross);
+  return hipGetLastError();
+}
+
+int64_t tape_waves(int64_t n) { return (int64_t)blocks_for(n, 256) * 4; }
+
+hipError_t launch_image_fwd_tape(bool fp32, const ProblemK &pb, int obs, int64_t n, const double *orig,
+                                 const double *x, const double *w, double *image, unsigned long long *ncross,
+                                 const TapeK &tp, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int b = 256;
+  const size_t lds = (size_t)(pb.L > 0 ? pb.L : 1) * b * sizeof(int);
+  if (fp32)
+    hipLaunchKernelGGL(k_image_fwd_tape<float>, dim3(blocks_for(n, b)), dim3(b), lds, st, pb, obs, n, orig, x, w,
+                       image, ncross, tp);
+  else
+    hipLaunchKernelGGL(k_image_fwd_tape<double>, dim3(blocks_for(n, b)), dim3(b), lds, st, pb, obs, n, orig, x, w,
+                       image, ncross, tp);
+  return hipGetLastError();
+}
+
+hipError_t launch_image_bwd_tape(bool fp32, const ProblemK &pb, int obs, int64_t n, const TapeK &tp,
+                                 const double *G, double inv_vth_ref, double *gn, double *gk, double *gv,
+                                 unsigned long long *ncross, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int b = 256;
+  if (fp32)
+    hipLaunchKernelGGL(k_image_bwd_tape<float>, dim3(blocks_for(n, b)), dim3(b), 0, st, pb, obs, n, tp, G,
+                       inv_vth_ref, gn, gk, gv, ncross);
+  else
+    hipLaunchKernelGGL(k_image_bwd_tape<double>, dim3(blocks_for(n, b)), dim3(b), 0, st, pb, obs, n, tp, G,
                        inv_vth_ref, gn, gk, gv, ncross);
   return hipGetLastError();
 }

@@ -35,6 +35,15 @@ hipError_t launch_image_fwd(bool fp32, const ProblemK &pb, int obs, int64_t n, c
 hipError_t launch_image_bwd(bool fp32, const ProblemK &pb, int obs, int64_t n, const double *orig,
                             const double *x, const double *w, const double *G, double inv_vth_ref,
                             double *gn, double *gk, double *gv, unsigned long long *ncross, hipStream_t st);
+// Tape-recording image pass and its adjoint (the tape's per-wave arrays
+// hold tape_waves(n) entries: every wave of the launch grid).
+int64_t tape_waves(int64_t n);
+hipError_t launch_image_fwd_tape(bool fp32, const ProblemK &pb, int obs, int64_t n, const double *orig,
+                                 const double *x, const double *w, double *image, unsigned long long *ncross,
+                                 const TapeK &tp, hipStream_t st);
+hipError_t launch_image_bwd_tape(bool fp32, const ProblemK &pb, int obs, int64_t n, const TapeK &tp,
+                                 const double *G, double inv_vth_ref, double *gn, double *gk, double *gv,
+                                 unsigned long long *ncross, hipStream_t st);
 hipError_t launch_hist(int64_t n, const int32_t *status, const double *x, int nbins, double x_min, double span,
                        unsigned long long *h, hipStream_t st);
 hipError_t launch_batch_reset(const ProblemK *d_probs, int n, unsigned long long *d_next, hipStream_t st);

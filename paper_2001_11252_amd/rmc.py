@@ -91,6 +91,8 @@ _sig = {
     "rmc_tau": (C.c_int, [_P, _i64, _P, _P, _P, _P, C.c_int]),
     "rmc_raycast_image": (C.c_int, [_P, C.c_int, _i64, _P, _P, _P, _P, C.c_int]),
     "rmc_raycast_image_backward": (C.c_int, [_P, C.c_int, _i64, _P, _P, _P, _P, _P, _P, _P, C.c_int]),
+    "rmc_raycast_image_tape": (C.c_int, [_P, C.c_int, _i64, _P, _P, _P, _P, C.c_int]),
+    "rmc_raycast_image_backward_tape": (C.c_int, [_P, _P, _P, _P, _P, C.c_int]),
     "rmc_image_stats": (C.c_int, [_P, C.POINTER(C.c_uint64), C.POINTER(C.c_double)]),
     "rmc_batch_run": (C.c_int, [_P, C.c_int, _P, _P, C.POINTER(RmcRunStats), C.POINTER(RmcRunStats)]),
     "rmc_batch_begin": (C.c_int, [_P, C.c_int, _P, _P]),
@@ -330,6 +332,40 @@ class Context:
                                                 _ptr(gk), _ptr(gv), HOST), "raycast_image_backward")
         return gn, gk, gv
 
+    def raycast_image_tape(self, oid, orig, x_ext, w):
+        """raycast_image that keeps the rays' crossing lists on the device
+        for raycast_image_backward_tape (tape_serial counts these calls)."""
+        ny, nx, _ = self.observers[oid]
+        if _is_dev(orig):
+            import torch
+            img = torch.zeros((ny, nx), dtype=torch.float64, device=orig.device)
+            self._chk(_L.rmc_raycast_image_tape(self._h, oid, orig.shape[0], _ptr(orig), _ptr(x_ext), _ptr(w),
+                                                _ptr(img), DEVICE), "raycast_image_tape")
+        else:
+            o, x, ww = _host(orig, np.float64), _host(x_ext, np.float64), _host(w, np.float64)
+            img = np.zeros((ny, nx))
+            self._chk(_L.rmc_raycast_image_tape(self._h, oid, len(x), _ptr(o), _ptr(x), _ptr(ww), _ptr(img), HOST),
+                      "raycast_image_tape")
+        self.tape_serial = getattr(self, "tape_serial", 0) + 1
+        return img
+
+    def raycast_image_backward_tape(self, grad_image):
+        """(g_nhi, g_kd, g_vlos) per leaf of sum(grad_image * image) for the
+        rays of the last raycast_image_tape call, read from its tape."""
+        n = self.n_leaves
+        if _is_dev(grad_image):
+            import torch
+            gn, gk, gv = (torch.zeros(n, dtype=torch.float64, device=grad_image.device) for _ in range(3))
+            G = grad_image.contiguous().to(torch.float64)
+            self._chk(_L.rmc_raycast_image_backward_tape(self._h, _ptr(G), _ptr(gn), _ptr(gk), _ptr(gv), DEVICE),
+                      "raycast_image_backward_tape")
+            return gn, gk, gv
+        G = _host(grad_image, np.float64)
+        gn, gk, gv = np.zeros(n), np.zeros(n), np.zeros(n)
+        self._chk(_L.rmc_raycast_image_backward_tape(self._h, _ptr(G), _ptr(gn), _ptr(gk), _ptr(gv), HOST),
+                  "raycast_image_backward_tape")
+        return gn, gk, gv
+
     def image_stats(self):
         """(ray-cell crossings, device ms) of the last image call."""
         n = C.c_uint64(0)
@@ -408,22 +444,29 @@ def _make_raycast_fn():
 
     class RayCastImage(torch.autograd.Function):
         """Peel-off image of fixed rays as a differentiable function of the
-        per-leaf gas: image = f(n_HI, kappa_d, v).  The backward pass replays
-        each ray on the GPU (rmc_raycast_image_backward); the gradient with
+        per-leaf gas: image = f(n_HI, kappa_d, v).  The forward pass keeps
+        the rays' crossing lists (rmc_raycast_image_tape) and the backward
+        pass reads them (rmc_raycast_image_backward_tape); if the context has
+        recorded another tape since, the backward sets this call's gas again
+        and replays the rays (rmc_raycast_image_backward).  The gradient with
         respect to v is dL/dv_los times the observer direction."""
 
         @staticmethod
         def forward(ctx, n_hi, kappa_d, v, rmc_ctx, T, oid, orig, x_ext, w, k_obs):
-            rmc_ctx.set_gas(n_hi.detach().cpu().numpy(), T, v.detach().cpu().numpy(),
-                            kappa_d.detach().cpu().numpy())
-            img = rmc_ctx.raycast_image(oid, orig, x_ext, w)
-            ctx.rmc = (rmc_ctx, oid, orig, x_ext, w, k_obs)
+            gas = (n_hi.detach().cpu().numpy(), T, v.detach().cpu().numpy(), kappa_d.detach().cpu().numpy())
+            rmc_ctx.set_gas(*gas)
+            img = rmc_ctx.raycast_image_tape(oid, orig, x_ext, w)
+            ctx.rmc = (rmc_ctx, oid, orig, x_ext, w, k_obs, gas, rmc_ctx.tape_serial)
             return img
 
         @staticmethod
         def backward(ctx, grad_image):
-            rmc_ctx, oid, orig, x_ext, w, k_obs = ctx.rmc
-            gn, gk, gv = rmc_ctx.raycast_image_backward(oid, orig, x_ext, w, grad_image)
+            rmc_ctx, oid, orig, x_ext, w, k_obs, gas, serial = ctx.rmc
+            if rmc_ctx.tape_serial == serial:
+                gn, gk, gv = rmc_ctx.raycast_image_backward_tape(grad_image)
+            else:
+                rmc_ctx.set_gas(*gas)
+                gn, gk, gv = rmc_ctx.raycast_image_backward(oid, orig, x_ext, w, grad_image)
             kv = torch.as_tensor(k_obs, dtype=gv.dtype, device=gv.device)
             return gn, gk, gv[:, None] * kv[None, :], None, None, None, None, None, None, None
 

@@ -368,7 +368,7 @@ def gaussian_field(n, slope=-3.0, seed=0):
     nz = k2 > 0
     amp[nz] = k2[nz] ** (slope / 4.0)
     noise = rng.standard_normal((n, n, n))
-    f = np.fft.irfftn(np.fft.rfftn(noise) * amp, s=(n, n, n))
+    f = np.fft.irfftn(np.fft.rfftn(noise) * amp, s=(n, n, n), axes=(0, 1, 2))
     f -= f.mean()
     f /= f.std()
     return f.astype(np.float32)

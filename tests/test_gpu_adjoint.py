@@ -122,3 +122,68 @@ def test_autograd_function(orc, galaxy):
     gvz = v.grad.cpu().numpy()
     assert np.allclose(gvz[:, 2], gv, rtol=1e-12, atol=1e-300)
     assert np.all(gvz[:, :2] == 0.0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_tape_matches_replay(orc, galaxy, prec):
+    # the backward read from the forward's crossing lists gives the
+    # replaying backward's gradients (summation order aside; the float
+    # path keeps its segments as float)
+    from paper_2001_11252_amd import rmc
+    pb = galaxy
+    orig, x, w, G = _rays(pb)
+    ctx = rmc.Context.from_problem(pb, prec, sources=False)
+    with pytest.raises(rmc.RmcError, match="no tape"):
+        ctx.raycast_image_backward_tape(G)
+    img = ctx.raycast_image(0, orig, x, w)
+    nf, _ = ctx.image_stats()
+    ref = ctx.raycast_image_backward(0, orig, x, w, G)
+    img_t = ctx.raycast_image_tape(0, orig, x, w)
+    nf_t, _ = ctx.image_stats()
+    got = ctx.raycast_image_backward_tape(G)
+    nb_t, mb_t = ctx.image_stats()
+    assert nf_t == nf and 0 < nb_t <= nf_t and mb_t > 0
+    assert np.allclose(img_t, img, rtol=1e-13, atol=0)
+    tol = 1e-10 if prec == "fp64" else 1e-5
+    for a, b in zip(got, ref):
+        assert np.count_nonzero(b) > 100
+        assert np.abs(a - b).max() <= tol * np.abs(b).max()
+    # the tape is kept for further backward calls of the same model
+    again = ctx.raycast_image_backward_tape(2.0 * G)
+    for a, b in zip(again, got):
+        assert np.abs(a - 2.0 * b).max() <= 1e-12 * np.abs(b).max()
+    # and dropped when the model changes
+    ctx.set_gas(pb.gas.n_hi, pb.gas.T, pb.gas.v, pb.gas.kappa_d)
+    with pytest.raises(rmc.RmcError, match="no tape"):
+        ctx.raycast_image_backward_tape(G)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_tape_grows_for_long_rays(orc, prec):
+    # diagonal rays through a periodic slab of 64^3 leaves cross ~190 leaves,
+    # more than the tape's first guess (128 per ray): the forward pass asks
+    # for more chunks and runs again; the results still match the replay
+    from paper_2001_11252_amd import rmc
+    s0 = lambda ln, T: orc.line_quantities(ln, T)["sigma0"]
+    pb = W.static_slab(s0, 20.0, 1e4, 1, level=6)
+    k = np.ones(3) / np.sqrt(3.0)
+    pb.observers = [W.Observer(tuple(k), 16, 16, 1, (-0.8, 0.8, -0.8, 0.8), -50.0, 50.0)]
+    rng = np.random.default_rng(3)
+    n = 3000
+    orig = np.column_stack([rng.uniform(0.2, 0.8, n), rng.uniform(0.2, 0.8, n), np.full(n, 1e-3)])
+    x = rng.uniform(-4.0, 4.0, n)
+    w = np.full(n, 1.0 / (4.0 * np.pi))
+    G = rng.standard_normal((16, 16))
+    ctx = rmc.Context.from_problem(pb, prec, sources=False)
+    img = ctx.raycast_image(0, orig, x, w)
+    nf, _ = ctx.image_stats()
+    assert nf > 150 * n
+    ref = ctx.raycast_image_backward(0, orig, x, w, G)
+    img_t = ctx.raycast_image_tape(0, orig, x, w)
+    assert ctx.image_stats()[0] == nf
+    got = ctx.raycast_image_backward_tape(G)
+    assert np.allclose(img_t, img, rtol=1e-13, atol=0)
+    tol = 1e-10 if prec == "fp64" else 1e-5
+    for a, b in zip(got, ref):
+        assert np.abs(a - b).max() <= tol * np.abs(b).max()
+
