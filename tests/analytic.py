@@ -1,4 +1,7 @@
-"""Closed forms the tests compare with (written from their papers)."""
+"""Closed forms the tests compare with (written from their papers), and the
+loader of the values the paper prints (tests/golden/)."""
+import os
+
 import numpy as np
 from scipy import integrate
 
@@ -26,3 +29,27 @@ def r2a_expected_counts(x_in, a, edges, n):
         vals = np.array([hummer_r2a(x_in, xp, a) for xp in xm])
         out.append(integrate.simpson(vals, x=xm) / phi * n)
     return np.array(out)
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def golden(name):
+    """Rows of the fixture tests/golden/<name>.txt (values the paper prints,
+    cited in the file's header): a list of whitespace-separated fields,
+    numbers converted to float."""
+    rows = []
+    with open(f"{GOLDEN}/{name}.txt") as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if not line:
+                continue
+            row = []
+            for tok in line.split():
+                try:
+                    row.append(float(tok))
+                except ValueError:
+                    row.append(tok)
+            rows.append(row)
+    return rows
+

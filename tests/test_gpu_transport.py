@@ -150,6 +150,30 @@ def test_first_flight_and_forward_budget(rmc, orc, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_forward_path_precision_in_one_cell(rmc, orc, prec):
+    # the paper's error budget for packets that scatter forward in one cell
+    # (Sect. 4.5; tests/golden/path_precision): exact without scattering,
+    # then within +-9e-16 at tau0 = 10 and +-2.5e-13 at tau0 = 1e6 (about a
+    # million segments per packet) for 98% of the packets
+    from tests.analytic import golden
+    n = 2000
+    for tau0, frac, lo, hi in golden("path_precision"):
+        pb = W.static_sphere(s0(orc), tau0, 1e4, n, level=0)
+        c = rmc.Context.from_problem(pb, prec, observers=False)
+        c.set_option(rmc.OPT_FORWARD_ONLY, 1)
+        st = c.run(5, 0, n)
+        check_conservation(st, n)
+        o = c.get_packets()
+        c.close()
+        assert np.all(o["status"] == rmc.ST_ESCAPED)
+        if tau0 > 1e5:
+            assert o["n_scat"].mean() > 0.9 * tau0
+        rel = o["path"] / 0.5 - 1
+        inside = (rel >= lo) & (rel <= hi)
+        assert inside.mean() >= frac, (tau0, np.percentile(np.abs(rel), 98))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_dusty_sphere_with_peel_off_matches_oracle(rmc, orc, prec):
     # C2 geometry and mesh at a reduced line-centre optical depth; errors of
     # the peel-off estimates from the spread of 10 independent packet ranges

@@ -10,13 +10,29 @@ from scipy import integrate
 from scipy.special import wofz
 
 from paper_2001_11252_amd import workloads as W
+from tests.analytic import golden
 
 
 def test_voigt_parameter_printed_values(orc):
-    # Sect. 3.4.2 prints a ~ 0.0149, 0.0047, 0.00047 for Lya at 10, 1e2, 1e4 K
-    for T, a_printed in ((10.0, 0.0149), (1e2, 0.0047), (1e4, 0.00047)):
+    # the paper's values of a for Lya at 10, 1e2, 1e4 K (Sect. 3.4.2)
+    rows = golden("voigt_parameter_lya")
+    assert len(rows) == 3
+    for T, a_printed in rows:
         a = orc.line_quantities(W.LYA, T)["a"]
         assert abs(a / a_printed - 1) < 0.005, (T, a)
+
+
+def test_line_and_dust_data_are_the_papers():
+    # Table 1 (lambda_0, A_ul, f_lu) and the Lya dust defaults (Sect. 3.2.2)
+    lines = {"Lya": W.LYA, "MgII2796": W.MGII_2796, "MgII2804": W.MGII_2804}
+    rows = golden("atomic_data")
+    assert {r[0] for r in rows} == set(lines)
+    for name, lam, A, f in rows:
+        ln = lines[name]
+        assert (ln.lambda0_A, ln.A_ul, ln.f_lu) == (lam, A, f), name
+    d = dict(golden("dust_defaults"))
+    pb = W.static_sphere(lambda ln, T: 1.0, 1.0, 1e4, 1)
+    assert (pb.dust.albedo, pb.dust.g) == (d["albedo"], d["g"])
 
 
 def test_voigt_parameter_scalings(orc):
