@@ -93,7 +93,8 @@ typedef struct {
   uint64_t scatterings;       /* line scatterings                            */
   uint64_t dust_scatterings;
   uint64_t crossings;         /* transport ray-cell segments run to their end */
-  uint64_t peel_rays;
+  uint64_t peel_rays;         /* peel-off rays whose pixel and bin lie in a
+                                 cube (one per event and observer)            */
   uint64_t peel_crossings;    /* ray-cell segments of peel-off rays           */
   uint64_t peel_dropped;      /* peel-off deposits outside a cube             */
   uint64_t peel_deferred;     /* peel-off rays handed from the transport

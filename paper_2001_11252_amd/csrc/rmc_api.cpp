@@ -31,6 +31,9 @@ const double E_CHARGE = 4.80320471e-10;
 const double M_ELECTRON = 9.1093837015e-28;
 const double AMU_G = 1.66053906660e-24;
 
+// Device allocation owned by a context; released explicitly (rmc_destroy
+// lists every buffer of the context), since observer records holding one
+// are copied when their vector grows.
 struct DevBuf {
   void *p = nullptr;
   size_t bytes = 0;
@@ -541,6 +544,8 @@ rmc_status rmc_create(rmc_ctx **out, int device, int precision) {
       hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
       hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
       hipEventCreate(&c->ev2) != hipSuccess) {
+    for (hipEvent_t e : {c->ev0, c->ev1, c->ev2})
+      if (e) (void)hipEventDestroy(e);
     delete c;
     return RMC_EDEVICE;
   }
@@ -558,7 +563,9 @@ void rmc_destroy(rmc_ctx *c) {
   DevBuf *bufs[] = {&c->nodes, &c->leaves, &c->spos, &c->sdir, &c->sx, &c->o_status, &c->o_x, &c->o_k,
                     &c->o_pos, &c->o_nscat, &c->o_path, &c->d_stats, &c->d_next, &c->d_prob, &c->d_starts,
                     &c->tmp1, &c->tmp2, &c->tmp3, &c->tmp4, &c->tmp5, &c->b_probs, &c->b_starts,
-                    &c->slots, &c->d_slice, &c->pq_ctl, &c->pq_jobs, &c->pq_counts};
+                    &c->slots, &c->d_slice, &c->pq_ctl, &c->pq_jobs, &c->pq_counts, &c->tp_leaf,
+                    &c->tp_seg, &c->tp_next, &c->tp_first, &c->tp_count, &c->tp_pix, &c->tp_wt, &c->tp_x,
+                    &c->tp_ctl};
   for (DevBuf *b : bufs) b->release();
   for (auto &o : c->obs) o.cube.release();
   if (c->ev0) (void)hipEventDestroy(c->ev0);

@@ -187,3 +187,22 @@ def test_tape_grows_for_long_rays(orc, prec):
     for a, b in zip(got, ref):
         assert np.abs(a - b).max() <= tol * np.abs(b).max()
 
+
+def test_destroy_releases_the_tape(orc, galaxy):
+    # a context's crossing lists (here ~150 MB: the rays ten times over) go
+    # back to the device when the context is destroyed
+    import torch
+    from paper_2001_11252_amd import rmc
+    pb = galaxy
+    orig, x, w, G = _rays(pb)
+    orig, x, w = np.tile(orig, (10, 1)), np.tile(x, 10), np.tile(w, 10)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    for _ in range(3):
+        ctx = rmc.Context.from_problem(pb, "fp64", sources=False)
+        ctx.raycast_image_tape(0, orig, x, w)
+        ctx.raycast_image_backward_tape(G)
+        ctx.close()
+    torch.cuda.synchronize()
+    assert free0 - torch.cuda.mem_get_info()[0] < (64 << 20)
+
