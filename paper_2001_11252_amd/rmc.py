@@ -452,20 +452,27 @@ def _make_raycast_fn():
         respect to v is dL/dv_los times the observer direction."""
 
         @staticmethod
+        def _set_gas(rmc_ctx, n_hi, kappa_d, v, T):
+            rmc_ctx.set_gas(n_hi.detach().cpu().numpy(), T, v.detach().cpu().numpy(),
+                            kappa_d.detach().cpu().numpy())
+
+        @staticmethod
         def forward(ctx, n_hi, kappa_d, v, rmc_ctx, T, oid, orig, x_ext, w, k_obs):
-            gas = (n_hi.detach().cpu().numpy(), T, v.detach().cpu().numpy(), kappa_d.detach().cpu().numpy())
-            rmc_ctx.set_gas(*gas)
+            RayCastImage._set_gas(rmc_ctx, n_hi, kappa_d, v, T)
             img = rmc_ctx.raycast_image_tape(oid, orig, x_ext, w)
-            ctx.rmc = (rmc_ctx, oid, orig, x_ext, w, k_obs, gas, rmc_ctx.tape_serial)
+            # this call's gas, kept by reference for the replay fallback
+            ctx.save_for_backward(n_hi, kappa_d, v)
+            ctx.rmc = (rmc_ctx, oid, orig, x_ext, w, k_obs, T, rmc_ctx.tape_serial)
             return img
 
         @staticmethod
         def backward(ctx, grad_image):
-            rmc_ctx, oid, orig, x_ext, w, k_obs, gas, serial = ctx.rmc
+            rmc_ctx, oid, orig, x_ext, w, k_obs, T, serial = ctx.rmc
             if rmc_ctx.tape_serial == serial:
                 gn, gk, gv = rmc_ctx.raycast_image_backward_tape(grad_image)
             else:
-                rmc_ctx.set_gas(*gas)
+                n_hi, kappa_d, v = ctx.saved_tensors
+                RayCastImage._set_gas(rmc_ctx, n_hi, kappa_d, v, T)
                 gn, gk, gv = rmc_ctx.raycast_image_backward(oid, orig, x_ext, w, grad_image)
             kv = torch.as_tensor(k_obs, dtype=gv.dtype, device=gv.device)
             return gn, gk, gv[:, None] * kv[None, :], None, None, None, None, None, None, None

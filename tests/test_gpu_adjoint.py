@@ -206,3 +206,28 @@ def test_destroy_releases_the_tape(orc, galaxy):
     torch.cuda.synchronize()
     assert free0 - torch.cuda.mem_get_info()[0] < (64 << 20)
 
+
+def test_autograd_falls_back_to_replay(orc, galaxy):
+    # a second forward call records its own tape; the backward of the first
+    # then sets the first call's gas again and replays its rays
+    import torch
+    from paper_2001_11252_amd import rmc
+    pb = galaxy
+    orig, x, w, G = _rays(pb)
+    dev = torch.device("cuda:0")
+    ctx = rmc.Context.from_problem(pb, "fp64", sources=False)
+    fn = rmc.raycast_image_fn()
+    t = lambda a, grad=False: torch.tensor(a, dtype=torch.float64, device=dev, requires_grad=grad)
+    n1, k1, v1 = t(pb.gas.n_hi, True), t(pb.gas.kappa_d, True), t(pb.gas.v, True)
+    n2, k2, v2 = t(1.3 * pb.gas.n_hi, True), t(pb.gas.kappa_d, True), t(pb.gas.v, True)
+    args = (ctx, pb.gas.T, 0, t(orig), t(x), t(w), pb.observers[0].k)
+    img1 = fn.apply(n1, k1, v1, *args)
+    img2 = fn.apply(n2, k2, v2, *args)
+    assert not torch.allclose(img1, img2)
+    (img1 * t(G)).sum().backward()
+    ctx.set_gas(pb.gas.n_hi, pb.gas.T, pb.gas.v, pb.gas.kappa_d)
+    gn, gk, gv = ctx.raycast_image_backward(0, orig, x, w, G)
+    assert np.allclose(n1.grad.cpu().numpy(), gn, rtol=1e-12, atol=1e-300)
+    assert np.allclose(k1.grad.cpu().numpy(), gk, rtol=1e-12, atol=1e-300)
+    assert np.allclose(v1.grad.cpu().numpy()[:, 2], gv, rtol=1e-12, atol=1e-300)
+
