@@ -492,7 +492,7 @@ def main():
     if not a.no_cpu_baseline:
         from oracle import oracle as O
         cores = max(1, min(16, os.cpu_count() or 1))
-        n_cpu = a.cpu_packets or 8 * cores
+        n_cpu = a.cpu_packets or 12 * cores
         t0 = time.perf_counter()
         r = O.run(pb, pb.seed, first=0, n=n_cpu, threads=cores)
         dt = time.perf_counter() - t0
