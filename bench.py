@@ -444,6 +444,16 @@ def main():
     # segment, and the first leaf of every peel-off ray) over its average
     # device duration; the rest of the peel-off rays is the ray-cast pass
     avg_ms = sum(kms) / nsteps
+    traffic = measured_traffic(head)
+    # the same launch against the HBM roof: algorithmic bytes (a leaf record
+    # and a node entry per transport segment; events inside a leaf and the
+    # peel-off tests use the record the lane holds) and, when the profiler's
+    # counters match these sources, the bytes moved
+    alg_bytes = tot["crossings"] * BYTES_PER_CROSSING[head] / nsteps
+    hbm = {"peak_GBps": 8000.0, "algorithmic_GBps": alg_bytes / (avg_ms * 1e-3) / 1e9,
+           "measured_GBps": None if traffic is None else traffic / (avg_ms * 1e-3) / 1e9}
+    hbm["frac_algorithmic"] = hbm["algorithmic_GBps"] / 8000.0
+    hbm["frac_measured"] = None if traffic is None else hbm["measured_GBps"] / 8000.0
     transport_cross = tot["crossings"] + tot["peel_rays"]
     flops_per_launch = (FLOP_PER_SCATTERING * tot["scatterings"] + FLOP_PER_CROSSING * transport_cross) / nsteps
     achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
@@ -480,8 +490,9 @@ def main():
                    "leaves": int(pb.mesh.n), "observer": "+z 128x128x100", "parallelism": "none"},
         "precisions": side,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK[head], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK[head], "traffic": measured_traffic(head),
+                     "frac": achieved / PEAK[head], "traffic": traffic,
                      "kernel": "k_transport<float,false,true,1>" if head == "fp32" else "k_transport<double,false,true,1>"},
+        "hbm": hbm,
         "hbm_copy_GBps": copy_GBps,
         # context set-up outside the timed region: octree build and
         # validation, leaf records, uploads (seconds)
