@@ -173,6 +173,34 @@ def test_forward_path_precision_in_one_cell(rmc, orc, prec):
         assert inside.mean() >= frac, (tau0, np.percentile(np.abs(rel), 98))
 
 
+def test_fp32_slab_and_sphere_spectra_match_the_analytic_solutions(rmc, orc):
+    # T = 10 K, tau0 = 1e6 (a tau0 = 1.5e4), isotropic, no recoil: the
+    # Neufeld slab and Dijkstra sphere spectra the paper compares with
+    # (Sect. 3.4.2), and the slab's mean scattering count
+    from scipy import stats
+    from tests.analytic import golden
+    from tests.test_oracle_transport import _dijkstra_cdf, _neufeld_cdf
+    n, tau0, T = 5000, 1e6, 10.0
+    atau = orc.line_quantities(W.LYA, T)["a"] * tau0
+    for geom, make, cdf, peak in (("slab", W.static_slab, _neufeld_cdf, 1.0664),
+                                  ("sphere", W.static_sphere, _dijkstra_cdf, 0.9310)):
+        pb = make(s0(orc), tau0, T, n, level=0, isotropic=True, recoil=False)
+        c = rmc.Context.from_problem(pb, "fp32", observers=False)
+        st = c.run(31, 0, n)
+        check_conservation(st, n)
+        out = c.get_packets()
+        c.close()
+        assert np.all(out["status"] == rmc.ST_ESCAPED)
+        x = out["x"]
+        D = stats.kstest(x, lambda v: cdf(v, atau)).statistic
+        assert D < 1.63 / np.sqrt(n) + 0.02, (geom, D)
+        assert abs(np.median(np.abs(x)) / (peak * atau ** (1 / 3)) - 1) < 0.06, geom
+        if geom == "slab":
+            coef = dict(golden("slab_scatterings"))["coefficient"]
+            ns = out["n_scat"]
+            assert abs(ns.mean() - coef * tau0) < 3 * ns.std() / np.sqrt(n) + 0.05 * coef * tau0
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_dusty_sphere_with_peel_off_matches_oracle(rmc, orc, prec):
     # C2 geometry and mesh at a reduced line-centre optical depth; errors of
