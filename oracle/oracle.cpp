@@ -561,6 +561,31 @@ void peel_deposit(const Problem &P, int n_obs, const orc_observer *obs, ThreadOu
   }
 }
 
+/* Core-skipping (Sect. 3.2.1 names the acceleration: the frequency
+ * redistribution is biased so that a packet deep in the line core of an
+ * optically thick cell jumps to the wing at once, Ahn et al. 2002,
+ * Laursen et al. 2009).  The perpendicular velocity of the scattering atom
+ * is drawn from the Gaussian restricted to |u_perp| >= x_crit: the 2-D
+ * density exp(-u^2)/pi on u^2 >= x_crit^2 has radial CDF
+ * 1 - exp(x_crit^2 - u^2), so |u_perp| = sqrt(x_crit^2 - ln r).  The paper
+ * takes x_crit from Smith et al. 2015; this library's criterion is its own,
+ * from the cell alone, with tau_cell = n_X sigma0(T) h the line-centre
+ * optical depth across the cell's edge:
+ *   x_crit = min( sqrt(ln(tau_cell / tau_skip)),  f (a tau_cell)^(1/3) ),
+ * the first term the frequency below which the cell stays optically thick
+ * by the factor tau_skip in the Gaussian core, the second a fraction f of
+ * the frequency at which packets leave a medium as thick as the cell
+ * (wings at |x| ~ (a tau)^(1/3)), so that a skip never carries a packet
+ * past the frequencies it would escape at.  The draw is biased only while
+ * |x| < x_crit.  Returns x_crit^2 for the draw, 0 when not skipping. */
+double core_skip_x2(double tau_skip, double frac, double a, double tau_cell, double x) {
+  if (!(tau_skip > 0.0) || !(tau_cell > tau_skip)) return 0.0;
+  double xt = std::sqrt(std::log(tau_cell / tau_skip));
+  double xw = frac * std::cbrt(a * tau_cell);
+  double xc = std::min(xt, xw);
+  return std::fabs(x) < xc ? xc * xc : 0.0;
+}
+
 /* ------------------------------------------------------------ transport
  * Sect. 3 (tau_event = -ln r, cell-by-cell subtraction), Sect. 3.2
  * (interaction choice by opacity fractions, resonant scattering with
@@ -665,7 +690,10 @@ void transport_packet(const Problem &P, uint64_t seed, uint64_t pid, const doubl
         double x_in = o.x[i];
         double upar;
         if (!sample_upar(x_in, q.a, rng, &upar)) { out.status = ORC_ST_STUCK; break; }
-        double rr = std::sqrt(-std::log(rng.u(J_PERP1)));
+        double tau_cell = pb.n_hi[c] * ln.abundance * q.sigma0 *
+                          std::ldexp(pb.box_cm, -(int)P.mesh.lev[c]);
+        double xc2 = core_skip_x2(pb.core_skip_tau, pb.core_skip_frac, q.a, tau_cell, x_in);
+        double rr = std::sqrt(xc2 - std::log(rng.u(J_PERP1)));
         double ph = 2.0 * PI * rng.u(J_PERP2);
         double up1 = rr * std::cos(ph), up2 = rr * std::sin(ph);
         double kin[3] = {k[0], k[1], k[2]};
@@ -784,6 +812,16 @@ void orc_sample_mu(int64_t n, int kind, double g, uint64_t seed, double *out) {
     else if (kind == 1) out[i] = mu_wing(r);
     else if (kind == 2) out[i] = mu_hg(r, g);
     else out[i] = 2.0 * r - 1.0;
+  }
+}
+
+void orc_sample_uperp(int64_t n, double x_crit, uint64_t seed, double *out) {
+  for (int64_t i = 0; i < n; ++i) {
+    Rng rng{seed, (uint64_t)i, 1};
+    double rr = std::sqrt(x_crit * x_crit - std::log(rng.u(J_PERP1)));
+    double ph = 2.0 * PI * rng.u(J_PERP2);
+    out[2 * i] = rr * std::cos(ph);
+    out[2 * i + 1] = rr * std::sin(ph);
   }
 }
 

@@ -30,7 +30,8 @@ class OrcProblem(C.Structure):
                 ("v", C.c_void_p), ("kappa_d", C.c_void_p), ("domain_kind", C.c_int),
                 ("domain", C.c_double * 4), ("n_lines", C.c_int), ("lines", OrcLine * 4),
                 ("T_ref", C.c_double), ("albedo", C.c_double), ("g_hg", C.c_double),
-                ("forward_only", C.c_int), ("max_events", C.c_int64)]
+                ("forward_only", C.c_int), ("max_events", C.c_int64),
+                ("core_skip_tau", C.c_double), ("core_skip_frac", C.c_double)]
 
 
 class OrcObserver(C.Structure):
@@ -72,6 +73,7 @@ def lib():
         L.orc_voigt_dhdx.argtypes = [C.c_double, C.c_double]
         L.orc_sample_upar.argtypes = [C.c_int64, C.c_double, C.c_double, C.c_uint64, P]
         L.orc_sample_mu.argtypes = [C.c_int64, C.c_int, C.c_double, C.c_uint64, P]
+        L.orc_sample_uperp.argtypes = [C.c_int64, C.c_double, C.c_uint64, P]
         L.orc_single_scatter.argtypes = [C.c_int64, P, C.c_double, C.c_double, C.c_uint64, P]
         L.orc_mesh_validate.restype = C.c_int
         L.orc_mesh_validate.argtypes = [C.c_int64, P, P]
@@ -101,7 +103,7 @@ def _line_struct(ln):
 class _Prob:
     """Keeps the numpy buffers alive for the lifetime of the C struct."""
 
-    def __init__(self, pb, forward_only=False, max_events=0):
+    def __init__(self, pb, forward_only=False, max_events=0, core_skip=None):
         m = pb.mesh
         self.level = np.ascontiguousarray(m.level, dtype=np.int8)
         self.ijk = np.ascontiguousarray(m.ijk, dtype=np.int32)
@@ -127,6 +129,7 @@ class _Prob:
         s.g_hg = pb.dust.g
         s.forward_only = int(forward_only)
         s.max_events = int(max_events)
+        s.core_skip_tau, s.core_skip_frac = core_skip if core_skip else (0.0, 0.0)
         self.s = s
 
 
@@ -181,6 +184,13 @@ def sample_mu(n, kind, g=0.0, seed=1):
     return out
 
 
+def sample_uperp(n, x_crit, seed=1):
+    """n core-skipping perpendicular velocity pairs, shape (n, 2)."""
+    out = np.zeros((n, 2))
+    lib().orc_sample_uperp(n, x_crit, seed, _ptr(out))
+    return out
+
+
 def single_scatter(n, line, T, x_in, seed=1):
     out = np.zeros(n)
     s = _line_struct(line)
@@ -227,12 +237,15 @@ def tau(pb, orig, dirs, x_ext):
     return out
 
 
-def run(pb, seed, first=0, n=None, threads=0, forward_only=False, max_events=0, with_cubes=True):
+def run(pb, seed, first=0, n=None, threads=0, forward_only=False, max_events=0, with_cubes=True,
+        core_skip=None):
     """Forward transport of packets [first, first+n) of pb.sources.
+    core_skip = (tau_skip, frac) turns core-skipping on (x_crit per cell:
+    min(sqrt(ln(tau_cell / tau_skip)), frac (a tau_cell)^(1/3))).
 
     Returns a dict with per-packet arrays (status, x, k, pos, n_scat, path),
     the observer cubes (list of [ny, nx, nbins] float64) and the stats."""
-    P = _Prob(pb, forward_only, max_events)
+    P = _Prob(pb, forward_only, max_events, core_skip)
     src = pb.sources
     pos = np.ascontiguousarray(src.pos, dtype=np.float64)
     dirs = None if src.dir is None else np.ascontiguousarray(src.dir, dtype=np.float64)

@@ -58,6 +58,9 @@ typedef struct {
   int forward_only;        /* scatterings keep direction and frequency */
   int64_t max_events;      /* >0: the packet stops, status stuck, at its
                               max_events-th interaction (0: no limit)  */
+  double core_skip_tau;    /* >0: core-skipping, x_crit from the cell:  */
+  double core_skip_frac;   /* min(sqrt(ln(tau_cell/core_skip_tau)),
+                              core_skip_frac (a tau_cell)^(1/3)); 0: off */
 } orc_problem;
 
 typedef struct {
@@ -88,6 +91,10 @@ double orc_voigt_dhdx(double a, double x);
 void orc_sample_upar(int64_t n, double x, double a, uint64_t seed, double *out);
 /* kind: 0 core, 1 wing, 2 Henyey-Greenstein(g), 3 isotropic */
 void orc_sample_mu(int64_t n, int kind, double g, uint64_t seed, double *out);
+/* core-skipping perpendicular atom velocities: n pairs (u1, u2) drawn
+ * from the two-dimensional Gaussian exp(-u^2)/pi restricted to
+ * |u| >= x_crit (counter-keyed by index) */
+void orc_sample_uperp(int64_t n, double x_crit, uint64_t seed, double *out);
 /* one scattering of a packet at x_in in a static cell at T, in the cell
  * frame; returns x_out per packet */
 void orc_single_scatter(int64_t n, const orc_line *ln, double T, double x_in,

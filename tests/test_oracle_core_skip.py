@@ -1,0 +1,110 @@
+"""Core-skipping in the oracle (Sect. 3.2.1 names the acceleration; the
+criterion for x_crit is the library's own, stated with rmc_set_core_skip).
+
+Pins:
+* the biased perpendicular velocity: |u|^2 - x_crit^2 is Exp(1), the angle
+  uniform, and one component follows the exact marginal of the Gaussian
+  restricted to |u| >= x_crit (derived below), the plain N(0, 1/2) at 0;
+* the threshold: a cell whose line-centre depth across its edge tau_c is
+  below tau_skip is never biased (bit-identical runs), one just above it is
+  (tau_c computed here from n_HI, sigma0(T) and the cell size);
+* dust-free slab and sphere at a tau0 = 1.5e4: the Neufeld and Dijkstra
+  spectra still hold while the scattering count drops by two orders of
+  magnitude (the paper's reason for the scheme);
+* where the cap f (a tau_c)^(1/3) binds (thin cells of a sphere at 100 K),
+  spectra and escape fractions agree with unbiased runs."""
+import numpy as np
+import pytest
+from scipy import integrate, special, stats
+
+from paper_2001_11252_amd import workloads as W
+from tests.test_oracle_transport import _dijkstra_cdf, _neufeld_cdf
+
+SKIP = (1.0, 0.2)
+
+
+def _marginal_pdf(u, xc):
+    # density of u1 for (u1, u2) ~ exp(-u1^2 - u2^2) / pi on u1^2 + u2^2 >= xc^2,
+    # normalised by exp(-xc^2): for |u1| >= xc the whole u2 line counts,
+    # e^{xc^2 - u1^2} / sqrt(pi); inside, |u2| >= sqrt(xc^2 - u1^2) only,
+    # which multiplies it by erfc(sqrt(xc^2 - u1^2))
+    u = np.asarray(u, dtype=float)
+    inner = np.abs(u) < xc
+    g = np.where(inner, special.erfc(np.sqrt(np.maximum(xc * xc - u * u, 0.0))), 1.0)
+    return np.exp(xc * xc - u * u) / np.sqrt(np.pi) * g
+
+
+@pytest.mark.parametrize("xc", [0.0, 1.0, 2.5])
+def test_uperp_radial_angular_and_marginal_laws(orc, xc):
+    n = 200_000
+    u = orc.sample_uperp(n, xc, seed=5)
+    r2 = (u ** 2).sum(axis=1)
+    assert r2.min() >= xc * xc * (1 - 1e-12)
+    assert stats.kstest(r2 - xc * xc, stats.expon.cdf).pvalue > 1e-3
+    ang = np.arctan2(u[:, 1], u[:, 0])
+    assert stats.kstest(ang, stats.uniform(-np.pi, 2 * np.pi).cdf).pvalue > 1e-3
+    # the marginal integrates to one
+    tot = integrate.quad(lambda v: _marginal_pdf(v, xc), -xc - 12, xc + 12, points=[-xc, xc] if xc else None,
+                         limit=200)[0]
+    assert abs(tot - 1) < 1e-9
+    grid = np.linspace(-xc - 7, xc + 7, 20001)
+    cdf = np.concatenate([[0.0], integrate.cumulative_trapezoid(_marginal_pdf(grid, xc), grid)])
+    D = stats.kstest(u[:, 0], lambda v: np.interp(v, grid, cdf)).statistic
+    assert D < 1.63 / np.sqrt(n) + 2e-4, D
+    if xc == 0.0:
+        assert stats.kstest(u[:, 0], stats.norm(scale=np.sqrt(0.5)).cdf).pvalue > 1e-3
+
+
+def test_threshold_from_the_cells_line_centre_depth(orc, sigma0_oracle):
+    # uniform level-3 sphere: every cell has tau_c = n_HI sigma0(T) h L_box
+    level, tau0, T, n = 3, 2e3, 1e4, 200
+    pb = W.static_sphere(sigma0_oracle, tau0, T, n, level=level)
+    tau_c = pb.meta["n_hi"] * orc.line_quantities(W.LYA, T)["sigma0"] * pb.mesh.box_cm / 2 ** level
+    off = orc.run(pb, 3, threads=4, with_cubes=False)
+    keys = ("status", "x", "n_scat", "pos", "k")
+    # at or above the cell depth: never biased, so bit-identical
+    for cs in ((tau_c * (1 + 1e-6), 1e6), (1e300, 1.0), (1.0, 0.0)):
+        on = orc.run(pb, 3, threads=4, with_cubes=False, core_skip=cs)
+        for k in keys:
+            assert np.array_equal(on[k], off[k]), (cs, k)
+    # just below it x_crit^2 = ln(tau_c / tau_skip) ~ 1e-6; the first
+    # scattering of each packet is at x = 0 exactly (static gas, x_in = 0),
+    # so it is biased and the walks change
+    on = orc.run(pb, 3, threads=4, with_cubes=False, core_skip=(tau_c * (1 - 1e-6), 1e6))
+    assert not np.array_equal(on["x"], off["x"])
+
+
+@pytest.mark.parametrize("geom", ["slab", "sphere"])
+def test_analytic_spectra_hold_with_skipping(orc, sigma0_oracle, geom):
+    # T = 10 K, tau0 = 1e6 (a tau0 = 1.5e4), isotropic, no recoil, one cell
+    tau0, T, n = 1e6, 10.0, 2000
+    make, cdf, peak = {"slab": (W.static_slab, _neufeld_cdf, 1.0664),
+                       "sphere": (W.static_sphere, _dijkstra_cdf, 0.9310)}[geom]
+    pb = make(sigma0_oracle, tau0, T, n, level=0, isotropic=True, recoil=False)
+    r = orc.run(pb, 101, threads=8, core_skip=SKIP)
+    atau = orc.line_quantities(W.LYA, T)["a"] * tau0
+    assert np.all(r["status"] == 1)
+    D = stats.kstest(r["x"], lambda v: cdf(v, atau)).statistic
+    assert D < 1.63 / np.sqrt(n) + 0.02, D
+    assert abs(np.median(np.abs(r["x"])) / (peak * atau ** (1 / 3)) - 1) < 0.06
+    # unbiased walks take ~1.6 tau0 (slab) scatterings; skipping the local
+    # core scatterings leaves under 1% of them
+    assert r["n_scat"].mean() < 0.01 * tau0
+
+
+@pytest.mark.slow
+def test_skipping_agrees_with_unbiased_runs_where_the_cap_binds(orc, sigma0_oracle):
+    # level-3 sphere at 100 K: a tau_c ~ 60, so x_crit = 0.2 (a tau_c)^(1/3)
+    # ~ 0.8 while the wing frequencies reach ~ 4
+    n = 1500
+    for td in (0.0, 1.0):
+        pb = W.static_sphere(sigma0_oracle, 1e5, 100.0, n, level=3, tau_dust=td)
+        off = orc.run(pb, 7, threads=8, with_cubes=False)
+        on = orc.run(pb, 7, threads=8, with_cubes=False, core_skip=SKIP)
+        eo, ef = on["status"] == 1, off["status"] == 1
+        assert on["n_scat"].mean() < 0.75 * off["n_scat"].mean()
+        assert stats.ks_2samp(on["x"][eo], off["x"][ef]).pvalue > 1e-3
+        p = (eo.sum() + ef.sum()) / (2 * n)
+        if 0 < p < 1:
+            z = (eo.mean() - ef.mean()) / np.sqrt(p * (1 - p) * 2 / n)
+            assert abs(z) < 4, (td, z)
