@@ -87,8 +87,10 @@ def parse():
     ap.add_argument("--cpu-packets", type=int, default=0, help="oracle packets (0: eight per core)")
     ap.add_argument("--only", choices=["fp32", "fp64", "both"], default="both")
     ap.add_argument("--copy-gib", type=float, default=1.0, help="size of the copy used to measure HBM bandwidth")
-    ap.add_argument("--workload", choices=["dusty_sphere", "shell", "batch", "adjoint"], default="dusty_sphere",
-                    help="dusty_sphere: the headline; shell, batch, adjoint: the other configurations")
+    ap.add_argument("--workload", choices=["dusty_sphere", "shell", "batch", "adjoint", "core_skip"],
+                    default="dusty_sphere",
+                    help="dusty_sphere: the headline; shell, batch, adjoint, core_skip: the other configurations")
+    ap.add_argument("--skip-packets", type=int, default=4_000_000, help="core_skip: packets per complete run")
     ap.add_argument("--vmax", type=float, default=200.0, help="shell: outflow speed at R (km/s)")
     ap.add_argument("--leaves", type=float, default=2e7, help="adjoint: target leaf count")
     ap.add_argument("--sources", type=int, default=100_000, help="adjoint: sources (100 rays each)")
@@ -207,6 +209,65 @@ def bench_batch(a, rmc, W):
                   "packets": int(sum(npk)), "tuned": best, "parallelism": "none"},
                  transport_roofline(tot, kms, "fp32", "k_transport<float,true,true,4>"),
                  crossings_per_s=(tot["crossings"] + tot["peel_crossings"]) / wall, cpu_baseline=cpu)
+
+
+def bench_core_skip(a, rmc, W):
+    """Core-skipping on a thick static sphere (tau0 = 1e7, T = 1e4 K, 8^3
+    grid, Lya dipole with recoil, +z 128x128x100 cube): each step is a
+    complete FP32 run of 4e6 packets with core-skipping (tau_skip = 1,
+    f = 0.2).  Unbiased walks here take ~1e7 scatterings each, so the
+    unbiased path is not run to completion: its scattering rate on the same
+    problem is measured over a few streaming launches."""
+    import torch
+    n = a.skip_packets
+    pb = W.thick_sphere(rmc.sigma0, n_packets=n)
+    print(f"# core_skip: {pb.mesh.n} leaves, {n} packets per step", file=sys.stderr, flush=True)
+    ctx = rmc.Context.from_problem(pb, "fp32")
+    ctx.set_stream(torch.cuda.current_stream())
+    ctx.set_core_skip(1.0, 0.2)
+    for _ in range(a.warmup):
+        ctx.run(pb.seed, 0, min(n, 20000))
+    torch.cuda.synchronize()
+    tot, kms = {}, []
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        ctx.reset_cubes()
+        st = ctx.run(pb.seed, 0, n)
+        kms.append(st["kernel_ms"])
+        for k, v in st.items():
+            tot[k] = tot.get(k, 0) + v
+        print(f"# core_skip run {i}: transport {st['kernel_ms']:.1f} ms, {st['scatterings']} scatterings, "
+              f"{st['escaped']} escaped", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.close()
+    # the unbiased path on the same problem, streaming
+    cu = rmc.Context.from_problem(pb, "fp32")
+    cu.set_stream(torch.cuda.current_stream())
+    cu.set_option(rmc.OPT_SLICE_ITERS, a.slice)
+    cu.stream_begin(pb.seed, 0, n)
+    wall_u, tot_u, _ = stream_rate(cu, 3, 1, "unbiased fp32")
+    cu.close()
+    cpu = None
+    if not a.no_cpu_baseline:
+        from oracle import oracle as O
+        cores = max(1, min(16, os.cpu_count() or 1))
+        m = 8 * cores
+        t0 = time.perf_counter()
+        r = O.run(pb, pb.seed, first=0, n=m, threads=cores, core_skip=(1.0, 0.2))
+        dt = time.perf_counter() - t0
+        cpu = {"value": m / dt, "unit": "packets/s", "cores": cores, "kind": "oracle",
+               "sample": f"{m} complete packets of the same problem with core-skipping and peel-off: "
+                         f"{r['stats']['scatterings']} scatterings in {dt:.1f} s"}
+    return _line("packets/s (complete runs, 1 GPU), FP32, core-skipping", n * a.steps / wall, "packets/s",
+                 a.steps, a.warmup, 1e3 * wall / a.steps, "f32",
+                 {"workload": f"thick_sphere_tau1e7_T1e4_{pb.mesh.n}_leaves_128x128x100", "packets": n,
+                  "core_skip": {"tau_skip": 1.0, "frac": 0.2}, "parallelism": "none"},
+                 transport_roofline(tot, kms, "fp32", "k_transport<float,false,true,1>"),
+                 scatterings_per_s=tot["scatterings"] / wall,
+                 scatterings_per_packet=tot["scatterings"] / (n * a.steps),
+                 unbiased_scatterings_per_s=tot_u["scatterings"] / wall_u,
+                 cpu_baseline=cpu)
 
 
 def bench_adjoint(a, rmc, W):
@@ -352,7 +413,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if a.workload != "dusty_sphere":
-        fn = {"shell": bench_shell, "batch": bench_batch, "adjoint": bench_adjoint}[a.workload]
+        fn = {"shell": bench_shell, "batch": bench_batch, "adjoint": bench_adjoint,
+              "core_skip": bench_core_skip}[a.workload]
         print(json.dumps(fn(a, rmc, W)), flush=True)
         return
     steps, warm, P = a.steps, a.warmup, a.packets

@@ -123,6 +123,23 @@ const char *rmc_last_error(const rmc_ctx *ctx);
  * null stream).  The stream must outlive its use by the context. */
 rmc_status rmc_set_stream(rmc_ctx *ctx, void *hip_stream);
 rmc_status rmc_set_option(rmc_ctx *ctx, int option, int64_t value);
+/* Core-skipping (Sect. 3.2.1, the acceleration of Ahn et al. 2002 and
+ * Laursen et al. 2009 the paper uses in its galaxy example): in a resonant
+ * scattering at cell-frame |x| < x_crit the atom's perpendicular velocity
+ * is drawn from the Gaussian restricted to |u_perp| >= x_crit, so that a
+ * packet deep in the core of a thick cell moves to the wing at once.  The
+ * paper takes x_crit from Smith et al. 2015; here it comes from the cell:
+ * with tau_c = n_X sigma0(T) h the line-centre optical depth across the
+ * cell's edge and a its damping parameter,
+ *   x_crit = min(sqrt(ln(tau_c / tau_skip)), frac (a tau_c)^(1/3)),
+ * and 0 (no bias) where tau_c <= tau_skip.  tau_skip = 1, frac = 0.2 keep
+ * the escape spectra of dust-free media (the tests check them against the
+ * slab and sphere solutions and against unbiased runs); with dust, skipped
+ * core scatterings take no path length, so extinction comes out slightly
+ * low, as the paper notes.  tau_skip <= 0 turns it off (the default); a
+ * non-finite tau_skip or a negative or non-finite frac gives RMC_EINVAL.
+ * Takes effect at the next run or stream_begin. */
+rmc_status rmc_set_core_skip(rmc_ctx *ctx, double tau_skip, double frac);
 
 /* ---------------------------------------------------------------- inputs */
 /* Leaves of a graded octree (Sect. 4.3): level[n] in [0,16], ijk[3n] the

@@ -83,6 +83,7 @@ struct rmc_ctx {
   std::string err;
   int forward_only = 0;
   int64_t max_events = 0;
+  double skip_tau = 0.0, skip_frac = 0.0;
   int block = 256;
   int waves_per_cu = 0;   // 0: as many as the transport kernel's occupancy allows
   int refill = 1;
@@ -443,6 +444,8 @@ void make_problem(rmc_ctx *c, int64_t first, int64_t n, uint64_t seed, ProblemK 
   pb.g_hg = c->g_hg;
   pb.forward_only = c->forward_only;
   pb.max_events = c->max_events;
+  pb.skip_tau = c->skip_tau;
+  pb.skip_frac = c->skip_frac;
   pb.src_pos = c->spos.as<double>();
   pb.src_dir = c->src_dir ? c->sdir.as<double>() : nullptr;
   pb.src_x = c->sx.as<double>();
@@ -528,7 +531,7 @@ void fill_stats(rmc_run_stats *s, const unsigned long long *h, double ms) {
 
 extern "C" {
 
-int rmc_abi_version(void) { return 3; }
+int rmc_abi_version(void) { return 4; }
 
 rmc_status rmc_create(rmc_ctx **out, int device, int precision) {
   if (!out) return RMC_EINVAL;
@@ -614,6 +617,16 @@ rmc_status rmc_set_option(rmc_ctx *c, int opt, int64_t v) {
       break;
     default: return fail(c, RMC_EINVAL, "unknown option %d", opt);
   }
+  return RMC_OK;
+}
+
+rmc_status rmc_set_core_skip(rmc_ctx *c, double tau_skip, double frac) {
+  rmc_status r = enter(c);
+  if (r) return r;
+  if (!std::isfinite(tau_skip)) return fail(c, RMC_EINVAL, "core-skip tau_skip not finite");
+  if (!std::isfinite(frac) || frac < 0) return fail(c, RMC_EINVAL, "core-skip frac must be finite and >= 0");
+  c->skip_tau = tau_skip > 0 ? tau_skip : 0.0;
+  c->skip_frac = tau_skip > 0 ? frac : 0.0;
   return RMC_OK;
 }
 

@@ -108,6 +108,7 @@ struct ProblemK {
   double albedo, g_hg;
   int forward_only;
   int64_t max_events;
+  double skip_tau, skip_frac; // core-skipping (skip_tau > 0: on)
   // sources (device)
   const double *src_pos, *src_dir, *src_x;
   int64_t first, n;         // packet range of this run
@@ -651,6 +652,28 @@ __device__ __forceinline__ void opacity(const ProblemK &pb, const LeafRec<R> &lf
       o.ktot += o.kl[i];
     }
   }
+}
+
+// Core-skipping (Sect. 3.2.1): while a packet sits deep in the line core of
+// a cell that is optically thick even well off line centre, the scattering
+// atom's perpendicular velocity is drawn with |u_perp| >= x_crit, which moves
+// the packet to the wing in one step instead of many local core scatterings.
+// x_crit comes from the cell: tau_c = n_X sigma0(T) h is its line-centre
+// optical depth across the edge; x_crit is the smaller of
+// sqrt(ln(tau_c / skip_tau)) (where the Gaussian core of the cell is still
+// skip_tau thick) and skip_frac (a tau_c)^(1/3) (a fraction of the wing
+// frequency at which a medium of the cell's depth lets packets out).
+// Returns x_crit^2 while |x| < x_crit, else 0 (the unbiased draw).
+template <class R>
+__device__ __forceinline__ R core_skip_x2(const ProblemK &pb, const LineK &ln, const LeafRec<R> &lf, int level,
+                                          R a, R x) {
+  const R tc = lf.nl * R(ln.kfac) * (R)ldexp(1.0, -level);
+  const R ts = R(pb.skip_tau);
+  if (!(tc > ts)) return R(0);
+  const R xt2 = M<R>::log(M<R>::div(tc, ts));
+  const R xw = R(pb.skip_frac) * M<R>::cbrt(a * tc);
+  const R x2 = fmin(xt2, xw * xw);
+  return x * x < x2 ? x2 : R(0);
 }
 
 }  // namespace rmc

@@ -448,9 +448,12 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R, NL> &o, in
     const R a = R(ln.alpha) * s.lf.irho;
     R upar;
     if (!sample_upar<R>(x, a, rng, &s.upar_iters, &upar)) return ST_STUCK;
+    // Gaussian u_perp (Box-Muller), restricted to |u_perp| >= x_crit while
+    // core-skipping applies
+    const R xc2 = pb.skip_tau > 0.0 ? core_skip_x2<R>(pb, ln, s.lf, s.c.level, a, x) : R(0);
     R sp, cp;
     M<R>::sincos2pi(rng.u(J_PERP2), &sp, &cp);
-    const R rr = M<R>::sqrt(-M<R>::log(rng.u(J_PERP1)));
+    const R rr = M<R>::sqrt(xc2 - M<R>::log(rng.u(J_PERP1)));
     const R up1 = rr * cp, up2 = rr * sp;
     R U[3];
 #pragma unroll

@@ -71,6 +71,7 @@ _sig = {
     "rmc_last_error": (C.c_char_p, [_P]),
     "rmc_set_stream": (C.c_int, [_P, _P]),
     "rmc_set_option": (C.c_int, [_P, C.c_int, _i64]),
+    "rmc_set_core_skip": (C.c_int, [_P, C.c_double, C.c_double]),
     "rmc_set_mesh": (C.c_int, [_P, _i64, _P, _P, C.c_double]),
     "rmc_set_gas": (C.c_int, [_P, _P, _P, _P, _P]),
     "rmc_set_lines": (C.c_int, [_P, C.c_int, _P, C.c_double]),
@@ -192,6 +193,11 @@ class Context:
 
     def set_option(self, opt, value):
         self._chk(_L.rmc_set_option(self._h, opt, int(value)), "set_option")
+
+    def set_core_skip(self, tau_skip=1.0, frac=0.2):
+        """Core-skipping on (tau_skip > 0) or off (tau_skip = 0); see
+        rmc_set_core_skip for the per-cell x_crit."""
+        self._chk(_L.rmc_set_core_skip(self._h, float(tau_skip), float(frac)), "set_core_skip")
 
     def set_mesh(self, level, ijk, box_cm):
         lv = _host(level, np.int8)

@@ -272,6 +272,18 @@ def c2_dusty_sphere(sigma0_fn, n_packets=1_000_000, tau0=1e6, mesh=None, nx=128,
                    meta=dict(tau0=tau0, T=T, n_hi=n_hi))
 
 
+def thick_sphere(sigma0_fn, n_packets=1_000_000, tau0=1e7, level=3, nx=128, nbins=100):
+    """Dust-free static sphere R = 1/2 at T = 1e4 K with tau0 = 1e7 from the
+    centre on a uniform 8^3 grid (a tau of a cell ~ 1.2e3: the thick-cell
+    regime where core-skipping acts), Lya with the dipole phase function and
+    recoil, packets from the centre at x = 0, one +z observer with a
+    128x128x100 cube over x in [-60, 60)."""
+    pb = static_sphere(sigma0_fn, tau0, 1e4, n_packets, level=level, name="thick_sphere")
+    pb.observers = [Observer((0.0, 0.0, 1.0), nx, nx, nbins, (-0.5, 0.5, -0.5, 0.5), -60.0, 60.0)]
+    pb.seed = 0x5EED0006
+    return pb
+
+
 def c3_rule_factory(R=0.25):
     c = np.array([0.5, 0.5, 0.5])
 

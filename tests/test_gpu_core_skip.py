@@ -1,0 +1,147 @@
+"""GPU core-skipping (rmc_set_core_skip) against the oracle.
+
+Both sides draw the same counter-based numbers and take x_crit from the
+same per-cell rule.  Skipping puts packets at |x| >= x_crit, where the
+u_parallel rejection step u = |x| + a tan(theta) is ill-conditioned (theta
+near -pi/2, condition ~|x|/a, a few hundred at 10 K) and stretches: with
+theta = -pi/2 + r (theta0 + pi/2), u ~ x - (x - u0)/r, so du/dx = 1 - 1/r
+and a frequency difference grows by a factor ~1.5-2 per event.  A last-ulp
+difference between the two sides' atan/tan (~1e-13 in u) thus reaches 1e-8
+within ~40 events and then flips a decision.  So the double path is
+compared with the oracle packet by packet over the first 12 events (a
+uniform one-cell
+slab, and the graded dusty sphere, where x_crit changes with the cell's
+level), and over whole walks in distribution; the float path matches the
+oracle in distribution and the slab solution; turning the option off
+restores the unbiased path bit for bit; in a batch each problem keeps its
+own setting."""
+import numpy as np
+import pytest
+from scipy import stats
+
+from paper_2001_11252_amd import workloads as W
+from tests.test_oracle_transport import _neufeld_cdf
+
+pytestmark = pytest.mark.gpu
+
+SKIP = (1.0, 0.2)
+
+
+@pytest.fixture(scope="module")
+def rmc():
+    from paper_2001_11252_amd import rmc as R
+    return R
+
+
+def s0(orc):
+    return lambda ln, T: orc.line_quantities(ln, T)["sigma0"]
+
+
+def _run(rmc, pb, prec, seed, n, skip=SKIP, observers=True, max_events=0):
+    c = rmc.Context.from_problem(pb, prec, observers=observers)
+    if skip is not None:
+        c.set_core_skip(*skip)
+    if max_events:
+        c.set_option(rmc.OPT_MAX_EVENTS, max_events)
+    st = c.run(seed, 0, n)
+    out = c.get_packets()
+    c.close()
+    return st, out
+
+
+EVENTS = 12
+
+
+def _same(ref, out, i):
+    return (ref["status"][i] == out["status"][i] and ref["n_scat"][i] == out["n_scat"][i]
+            and abs(ref["x"][i] - out["x"][i]) < 1e-8
+            and np.abs(ref["pos"][i] - out["pos"][i]).max() < 1e-9
+            and np.abs(ref["k"][i] - out["k"][i]).max() < 1e-9)
+
+
+def _follow(rmc, orc, pb, seed, n, slack):
+    # the first EVENTS events of each packet, one by one
+    _, out = _run(rmc, pb, "fp64", seed, n, max_events=EVENTS)
+    ref = orc.run(pb, seed, threads=8, with_cubes=False, core_skip=SKIP, max_events=EVENTS)
+    same = sum(_same(ref, out, i) for i in range(n))
+    assert same >= n - slack, (same, n)
+    # whole walks, in distribution
+    _, out = _run(rmc, pb, "fp64", seed, n)
+    ref = orc.run(pb, seed, threads=8, with_cubes=False, core_skip=SKIP)
+    for k in (1, 2):
+        a, b = out["status"] == k, ref["status"] == k
+        assert abs(a.sum() - b.sum()) <= 4 * np.sqrt(max(a.sum(), 1)) + 2, k
+    ea, eb = out["status"] == 1, ref["status"] == 1
+    assert stats.ks_2samp(out["x"][ea], ref["x"][eb]).pvalue > 1e-3
+    a, b = out["n_scat"], ref["n_scat"]
+    z = (a.mean() - b.mean()) / np.sqrt(a.var() / n + b.var() / n + 1e-12)
+    assert abs(z) < 4, z
+    return out
+
+
+def test_fp64_slab_packets_follow_the_oracle(rmc, orc):
+    # one cell, tau0 = 1e6 at 10 K: x_crit = sqrt(ln tau_c) ~ 3.8
+    n = 2000
+    pb = W.static_slab(s0(orc), 1e6, 10.0, n, level=0, isotropic=True, recoil=False)
+    out = _follow(rmc, orc, pb, 21, n, 4)
+    assert out["n_scat"].mean() < 0.01 * 1e6
+
+
+def test_fp64_dusty_sphere_packets_follow_the_oracle(rmc, orc):
+    # graded mesh (levels 3-7), dust, dipole phase and recoil, +z observer
+    n = 1000
+    pb = W.c2_dusty_sphere(s0(orc), n_packets=n, tau0=1e5)
+    out = _follow(rmc, orc, pb, 22, n, 4)
+    # and the bias did act: each packet's first scattering (x = 0, in a
+    # level-7 cell with a tau_c ~ 0.7, so x_crit = 0.2 (a tau_c)^(1/3) ~ 0.18)
+    # is biased, so every walk that scatters ends elsewhere
+    _, plain = _run(rmc, pb, "fp64", 22, n, skip=None)
+    sc = plain["n_scat"] > 0
+    assert np.count_nonzero(plain["x"][sc] != out["x"][sc]) >= 0.9 * sc.sum()
+
+
+def test_fp32_slab_matches_the_oracle_and_the_slab_solution(rmc, orc):
+    n_gpu, n_orc, tau0, T = 20000, 3000, 1e6, 10.0
+    pb = W.static_slab(s0(orc), tau0, T, n_gpu, level=0, isotropic=True, recoil=False)
+    _, out = _run(rmc, pb, "fp32", 23, n_gpu)
+    assert np.all(out["status"] == 1)
+    ref = orc.run(pb, 24, n=n_orc, threads=8, with_cubes=False, core_skip=SKIP)
+    assert stats.ks_2samp(out["x"], ref["x"]).pvalue > 1e-3
+    a, b = out["n_scat"], ref["n_scat"]
+    z = (a.mean() - b.mean()) / np.sqrt(a.var() / len(a) + b.var() / len(b))
+    assert abs(z) < 4, z
+    atau = orc.line_quantities(W.LYA, T)["a"] * tau0
+    D = stats.kstest(out["x"], lambda v: _neufeld_cdf(v, atau)).statistic
+    assert D < 1.63 / np.sqrt(n_gpu) + 0.02, D
+
+
+def test_off_is_the_unbiased_path_and_bad_values_are_refused(rmc, orc):
+    n = 200
+    pb = W.static_sphere(s0(orc), 1e4, 1e4, n, level=3, tau_dust=0.5)
+    _, plain = _run(rmc, pb, "fp64", 25, n, skip=None)
+    c = rmc.Context.from_problem(pb, "fp64")
+    c.set_core_skip(*SKIP)
+    c.set_core_skip(0.0, 0.2)  # off again
+    c.run(25, 0, n)
+    off = c.get_packets()
+    for bad in ((float("nan"), 0.2), (float("inf"), 0.2), (1.0, -0.1), (1.0, float("nan"))):
+        with pytest.raises(rmc.RmcError):
+            c.set_core_skip(*bad)
+    c.close()
+    for k in ("status", "x", "n_scat", "pos", "k"):
+        assert np.array_equal(plain[k], off[k]), k
+
+
+def test_batch_problems_keep_their_own_setting(rmc, orc):
+    n = 300
+    pbs = [W.static_slab(s0(orc), 1e6, 10.0, n, level=0, isotropic=True, recoil=False),
+           W.static_sphere(s0(orc), 1e4, 1e4, n, level=3)]
+    single = [_run(rmc, pbs[0], "fp64", 31, n)[1], _run(rmc, pbs[1], "fp64", 32, n, skip=None)[1]]
+    ctxs = [rmc.Context.from_problem(p, "fp64") for p in pbs]
+    ctxs[0].set_core_skip(*SKIP)
+    rmc.batch_run(ctxs, [31, 32], [n, n])
+    for c, ref in zip(ctxs, single):
+        out = c.get_packets()
+        for k in ("status", "x", "n_scat", "pos", "k"):
+            assert np.array_equal(out[k], ref[k]), k
+        c.close()

@@ -94,8 +94,9 @@ def test_analytic_spectra_hold_with_skipping(orc, sigma0_oracle, geom):
 
 @pytest.mark.slow
 def test_skipping_agrees_with_unbiased_runs_where_the_cap_binds(orc, sigma0_oracle):
-    # level-3 sphere at 100 K: a tau_c ~ 60, so x_crit = 0.2 (a tau_c)^(1/3)
-    # ~ 0.8 while the wing frequencies reach ~ 4
+    # level-3 sphere at 100 K: a tau_c ~ 120, so x_crit = 0.2 (a tau_c)^(1/3)
+    # ~ 1.0 (below sqrt(ln tau_c) ~ 3.2) while the spectrum peaks near
+    # 0.93 (a tau0)^(1/3) ~ 7
     n = 1500
     for td in (0.0, 1.0):
         pb = W.static_sphere(sigma0_oracle, 1e5, 100.0, n, level=3, tau_dust=td)
