@@ -31,7 +31,7 @@ class OrcProblem(C.Structure):
                 ("domain", C.c_double * 4), ("n_lines", C.c_int), ("lines", OrcLine * 4),
                 ("T_ref", C.c_double), ("albedo", C.c_double), ("g_hg", C.c_double),
                 ("forward_only", C.c_int), ("max_events", C.c_int64),
-                ("core_skip_tau", C.c_double), ("core_skip_frac", C.c_double)]
+                ("core_skip_tau", C.c_double), ("core_skip_frac", C.c_double), ("voigt_exact", C.c_int)]
 
 
 class OrcObserver(C.Structure):
@@ -71,6 +71,8 @@ def lib():
         L.orc_voigt_h.argtypes = [C.c_double, C.c_double]
         L.orc_voigt_dhdx.restype = C.c_double
         L.orc_voigt_dhdx.argtypes = [C.c_double, C.c_double]
+        L.orc_voigt_h_exact.restype = C.c_double
+        L.orc_voigt_h_exact.argtypes = [C.c_double, C.c_double]
         L.orc_sample_upar.argtypes = [C.c_int64, C.c_double, C.c_double, C.c_uint64, P]
         L.orc_sample_mu.argtypes = [C.c_int64, C.c_int, C.c_double, C.c_uint64, P]
         L.orc_sample_uperp.argtypes = [C.c_int64, C.c_double, C.c_uint64, P]
@@ -103,7 +105,7 @@ def _line_struct(ln):
 class _Prob:
     """Keeps the numpy buffers alive for the lifetime of the C struct."""
 
-    def __init__(self, pb, forward_only=False, max_events=0, core_skip=None):
+    def __init__(self, pb, forward_only=False, max_events=0, core_skip=None, voigt_exact=False):
         m = pb.mesh
         self.level = np.ascontiguousarray(m.level, dtype=np.int8)
         self.ijk = np.ascontiguousarray(m.ijk, dtype=np.int32)
@@ -130,6 +132,7 @@ class _Prob:
         s.forward_only = int(forward_only)
         s.max_events = int(max_events)
         s.core_skip_tau, s.core_skip_frac = core_skip if core_skip else (0.0, 0.0)
+        s.voigt_exact = int(bool(voigt_exact))
         self.s = s
 
 
@@ -169,6 +172,12 @@ def voigt_h(a, x):
 
 def voigt_dhdx(a, x):
     return lib().orc_voigt_dhdx(a, x)
+
+
+def voigt_h_exact(a, x):
+    """H(a, x) from its defining integral (adaptive quadrature), elementwise."""
+    f = np.vectorize(lambda aa, xx: lib().orc_voigt_h_exact(float(aa), float(xx)))
+    return f(a, x)
 
 
 def sample_upar(n, x, a, seed=1):
@@ -225,8 +234,8 @@ def trace(pb, orig, dirs, max_cells):
     return leaf, seg, cnt
 
 
-def tau(pb, orig, dirs, x_ext):
-    P = _Prob(pb)
+def tau(pb, orig, dirs, x_ext, voigt_exact=False):
+    P = _Prob(pb, voigt_exact=voigt_exact)
     o = np.ascontiguousarray(orig, dtype=np.float64).reshape(-1, 3)
     d = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 3)
     x = np.ascontiguousarray(x_ext, dtype=np.float64)
@@ -238,14 +247,15 @@ def tau(pb, orig, dirs, x_ext):
 
 
 def run(pb, seed, first=0, n=None, threads=0, forward_only=False, max_events=0, with_cubes=True,
-        core_skip=None):
+        core_skip=None, voigt_exact=False):
     """Forward transport of packets [first, first+n) of pb.sources.
     core_skip = (tau_skip, frac) turns core-skipping on (x_crit per cell:
     min(sqrt(ln(tau_cell / tau_skip)), frac (a tau_cell)^(1/3))).
+    voigt_exact: H from its defining integral instead of the Tasitsiomi form.
 
     Returns a dict with per-packet arrays (status, x, k, pos, n_scat, path),
     the observer cubes (list of [ny, nx, nbins] float64) and the stats."""
-    P = _Prob(pb, forward_only, max_events, core_skip)
+    P = _Prob(pb, forward_only, max_events, core_skip, voigt_exact)
     src = pb.sources
     pos = np.ascontiguousarray(src.pos, dtype=np.float64)
     dirs = None if src.dir is None else np.ascontiguousarray(src.dir, dtype=np.float64)
@@ -276,12 +286,12 @@ def run(pb, seed, first=0, n=None, threads=0, forward_only=False, max_events=0, 
                 cubes=cubes, stats=st.as_dict())
 
 
-def raycast_image(pb, observer, orig, x_ext, w, grad_image=None, threads=0, crossings=None):
+def raycast_image(pb, observer, orig, x_ext, w, grad_image=None, threads=0, crossings=None, voigt_exact=False):
     """Peel-off image of fixed rays toward `observer` and, if grad_image is
     given, the exact gradient of sum(grad_image * image) with respect to the
     per-leaf n_HI, kappa_d and v_los = k_obs . v.  crossings (optional, a
     one-element int64 array) receives the ray-cell segments walked."""
-    P = _Prob(pb)
+    P = _Prob(pb, voigt_exact=voigt_exact)
     ob = _obs_struct(observer)
     o = np.ascontiguousarray(orig, dtype=np.float64).reshape(-1, 3)
     x = np.ascontiguousarray(x_ext, dtype=np.float64)

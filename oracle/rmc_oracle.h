@@ -61,6 +61,8 @@ typedef struct {
   double core_skip_tau;    /* >0: core-skipping, x_crit from the cell:  */
   double core_skip_frac;   /* min(sqrt(ln(tau_cell/core_skip_tau)),
                               core_skip_frac (a tau_cell)^(1/3)); 0: off */
+  int voigt_exact;         /* 1: H from its defining integral (quadrature)
+                              instead of the Tasitsiomi form             */
 } orc_problem;
 
 typedef struct {
@@ -86,6 +88,8 @@ double orc_uniform(uint64_t seed, uint64_t pid, uint32_t event, uint32_t j);
 void orc_line_quantities(const orc_line *ln, double T, double out[5]);
 double orc_voigt_h(double a, double x);
 double orc_voigt_dhdx(double a, double x);
+/* H(a,x) from its defining integral by adaptive quadrature (~1e-14) */
+double orc_voigt_h_exact(double a, double x);
 
 /* sampler batches for distribution tests (counter-keyed by index) */
 void orc_sample_upar(int64_t n, double x, double a, uint64_t seed, double *out);
