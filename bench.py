@@ -87,10 +87,12 @@ def parse():
     ap.add_argument("--cpu-packets", type=int, default=0, help="oracle packets (0: eight per core)")
     ap.add_argument("--only", choices=["fp32", "fp64", "both"], default="both")
     ap.add_argument("--copy-gib", type=float, default=1.0, help="size of the copy used to measure HBM bandwidth")
-    ap.add_argument("--workload", choices=["dusty_sphere", "shell", "batch", "adjoint", "core_skip"],
+    ap.add_argument("--workload", choices=["dusty_sphere", "shell", "batch", "adjoint", "core_skip",
+                                           "voigt_accuracy"],
                     default="dusty_sphere",
-                    help="dusty_sphere: the headline; shell, batch, adjoint, core_skip: the other configurations")
+                    help="dusty_sphere: the headline; the others: the other configurations")
     ap.add_argument("--skip-packets", type=int, default=4_000_000, help="core_skip: packets per complete run")
+    ap.add_argument("--voigt-packets", type=int, default=200_000, help="voigt_accuracy: packets per run")
     ap.add_argument("--vmax", type=float, default=200.0, help="shell: outflow speed at R (km/s)")
     ap.add_argument("--leaves", type=float, default=2e7, help="adjoint: target leaf count")
     ap.add_argument("--sources", type=int, default=100_000, help="adjoint: sources (100 rays each)")
@@ -270,6 +272,88 @@ def bench_core_skip(a, rmc, W):
                  cpu_baseline=cpu)
 
 
+def bench_voigt_accuracy(a, rmc, W):
+    """The paper's accumulated Voigt-error experiment (Sect. 4.2, static
+    slab, central monochromatic Lya source, T = 10 K so a = 0.015) at
+    tau0 = 1e6: the same packets run to completion on the double path with
+    the Tasitsiomi form and with the accurate H (RMC_OPT_VOIGT = 1), and
+    the two escape spectra are compared bin by bin in units of the Poisson
+    error.  The accurate run's scatterings/s is the line's value."""
+    import numpy as np
+    import torch
+    from scipy import stats
+    n = a.voigt_packets
+    pb = W.static_slab(rmc.sigma0, 1e6, 10.0, n, level=0)
+    print(f"# voigt_accuracy: slab tau0 = 1e6, T = 10 K, {n} packets, FP64", file=sys.stderr, flush=True)
+    res = {}
+    for mode in (0, 1):
+        ctx = rmc.Context.from_problem(pb, "fp64", observers=False)
+        ctx.set_stream(torch.cuda.current_stream())
+        ctx.set_option(rmc.OPT_VOIGT, mode)
+        ctx.set_option(rmc.OPT_SLICE_ITERS, a.slice)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.stream_begin(pb.seed, 0, n)
+        tot, kms, step, rem = {}, [], 0, n
+        while rem > 0:
+            st, rem = ctx.stream_step()
+            kms.append(st["kernel_ms"])
+            for k, v in st.items():
+                tot[k] = tot.get(k, 0) + v
+            step += 1
+            if step % 200 == 0:
+                print(f"# voigt {mode}: step {step}, {rem} packets left", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out = ctx.get_packets()
+        ctx.close()
+        print(f"# voigt {mode}: {step} launches in {wall:.1f} s, {tot['scatterings']} scatterings",
+              file=sys.stderr, flush=True)
+        res[mode] = (wall, tot, kms, out)
+    (w0, t0_, k0, o0), (w1, t1_, k1, o1) = res[0], res[1]
+    e0, e1 = o0["status"] == 1, o1["status"] == 1
+    h0, edges = np.histogram(o0["x"][e0], bins=120, range=(-60, 60))
+    h1, _ = np.histogram(o1["x"][e1], bins=120, range=(-60, 60))
+    sel = (h0 + h1) > 0
+    zb = (h1[sel] - h0[sel]) / np.sqrt(h0[sel] + h1[sel])
+    both = e0 & e1
+    dx = np.abs(o1["x"][both]) - np.abs(o0["x"][both])
+    steps = len(k1)
+    rl = transport_roofline(t1_, k1, "fp64", "k_transport<double,false,true,1>")
+    return _line("scatterings/s (1 GPU), FP64 with the accurate Voigt function", t1_["scatterings"] / w1,
+                 "scatterings/s", steps, 0, 1e3 * w1 / steps, "f64",
+                 {"workload": "static_slab_tau1e6_T10_lya_central_source", "packets": n,
+                  "iterations_per_lane_per_step": a.slice, "parallelism": "none"}, rl,
+                 tasitsiomi_scatterings_per_s=t0_["scatterings"] / w0,
+                 packets_per_s={"accurate": n / w1, "tasitsiomi": n / w0},
+                 spectrum_difference={
+                     "bins": int(sel.sum()), "within_1_sigma": float(np.mean(np.abs(zb) <= 1)),
+                     "within_2_sigma": float(np.mean(np.abs(zb) <= 2)), "chi2_per_bin": float(np.mean(zb ** 2)),
+                     "note": "same packets and draws in both runs (common random numbers): the bin "
+                             "differences are the systematic effect of H plus the walks it decorrelates",
+                     "ks_p": float(stats.ks_2samp(o0["x"][e0], o1["x"][e1]).pvalue),
+                     "mean_abs_x": {"tasitsiomi": float(np.abs(o0["x"][e0]).mean()),
+                                    "accurate": float(np.abs(o1["x"][e1]).mean())},
+                     "paired_abs_x_shift": float(dx.mean()),
+                     "paired_abs_x_shift_se": float(dx.std() / np.sqrt(max(len(dx), 1))),
+                     "mean_scatterings": {"tasitsiomi": float(o0["n_scat"].mean()),
+                                          "accurate": float(o1["n_scat"].mean())}},
+                 cpu_baseline=None if a.no_cpu_baseline else oracle_voigt_baseline(pb))
+
+
+def oracle_voigt_baseline(pb):
+    """The oracle with the accurate H on a bounded sample of the same slab."""
+    from oracle import oracle as O
+    cores = max(1, min(16, os.cpu_count() or 1))
+    m, ev = 2 * cores, 20000
+    t0 = time.perf_counter()
+    r = O.run(pb, pb.seed, first=0, n=m, threads=cores, max_events=ev, with_cubes=False, voigt_exact=True)
+    dt = time.perf_counter() - t0
+    return {"value": r["stats"]["scatterings"] / dt, "unit": "scatterings/s", "cores": cores, "kind": "oracle",
+            "sample": f"{m} packets of the same slab with the accurate H (quadrature), each stopped after {ev} "
+                      f"interactions: {r['stats']['scatterings']} scatterings in {dt:.1f} s"}
+
+
 def bench_adjoint(a, rmc, W):
     """C5: galaxy-like adaptive mesh (~2e7 leaves), 1e7 fixed rays toward
     +z, 512^2 image; one forward image and one backward (gradients per
@@ -414,7 +498,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if a.workload != "dusty_sphere":
         fn = {"shell": bench_shell, "batch": bench_batch, "adjoint": bench_adjoint,
-              "core_skip": bench_core_skip}[a.workload]
+              "core_skip": bench_core_skip, "voigt_accuracy": bench_voigt_accuracy}[a.workload]
         print(json.dumps(fn(a, rmc, W)), flush=True)
         return
     steps, warm, P = a.steps, a.warmup, a.packets

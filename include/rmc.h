@@ -73,8 +73,22 @@ enum {
                                 transport launch; 0: walked inline by the
                                 transport kernel.  Results agree up to the
                                 order of the cube additions.                 */
-  RMC_OPT_SLICE_ITERS = 7    /* loop iterations (events or cell crossings)
+  RMC_OPT_SLICE_ITERS = 7,   /* loop iterations (events or cell crossings)
                                 per lane in one transport launch            */
+  RMC_OPT_VOIGT = 8          /* Voigt function H(a,x) of the opacity:
+                                0 (default) the Tasitsiomi form the paper
+                                uses (Sect. 3.3.2; within ~1% for Lya at
+                                1e4 K, 2.5% at a = 0.022); 1 H to ~1e-14
+                                relative, for RMC_FP64 contexts only
+                                (RMC_EUNSUPPORTED on RMC_FP32_BULK; the
+                                float kernels are built without it) (Sect.
+                                3.1.1 definition): the
+                                trapezoidal rule for the Faddeeva integral
+                                with its pole term, an asymptotic series
+                                for |x| >= 30.  With 1 the image gradient
+                                (rmc_raycast_image_backward*) returns
+                                RMC_EUNSUPPORTED: it uses dH/dx of the
+                                Tasitsiomi form.                            */
 };
 
 /* One transition (Table 1 of the paper). */

@@ -84,6 +84,7 @@ struct rmc_ctx {
   int forward_only = 0;
   int64_t max_events = 0;
   double skip_tau = 0.0, skip_frac = 0.0;
+  int voigt_exact = 0;
   int block = 256;
   int waves_per_cu = 0;   // 0: as many as the transport kernel's occupancy allows
   int refill = 1;
@@ -446,6 +447,7 @@ void make_problem(rmc_ctx *c, int64_t first, int64_t n, uint64_t seed, ProblemK 
   pb.max_events = c->max_events;
   pb.skip_tau = c->skip_tau;
   pb.skip_frac = c->skip_frac;
+  pb.voigt_exact = c->voigt_exact;
   pb.src_pos = c->spos.as<double>();
   pb.src_dir = c->src_dir ? c->sdir.as<double>() : nullptr;
   pb.src_x = c->sx.as<double>();
@@ -531,7 +533,7 @@ void fill_stats(rmc_run_stats *s, const unsigned long long *h, double ms) {
 
 extern "C" {
 
-int rmc_abi_version(void) { return 4; }
+int rmc_abi_version(void) { return 5; }
 
 rmc_status rmc_create(rmc_ctx **out, int device, int precision) {
   if (!out) return RMC_EINVAL;
@@ -614,6 +616,12 @@ rmc_status rmc_set_option(rmc_ctx *c, int opt, int64_t v) {
     case RMC_OPT_SLICE_ITERS:
       if (v < 1 || v > (1 << 30)) return fail(c, RMC_EINVAL, "slice iterations in [1, 2^30]");
       c->slice_iters = (int)v;
+      break;
+    case RMC_OPT_VOIGT:
+      if (v != 0 && v != 1) return fail(c, RMC_EINVAL, "voigt is 0 (Tasitsiomi) or 1 (accurate)");
+      if (v == 1 && c->precision != RMC_FP64)
+        return fail(c, RMC_EUNSUPPORTED, "the accurate Voigt function is an RMC_FP64 option");
+      c->voigt_exact = (int)v;
       break;
     default: return fail(c, RMC_EINVAL, "unknown option %d", opt);
   }
@@ -1294,6 +1302,7 @@ rmc_status rmc_raycast_image_backward(rmc_ctx *c, int id, int64_t n, const doubl
                                       const double *w, const double *G, double *gn, double *gk, double *gv, int mem) {
   rmc_status r = enter(c);
   if (r) return r;
+  if (c->voigt_exact) return fail(c, RMC_EUNSUPPORTED, "the image gradient needs RMC_OPT_VOIGT 0 (Tasitsiomi dH/dx)");
   const double *o, *x, *ww;
   if ((r = image_common(c, id, n, orig, x_ext, w, mem, &o, &x, &ww))) return r;
   if (!G || !gn || !gk || !gv) return fail(c, RMC_EINVAL, "null gradient buffer");
@@ -1412,6 +1421,7 @@ rmc_status rmc_raycast_image_backward_tape(rmc_ctx *c, const double *G, double *
                                            int mem) {
   rmc_status r = enter(c);
   if (r) return r;
+  if (c->voigt_exact) return fail(c, RMC_EUNSUPPORTED, "the image gradient needs RMC_OPT_VOIGT 0 (Tasitsiomi dH/dx)");
   if ((r = ready(c, false))) return r;
   if (!c->tp_valid || c->tp_gen != c->gen || c->tp_obs >= (int)c->obs.size())
     return fail(c, RMC_ESTATE, "no tape for the current model (rmc_raycast_image_tape)");

@@ -109,6 +109,7 @@ struct ProblemK {
   int forward_only;
   int64_t max_events;
   double skip_tau, skip_frac; // core-skipping (skip_tau > 0: on)
+  int voigt_exact;          // 1: H from voigt_h_exact, 0: the Tasitsiomi form
   // sources (device)
   const double *src_pos, *src_dir, *src_x;
   int64_t first, n;         // packet range of this run
@@ -278,6 +279,66 @@ template <class R> __device__ __forceinline__ R voigt_h(R a, R x) {
     const R P = ((R(5.674) * z - R(9.207)) * z + R(4.421)) * z + R(0.1117);
     const R q = M<R>::div(z * (R(1) + M<R>::div(R(21), x2)) * (a * R(1.0 / PI_D)), x2 + R(1)) * P;
     h += R(1.7724538509055160273) * q;
+  }
+  return h;
+}
+
+// H(a, x) = Re w(x + ia) in double to ~1e-14 relative (the accurate
+// evaluator Sect. 3.3.2 measures its fast forms against; H from its
+// Sect. 3.1.1 definition).  For Im z > 0, w(z) = (i/pi) int e^{-t^2} /
+// (z - t) dt.  The trapezoidal rule with step s = 1/2 converges like
+// e^{-pi^2/s^2} once the pole at t = z is accounted for:
+//   w(z) ~ (i s/pi) sum_n e^{-t_n^2}/(z - t_n) + 2 e^{-z^2}/(1 -+ e^{-2 pi i z/s}),
+// nodes t_n = n s ("-") or (n - 1/2) s ("+"), whichever set keeps x at
+// least s/4 from every node (the two parts of the formula then stay
+// moderate).  Pairing t and -t, the real part of the sum is
+//   (s/pi) a sum_n e^{-t_n^2} (x^2 + a^2 + t_n^2) / ((x^2 - t_n^2 - a^2)^2 + 4 a^2 x^2),
+// a sum of positive terms (the t = 0 node contributes 1/(x^2 + a^2) once).
+// For |x| >= 30 the asymptotic series w ~ (i/sqrt(pi)) sum_k (2k-1)!!/2^k
+// z^-(2k+1) is used (the imaginary parts of its powers share one sign).
+__device__ __attribute__((noinline)) double voigt_h_exact(double a, double x) {
+  const double ax = fabs(x);
+  if (ax >= 30.0) {
+    const double d = x * x + a * a;
+    const double ur = x / d, ui = -a / d;                      // 1/z
+    const double vr = ur * ur - ui * ui, vi = 2.0 * ur * ui;  // 1/z^2
+    double tr = ur, ti = ui, si = ui;
+    for (int k = 1; k < 12; ++k) {
+      const double c = (2.0 * k - 1.0) * 0.5;
+      const double nr = (tr * vr - ti * vi) * c, ni = (tr * vi + ti * vr) * c;
+      tr = nr;
+      ti = ni;
+      si += ti;
+    }
+    return -si * 0.56418958354775628695;  // 1/sqrt(pi)
+  }
+  const double q = 2.0 * ax;  // |x| / s
+  const double fr = q - floor(q);
+  const bool mid = fr < 0.25 || fr > 0.75;
+  const double a2 = a * a, x2a2 = x * x + a2, fa2x2 = 4.0 * a2 * x * x;
+  double sum = mid ? 0.0 : 1.0 / x2a2;
+  // e^{-t_n^2} by ratios: nodes n/2 have e^{-n^2/4}, ratio e^{-(2n-1)/4};
+  // half-nodes (2n-1)/4 have e^{-(2n-1)^2/16}, ratio e^{-(n-1)/2}
+  double c = mid ? 0.93941306281347578612 : 0.77880078307140486825;   // e^{-1/16}, e^{-1/4}
+  double rho = mid ? 0.60653065971263342360 : 0.47236655274101470714;  // e^{-1/2}, e^{-3/4}
+  for (int n = 1; n <= 14; ++n) {
+    const double t = mid ? 0.5 * n - 0.25 : 0.5 * n;
+    const double dd = (ax - t) * (ax + t) - a2;
+    sum += 2.0 * c * (x2a2 + t * t) / (dd * dd + fa2x2);
+    c *= rho;
+    rho *= 0.60653065971263342360;  // e^{-1/2}
+  }
+  double h = 0.15915494309189533577 * a * sum;  // s/pi = 1/(2 pi)
+  const double g = exp(a2 - x * x);
+  if (g > 0.0 && a < 20.0) {  // (the pole term is below e^{-37} for a > 3)
+    // Re[2 E / D], E = e^{-z^2} = g (cos 2ax - i sin 2ax),
+    // D = 1 - sg e^{4 pi a} (cos 4 pi x - i sin 4 pi x), sg = +1 ("-"), -1 ("+")
+    double s1, c1, s2, c2;
+    sincos(2.0 * a * x, &s1, &c1);
+    sincospi(4.0 * x, &s2, &c2);
+    const double e = (mid ? -1.0 : 1.0) * exp(12.566370614359172954 * a);
+    const double dr = 1.0 - e * c2, di = e * s2;
+    h += 2.0 * g * (c1 * dr - s1 * di) / (dr * dr + di * di);
   }
   return h;
 }
@@ -648,7 +709,14 @@ __device__ __forceinline__ void opacity(const ProblemK &pb, const LeafRec<R> &lf
     if (NL == 1 || i < pb.n_lines) {
       const LineK &ln = pb.lines[i];
       o.x[i] = (R)(ln.delta + ln.s * x_ext - wd) * lf.irho * R(ln.inv_mu) * inv_den;
-      o.kl[i] = lf.nl * R(ln.kfac) * voigt_h<R>(R(ln.alpha) * lf.irho, o.x[i]);
+      const R a = R(ln.alpha) * lf.irho;
+      R H;
+      // the accurate H is a double-path option (the float kernels stay free of it)
+      if constexpr (sizeof(R) == 8)
+        H = pb.voigt_exact ? voigt_h_exact(a, o.x[i]) : voigt_h<R>(a, o.x[i]);
+      else
+        H = voigt_h<R>(a, o.x[i]);
+      o.kl[i] = lf.nl * R(ln.kfac) * H;
       o.ktot += o.kl[i];
     }
   }

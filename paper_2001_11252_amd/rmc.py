@@ -23,6 +23,7 @@ HOST, DEVICE = 0, 1
 F32, F64 = 0, 1
 OPT_FORWARD_ONLY, OPT_MAX_EVENTS, OPT_BLOCK, OPT_WAVES_PER_CU, OPT_REFILL, OPT_PEEL_DEFER = 1, 2, 3, 4, 5, 6
 OPT_SLICE_ITERS = 7
+OPT_VOIGT = 8
 ST_NONE, ST_ESCAPED, ST_ABSORBED, ST_STUCK = 0, 1, 2, 3
 _NAMES = {EINVAL: "RMC_EINVAL", ENOMEM: "RMC_ENOMEM", EDEVICE: "RMC_EDEVICE", EMESH: "RMC_EMESH",
           ESTATE: "RMC_ESTATE", EUNSUPPORTED: "RMC_EUNSUPPORTED"}
