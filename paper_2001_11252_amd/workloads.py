@@ -272,6 +272,22 @@ def c2_dusty_sphere(sigma0_fn, n_packets=1_000_000, tau0=1e6, mesh=None, nx=128,
                    meta=dict(tau0=tau0, T=T, n_hi=n_hi))
 
 
+def deuterium_sphere(sigma0_fn, n_packets, N_HI=2e19, T=1e4, d_to_h=3e-5, level=3):
+    """Static uniform sphere R = 1/2 of H I mixed with deuterium (the paper's
+    appendix test: T = 1e4 K, column N_HI = 2e19 cm^-2 from the centre,
+    D/H = 3e-5), Lya and D Lya with the dipole phase function and recoil,
+    central source at x = 0, one +z observer (128x128x100 over x in
+    [-20, 20))."""
+    from dataclasses import replace
+    tau0 = N_HI * sigma0_fn(LYA, T)
+    pb = static_sphere(sigma0_fn, tau0, T, n_packets, level=level, name="deuterium_sphere")
+    pb.lines = [LYA, replace(D_LYA, abundance=d_to_h)]
+    pb.observers = [Observer((0.0, 0.0, 1.0), 128, 128, 100, (-0.5, 0.5, -0.5, 0.5), -20.0, 20.0)]
+    pb.seed = 0x5EED0007
+    pb.meta.update(N_HI=N_HI, d_to_h=d_to_h)
+    return pb
+
+
 def thick_sphere(sigma0_fn, n_packets=1_000_000, tau0=1e7, level=3, nx=128, nbins=100):
     """Dust-free static sphere R = 1/2 at T = 1e4 K with tau0 = 1e7 from the
     centre on a uniform 8^3 grid (a tau of a cell ~ 1.2e3: the thick-cell

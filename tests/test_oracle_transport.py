@@ -265,3 +265,33 @@ def test_adjoint_gradient_matches_finite_differences(orc, sigma0_oracle):
         pb.gas.v[c, 2] = old
         fd = (Lp - Lm) / (2 * h)
         assert abs(fd - gv[c]) <= 1e-4 * abs(gv[c]) + 1e-9 * abs(L(pb)) / h, (c, fd, gv[c])
+
+
+def test_hydrogen_deuterium_optical_depth(orc, sigma0_oracle):
+    # App. (multi-species): H I mixed with D at the paper's parameters.  From
+    # the centre of the static sphere, tau(x) = N_HI sigma0_H H(a_H, x)
+    #   + N_D sigma0_D H(a_D, x_D), with x_D the same frequency measured
+    # from the D line centre in D Doppler units; both terms are built here
+    # from the line data, and the D line centre must fall at the printed x.
+    g = dict(golden("deuterium"))
+    T, N_HI, dh = g["T"], g["N_HI"], g["d_to_h"]
+    assert (W.D_LYA.lambda0_A, W.D_LYA.A_ul, W.D_LYA.f_lu) == (g["lambda_D"], g["A_ul"], g["f_lu"])
+    pb = W.deuterium_sphere(sigma0_oracle, 1, N_HI=N_HI, T=T, d_to_h=dh)
+    qh, qd = orc.line_quantities(W.LYA, T), orc.line_quantities(pb.lines[1], T)
+    c = 2.99792458e10
+    nu_h, nu_d = c / (W.LYA.lambda0_A * 1e-8), c / (W.D_LYA.lambda0_A * 1e-8)
+    x_line = (nu_d - nu_h) / qh["dnu"]
+    assert abs(x_line - g["feature_x"]) < 0.05, x_line
+    xs = np.array([-3.0, 0.0, 2.0, 5.0, 5.9, 6.2, x_line, 6.6, 7.5, 12.0])
+    n = len(xs)
+    orig = np.tile([0.5, 0.5, 0.5], (n, 1))
+    dirs = np.tile([0.0, 0.6, 0.8], (n, 1))
+    tau = orc.tau(pb, orig, dirs, xs)
+    x_d = (xs * qh["dnu"] + nu_h - nu_d) / qd["dnu"]
+    H = lambda a, v: np.array([orc.voigt_h(a, float(u)) for u in v])
+    want = N_HI * (qh["sigma0"] * H(qh["a"], xs) + dh * qd["sigma0"] * H(qd["a"], x_d))
+    assert np.max(np.abs(tau / want - 1)) < 1e-11
+    # the deuterium term dominates the optical depth near the feature only
+    d_part = N_HI * dh * qd["sigma0"] * H(qd["a"], x_d)
+    assert d_part[xs == x_line][0] > 3 * (want - d_part)[xs == x_line][0]
+    assert d_part[xs == 2.0][0] < 1e-3 * want[xs == 2.0][0]
