@@ -471,7 +471,16 @@ struct Problem {
   const orc_problem *pb;
   Mesh mesh;
   double nu_ref, dnu_ref;
+  double lambda_ref_A;     /* rest wavelength of the reference line */
 };
+
+/* nu_i - nu_ref for line i, from the wavelengths (nu = c/lambda):
+ * c (lambda_ref - lambda_i) / (lambda_i lambda_ref).  Differencing the two
+ * absolute frequencies (~2.5e15 Hz for Lya) instead would leave ~0.25 Hz of
+ * rounding, ~1e-11 of a narrow line's Doppler width. */
+double line_offset(const Problem &P, const orc_line &ln) {
+  return C_LIGHT * ((P.lambda_ref_A - ln.lambda0_A) / (ln.lambda0_A * P.lambda_ref_A)) * 1e8;
+}
 
 struct Opac {
   double dnu_cell;
@@ -491,7 +500,7 @@ void opacity(const Problem &P, int64_t c, double dnu_ext, const double k[3], Opa
   o.ktot = o.kd;
   for (int i = 0; i < pb.n_lines; ++i) {
     o.q[i] = line_q(pb.lines[i], pb.T[c]);
-    o.x[i] = (o.dnu_cell - (o.q[i].nu0 - P.nu_ref)) / o.q[i].dnu;
+    o.x[i] = (o.dnu_cell - line_offset(P, pb.lines[i])) / o.q[i].dnu;
     double H = pb.voigt_exact ? voigt_h_exact(o.q[i].a, o.x[i]) : voigt_h(o.q[i].a, o.x[i]);
     o.kl[i] = pb.n_hi[c] * pb.lines[i].abundance * o.q[i].sigma0 * H;
     o.ktot += o.kl[i];
@@ -783,7 +792,7 @@ void transport_packet(const Problem &P, uint64_t seed, uint64_t pid, const doubl
         for (int d = 0; d < 3; ++d) vatom[d] = (upar * kin[d] + up1 * e1[d] + up2 * e2[d]) * q.vth;
         /* core or wing, from the frequency seen by the atom,
          * nu_scat,in = nu_in (1 - k_in . v_X / c), within 0.2 dnu_D of nu_lu */
-        double off = (dnu_in - (q.nu0 - P.nu_ref)) - (P.nu_ref + dnu_in) * dot3(kin, vatom) / C_LIGHT;
+        double off = (dnu_in - line_offset(P, ln)) - (P.nu_ref + dnu_in) * dot3(kin, vatom) / C_LIGHT;
         int core = std::fabs(off) < 0.2 * q.dnu;
         nscat += 1;
         to.st.scatterings += 1;
@@ -836,10 +845,12 @@ int setup_problem(const orc_problem *pb, Problem &P) {
     LineQ q = line_q(pb->lines[0], pb->T_ref);
     P.nu_ref = q.nu0;
     P.dnu_ref = q.dnu;
+    P.lambda_ref_A = pb->lines[0].lambda0_A;
   } else { /* continuum: x is measured in units of 1e-5 of an arbitrary
               1215.67 A reference */
     P.nu_ref = C_LIGHT / 1215.67e-8;
     P.dnu_ref = P.nu_ref * 1e-5;
+    P.lambda_ref_A = 1215.67;
   }
   return 0;
 }
@@ -913,6 +924,7 @@ void orc_single_scatter(int64_t n, const orc_line *ln, double T, double x_in, ui
   P.pb = nullptr;
   P.nu_ref = q.nu0;
   P.dnu_ref = q.dnu;
+  P.lambda_ref_A = ln->lambda0_A;
   double dnu_in = x_in * q.dnu;
   for (int64_t i = 0; i < n; ++i) {
     Rng rng{seed, (uint64_t)i, 1};

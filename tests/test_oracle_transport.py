@@ -278,19 +278,23 @@ def test_hydrogen_deuterium_optical_depth(orc, sigma0_oracle):
     assert (W.D_LYA.lambda0_A, W.D_LYA.A_ul, W.D_LYA.f_lu) == (g["lambda_D"], g["A_ul"], g["f_lu"])
     pb = W.deuterium_sphere(sigma0_oracle, 1, N_HI=N_HI, T=T, d_to_h=dh)
     qh, qd = orc.line_quantities(W.LYA, T), orc.line_quantities(pb.lines[1], T)
-    c = 2.99792458e10
-    nu_h, nu_d = c / (W.LYA.lambda0_A * 1e-8), c / (W.D_LYA.lambda0_A * 1e-8)
-    x_line = (nu_d - nu_h) / qh["dnu"]
+    # nu_D - nu_H = c (1/lambda_D - 1/lambda_H), in exact rational arithmetic
+    # on the wavelengths as stored (their binary values: the decimal ones
+    # differ by ~1e-13 A, which the 0.33 A difference magnifies to ~0.3 Hz)
+    from fractions import Fraction as Fr
+    lh, ld = Fr(W.LYA.lambda0_A), Fr(W.D_LYA.lambda0_A)
+    offset = float(Fr(29979245800) * (lh - ld) / (lh * ld) * 10 ** 8)
+    x_line = offset / qh["dnu"]
     assert abs(x_line - g["feature_x"]) < 0.05, x_line
     xs = np.array([-3.0, 0.0, 2.0, 5.0, 5.9, 6.2, x_line, 6.6, 7.5, 12.0])
     n = len(xs)
     orig = np.tile([0.5, 0.5, 0.5], (n, 1))
     dirs = np.tile([0.0, 0.6, 0.8], (n, 1))
     tau = orc.tau(pb, orig, dirs, xs)
-    x_d = (xs * qh["dnu"] + nu_h - nu_d) / qd["dnu"]
+    x_d = (xs * qh["dnu"] - offset) / qd["dnu"]
     H = lambda a, v: np.array([orc.voigt_h(a, float(u)) for u in v])
     want = N_HI * (qh["sigma0"] * H(qh["a"], xs) + dh * qd["sigma0"] * H(qd["a"], x_d))
-    assert np.max(np.abs(tau / want - 1)) < 1e-11
+    assert np.max(np.abs(tau / want - 1)) < 1e-13
     # the deuterium term dominates the optical depth near the feature only
     d_part = N_HI * dh * qd["sigma0"] * H(qd["a"], x_d)
     assert d_part[xs == x_line][0] > 3 * (want - d_part)[xs == x_line][0]
