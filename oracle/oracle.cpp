@@ -82,7 +82,9 @@ enum {
   J_ALBEDO = 6,   /* dust: scatter or absorb                   */
   J_GAUSS1 = 6,   /* line, |x| >= 8: Box-Muller pair           */
   J_GAUSS2 = 7,
-  J_REJ = 6       /* line, |x| < 8: round i uses 6+3i .. 8+3i  */
+  J_REJ = 6,      /* line, |x| < 8: round i uses 6+3i .. 8+3i  */
+  J_SRC1 = 4,     /* emission (event 0): source-spectrum draws */
+  J_SRC2 = 5
 };
 
 struct Rng {
@@ -686,6 +688,34 @@ struct PacketOut {
   int32_t nscat;
 };
 
+/* Source spectrum (Sect. 2.1): the emitted frequency, as an offset in Hz
+ * added to the source's own x.  Monochromatic: 0.  Gaussian line: the
+ * Box-Muller draw sqrt(-2 ln r1) cos(2 pi r2) times the standard deviation
+ * (given in Doppler widths of the reference line).  Power-law continuum
+ * F_lambda ~ lambda^beta on [lambda_min, lambda_max]: the photon-number
+ * distribution lambda F_lambda has the inverse CDF
+ *   lambda = [lambda_min^(2+b) + r (lambda_max^(2+b) - lambda_min^(2+b))]^(1/(2+b)),
+ *   lambda = lambda_min exp(r ln(lambda_max/lambda_min))  (b = -2),
+ * and nu - nu_ref = c (lambda_ref - lambda) / (lambda lambda_ref). */
+double spectrum_offset(const Problem &P, const Rng &rng) {
+  const orc_problem &pb = *P.pb;
+  if (pb.spec_kind == 1) {
+    double g = std::sqrt(-2.0 * std::log(rng.u(J_SRC1))) * std::cos(2.0 * PI * rng.u(J_SRC2));
+    return g * pb.spec_p[0] * P.dnu_ref;
+  }
+  if (pb.spec_kind == 2) {
+    double lmin = pb.spec_p[0], lmax = pb.spec_p[1], b = pb.spec_p[2], r = rng.u(J_SRC1), lam;
+    if (b == -2.0) {
+      lam = lmin * std::exp(r * std::log(lmax / lmin));
+    } else {
+      double e = 2.0 + b;
+      lam = std::pow(std::pow(lmin, e) + r * (std::pow(lmax, e) - std::pow(lmin, e)), 1.0 / e);
+    }
+    return C_LIGHT * ((P.lambda_ref_A - lam) / (lam * P.lambda_ref_A)) * 1e8;
+  }
+  return 0.0;
+}
+
 void transport_packet(const Problem &P, uint64_t seed, uint64_t pid, const double src_p[3],
                       const double *src_k, double src_x, int n_obs, const orc_observer *obs,
                       ThreadOut &to, PacketOut &out) {
@@ -701,7 +731,7 @@ void transport_packet(const Problem &P, uint64_t seed, uint64_t pid, const doubl
     double s = std::sqrt(1.0 - mu * mu);
     k[0] = s * std::cos(phi); k[1] = s * std::sin(phi); k[2] = mu;
   }
-  double dnu_ext = dnu_from_x(P, src_x);
+  double dnu_ext = dnu_from_x(P, src_x) + spectrum_offset(P, rng);
   double tau_ev = -std::log(rng.u(J_TAU));
   double path = 0.0;
   int32_t nscat = 0;

@@ -31,7 +31,8 @@ class OrcProblem(C.Structure):
                 ("domain", C.c_double * 4), ("n_lines", C.c_int), ("lines", OrcLine * 4),
                 ("T_ref", C.c_double), ("albedo", C.c_double), ("g_hg", C.c_double),
                 ("forward_only", C.c_int), ("max_events", C.c_int64),
-                ("core_skip_tau", C.c_double), ("core_skip_frac", C.c_double), ("voigt_exact", C.c_int)]
+                ("core_skip_tau", C.c_double), ("core_skip_frac", C.c_double), ("voigt_exact", C.c_int),
+                ("spec_kind", C.c_int), ("spec_p", C.c_double * 3)]
 
 
 class OrcObserver(C.Structure):
@@ -133,6 +134,11 @@ class _Prob:
         s.max_events = int(max_events)
         s.core_skip_tau, s.core_skip_frac = core_skip if core_skip else (0.0, 0.0)
         s.voigt_exact = int(bool(voigt_exact))
+        sp = getattr(pb, "spectrum", None)
+        if sp:
+            s.spec_kind = int(sp[0])
+            for i, v in enumerate(sp[1:4]):
+                s.spec_p[i] = float(v)
         self.s = s
 
 

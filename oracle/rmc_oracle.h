@@ -63,6 +63,12 @@ typedef struct {
                               core_skip_frac (a tau_cell)^(1/3)); 0: off */
   int voigt_exact;         /* 1: H from its defining integral (quadrature)
                               instead of the Tasitsiomi form             */
+  int spec_kind;           /* source spectrum: 0 monochromatic (src x),
+                              1 Gaussian (spec_p[0] = sigma in Doppler
+                              widths of the reference line), 2 power-law
+                              continuum (spec_p = lambda_min, lambda_max
+                              in Angstrom, beta of F_lambda)             */
+  double spec_p[3];
 } orc_problem;
 
 typedef struct {

@@ -110,6 +110,9 @@ class Problem:
     sources: Sources
     observers: List[Observer] = field(default_factory=list)
     seed: int = 0
+    # source spectrum: None (monochromatic at each source's x) or
+    # (1, sigma_x) Gaussian, (2, lambda_min, lambda_max, beta) power law
+    spectrum: tuple = None
     meta: dict = field(default_factory=dict)
 
 

@@ -299,3 +299,41 @@ def test_hydrogen_deuterium_optical_depth(orc, sigma0_oracle):
     d_part = N_HI * dh * qd["sigma0"] * H(qd["a"], x_d)
     assert d_part[xs == x_line][0] > 3 * (want - d_part)[xs == x_line][0]
     assert d_part[xs == 2.0][0] < 1e-3 * want[xs == 2.0][0]
+
+
+def _escaped_spectrum(orc, sigma0_oracle, spectrum, n=20000):
+    # an empty sphere: every packet leaves at its emitted frequency
+    pb = W.static_sphere(sigma0_oracle, 0.0, 1e4, n, level=2)
+    pb.spectrum = spectrum
+    r = orc.run(pb, 81, threads=8, with_cubes=False)
+    assert np.all(r["status"] == 1) and np.all(r["n_scat"] == 0)
+    b = orc.line_quantities(W.LYA, 1e4)["vth"] / 2.99792458e10
+    return r["x"], b
+
+
+def test_gaussian_line_source(orc, sigma0_oracle):
+    # Sect. 2.1 (Gaussian line, Box-Muller): x ~ N(x_src, sigma^2)
+    for sigma in (0.5, 7.0):
+        x, _ = _escaped_spectrum(orc, sigma0_oracle, (1, sigma))
+        assert stats.kstest(x, stats.norm(scale=sigma).cdf).pvalue > 1e-3
+
+
+@pytest.mark.parametrize("beta", [-2.0, -1.0, 0.5])
+def test_power_law_continuum_source(orc, sigma0_oracle, beta):
+    # Sect. 2.1 (power-law continuum): the photon-number distribution
+    # lambda F_lambda, F_lambda ~ lambda^beta on [1200, 1230] A, has
+    # P(<lambda) = (lambda^(2+b) - lmin^(2+b)) / (lmax^(2+b) - lmin^(2+b)),
+    # or ln(lambda/lmin) / ln(lmax/lmin) for b = -2
+    lmin, lmax = 1200.0, 1230.0
+    x, b = _escaped_spectrum(orc, sigma0_oracle, (2, lmin, lmax, beta))
+    lam = W.LYA.lambda0_A / (1.0 + b * x)          # x = (lambda_ref - lambda) / (lambda b)
+    assert lam.min() >= lmin * (1 - 1e-12) and lam.max() <= lmax * (1 + 1e-12)
+    if beta == -2.0:
+        cdf = lambda l: np.log(l / lmin) / np.log(lmax / lmin)
+    else:
+        e = 2.0 + beta
+        cdf = lambda l: (l ** e - lmin ** e) / (lmax ** e - lmin ** e)
+    assert stats.kstest(lam, cdf).pvalue > 1e-3
+    if beta == -1.0:
+        # lambda F_lambda constant: uniform in lambda
+        assert abs(lam.mean() / (0.5 * (lmin + lmax)) - 1) < 1e-3
