@@ -154,6 +154,25 @@ rmc_status rmc_set_option(rmc_ctx *ctx, int option, int64_t value);
  * non-finite tau_skip or a negative or non-finite frac gives RMC_EINVAL.
  * Takes effect at the next run or stream_begin. */
 rmc_status rmc_set_core_skip(rmc_ctx *ctx, double tau_skip, double frac);
+/* Source spectrum (Sect. 2.1), drawn on the device at each packet's
+ * emission from its own counter-based stream and added to the x_ext the
+ * source was given (rmc_set_sources):
+ *   RMC_SPEC_MONO (default): no change (monochromatic; params unused);
+ *   RMC_SPEC_GAUSS: Gaussian line, params[0] = standard deviation in
+ *     Doppler widths of line 0 at T_ref (the paper's relative width
+ *     sigma_nu is sigma x Doppler width / nu_0), Box-Muller draw;
+ *   RMC_SPEC_POWER_LAW: continuum F_lambda ~ lambda^beta, params = {
+ *     lambda_min, lambda_max (Angstrom), beta}: the photon-number
+ *     distribution lambda F_lambda is sampled by its inverse CDF (the
+ *     beta = -2 branch logarithmic) and lambda becomes
+ *     x_ext += (lambda_0 - lambda) / (lambda b), b = v_th(T_ref) / c of
+ *     line 0 (nu = c / lambda).
+ * params is a host array of 3 doubles (copied).  Errors: RMC_EINVAL for an
+ * unknown kind, a null params (other than MONO), sigma < 0 or not finite,
+ * lambda_min <= 0, lambda_max <= lambda_min or a non-finite value.  Takes
+ * effect at the next run or stream_begin. */
+enum { RMC_SPEC_MONO = 0, RMC_SPEC_GAUSS = 1, RMC_SPEC_POWER_LAW = 2 };
+rmc_status rmc_set_source_spectrum(rmc_ctx *ctx, int kind, const double *params);
 
 /* ---------------------------------------------------------------- inputs */
 /* Leaves of a graded octree (Sect. 4.3): level[n] in [0,16], ijk[3n] the

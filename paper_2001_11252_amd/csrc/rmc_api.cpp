@@ -85,6 +85,8 @@ struct rmc_ctx {
   int64_t max_events = 0;
   double skip_tau = 0.0, skip_frac = 0.0;
   int voigt_exact = 0;
+  int spec_kind = 0;
+  double spec_p[3] = {0.0, 0.0, 0.0};
   int block = 256;
   int waves_per_cu = 0;   // 0: as many as the transport kernel's occupancy allows
   int refill = 1;
@@ -121,6 +123,7 @@ struct rmc_ctx {
   int64_t last_n = 0;
   DevBuf o_status, o_x, o_k, o_pos, o_nscat, o_path;
   DevBuf d_stats, d_next, d_prob, d_starts, tmp1, tmp2, tmp3, tmp4, tmp5;
+  DevBuf sx_eff;  // emitted x per source under a source spectrum
   ProblemK pb_host;
   int64_t starts_host[2];
   int num_cus = 0;
@@ -448,6 +451,9 @@ void make_problem(rmc_ctx *c, int64_t first, int64_t n, uint64_t seed, ProblemK 
   pb.skip_tau = c->skip_tau;
   pb.skip_frac = c->skip_frac;
   pb.voigt_exact = c->voigt_exact;
+  pb.spec_kind = c->spec_kind;
+  for (int q = 0; q < 3; ++q) pb.spec_p[q] = c->spec_p[q];
+  pb.lambda_ref = c->lines[0].lambda0_A;
   pb.src_pos = c->spos.as<double>();
   pb.src_dir = c->src_dir ? c->sdir.as<double>() : nullptr;
   pb.src_x = c->sx.as<double>();
@@ -463,6 +469,18 @@ void make_problem(rmc_ctx *c, int64_t first, int64_t n, uint64_t seed, ProblemK 
   pb.n_obs = (int)c->obs.size();
   for (int o = 0; o < pb.n_obs; ++o) pb.obs[o] = c->obs[o].k;
   pb.stats = c->d_stats.as<unsigned long long>();
+}
+
+// The emitted x of packets [first, first+n) under the source spectrum,
+// computed on stream st before the transport; pb.src_x then points at them.
+// Monochromatic sources: nothing to do.
+rmc_status apply_spectrum(rmc_ctx *c, ProblemK &pb, int64_t first, int64_t n, hipStream_t st) {
+  if (!c->spec_kind || n <= 0) return RMC_OK;
+  HIPCHK(c, c->sx_eff.ensure(sizeof(double) * (size_t)c->n_src));
+  HIPCHK(c, launch_source_x(c->precision == RMC_FP32_BULK, pb, c->sx.as<double>(), c->sx_eff.as<double>(), first,
+                            n, st));
+  pb.src_x = c->sx_eff.as<double>();
+  return RMC_OK;
 }
 
 rmc_status ready(rmc_ctx *c, bool need_sources) {
@@ -533,7 +551,7 @@ void fill_stats(rmc_run_stats *s, const unsigned long long *h, double ms) {
 
 extern "C" {
 
-int rmc_abi_version(void) { return 5; }
+int rmc_abi_version(void) { return 6; }
 
 rmc_status rmc_create(rmc_ctx **out, int device, int precision) {
   if (!out) return RMC_EINVAL;
@@ -570,7 +588,7 @@ void rmc_destroy(rmc_ctx *c) {
                     &c->tmp1, &c->tmp2, &c->tmp3, &c->tmp4, &c->tmp5, &c->b_probs, &c->b_starts,
                     &c->slots, &c->d_slice, &c->pq_ctl, &c->pq_jobs, &c->pq_counts, &c->tp_leaf,
                     &c->tp_seg, &c->tp_next, &c->tp_first, &c->tp_count, &c->tp_pix, &c->tp_wt, &c->tp_x,
-                    &c->tp_ctl};
+                    &c->tp_ctl, &c->sx_eff};
   for (DevBuf *b : bufs) b->release();
   for (auto &o : c->obs) o.cube.release();
   if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -625,6 +643,28 @@ rmc_status rmc_set_option(rmc_ctx *c, int opt, int64_t v) {
       break;
     default: return fail(c, RMC_EINVAL, "unknown option %d", opt);
   }
+  return RMC_OK;
+}
+
+rmc_status rmc_set_source_spectrum(rmc_ctx *c, int kind, const double *params) {
+  rmc_status r = enter(c);
+  if (r) return r;
+  if (kind == RMC_SPEC_MONO) {
+    c->spec_kind = 0;
+    return RMC_OK;
+  }
+  if (!params) return fail(c, RMC_EINVAL, "null spectrum parameters");
+  if (kind == RMC_SPEC_GAUSS) {
+    if (!finite_nonneg(params[0])) return fail(c, RMC_EINVAL, "Gaussian sigma must be finite and >= 0");
+  } else if (kind == RMC_SPEC_POWER_LAW) {
+    if (!(std::isfinite(params[0]) && std::isfinite(params[1]) && std::isfinite(params[2])) ||
+        !(params[0] > 0.0) || !(params[1] > params[0]))
+      return fail(c, RMC_EINVAL, "power law needs 0 < lambda_min < lambda_max and a finite beta");
+  } else {
+    return fail(c, RMC_EINVAL, "unknown spectrum kind %d", kind);
+  }
+  c->spec_kind = kind;
+  for (int q = 0; q < 3; ++q) c->spec_p[q] = kind == RMC_SPEC_GAUSS && q > 0 ? 0.0 : params[q];
   return RMC_OK;
 }
 
@@ -1029,6 +1069,8 @@ rmc_status stream_begin_single(rmc_ctx *c, uint64_t seed, int64_t first, int64_t
   if (r) return r;
   c->last_n = n;
   make_problem(c, first, n, seed, c->pb_host);
+  r = apply_spectrum(c, c->pb_host, first, n, c->stream);
+  if (r) return r;
   r = peel_queue(c, &c->s_pq);
   if (r) return r;
   if (c->obs.empty()) c->s_pq = nullptr;
@@ -1493,6 +1535,8 @@ rmc_status batch_open(rmc_ctx *const *P, int np, const uint64_t *seeds, const in
   for (int i = 0; i < np; ++i) {
     P[i]->last_n = npk[i];
     make_problem(P[i], 0, npk[i], seeds[i], c0->b_host[i]);
+    r = apply_spectrum(P[i], c0->b_host[i], 0, npk[i], c0->stream);
+    if (r) return fail(c0, r, "problem %d: %s", i, P[i]->err.c_str());
     c0->b_host[i].pq = c0->s_pq;
     c0->b_host[i].index = i;
     c0->b_starts_host[i + 1] = c0->b_starts_host[i] + npk[i];

@@ -110,6 +110,9 @@ struct ProblemK {
   int64_t max_events;
   double skip_tau, skip_frac; // core-skipping (skip_tau > 0: on)
   int voigt_exact;          // 1: H from voigt_h_exact, 0: the Tasitsiomi form
+  int spec_kind;            // source spectrum: 0 monochromatic, 1 Gaussian, 2 power law
+  double spec_p[3];         // sigma_x | lambda_min, lambda_max (A), beta
+  double lambda_ref;        // rest wavelength of line 0 (A)
   // sources (device)
   const double *src_pos, *src_dir, *src_x;
   int64_t first, n;         // packet range of this run
@@ -149,8 +152,10 @@ enum {
   J_ALBEDO = 6,   // dust: scatter or absorb
   J_GAUSS1 = 6,   // line, |x| >= 8: Box-Muller pair for the Gaussian
   J_GAUSS2 = 7,
-  J_REJ = 6       // line, |x| < 8: rejection round i uses J_REJ+3i .. +2
+  J_REJ = 6,      // line, |x| < 8: rejection round i uses J_REJ+3i .. +2
                   // (double) or J_REJ+2i, +1 (float)
+  J_SRC1 = 4,     // emission (event 0): source-spectrum draws
+  J_SRC2 = 5
 };
 
 // Uniforms of one event.  Double: draw j uses the word pair (2(j%2),

@@ -347,6 +347,53 @@ __device__ void finish(const ProblemK &pb, Lane<R> &s, int status) {
 
 // Emission (Sect. 2): position and frequency from the source list,
 // isotropic direction unless given, tau_event = -ln r.
+// Source spectrum (Sect. 2.1), added to the source's own x, in double in
+// both precisions, by a pass before the transport (k_source_x) so that the
+// transport kernels carry none of it.  Gaussian line: Box-Muller draw times
+// sigma (Doppler widths of the reference line).  Power-law continuum,
+// F_lambda ~ lambda^beta on [lambda_min, lambda_max]: inverse CDF of the
+// photon-number distribution lambda F_lambda, then
+// x = (lambda_ref - lambda) / (lambda b_ref)  (nu = c / lambda).
+// r1, r2: the packet's emission draws J_SRC1, J_SRC2.
+__device__ inline double source_spectrum_x(const ProblemK &pb, double r1, double r2) {
+  if (pb.spec_kind == 1) return pb.spec_p[0] * sqrt(-2.0 * log(r1)) * cospi(2.0 * r2);
+  const double lmin = pb.spec_p[0], lmax = pb.spec_p[1], beta = pb.spec_p[2];
+  const double r = r1;
+  double lam;
+  if (beta == -2.0) {
+    lam = lmin * exp(r * log(lmax / lmin));
+  } else {
+    const double e = 2.0 + beta, a = pow(lmin, e);
+    lam = pow(a + r * (pow(lmax, e) - a), 1.0 / e);
+  }
+  return (pb.lambda_ref - lam) / (lam * pb.b_ref);
+}
+
+// x_out[pid] = src_x[pid] + the packet's spectral draw, for pid in
+// [first, first + n): the same counter-based emission draws (event 0,
+// slots J_SRC1 and J_SRC2) the transport's precision would take.
+template <class R>
+__global__ void __launch_bounds__(256) k_source_x(const ProblemK pb, const double *__restrict__ src_x,
+                                                  double *__restrict__ x_out, int64_t first, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t pid = first + i;
+  EventRng<R> rng(pb.seed, (uint64_t)pid, 0u);
+  const double r1 = (double)rng.u(J_SRC1), r2 = (double)rng.u(J_SRC2);
+  x_out[pid] = src_x[pid] + source_spectrum_x(pb, r1, r2);
+}
+
+hipError_t launch_source_x(bool f32, const ProblemK &pb, const double *src_x, double *x_out, int64_t first,
+                           int64_t n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((n + 255) / 256);
+  if (f32)
+    hipLaunchKernelGGL(k_source_x<float>, dim3(blocks), dim3(256), 0, stream, pb, src_x, x_out, first, n);
+  else
+    hipLaunchKernelGGL(k_source_x<double>, dim3(blocks), dim3(256), 0, stream, pb, src_x, x_out, first, n);
+  return hipGetLastError();
+}
+
 template <class R, bool DEFER, int NL>
 __device__ void emit(const ProblemK &pb, int64_t pid, Lane<R> &s, int *stk, int *pstk, int stride,
                      const PeelSink &snk) {

@@ -51,5 +51,8 @@ hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long 
 hipError_t launch_u64_to_f64(const unsigned long long *a, double *b, int64_t n, hipStream_t st);
 hipError_t launch_f32_to_f64(const float *a, double *b, int64_t n, hipStream_t st);
 hipError_t launch_f64_to_f32(const double *a, float *b, int64_t n, hipStream_t st);
+// emitted x of packets [first, first+n) under the problem's source spectrum
+hipError_t launch_source_x(bool f32, const ProblemK &pb, const double *src_x, double *x_out, int64_t first,
+                           int64_t n, hipStream_t stream);
 
 }  // namespace rmc

@@ -73,6 +73,7 @@ _sig = {
     "rmc_set_stream": (C.c_int, [_P, _P]),
     "rmc_set_option": (C.c_int, [_P, C.c_int, _i64]),
     "rmc_set_core_skip": (C.c_int, [_P, C.c_double, C.c_double]),
+    "rmc_set_source_spectrum": (C.c_int, [_P, C.c_int, _P]),
     "rmc_set_mesh": (C.c_int, [_P, _i64, _P, _P, C.c_double]),
     "rmc_set_gas": (C.c_int, [_P, _P, _P, _P, _P]),
     "rmc_set_lines": (C.c_int, [_P, C.c_int, _P, C.c_double]),
@@ -194,6 +195,13 @@ class Context:
 
     def set_option(self, opt, value):
         self._chk(_L.rmc_set_option(self._h, opt, int(value)), "set_option")
+
+    def set_source_spectrum(self, kind, params=(0.0, 0.0, 0.0)):
+        """Source spectrum: 0 monochromatic, 1 Gaussian (sigma_x,), 2 power
+        law (lambda_min, lambda_max, beta); see rmc_set_source_spectrum."""
+        p = np.zeros(3)
+        p[:len(params)] = params
+        self._chk(_L.rmc_set_source_spectrum(self._h, int(kind), p.ctypes.data), "set_source_spectrum")
 
     def set_core_skip(self, tau_skip=1.0, frac=0.2):
         """Core-skipping on (tau_skip > 0) or off (tau_skip = 0); see
@@ -394,6 +402,8 @@ class Context:
             if sources:
                 c.set_sources(pb.sources.pos, pb.sources.x, pb.sources.dir)
                 c.n_src = len(pb.sources.x)
+                if getattr(pb, "spectrum", None):
+                    c.set_source_spectrum(pb.spectrum[0], pb.spectrum[1:])
             if observers:
                 for o in pb.observers:
                     c.add_observer(o.k, o.nx, o.ny, o.nbins, o.fov, o.x_min, o.x_max)
