@@ -84,7 +84,9 @@ enum {
   J_GAUSS2 = 7,
   J_REJ = 6,      /* line, |x| < 8: round i uses 6+3i .. 8+3i  */
   J_SRC1 = 4,     /* emission (event 0): source-spectrum draws */
-  J_SRC2 = 5
+  J_SRC2 = 5,
+  J_DECAY = 1 << 30 /* line: resonant or fluorescent decay; above
+                       any rejection round (they stop at 2^20)    */
 };
 
 struct Rng {
@@ -480,8 +482,22 @@ struct Problem {
  * c (lambda_ref - lambda_i) / (lambda_i lambda_ref).  Differencing the two
  * absolute frequencies (~2.5e15 Hz for Lya) instead would leave ~0.25 Hz of
  * rounding, ~1e-11 of a narrow line's Doppler width. */
-double line_offset(const Problem &P, const orc_line &ln) {
-  return C_LIGHT * ((P.lambda_ref_A - ln.lambda0_A) / (ln.lambda0_A * P.lambda_ref_A)) * 1e8;
+double lambda_offset(const Problem &P, double lambda_A) {
+  return C_LIGHT * ((P.lambda_ref_A - lambda_A) / (lambda_A * P.lambda_ref_A)) * 1e8;
+}
+double line_offset(const Problem &P, const orc_line &ln) { return lambda_offset(P, ln.lambda0_A); }
+
+/* Fluorescent re-emission (Sect. 3.2.1): the photon leaves along k at the
+ * rest frequency nu_j of channel j in the frame of the scatterer (atom
+ * velocity vatom), nu_cell = nu_j (1 + k.vatom/c), then to the external
+ * frame through the cell velocity; returned as an offset from nu_ref. */
+double to_external(const Problem &P, double dnu_cell, const double k[3], const double vc[3]);
+double fluor_dnu_ext(const Problem &P, const orc_line &ln, int j, const double k[3], const double vatom[3],
+                     const double vc[3]) {
+  double off = lambda_offset(P, ln.fluor_lambda_A[j]);
+  double nu_j = P.nu_ref + off;
+  double dnu_cell = off + nu_j * (k[0] * vatom[0] + k[1] * vatom[1] + k[2] * vatom[2]) / C_LIGHT;
+  return to_external(P, dnu_cell, k, vc);
 }
 
 struct Opac {
@@ -629,6 +645,9 @@ void peel_deposit(const Problem &P, int n_obs, const orc_observer *obs, ThreadOu
     if (kind == 0) { /* emission */
       weight = 1.0 / (4.0 * PI);
       dnu_ext_o = dnu_ext_emit;
+    } else if (kind == 3) { /* fluorescent re-emission, isotropic; `core` is the channel */
+      weight = 1.0 / (4.0 * PI);
+      dnu_ext_o = fluor_dnu_ext(P, *ln, core, ko, vatom, vcell);
     } else if (kind == 1) { /* line scattering, same atom velocity */
       double mu = dot3(kin, ko);
       double P_ = (ln->phase == ORC_PHASE_ISO) ? 0.5 : (core ? p_core(mu) : p_wing(mu));
@@ -824,8 +843,28 @@ void transport_packet(const Problem &P, uint64_t seed, uint64_t pid, const doubl
          * nu_scat,in = nu_in (1 - k_in . v_X / c), within 0.2 dnu_D of nu_lu */
         double off = (dnu_in - line_offset(P, ln)) - (P.nu_ref + dnu_in) * dot3(kin, vatom) / C_LIGHT;
         int core = std::fabs(off) < 0.2 * q.dnu;
+        /* decay channel (Sect. 3.2.1): resonant with probability
+         * A_ul / (A_ul + sum A_j), else fluorescent channel j by the
+         * cumulative ratios */
+        int fch = -1;
+        if (ln.n_fluor > 0 && !pb.forward_only) {
+          double a_tot = ln.A_ul + ln.fluor_A_ul[0] + (ln.n_fluor > 1 ? ln.fluor_A_ul[1] : 0.0);
+          double u = rng.u(J_DECAY);
+          if (u >= ln.A_ul / a_tot) fch = (ln.n_fluor > 1 && u >= (ln.A_ul + ln.fluor_A_ul[0]) / a_tot) ? 1 : 0;
+        }
         nscat += 1;
         to.st.scatterings += 1;
+        if (fch >= 0) {
+          peel_deposit(P, n_obs, obs, to, p, 3, kin, dnu_in, vatom, &ln, fch, vc, 0.0);
+          double mu = 2.0 * rng.u(J_MU) - 1.0;
+          double phi = 2.0 * PI * rng.u(J_PHI);
+          double s = std::sqrt(std::max(0.0, 1.0 - mu * mu));
+          for (int d = 0; d < 3; ++d)
+            k[d] = mu * kin[d] + s * (std::cos(phi) * e1[d] + std::sin(phi) * e2[d]);
+          dnu_ext = fluor_dnu_ext(P, ln, fch, k, vatom, vc);
+          tau_ev = -std::log(rng.u(J_TAU));
+          continue;
+        }
         peel_deposit(P, n_obs, obs, to, p, 1, kin, dnu_in, vatom, &ln, core, vc, 0.0);
         if (!pb.forward_only) {
           double ru = rng.u(J_MU);

@@ -38,6 +38,8 @@ typedef struct {
   double abundance;  /* n_X / n_HI                                     */
   int phase;         /* ORC_PHASE_LYA (core/wing dipole) or ISO        */
   int recoil;        /* 1: recoil term of the nu_out relation on       */
+  int n_fluor;       /* fluorescent decay channels (0..2)              */
+  double fluor_lambda_A[2], fluor_A_ul[2];
 } orc_line;
 
 typedef struct {

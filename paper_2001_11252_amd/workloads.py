@@ -37,12 +37,18 @@ class Line:
     abundance: float = 1.0
     phase: int = PHASE_LYA
     recoil: int = 1
+    fluor: tuple = ()        # fluorescent channels ((lambda_A, A_ul), ...)
 
 
 LYA = Line("Lya", 1215.67, 6.265e8, 0.416, M_H_AMU, 1.0, PHASE_LYA, 1)
 D_LYA = Line("DLya", 1215.34, 6.265e8, 0.416, 2.01410, 3e-5, PHASE_LYA, 1)
 MGII_2796 = Line("MgII2796", 2796.35, 2.60e8, 0.608, M_MG_AMU, 1.0, PHASE_ISO, 1)
 MGII_2804 = Line("MgII2804", 2803.53, 2.57e8, 0.303, M_MG_AMU, 1.0, PHASE_ISO, 1)
+# Fe II UV1 (Table 1): the two resonant lines and their fluorescent channels
+M_FE_AMU = 55.845
+FEII_2587 = Line("FeII2587", 2586.65, 8.94e7, 0.0717, M_FE_AMU, 1.0, PHASE_ISO, 1,
+                 ((2612.65, 1.20e8), (2632.11, 6.29e7)))
+FEII_2600 = Line("FeII2600", 2600.17, 2.35e8, 0.239, M_FE_AMU, 1.0, PHASE_ISO, 1, ((2626.45, 3.52e7),))
 
 
 @dataclass
