@@ -100,6 +100,16 @@ typedef struct {
   double abundance;   /* scatterer density / n_HI                           */
   int phase;          /* RMC_PHASE_LYA_DIPOLE (core/wing) or ISOTROPIC      */
   int recoil;         /* 1: recoil term of the outgoing-frequency relation  */
+  /* Fluorescent decay channels of the upper level (Sect. 3.2.1, Table 1):
+   * after an absorption the atom decays through channel i with probability
+   * A_i / (A_ul + sum A_i), else resonantly; a fluorescent photon leaves
+   * isotropically at the channel's rest frequency in the scatterer's frame
+   * (no recoil) and is not absorbed by any line again.  n_fluor in [0, 2];
+   * wavelengths (Angstrom) and A (s^-1) positive and finite.  Lines with
+   * channels run in the multi-line transport kernel.                       */
+  int n_fluor;
+  double fluor_lambda_A[2];
+  double fluor_A_ul[2];
 } rmc_line;
 
 typedef struct {

@@ -440,6 +440,19 @@ void make_problem(rmc_ctx *c, int64_t first, int64_t n, uint64_t seed, ProblemK 
     k.rec = H_PLANCK * q.nu0 / (ln.mass_amu * AMU_G * C_LIGHT * C_LIGHT);
     k.phase = ln.phase;
     k.recoil = ln.recoil;
+    k.n_fluor = ln.n_fluor;
+    k.a_res = k.a_cum0 = 1.0;
+    for (int j = 0; j < 2; ++j) k.xf0[j] = k.sf[j] = 0.0;
+    if (ln.n_fluor > 0) {
+      const double a_tot = ln.A_ul + ln.fluor_A_ul[0] + (ln.n_fluor > 1 ? ln.fluor_A_ul[1] : 0.0);
+      k.a_res = ln.A_ul / a_tot;
+      k.a_cum0 = (ln.A_ul + ln.fluor_A_ul[0]) / a_tot;
+      for (int j = 0; j < ln.n_fluor; ++j) {
+        const double lf = ln.fluor_lambda_A[j], l0 = c->lines[0].lambda0_A;
+        k.xf0[j] = (l0 - lf) / (lf * pb.b_ref);
+        k.sf[j] = l0 / lf;
+      }
+    }
   }
   pb.box_cm = c->box_cm;
   pb.domain = c->domain;
@@ -551,7 +564,7 @@ void fill_stats(rmc_run_stats *s, const unsigned long long *h, double ms) {
 
 extern "C" {
 
-int rmc_abi_version(void) { return 6; }
+int rmc_abi_version(void) { return 7; }
 
 rmc_status rmc_create(rmc_ctx **out, int device, int precision) {
   if (!out) return RMC_EINVAL;
@@ -711,6 +724,11 @@ rmc_status rmc_set_lines(rmc_ctx *c, int n, const rmc_line *lines, double T_ref)
     if (!(l.lambda0_A > 0) || !(l.A_ul > 0) || !(l.f_lu >= 0) || !(l.mass_amu > 0) || !finite_nonneg(l.abundance) ||
         (l.phase != RMC_PHASE_LYA_DIPOLE && l.phase != RMC_PHASE_ISOTROPIC))
       return fail(c, RMC_EINVAL, "line %d: bad parameters", i);
+    if (l.n_fluor < 0 || l.n_fluor > 2) return fail(c, RMC_EINVAL, "line %d: 0..2 fluorescent channels", i);
+    for (int j = 0; j < l.n_fluor; ++j)
+      if (!(l.fluor_lambda_A[j] > 0) || !std::isfinite(l.fluor_lambda_A[j]) || !(l.fluor_A_ul[j] > 0) ||
+          !std::isfinite(l.fluor_A_ul[j]))
+        return fail(c, RMC_EINVAL, "line %d: bad fluorescent channel %d", i, j);
     c->lines[i] = l;
   }
   c->n_lines = n;
@@ -1077,7 +1095,7 @@ rmc_status stream_begin_single(rmc_ctx *c, uint64_t seed, int64_t first, int64_t
   c->s_defer = c->s_pq != nullptr || c->obs.empty();
   c->pb_host.pq = c->s_pq;
   c->pb_host.index = 0;
-  c->s_one_line = c->n_lines == 1;
+  c->s_one_line = c->n_lines == 1 && c->lines[0].n_fluor == 0;
   c->starts_host[0] = 0;
   c->starts_host[1] = n;
   HIPCHK(c, c->d_prob.ensure(sizeof(ProblemK)));
@@ -1529,7 +1547,8 @@ rmc_status batch_open(rmc_ctx *const *P, int np, const uint64_t *seeds, const in
   if (!any_obs) c0->s_pq = nullptr;
   c0->s_defer = c0->s_pq != nullptr || !any_obs;
   c0->s_one_line = true;
-  for (int i = 0; i < np; ++i) c0->s_one_line = c0->s_one_line && P[i]->n_lines == 1;
+  for (int i = 0; i < np; ++i)
+    c0->s_one_line = c0->s_one_line && P[i]->n_lines == 1 && P[i]->lines[0].n_fluor == 0;
   c0->b_host.resize(np);
   c0->b_starts_host.assign(np + 1, 0);
   for (int i = 0; i < np; ++i) {

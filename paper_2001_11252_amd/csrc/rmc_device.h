@@ -40,6 +40,13 @@ struct LineK {
   double delta, s, inv_s, inv_mu, mu, alpha, kfac;
   double rec;      // h nu_i / (m_i c^2)
   int phase, recoil;
+  // fluorescent channels: decay through channel j when the draw u lies at
+  // or above a_res (j = 0) / a_cum0 (j = 1); the photon leaves at
+  // x_ext = xf0[j] + sf[j] (b_a + b_c + b_a b_c) / b_ref with b_a, b_c the
+  // atom's and the cell's k.v/c, xf0 = (lambda_ref - lambda_j)/(lambda_j b_ref),
+  // sf = lambda_ref / lambda_j (nu_j / nu_ref)
+  int n_fluor;
+  double a_res, a_cum0, xf0[2], sf[2];
 };
 
 struct ObsK {
@@ -155,7 +162,9 @@ enum {
   J_REJ = 6,      // line, |x| < 8: rejection round i uses J_REJ+3i .. +2
                   // (double) or J_REJ+2i, +1 (float)
   J_SRC1 = 4,     // emission (event 0): source-spectrum draws
-  J_SRC2 = 5
+  J_SRC2 = 5,
+  J_DECAY = 1 << 30  // line: resonant or fluorescent decay (far above any
+                     // rejection round, which stops at 2^20)
 };
 
 // Uniforms of one event.  Double: draw j uses the word pair (2(j%2),

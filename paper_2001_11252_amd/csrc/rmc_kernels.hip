@@ -156,14 +156,14 @@ struct LaneCount {
 
 // What a scattering (or emission) needs to be redone toward an observer.
 template <class R> struct PeelSrc {
-  int kind;        // 0 emission, 1 line, 2 dust
+  int kind;        // 0 emission, 1 line, 2 dust, 3 fluorescent re-emission
   R kin[3];
   R x;             // emission / dust: x_ext of the packet; line: cell-frame x
   R w;             // k_in . u of the cell (dust)
   R U[3];          // atom velocity / v_th of the line (line)
   R bc;            // v_th,line,cell / c (line)
   R rho;           // sqrt(T/T_ref) (line)
-  int line, core;
+  int line, core;  // (fluorescent: core holds the channel)
   R ux, uy, uz;    // cell bulk velocity / v_th,ref
 };
 
@@ -253,6 +253,14 @@ __device__ void peel_all(const ProblemK &pb, const double p[3], const PeelSrc<R>
     if (s.kind == 0) {
       weight = R(1.0 / (4.0 * PI_D));
       xo = s.x;
+    } else if (NL > 1 && s.kind == 3) {
+      // fluorescent re-emission: isotropic, at the channel's rest frequency
+      // in the atom frame, then through the cell's velocity
+      const LineK &ln = pb.lines[s.line];
+      weight = R(1.0 / (4.0 * PI_D));
+      const R ba = s.bc * (ko[0] * s.U[0] + ko[1] * s.U[1] + ko[2] * s.U[2]);
+      const R bw = R(pb.b_ref) * (ko[0] * s.ux + ko[1] * s.uy + ko[2] * s.uz);
+      xo = R(ln.xf0[s.core]) + M<R>::div(R(ln.sf[s.core]) * (ba + bw + ba * bw), R(pb.b_ref));
     } else if (s.kind == 1) {
       const LineK &ln = pb.lines[s.line];
       const R mu = s.kin[0] * ko[0] + s.kin[1] * ko[1] + s.kin[2] * ko[2];
@@ -510,7 +518,38 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R, NL> &o, in
     // frequency seen by the atom, nu_in (1 - k_in.v/c), within 0.2 dnu_D
     const R g1 = R(1) + bc * x;
     const int core = fabs(x - g1 * upar) < R(0.2);
+    // decay channel (Sect. 3.2.1): fluorescent channel j when the draw lies
+    // at or above A_ul / sum A (then (A_ul + A_0) / sum A for j = 1); lines
+    // with channels run in the multi-line kernels only
+    int fch = -1;
+    if constexpr (NL > 1) {
+      if (ln.n_fluor > 0 && !pb.forward_only) {
+        const R ud = rng.u(J_DECAY);
+        if (ud >= R(ln.a_res)) fch = (ln.n_fluor > 1 && ud >= R(ln.a_cum0)) ? 1 : 0;
+      }
+    }
     ++s.nscat;
+    if (NL > 1 && fch >= 0) {
+      if (pb.n_obs) {
+        ps.kind = 3;
+        ps.U[0] = U[0]; ps.U[1] = U[1]; ps.U[2] = U[2];
+        ps.bc = bc;
+        ps.line = i;
+        ps.core = fch;
+        peel_all<R, DEFER, NL>(pb, s.p, ps, pstk, stride, s.cnt, snk, &sc);
+      }
+      const R mu = R(2) * rng.u(J_MU) - R(1);
+      M<R>::sincos2pi(rng.u(J_PHI), &sp, &cp);
+      const R st = M<R>::sqrt(fmax(R(0), R(1) - mu * mu));
+#pragma unroll
+      for (int d = 0; d < 3; ++d) s.k[d] = mu * kin[d] + st * (cp * e1[d] + sp * e2[d]);
+      set_geom_dir(s);
+      const R ba = bc * (s.k[0] * U[0] + s.k[1] * U[1] + s.k[2] * U[2]);
+      const R bw = R(pb.b_ref) * (s.k[0] * s.lf.ux + s.k[1] * s.lf.uy + s.k[2] * s.lf.uz);
+      s.x = R(ln.xf0[fch]) + M<R>::div(R(ln.sf[fch]) * (ba + bw + ba * bw), R(pb.b_ref));
+      s.tau = -(double)M<R>::log(rng.u(J_TAU));
+      return ST_NONE;
+    }
     if (pb.n_obs) {
       ps.kind = 1;
       ps.x = x;

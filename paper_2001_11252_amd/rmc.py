@@ -37,7 +37,8 @@ class RmcError(RuntimeError):
 
 class RmcLine(C.Structure):
     _fields_ = [("lambda0_A", C.c_double), ("A_ul", C.c_double), ("f_lu", C.c_double),
-                ("mass_amu", C.c_double), ("abundance", C.c_double), ("phase", C.c_int), ("recoil", C.c_int)]
+                ("mass_amu", C.c_double), ("abundance", C.c_double), ("phase", C.c_int), ("recoil", C.c_int),
+                ("n_fluor", C.c_int), ("fluor_lambda_A", C.c_double * 2), ("fluor_A_ul", C.c_double * 2)]
 
 
 class RmcRunStats(C.Structure):
@@ -132,7 +133,13 @@ def _host(a, dtype):
 
 
 def _line(ln):
-    return RmcLine(ln.lambda0_A, ln.A_ul, ln.f_lu, ln.mass_amu, ln.abundance, ln.phase, ln.recoil)
+    s = RmcLine(ln.lambda0_A, ln.A_ul, ln.f_lu, ln.mass_amu, ln.abundance, ln.phase, ln.recoil)
+    fl = getattr(ln, "fluor", ())
+    s.n_fluor = len(fl)
+    for j, (lam, a) in enumerate(fl):
+        s.fluor_lambda_A[j] = lam
+        s.fluor_A_ul[j] = a
+    return s
 
 
 def line_quantities(line, T):

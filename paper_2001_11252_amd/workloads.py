@@ -297,6 +297,35 @@ def deuterium_sphere(sigma0_fn, n_packets, N_HI=2e19, T=1e4, d_to_h=3e-5, level=
     return pb
 
 
+def feii_wind(sigma0_fn, n_packets, N=1e17, vmax_kms=100.0, b_kms=30.0, level=6, r_min_frac=0.05):
+    """Fe II UV1 wind (the paper's idealised-set-up example, Sect. 5):
+    sphere R = 1/2 with Fe II from r_min = R/20 to R, density ~ r^-3 (column
+    N from r_min outwards), radial velocity v_max r/R, Doppler parameter
+    b = 30 km/s (as the temperature m b^2 / 2k), the Fe II 2587 and 2600
+    lines with their fluorescent channels (2612, 2632; 2626), central
+    source with a flat continuum F_lambda over 2570-2640 A; uniform grid of
+    level 6, values at cell centres."""
+    mesh = uniform_mesh(level)
+    R = 0.5
+    r_min = r_min_frac * R
+    cen, _ = mesh.centres()
+    rv = cen - 0.5
+    r = np.linalg.norm(rv, axis=1)
+    # N = int_rmin^R n0 (r/rmin)^-3 dr = n0 rmin (1 - (rmin/R)^2) / 2 (box units)
+    n0 = 2.0 * N / (r_min * mesh.box_cm * (1.0 - r_min_frac ** 2))
+    inside = (r >= r_min) & (r < R)
+    n = np.where(inside, n0 * (np.maximum(r, r_min) / r_min) ** -3.0, 0.0)
+    v = np.zeros((mesh.n, 3))
+    v[inside] = (vmax_kms * KMS / R) * rv[inside]
+    T = M_FE_AMU * 1.66053907e-24 * (b_kms * KMS) ** 2 / (2.0 * 1.380649e-16)
+    gas = Gas(n, np.full(mesh.n, T), v, np.zeros(mesh.n))
+    pb = Problem("feii_wind", mesh, gas, Domain(DOM_SPHERE, (0.5, 0.5, 0.5, R)), [FEII_2587, FEII_2600], T,
+                 Dust(0.0, 0.0), _point_sources(n_packets), [], seed=0x5EED0008,
+                 meta=dict(N=N, vmax_kms=vmax_kms, b_kms=b_kms, T=T))
+    pb.spectrum = (2, 2570.0, 2640.0, 0.0)
+    return pb
+
+
 def thick_sphere(sigma0_fn, n_packets=1_000_000, tau0=1e7, level=3, nx=128, nbins=100):
     """Dust-free static sphere R = 1/2 at T = 1e4 K with tau0 = 1e7 from the
     centre on a uniform 8^3 grid (a tau of a cell ~ 1.2e3: the thick-cell
