@@ -49,6 +49,11 @@ M_FE_AMU = 55.845
 FEII_2587 = Line("FeII2587", 2586.65, 8.94e7, 0.0717, M_FE_AMU, 1.0, PHASE_ISO, 1,
                  ((2612.65, 1.20e8), (2632.11, 6.29e7)))
 FEII_2600 = Line("FeII2600", 2600.17, 2.35e8, 0.239, M_FE_AMU, 1.0, PHASE_ISO, 1, ((2626.45, 3.52e7),))
+# Si II (Table 1): three resonant lines, each with one fluorescent channel
+M_SI_AMU = 28.0855
+SIII_1190 = Line("SiII1190", 1190.42, 6.53e8, 0.277, M_SI_AMU, 1.0, PHASE_ISO, 1, ((1194.50, 3.45e9),))
+SIII_1193 = Line("SiII1193", 1193.28, 2.69e9, 0.575, M_SI_AMU, 1.0, PHASE_ISO, 1, ((1197.39, 1.40e9),))
+SIII_1260 = Line("SiII1260", 1260.42, 2.57e9, 1.22, M_SI_AMU, 1.0, PHASE_ISO, 1, ((1265.02, 4.73e8),))
 
 
 @dataclass

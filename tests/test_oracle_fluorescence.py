@@ -102,3 +102,21 @@ def test_fluorescent_peel_off_normalisation(orc):
     total = r["cubes"][0].sum()
     expect = fluor.sum() / (4 * np.pi)
     assert abs(total / expect - 1) < 1e-9
+
+
+@pytest.mark.parametrize("name", ["SiII1190", "SiII1193", "SiII1260"])
+def test_si_ii_lines_and_branching(orc, name):
+    # Table 1 Si II data; a fluorescent channel stronger than the resonance
+    # (1190 -> 1194: A_f / sum A = 0.84) still splits the first decays as A_j / sum A
+    row = {r[0]: r[1:] for r in golden("si_ii")}[name]
+    line = {"SiII1190": W.SIII_1190, "SiII1193": W.SIII_1193, "SiII1260": W.SIII_1260}[name]
+    assert (line.lambda0_A, line.A_ul, line.f_lu) == tuple(row[:3])
+    assert line.fluor == ((row[3], row[4]),)
+    n = 40000
+    r = orc.run(_sphere(orc, line, n), 8, threads=8, with_cubes=False)
+    m = (r["n_scat"] >= 1).sum()
+    xj = _channel_x(orc, line, 0)[0]
+    k = ((np.abs(r["x"] - xj) < 20) & (r["n_scat"] == 1)).sum()
+    p = row[4] / (row[1] + row[4])
+    z = (k - m * p) / np.sqrt(m * p * (1 - p))
+    assert abs(z) < 4, z
