@@ -321,8 +321,9 @@ rmc_status rmc_batch_begin(rmc_ctx *const *problems, int n_problems, const uint6
 
 /* Pick the transport launch shape for a batch by measurement: every
  * candidate (threads per block x idle lanes a wave gathers before refilling
- * x loop iterations per launch) runs `trial_slices` launches of this batch
- * (their results are discarded) and the one with the most scatterings plus
+ * x loop iterations per launch) runs one untimed launch of this batch, then
+ * `trial_slices` timed ones (their results are discarded), and the one with
+ * the most scatterings plus
  * ray-cell crossings per second is kept as the options of problems[0] for
  * later rmc_batch_run calls.  best[3] (may be NULL) receives the chosen
  * {block, refill, slice_iters}. */

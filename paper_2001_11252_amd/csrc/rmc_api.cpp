@@ -1610,14 +1610,19 @@ rmc_status rmc_batch_autotune(rmc_ctx *const *P, int np, const uint64_t *seeds, 
         c0->slice_iters = sl;
         r = batch_open(P, np, seeds, npk);
         if (r) return r;
+        // the stream's first launch (lanes starting their first packets) is
+        // left out, so that shapes are ranked in the state a run spends its
+        // time in
         double work = 0.0, ms = 0.0;
-        for (int t = 0; t < trials; ++t) {
+        for (int t = 0; t <= trials; ++t) {
           rmc_run_stats st;
           int64_t rem = 0;
           r = stream_step(c0, &st, &rem);
           if (r) return r;
-          work += (double)st.scatterings + (double)st.crossings + (double)st.peel_crossings;
-          ms += st.kernel_ms + st.peel_pass_ms;
+          if (t > 0 || rem == 0) {
+            work += (double)st.scatterings + (double)st.crossings + (double)st.peel_crossings;
+            ms += st.kernel_ms + st.peel_pass_ms;
+          }
           if (rem == 0) break;
         }
         c0->s_open = false;
