@@ -722,6 +722,34 @@ double spectrum_offset(const Problem &P, const Rng &rng) {
     double g = std::sqrt(-2.0 * std::log(rng.u(J_SRC1))) * std::cos(2.0 * PI * rng.u(J_SRC2));
     return g * pb.spec_p[0] * P.dnu_ref;
   }
+  if (pb.spec_kind == 3) {
+    /* tabulated continuum: between neighbouring points F_lambda is the
+     * power law through them; the photon count of bin i is the integral of
+     * lambda F_lambda over it; a packet takes bin i with probability
+     * N_i / sum N, then lambda inside it by the power-law inverse CDF */
+    const int m = pb.spec_n;
+    std::vector<double> beta(m - 1), cum(m, 0.0);
+    for (int i = 0; i + 1 < m; ++i) {
+      double l0 = pb.spec_lambda[i], l1 = pb.spec_lambda[i + 1];
+      double b = std::log(pb.spec_flux[i + 1] / pb.spec_flux[i]) / std::log(l1 / l0);
+      beta[i] = b;
+      /* int_l0^l1 lambda F_i (lambda/l0)^b dlambda, in ratios (steep
+       * slopes between close points would overflow lambda^(b+2)) */
+      double n = (b == -2.0) ? pb.spec_flux[i] * l0 * l0 * std::log(l1 / l0)
+                             : pb.spec_flux[i] * l0 * l0 * (std::pow(l1 / l0, b + 2.0) - 1.0) / (b + 2.0);
+      cum[i + 1] = cum[i] + n;
+    }
+    double r1 = rng.u(J_SRC1) * cum[m - 1];
+    int i = (int)(std::upper_bound(cum.begin() + 1, cum.end() - 1, r1) - (cum.begin() + 1));
+    double l0 = pb.spec_lambda[i], l1 = pb.spec_lambda[i + 1], b = beta[i], r = rng.u(J_SRC2), lam;
+    if (b == -2.0) {
+      lam = l0 * std::exp(r * std::log(l1 / l0));
+    } else {
+      double e = 2.0 + b;
+      lam = l0 * std::pow(1.0 + r * (std::pow(l1 / l0, e) - 1.0), 1.0 / e);
+    }
+    return C_LIGHT * ((P.lambda_ref_A - lam) / (lam * P.lambda_ref_A)) * 1e8;
+  }
   if (pb.spec_kind == 2) {
     double lmin = pb.spec_p[0], lmax = pb.spec_p[1], b = pb.spec_p[2], r = rng.u(J_SRC1), lam;
     if (b == -2.0) {

@@ -33,7 +33,8 @@ class OrcProblem(C.Structure):
                 ("T_ref", C.c_double), ("albedo", C.c_double), ("g_hg", C.c_double),
                 ("forward_only", C.c_int), ("max_events", C.c_int64),
                 ("core_skip_tau", C.c_double), ("core_skip_frac", C.c_double), ("voigt_exact", C.c_int),
-                ("spec_kind", C.c_int), ("spec_p", C.c_double * 3)]
+                ("spec_kind", C.c_int), ("spec_p", C.c_double * 3),
+                ("spec_n", C.c_int), ("spec_lambda", C.c_void_p), ("spec_flux", C.c_void_p)]
 
 
 class OrcObserver(C.Structure):
@@ -142,7 +143,14 @@ class _Prob:
         s.core_skip_tau, s.core_skip_frac = core_skip if core_skip else (0.0, 0.0)
         s.voigt_exact = int(bool(voigt_exact))
         sp = getattr(pb, "spectrum", None)
-        if sp:
+        if sp and int(sp[0]) == 3:
+            # tabulated continuum: (3, lambda[], F_lambda[])
+            s.spec_kind = 3
+            self.spec_l = np.ascontiguousarray(sp[1], dtype=np.float64)
+            self.spec_f = np.ascontiguousarray(sp[2], dtype=np.float64)
+            s.spec_n = len(self.spec_l)
+            s.spec_lambda, s.spec_flux = _ptr(self.spec_l), _ptr(self.spec_f)
+        elif sp:
             s.spec_kind = int(sp[0])
             for i, v in enumerate(sp[1:4]):
                 s.spec_p[i] = float(v)

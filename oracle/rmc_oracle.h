@@ -71,6 +71,9 @@ typedef struct {
                               continuum (spec_p = lambda_min, lambda_max
                               in Angstrom, beta of F_lambda)             */
   double spec_p[3];
+  int spec_n;              /* spec_kind 3, tabulated continuum: spec_n
+                              wavelengths (A, increasing) and F_lambda > 0 */
+  const double *spec_lambda, *spec_flux;
 } orc_problem;
 
 typedef struct {

@@ -122,7 +122,8 @@ class Problem:
     observers: List[Observer] = field(default_factory=list)
     seed: int = 0
     # source spectrum: None (monochromatic at each source's x) or
-    # (1, sigma_x) Gaussian, (2, lambda_min, lambda_max, beta) power law
+    # (1, sigma_x) Gaussian, (2, lambda_min, lambda_max, beta) power law,
+    # (3, lambda[], F_lambda[]) tabulated continuum
     spectrum: tuple = None
     meta: dict = field(default_factory=dict)
 

@@ -337,3 +337,31 @@ def test_power_law_continuum_source(orc, sigma0_oracle, beta):
     if beta == -1.0:
         # lambda F_lambda constant: uniform in lambda
         assert abs(lam.mean() / (0.5 * (lmin + lmax)) - 1) < 1e-3
+
+
+def test_tabulated_continuum_source(orc, sigma0_oracle):
+    # Sect. 2.1 (tabulated continuum): a table sampled from an exact power
+    # law reproduces that power law's photon-number distribution, and a
+    # two-slope table puts each bin's share of photons where its integral says
+    lam_t = np.linspace(1195.0, 1240.0, 13)
+    beta = -1.6
+    x, b = _escaped_spectrum(orc, sigma0_oracle, (3, lam_t, 3.0 * (lam_t / 1200.0) ** beta))
+    lam = W.LYA.lambda0_A / (1.0 + b * x)
+    e = 2.0 + beta
+    lmin, lmax = lam_t[0], lam_t[-1]
+    assert stats.kstest(lam, lambda l: (l ** e - lmin ** e) / (lmax ** e - lmin ** e)).pvalue > 1e-3
+    lam_t = np.array([1200.0, 1210.0, 1230.0])
+    f_t = np.array([1.0, 4.0, 0.5])
+    x, b = _escaped_spectrum(orc, sigma0_oracle, (3, lam_t, f_t))
+    lam = W.LYA.lambda0_A / (1.0 + b * x)
+    # bin photon counts: int lambda F dlambda with F the power law through the ends
+    from scipy import integrate
+    counts = []
+    for i in range(2):
+        bb = np.log(f_t[i + 1] / f_t[i]) / np.log(lam_t[i + 1] / lam_t[i])
+        counts.append(integrate.quad(lambda l: l * f_t[i] * (l / lam_t[i]) ** bb, lam_t[i], lam_t[i + 1])[0])
+    p = counts[0] / sum(counts)
+    k = np.count_nonzero(lam < 1210.0)
+    z = (k - len(lam) * p) / np.sqrt(len(lam) * p * (1 - p))
+    assert abs(z) < 4, z
+    assert lam.min() >= 1200.0 * (1 - 1e-12) and lam.max() <= 1230.0 * (1 + 1e-12)
