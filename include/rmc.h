@@ -181,8 +181,19 @@ rmc_status rmc_set_core_skip(rmc_ctx *ctx, double tau_skip, double frac);
  * unknown kind, a null params (other than MONO), sigma < 0 or not finite,
  * lambda_min <= 0, lambda_max <= lambda_min or a non-finite value.  Takes
  * effect at the next run or stream_begin. */
-enum { RMC_SPEC_MONO = 0, RMC_SPEC_GAUSS = 1, RMC_SPEC_POWER_LAW = 2 };
+enum { RMC_SPEC_MONO = 0, RMC_SPEC_GAUSS = 1, RMC_SPEC_POWER_LAW = 2, RMC_SPEC_TABLE = 3 };
 rmc_status rmc_set_source_spectrum(rmc_ctx *ctx, int kind, const double *params);
+/* Tabulated continuum (Sect. 2.1): n >= 2 points (host arrays, copied),
+ * wavelengths lambda_A increasing (Angstrom) and F_lambda > 0.  Between
+ * neighbouring points F_lambda is the power law through them; a packet
+ * takes a bin with probability proportional to the integral of
+ * lambda F_lambda over it (bisection on the cumulative counts), then
+ * lambda inside it by that power law's inverse CDF, and x_ext as for
+ * RMC_SPEC_POWER_LAW.  Selects RMC_SPEC_TABLE (rmc_set_source_spectrum with
+ * another kind switches it off again).  Errors: RMC_EINVAL for n < 2, null
+ * arrays, non-increasing or non-positive wavelengths, non-positive or
+ * non-finite F_lambda, or a bin whose photon count overflows. */
+rmc_status rmc_set_source_table(rmc_ctx *ctx, int n, const double *lambda_A, const double *f_lambda);
 
 /* ---------------------------------------------------------------- inputs */
 /* Leaves of a graded octree (Sect. 4.3): level[n] in [0,16], ijk[3n] the

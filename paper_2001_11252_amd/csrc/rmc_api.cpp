@@ -124,6 +124,8 @@ struct rmc_ctx {
   DevBuf o_status, o_x, o_k, o_pos, o_nscat, o_path;
   DevBuf d_stats, d_next, d_prob, d_starts, tmp1, tmp2, tmp3, tmp4, tmp5;
   DevBuf sx_eff;  // emitted x per source under a source spectrum
+  DevBuf tab;     // tabulated continuum: lambda[n], beta[n-1], cum[n]
+  int tab_n = 0;
   ProblemK pb_host;
   int64_t starts_host[2];
   int num_cus = 0;
@@ -467,6 +469,10 @@ void make_problem(rmc_ctx *c, int64_t first, int64_t n, uint64_t seed, ProblemK 
   pb.spec_kind = c->spec_kind;
   for (int q = 0; q < 3; ++q) pb.spec_p[q] = c->spec_p[q];
   pb.lambda_ref = c->lines[0].lambda0_A;
+  pb.tab_n = c->tab_n;
+  pb.tab_lam = c->tab_n ? c->tab.as<double>() : nullptr;
+  pb.tab_beta = c->tab_n ? c->tab.as<double>() + c->tab_n : nullptr;
+  pb.tab_cum = c->tab_n ? c->tab.as<double>() + 2 * c->tab_n - 1 : nullptr;
   pb.src_pos = c->spos.as<double>();
   pb.src_dir = c->src_dir ? c->sdir.as<double>() : nullptr;
   pb.src_x = c->sx.as<double>();
@@ -564,7 +570,7 @@ void fill_stats(rmc_run_stats *s, const unsigned long long *h, double ms) {
 
 extern "C" {
 
-int rmc_abi_version(void) { return 7; }
+int rmc_abi_version(void) { return 8; }
 
 rmc_status rmc_create(rmc_ctx **out, int device, int precision) {
   if (!out) return RMC_EINVAL;
@@ -601,7 +607,7 @@ void rmc_destroy(rmc_ctx *c) {
                     &c->tmp1, &c->tmp2, &c->tmp3, &c->tmp4, &c->tmp5, &c->b_probs, &c->b_starts,
                     &c->slots, &c->d_slice, &c->pq_ctl, &c->pq_jobs, &c->pq_counts, &c->tp_leaf,
                     &c->tp_seg, &c->tp_next, &c->tp_first, &c->tp_count, &c->tp_pix, &c->tp_wt, &c->tp_x,
-                    &c->tp_ctl, &c->sx_eff};
+                    &c->tp_ctl, &c->sx_eff, &c->tab};
   for (DevBuf *b : bufs) b->release();
   for (auto &o : c->obs) o.cube.release();
   if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -678,6 +684,37 @@ rmc_status rmc_set_source_spectrum(rmc_ctx *c, int kind, const double *params) {
   }
   c->spec_kind = kind;
   for (int q = 0; q < 3; ++q) c->spec_p[q] = kind == RMC_SPEC_GAUSS && q > 0 ? 0.0 : params[q];
+  return RMC_OK;
+}
+
+rmc_status rmc_set_source_table(rmc_ctx *c, int n, const double *lambda_A, const double *f_lambda) {
+  rmc_status r = enter(c);
+  if (r) return r;
+  if (n < 2 || !lambda_A || !f_lambda) return fail(c, RMC_EINVAL, "a table needs at least 2 points");
+  for (int i = 0; i < n; ++i) {
+    if (!(lambda_A[i] > 0.0) || !std::isfinite(lambda_A[i]) || !(f_lambda[i] > 0.0) || !std::isfinite(f_lambda[i]))
+      return fail(c, RMC_EINVAL, "table point %d: wavelength and F_lambda must be positive and finite", i);
+    if (i > 0 && !(lambda_A[i] > lambda_A[i - 1])) return fail(c, RMC_EINVAL, "table wavelengths must increase");
+  }
+  // per bin: the slope of the power law through its ends and the integral
+  // of lambda F_lambda over it (ratio form), accumulated
+  std::vector<double> h(3 * (size_t)n - 1);
+  double *lam = h.data(), *beta = lam + n, *cum = beta + (n - 1);
+  cum[0] = 0.0;
+  for (int i = 0; i < n; ++i) lam[i] = lambda_A[i];
+  for (int i = 0; i + 1 < n; ++i) {
+    const double l0 = lambda_A[i], l1 = lambda_A[i + 1], q = l1 / l0;
+    const double b = std::log(f_lambda[i + 1] / f_lambda[i]) / std::log(q);
+    beta[i] = b;
+    const double cnt = b == -2.0 ? f_lambda[i] * l0 * l0 * std::log(q)
+                                 : f_lambda[i] * l0 * l0 * (std::pow(q, b + 2.0) - 1.0) / (b + 2.0);
+    if (!std::isfinite(cnt)) return fail(c, RMC_EINVAL, "table bin %d: photon count overflows", i);
+    cum[i + 1] = cum[i] + cnt;
+  }
+  HIPCHK(c, c->tab.ensure(h.size() * sizeof(double)));
+  HIPCHK(c, hipMemcpy(c->tab.p, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+  c->tab_n = n;
+  c->spec_kind = RMC_SPEC_TABLE;
   return RMC_OK;
 }
 

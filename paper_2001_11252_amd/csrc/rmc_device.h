@@ -120,6 +120,10 @@ struct ProblemK {
   int spec_kind;            // source spectrum: 0 monochromatic, 1 Gaussian, 2 power law
   double spec_p[3];         // sigma_x | lambda_min, lambda_max (A), beta
   double lambda_ref;        // rest wavelength of line 0 (A)
+  // tabulated continuum (spec_kind 3): tab_n wavelengths, the power-law
+  // slope of F_lambda in each of the tab_n - 1 bins, cumulative photon counts
+  int tab_n;
+  const double *tab_lam, *tab_beta, *tab_cum;
   // sources (device)
   const double *src_pos, *src_dir, *src_x;
   int64_t first, n;         // packet range of this run

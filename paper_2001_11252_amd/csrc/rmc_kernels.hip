@@ -365,6 +365,25 @@ __device__ void finish(const ProblemK &pb, Lane<R> &s, int status) {
 // r1, r2: the packet's emission draws J_SRC1, J_SRC2.
 __device__ inline double source_spectrum_x(const ProblemK &pb, double r1, double r2) {
   if (pb.spec_kind == 1) return pb.spec_p[0] * sqrt(-2.0 * log(r1)) * cospi(2.0 * r2);
+  if (pb.spec_kind == 3) {
+    // tabulated continuum: bin i with probability (cum[i+1] - cum[i]) / cum[n-1]
+    // (bisection), then the bin's power law by its inverse CDF in ratio form
+    const double t = r1 * pb.tab_cum[pb.tab_n - 1];
+    int lo = 0, hi = pb.tab_n - 2;  // the bin: first i with t < cum[i+1]
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (t < pb.tab_cum[mid + 1]) hi = mid; else lo = mid + 1;
+    }
+    const double l0 = pb.tab_lam[lo], l1 = pb.tab_lam[lo + 1], b = pb.tab_beta[lo];
+    double lam;
+    if (b == -2.0) {
+      lam = l0 * exp(r2 * log(l1 / l0));
+    } else {
+      const double e = 2.0 + b;
+      lam = l0 * pow(1.0 + r2 * (pow(l1 / l0, e) - 1.0), 1.0 / e);
+    }
+    return (pb.lambda_ref - lam) / (lam * pb.b_ref);
+  }
   const double lmin = pb.spec_p[0], lmax = pb.spec_p[1], beta = pb.spec_p[2];
   const double r = r1;
   double lam;

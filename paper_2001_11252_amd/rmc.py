@@ -75,6 +75,7 @@ _sig = {
     "rmc_set_option": (C.c_int, [_P, C.c_int, _i64]),
     "rmc_set_core_skip": (C.c_int, [_P, C.c_double, C.c_double]),
     "rmc_set_source_spectrum": (C.c_int, [_P, C.c_int, _P]),
+    "rmc_set_source_table": (C.c_int, [_P, C.c_int, _P, _P]),
     "rmc_set_mesh": (C.c_int, [_P, _i64, _P, _P, C.c_double]),
     "rmc_set_gas": (C.c_int, [_P, _P, _P, _P, _P]),
     "rmc_set_lines": (C.c_int, [_P, C.c_int, _P, C.c_double]),
@@ -209,6 +210,14 @@ class Context:
         p = np.zeros(3)
         p[:len(params)] = params
         self._chk(_L.rmc_set_source_spectrum(self._h, int(kind), p.ctypes.data), "set_source_spectrum")
+
+    def set_source_table(self, lambda_A, f_lambda):
+        """Tabulated continuum source (see rmc_set_source_table)."""
+        lam = np.ascontiguousarray(lambda_A, dtype=np.float64)
+        f = np.ascontiguousarray(f_lambda, dtype=np.float64)
+        if len(lam) != len(f):
+            raise ValueError("lambda_A and f_lambda differ in length")
+        self._chk(_L.rmc_set_source_table(self._h, len(lam), lam.ctypes.data, f.ctypes.data), "set_source_table")
 
     def set_core_skip(self, tau_skip=1.0, frac=0.2):
         """Core-skipping on (tau_skip > 0) or off (tau_skip = 0); see
@@ -409,8 +418,11 @@ class Context:
             if sources:
                 c.set_sources(pb.sources.pos, pb.sources.x, pb.sources.dir)
                 c.n_src = len(pb.sources.x)
-                if getattr(pb, "spectrum", None):
-                    c.set_source_spectrum(pb.spectrum[0], pb.spectrum[1:])
+                sp = getattr(pb, "spectrum", None)
+                if sp and int(sp[0]) == 3:
+                    c.set_source_table(sp[1], sp[2])
+                elif sp:
+                    c.set_source_spectrum(sp[0], sp[1:])
             if observers:
                 for o in pb.observers:
                     c.add_observer(o.k, o.nx, o.ny, o.nbins, o.fov, o.x_min, o.x_max)

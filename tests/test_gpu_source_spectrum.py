@@ -3,8 +3,9 @@ the oracle: a pass before the transport draws each packet's emitted x from
 its own emission stream.
 
 * an empty sphere, where every packet leaves at its emitted x: the double
-  path equals the oracle packet by packet (Gaussian line and power-law
-  continuum), the float path (24-bit draws) matches the closed forms;
+  path equals the oracle packet by packet (Gaussian line, power-law and
+  tabulated continua), the float path (24-bit draws) matches the closed
+  forms;
 * a slab with a Gaussian-line source: double-path packets follow the oracle
   one by one;
 * in a batch each problem keeps its spectrum; bad parameters are refused."""
@@ -27,7 +28,16 @@ def s0(orc):
     return lambda ln, T: orc.line_quantities(ln, T)["sigma0"]
 
 
-SPECTRA = [(1, 3.0), (2, 1200.0, 1230.0, -1.0), (2, 1150.0, 1300.0, -2.0), (2, 1180.0, 1260.0, 0.7)]
+_LT = np.linspace(1195.0, 1240.0, 13)
+SPECTRA = [(1, 3.0), (2, 1200.0, 1230.0, -1.0), (2, 1150.0, 1300.0, -2.0), (2, 1180.0, 1260.0, 0.7),
+           # tabulated: sampled from an exact power law; two slopes, one steep
+           (3, _LT, 3.0 * (_LT / 1200.0) ** -1.6), (3, np.array([1200.0, 1210.0, 1230.0]), np.array([1.0, 4.0, 0.5]))]
+
+
+def _range(spectrum):
+    if spectrum[0] == 3:
+        return spectrum[1][0], spectrum[1][-1]
+    return spectrum[1], spectrum[2]
 
 
 def _empty(orc, spectrum, n):
@@ -52,7 +62,8 @@ def test_fp64_emitted_x_equals_the_oracle(rmc, orc, spectrum):
         # lambda from pow/exp (the two sides' library functions may differ by
         # an ulp), then x = (lambda_0 - lambda) / (lambda b): 4 ulp of lambda
         b = orc.line_quantities(W.LYA, 1e4)["vth"] / 2.99792458e10
-        tol = 4 * np.spacing(spectrum[2]) / (spectrum[1] * b)
+        lmin, lmax = _range(spectrum)
+        tol = 4 * np.spacing(lmax) / (lmin * b)
     assert np.max(np.abs(out["x"] - ref["x"]) - tol) < 0
 
 
@@ -67,9 +78,22 @@ def test_fp32_emitted_x_follows_the_spectrum(rmc, orc, spectrum):
     if spectrum[0] == 1:
         assert stats.kstest(x, stats.norm(scale=spectrum[1]).cdf).pvalue > 1e-3
         return
-    _, lmin, lmax, beta = spectrum
     b = orc.line_quantities(W.LYA, 1e4)["vth"] / 2.99792458e10
     lam = W.LYA.lambda0_A / (1.0 + b * x)
+    if spectrum[0] == 3:
+        lt, ft = spectrum[1], spectrum[2]
+        if len(lt) > 3:   # the exact power law lambda^-1.6
+            e = 0.4
+            cdf = lambda l: (l ** e - lt[0] ** e) / (lt[-1] ** e - lt[0] ** e)
+            assert stats.kstest(lam, cdf).pvalue > 1e-3
+        else:             # share of the first bin: its integral of lambda F_lambda
+            bb = [np.log(ft[i + 1] / ft[i]) / np.log(lt[i + 1] / lt[i]) for i in range(2)]
+            cnt = [ft[i] * lt[i] ** 2 * ((lt[i + 1] / lt[i]) ** (bb[i] + 2) - 1) / (bb[i] + 2) for i in range(2)]
+            p = cnt[0] / sum(cnt)
+            k = np.count_nonzero(lam < lt[1])
+            assert abs(k - n * p) < 4 * np.sqrt(n * p * (1 - p))
+        return
+    _, lmin, lmax, beta = spectrum
     if beta == -2.0:
         cdf = lambda l: np.log(l / lmin) / np.log(lmax / lmin)
     else:
@@ -115,5 +139,9 @@ def test_batch_and_errors(rmc, orc):
                          (2, (1200.0, 1300.0, np.inf)), (7, (1.0,))):
         with pytest.raises(rmc.RmcError):
             c.set_source_spectrum(kind, params)
+    for lam, f in (([1200.0], [1.0]), ([1200.0, 1200.0], [1.0, 1.0]), ([1210.0, 1200.0], [1.0, 1.0]),
+                   ([1200.0, 1210.0], [1.0, 0.0]), ([1200.0, 1210.0], [1.0, np.nan])):
+        with pytest.raises(rmc.RmcError):
+            c.set_source_table(lam, f)
     for c in ctxs:
         c.close()
