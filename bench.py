@@ -88,11 +88,12 @@ def parse():
     ap.add_argument("--only", choices=["fp32", "fp64", "both"], default="both")
     ap.add_argument("--copy-gib", type=float, default=1.0, help="size of the copy used to measure HBM bandwidth")
     ap.add_argument("--workload", choices=["dusty_sphere", "shell", "batch", "adjoint", "core_skip",
-                                           "voigt_accuracy"],
+                                           "voigt_accuracy", "upar_cost"],
                     default="dusty_sphere",
                     help="dusty_sphere: the headline; the others: the other configurations")
     ap.add_argument("--skip-packets", type=int, default=4_000_000, help="core_skip: packets per complete run")
     ap.add_argument("--voigt-packets", type=int, default=200_000, help="voigt_accuracy: packets per run")
+    ap.add_argument("--upar-packets", type=int, default=1_000_000, help="upar_cost: packets per run")
     ap.add_argument("--vmax", type=float, default=200.0, help="shell: outflow speed at R (km/s)")
     ap.add_argument("--leaves", type=float, default=2e7, help="adjoint: target leaf count")
     ap.add_argument("--sources", type=int, default=100_000, help="adjoint: sources (100 rays each)")
@@ -354,6 +355,66 @@ def oracle_voigt_baseline(pb):
                       f"interactions: {r['stats']['scatterings']} scatterings in {dt:.1f} s"}
 
 
+def bench_upar_cost(a, rmc, W):
+    """Cost of the scattering against the incoming frequency (the paper's
+    u_parallel timing, Sect. 3.3.3): forward-only flights (each scattering
+    keeps direction and frequency but draws its atom velocity as usual) in
+    a static Lya medium of tau0 = 1e12, every packet emitted at x_in and
+    stopped at its 2000th event, so the kernel's time is that of scatterings
+    at x_in; a = 1e-4, 1e-3, 1e-2 (T from a), x_in = 0..10.  The oracle's
+    u_parallel sampler is timed on one core beside it."""
+    import numpy as np
+    import torch
+    from oracle import oracle as O
+    n = a.upar_packets
+    q1 = O.line_quantities(W.LYA, 1e4)
+    xs = [0.0, 1.0, 2.0, 3.0, 4.0, 5.0, 6.0, 8.0, 10.0]
+    rows, rates, walls = [], [], []
+    for av in (1e-4, 1e-3, 1e-2):
+        T = 1e4 * (q1["a"] / av) ** 2          # a ~ T^-1/2
+        for x in xs:
+            pb = W.static_sphere(rmc.sigma0, 1e12, T, n, level=0, isotropic=True, recoil=False)
+            pb.sources.x[:] = x
+            ctx = rmc.Context.from_problem(pb, "fp32", observers=False)
+            ctx.set_stream(torch.cuda.current_stream())
+            ctx.set_option(rmc.OPT_FORWARD_ONLY, 1)
+            ctx.set_option(rmc.OPT_MAX_EVENTS, 2000)
+            ctx.run(pb.seed, 0, n)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ms, sc = 0.0, 0
+            for _ in range(a.steps):
+                st = ctx.run(pb.seed, 0, n)
+                ms += st["kernel_ms"]
+                sc += st["scatterings"]
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            walls.append(wall / a.steps)
+            ctx.close()
+            m = 20000
+            t1 = time.perf_counter()
+            O.sample_upar(m, x, av, seed=3)
+            cpu = m / (time.perf_counter() - t1)
+            rate = sc / (ms * 1e-3)
+            rates.append(rate)
+            rows.append({"a": av, "x_in": x, "gpu_scatterings_per_s": rate, "wall_scatterings_per_s": sc / wall,
+                         "oracle_draws_per_s_1core": cpu})
+            print(f"# upar a={av:g} x={x:g}: {rate:.3e} scatterings/s (kernel), oracle {cpu:.3e} draws/s",
+                  file=sys.stderr, flush=True)
+    geo = float(np.exp(np.mean(np.log(rates))))
+    return _line("scatterings/s at fixed x_in (1 GPU, FP32), u_parallel cost against x_in", geo, "scatterings/s",
+                 a.steps, 1, 1e3 * float(np.mean(walls)), "f32",
+                 {"workload": "forward_only_scatterings_lya_tau1e12_a1e-4_1e-3_1e-2_x0-10", "packets": n,
+                  "events_per_packet": 2000,
+                  "parallelism": "none"}, None,
+                 note="value: geometric mean over the (a, x_in) grid of the transport kernel's rate; every "
+                      "scattering of a run happens at x_in",
+                 grid=rows, spread=float(max(rates) / min(rates)),
+                 cpu_baseline={"value": float(np.exp(np.mean(np.log([r["oracle_draws_per_s_1core"] for r in rows])))),
+                               "unit": "u_parallel draws/s", "cores": 1, "kind": "oracle",
+                               "sample": "20,000 u_parallel draws per grid point on one core (geometric mean)"})
+
+
 def bench_adjoint(a, rmc, W):
     """C5: galaxy-like adaptive mesh (~2e7 leaves), 1e7 fixed rays toward
     +z, 512^2 image; one forward image and one backward (gradients per
@@ -498,7 +559,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if a.workload != "dusty_sphere":
         fn = {"shell": bench_shell, "batch": bench_batch, "adjoint": bench_adjoint,
-              "core_skip": bench_core_skip, "voigt_accuracy": bench_voigt_accuracy}[a.workload]
+              "core_skip": bench_core_skip, "voigt_accuracy": bench_voigt_accuracy,
+              "upar_cost": bench_upar_cost}[a.workload]
         print(json.dumps(fn(a, rmc, W)), flush=True)
         return
     steps, warm, P = a.steps, a.warmup, a.packets
