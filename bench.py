@@ -88,7 +88,7 @@ def parse():
     ap.add_argument("--only", choices=["fp32", "fp64", "both"], default="both")
     ap.add_argument("--copy-gib", type=float, default=1.0, help="size of the copy used to measure HBM bandwidth")
     ap.add_argument("--workload", choices=["dusty_sphere", "shell", "batch", "adjoint", "core_skip",
-                                           "voigt_accuracy", "upar_cost"],
+                                           "voigt_accuracy", "upar_cost", "c1_slab"],
                     default="dusty_sphere",
                     help="dusty_sphere: the headline; the others: the other configurations")
     ap.add_argument("--skip-packets", type=int, default=4_000_000, help="core_skip: packets per complete run")
@@ -355,6 +355,52 @@ def oracle_voigt_baseline(pb):
                       f"interactions: {r['stats']['scatterings']} scatterings in {dt:.1f} s"}
 
 
+def bench_c1_slab(a, rmc, W):
+    """C1: the plain FP64 slab (tau0 = 1e4, T = 1e4 K, 512 leaves, 1000
+    packets from the mid-plane at x = 0): a latency and parity case.  Each
+    step is a complete run of the 1000 packets; the oracle runs the same
+    packets, and the two 200-bin spectra over x in [-60, 60) and mean
+    scattering counts are compared."""
+    import numpy as np
+    import torch
+    from scipy import stats
+    from oracle import oracle as O
+    pb = W.c1_slab(rmc.sigma0)
+    n = len(pb.sources.x)
+    ctx = rmc.Context.from_problem(pb, "fp64", observers=False)
+    ctx.set_stream(torch.cuda.current_stream())
+    for _ in range(a.warmup):
+        ctx.run(pb.seed, 0, n)
+    torch.cuda.synchronize()
+    sc, t0 = 0, time.perf_counter()
+    for _ in range(a.steps):
+        st = ctx.run(pb.seed, 0, n)
+        sc += st["scatterings"]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out = ctx.get_packets()
+    ctx.close()
+    cores = max(1, min(16, os.cpu_count() or 1))
+    t1 = time.perf_counter()
+    ref = O.run(pb, pb.seed, threads=cores, with_cubes=False)
+    dt = time.perf_counter() - t1
+    hg, _ = np.histogram(out["x"], bins=200, range=(-60, 60))
+    ho, _ = np.histogram(ref["x"], bins=200, range=(-60, 60))
+    return _line("run time of the slab (1 GPU, FP64), as scatterings/s", sc / wall, "scatterings/s", a.steps,
+                 a.warmup, 1e3 * wall / a.steps, "f64",
+                 {"workload": "c1_slab_tau1e4_T1e4_512_leaves_1000_packets", "packets": n, "parallelism": "none"},
+                 None, ms_per_complete_run=1e3 * wall / a.steps,
+                 parity={"identical_packets": int(np.sum((out["status"] == ref["status"]) &
+                                                         (out["n_scat"] == ref["n_scat"]) &
+                                                         (np.abs(out["x"] - ref["x"]) < 1e-9))),
+                         "histogram_identical": bool(np.array_equal(hg, ho)),
+                         "mean_scatterings": {"gpu": float(out["n_scat"].mean()), "oracle": float(ref["n_scat"].mean())},
+                         "ks_p": float(stats.ks_2samp(out["x"], ref["x"]).pvalue)},
+                 cpu_baseline={"value": ref["stats"]["scatterings"] / dt, "unit": "scatterings/s", "cores": cores,
+                               "kind": "oracle", "sample": f"the same {n} packets, complete: "
+                                                           f"{ref['stats']['scatterings']} scatterings in {dt:.1f} s"})
+
+
 def bench_upar_cost(a, rmc, W):
     """Cost of the scattering against the incoming frequency (the paper's
     u_parallel timing, Sect. 3.3.3): forward-only flights (each scattering
@@ -560,7 +606,7 @@ def main():
     if a.workload != "dusty_sphere":
         fn = {"shell": bench_shell, "batch": bench_batch, "adjoint": bench_adjoint,
               "core_skip": bench_core_skip, "voigt_accuracy": bench_voigt_accuracy,
-              "upar_cost": bench_upar_cost}[a.workload]
+              "upar_cost": bench_upar_cost, "c1_slab": bench_c1_slab}[a.workload]
         print(json.dumps(fn(a, rmc, W)), flush=True)
         return
     steps, warm, P = a.steps, a.warmup, a.packets
