@@ -116,3 +116,26 @@ def test_fe_ii_wind(rmc, orc):
     for lamf in (2612.65, 2626.45, 2632.11):
         peak = h[np.abs(mid - lamf) < 0.6].max()
         assert peak > cont + 6 * np.sqrt(cont), (lamf, peak, cont)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_with_a_fluorescent_problem_equals_single_runs(rmc, orc, prec):
+    # the batch runs the multi-line kernel for both problems; each problem's
+    # packets depend only on the problem and their index
+    s = s0(orc)
+    pbs = [W.static_sphere(s, 3.0, 1e4, 3000, level=2, line=W.FEII_2587), W.c1_slab(s, n_packets=500)]
+    seeds = [111, 112]
+    npk = [3000, 500]
+    single = []
+    for p, sd, n in zip(pbs, seeds, npk):
+        c = rmc.Context.from_problem(p, prec, observers=False)
+        c.run(sd, 0, n)
+        single.append(c.get_packets())
+        c.close()
+    ctxs = [rmc.Context.from_problem(p, prec, observers=False) for p in pbs]
+    rmc.batch_run(ctxs, seeds, npk)
+    for c, ref in zip(ctxs, single):
+        out = c.get_packets()
+        for k in ("status", "x", "n_scat", "pos", "k"):
+            assert np.array_equal(out[k], ref[k]), k
+        c.close()
