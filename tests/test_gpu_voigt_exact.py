@@ -119,3 +119,28 @@ def test_option_errors(rmc, orc, sigma0_oracle):
     with pytest.raises(rmc.RmcError):
         c.raycast_image_backward(0, o, x, w, np.ones((pb.observers[0].ny, pb.observers[0].nx)))
     c.close()
+
+
+def test_batch_keeps_each_problems_voigt_function(rmc, orc, sigma0_oracle):
+    pbs = [W.static_sphere(sigma0_oracle, 1e3, 100.0, 400, level=3, line=W.MGII_2796),
+           W.static_sphere(sigma0_oracle, 1e3, 100.0, 400, level=3, line=W.MGII_2796)]
+    modes, seeds = (1, 0), (121, 121)
+    single = []
+    for p, m, sd in zip(pbs, modes, seeds):
+        c = rmc.Context.from_problem(p, "fp64", observers=False)
+        c.set_option(rmc.OPT_VOIGT, m)
+        c.run(sd, 0, 400)
+        single.append(c.get_packets())
+        c.close()
+    ctxs = [rmc.Context.from_problem(p, "fp64", observers=False) for p in pbs]
+    for c, m in zip(ctxs, modes):
+        c.set_option(rmc.OPT_VOIGT, m)
+    rmc.batch_run(ctxs, list(seeds), [400, 400])
+    outs = [c.get_packets() for c in ctxs]
+    for c in ctxs:
+        c.close()
+    for out, ref in zip(outs, single):
+        for k in ("status", "x", "n_scat", "pos"):
+            assert np.array_equal(out[k], ref[k]), k
+    # the same packets with the two forms of H end elsewhere
+    assert np.count_nonzero(np.abs(outs[0]["pos"] - outs[1]["pos"]).max(axis=1) > 1e-9) > 300
