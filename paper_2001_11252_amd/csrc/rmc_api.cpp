@@ -711,8 +711,11 @@ rmc_status rmc_set_source_table(rmc_ctx *c, int n, const double *lambda_A, const
     if (!std::isfinite(cnt)) return fail(c, RMC_EINVAL, "table bin %d: photon count overflows", i);
     cum[i + 1] = cum[i] + cnt;
   }
+  // work already queued on the context's stream may still read the old table
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   HIPCHK(c, c->tab.ensure(h.size() * sizeof(double)));
-  HIPCHK(c, hipMemcpy(c->tab.p, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpyAsync(c->tab.p, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   c->tab_n = n;
   c->spec_kind = RMC_SPEC_TABLE;
   return RMC_OK;
