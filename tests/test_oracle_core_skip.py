@@ -7,7 +7,8 @@ Pins:
   restricted to |u| >= x_crit (derived below), the plain N(0, 1/2) at 0;
 * the threshold: a cell whose line-centre depth across its edge tau_c is
   below tau_skip is never biased (bit-identical runs), one just above it is
-  (tau_c computed here from n_HI, sigma0(T) and the cell size);
+  (tau_c computed here from n_HI, sigma0(T) and the cell size); the cap
+  f (a tau_c)^(1/3) likewise, at a first scattering at x = X;
 * dust-free slab and sphere at a tau0 = 1.5e4: the Neufeld and Dijkstra
   spectra still hold while the scattering count drops by two orders of
   magnitude (the paper's reason for the scheme);
@@ -109,3 +110,24 @@ def test_skipping_agrees_with_unbiased_runs_where_the_cap_binds(orc, sigma0_orac
         if 0 < p < 1:
             z = (eo.mean() - ef.mean()) / np.sqrt(p * (1 - p) * 2 / n)
             assert abs(z) < 4, (td, z)
+
+
+def test_cap_from_the_cells_damping_depth(orc, sigma0_oracle):
+    # packets emitted at x_in = X in static gas at T_ref take their first
+    # scattering at cell-frame x = X; with tau_skip tiny the rule's cap
+    # f (a tau_c)^(1/3) decides alone: just above X the draw is biased, just
+    # below it is not (a and tau_c computed here from the line data)
+    level, tau0, T, n, X = 3, 2e3, 1e4, 200, 0.05
+    pb = W.static_sphere(sigma0_oracle, tau0, T, n, level=level)
+    pb.sources.x[:] = X
+    q = orc.line_quantities(W.LYA, T)
+    tau_c = pb.meta["n_hi"] * q["sigma0"] * pb.mesh.box_cm / 2 ** level
+    f0 = X / np.cbrt(q["a"] * tau_c)
+    # stopped at the second interaction: only that first scattering happened
+    run = lambda cs: orc.run(pb, 4, threads=4, with_cubes=False, max_events=2, core_skip=cs)
+    off = run(None)
+    below = run((1e-30, f0 * (1 - 1e-6)))
+    above = run((1e-30, f0 * (1 + 1e-6)))
+    for k in ("status", "x", "n_scat", "pos"):
+        assert np.array_equal(below[k], off[k]), k
+    assert not np.array_equal(above["x"], off["x"])
