@@ -145,3 +145,23 @@ def test_batch_problems_keep_their_own_setting(rmc, orc):
         for k in ("status", "x", "n_scat", "pos", "k"):
             assert np.array_equal(out[k], ref[k]), k
         c.close()
+
+
+def test_fp64_threshold_and_cap_decide_as_in_the_oracle(rmc, orc):
+    # a first scattering at cell-frame x = X (static gas at T_ref, packets
+    # stopped at their second interaction): just below the cap f (a tau_c)^(1/3)
+    # nothing changes, just above the draw is biased, as in the oracle
+    level, tau0, T, n, X = 3, 2e3, 1e4, 300, 0.05
+    pb = W.static_sphere(s0(orc), tau0, T, n, level=level)
+    pb.sources.x[:] = X
+    q = orc.line_quantities(W.LYA, T)
+    tau_c = pb.meta["n_hi"] * q["sigma0"] * pb.mesh.box_cm / 2 ** level
+    f0 = X / np.cbrt(q["a"] * tau_c)
+    outs = {}
+    for name, skip in (("off", None), ("below", (1e-30, f0 * (1 - 1e-6))), ("above", (1e-30, f0 * (1 + 1e-6)))):
+        _, outs[name] = _run(rmc, pb, "fp64", 4, n, skip=skip, max_events=2)
+        ref = orc.run(pb, 4, threads=8, with_cubes=False, max_events=2, core_skip=skip)
+        assert sum(_same(ref, outs[name], i) for i in range(n)) == n, name
+    for k in ("status", "x", "n_scat", "pos"):
+        assert np.array_equal(outs["below"][k], outs["off"][k]), k
+    assert np.count_nonzero(outs["above"]["x"] != outs["off"]["x"]) > n // 2
