@@ -349,6 +349,8 @@ rmc_status rmc_mesh_check(int64_t n_leaves, const int8_t *level, const int32_t *
 /* Line quantities at T (Sect. 3.1.1): out = {nu0 [Hz], v_th [cm/s],
  * dnu_D [Hz], a, sigma0 [cm^2]}. */
 rmc_status rmc_line_quantities(const rmc_line *line, double T_K, double out[5]);
+/* Version of this interface; it changes whenever a declaration or a struct
+ * layout here changes (8: rmc_set_source_table). */
 int rmc_abi_version(void);
 
 #ifdef __cplusplus
