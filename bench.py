@@ -88,7 +88,7 @@ def parse():
     ap.add_argument("--only", choices=["fp32", "fp64", "both"], default="both")
     ap.add_argument("--copy-gib", type=float, default=1.0, help="size of the copy used to measure HBM bandwidth")
     ap.add_argument("--workload", choices=["dusty_sphere", "shell", "batch", "adjoint", "core_skip",
-                                           "voigt_accuracy", "upar_cost", "c1_slab"],
+                                           "voigt_accuracy", "upar_cost", "c1_slab", "multi_species"],
                     default="dusty_sphere",
                     help="dusty_sphere: the headline; the others: the other configurations")
     ap.add_argument("--skip-packets", type=int, default=4_000_000, help="core_skip: packets per complete run")
@@ -355,6 +355,50 @@ def oracle_voigt_baseline(pb):
                       f"interactions: {r['stats']['scatterings']} scatterings in {dt:.1f} s"}
 
 
+def bench_multi_species(a, rmc, W):
+    """Multi-species media: the Fe II wind of the paper's idealised-set-up
+    example (Fe II 2587 and 2600 with their three fluorescent channels,
+    flat continuum source, v ~ r to 100 km/s, density ~ r^-3, 64^3 grid) as
+    complete FP32 runs of 4e6 packets, and the appendix's H I + D sphere
+    (N_HI = 2e19, D/H = 3e-5, T = 1e4 K) as FP32 streaming steps."""
+    import torch
+    n = 4_000_000
+    pb = W.feii_wind(rmc.sigma0, n)
+    ctx = rmc.Context.from_problem(pb, "fp32", observers=False)
+    ctx.set_stream(torch.cuda.current_stream())
+    ctx.run(pb.seed, 0, 100_000)
+    torch.cuda.synchronize()
+    tot, t0 = {}, time.perf_counter()
+    for _ in range(a.steps):
+        st = ctx.run(pb.seed, 0, n)
+        for k, v in st.items():
+            tot[k] = tot.get(k, 0) + v
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.close()
+    print(f"# feii wind: {a.steps} runs of {n} packets in {wall:.2f} s, {tot['scatterings']} scatterings",
+          file=sys.stderr, flush=True)
+    pd = W.deuterium_sphere(rmc.sigma0, 1_000_000)
+    cd = rmc.Context.from_problem(pd, "fp32", observers=False)
+    cd.set_stream(torch.cuda.current_stream())
+    cd.set_option(rmc.OPT_SLICE_ITERS, a.slice)
+    cd.stream_begin(pd.seed, 0, 1_000_000)
+    wd, td, kd = stream_rate(cd, a.steps, a.warmup, "H+D sphere fp32")
+    cd.close()
+    return _line("packets/s (complete runs, 1 GPU), FP32, Fe II wind with fluorescence", n * a.steps / wall,
+                 "packets/s", a.steps, 1, 1e3 * wall / a.steps, "f32",
+                 {"workload": "feii_wind_2587_2600_fluorescent_flat_continuum_64cubed", "packets": n,
+                  "parallelism": "none"},
+                 transport_roofline(td, kd, "fp32", "k_transport<float,false,true,4>"),
+                 feii_wind={"packets_per_s": n * a.steps / wall, "scatterings_per_s": tot["scatterings"] / wall,
+                            "scatterings_per_packet": tot["scatterings"] / (n * a.steps)},
+                 deuterium_sphere={"scatterings_per_s": td["scatterings"] / wd,
+                                   "transport_ms_avg": sum(kd) / len(kd),
+                                   "workload": "static_sphere_NHI2e19_DH3e-5_T1e4_lya_dlya",
+                                   "note": "the roofline object is this sphere's transport kernel (two lines: "
+                                           "the multi-line kernel)"})
+
+
 def bench_c1_slab(a, rmc, W):
     """C1: the plain FP64 slab (tau0 = 1e4, T = 1e4 K, 512 leaves, 1000
     packets from the mid-plane at x = 0): a latency and parity case.  Each
@@ -606,7 +650,8 @@ def main():
     if a.workload != "dusty_sphere":
         fn = {"shell": bench_shell, "batch": bench_batch, "adjoint": bench_adjoint,
               "core_skip": bench_core_skip, "voigt_accuracy": bench_voigt_accuracy,
-              "upar_cost": bench_upar_cost, "c1_slab": bench_c1_slab}[a.workload]
+              "upar_cost": bench_upar_cost, "c1_slab": bench_c1_slab,
+              "multi_species": bench_multi_species}[a.workload]
         print(json.dumps(fn(a, rmc, W)), flush=True)
         return
     steps, warm, P = a.steps, a.warmup, a.packets
