@@ -385,6 +385,18 @@ def bench_multi_species(a, rmc, W):
     cd.stream_begin(pd.seed, 0, 1_000_000)
     wd, td, kd = stream_rate(cd, a.steps, a.warmup, "H+D sphere fp32")
     cd.close()
+    cpu = None
+    if not a.no_cpu_baseline:
+        from oracle import oracle as O
+        cores = max(1, min(16, os.cpu_count() or 1))
+        m = 250000 * cores     # a few seconds of the oracle
+        pw = W.feii_wind(rmc.sigma0, m)
+        t1 = time.perf_counter()
+        r = O.run(pw, pw.seed, threads=cores, with_cubes=False)
+        dt = time.perf_counter() - t1
+        cpu = {"value": m / dt, "unit": "packets/s", "cores": cores, "kind": "oracle",
+               "sample": f"{m} complete packets of the Fe II wind ({r['stats']['scatterings']} scatterings) "
+                         f"in {dt:.1f} s"}
     return _line("packets/s (complete runs, 1 GPU), FP32, Fe II wind with fluorescence", n * a.steps / wall,
                  "packets/s", a.steps, 1, 1e3 * wall / a.steps, "f32",
                  {"workload": "feii_wind_2587_2600_fluorescent_flat_continuum_64cubed", "packets": n,
@@ -396,7 +408,8 @@ def bench_multi_species(a, rmc, W):
                                    "transport_ms_avg": sum(kd) / len(kd),
                                    "workload": "static_sphere_NHI2e19_DH3e-5_T1e4_lya_dlya",
                                    "note": "the roofline object is this sphere's transport kernel (two lines: "
-                                           "the multi-line kernel)"})
+                                           "the multi-line kernel)"},
+                 cpu_baseline=cpu)
 
 
 def bench_c1_slab(a, rmc, W):
