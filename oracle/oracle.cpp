@@ -557,14 +557,14 @@ double scatter_dnu(const Problem &P, double dnu_in, const double kin[3], const d
  * leaf adds kappa * l * box.  `visit` receives (leaf, segment, Opac). */
 template <class F>
 double ray_tau(const Problem &P, const double p0[3], const double k[3], double dnu_ext,
-               int64_t *ncross, F visit) {
+               int64_t *ncross, F visit, double tau_stop = HUGE_VAL) {
   const orc_problem &pb = *P.pb;
   double p[3] = {p0[0], p0[1], p0[2]};
   int64_t c = locate(P.mesh, p, k);
   double tau = 0.0;
   Opac o;
   int64_t steps = 0;
-  while (c >= 0 && steps++ < MAX_CROSS) {
+  while (c >= 0 && steps++ < MAX_CROSS && !(tau >= tau_stop)) {
     opacity(P, c, dnu_ext, k, o);
     double pn[3];
     double te = exit_step(P.mesh, c, p, k, pn);
@@ -660,7 +660,10 @@ void peel_deposit(const Problem &P, int n_obs, const orc_observer *obs, ThreadOu
       dnu_ext_o = to_external(P, dnu_in_cell, ko, vcell);
     }
     int64_t nc = 0;
-    double tau = ray_tau(P, p, ko, dnu_ext_o, &nc, [](int64_t, double, const Opac &) {});
+    /* with peel_tau_cut > 0 the walk stops once tau reaches it; from 746 on
+     * exp(-tau) rounds to exactly 0 in double, so the deposit is the same */
+    const double stop = pb.peel_tau_cut > 0.0 ? pb.peel_tau_cut : HUGE_VAL;
+    double tau = ray_tau(P, p, ko, dnu_ext_o, &nc, [](int64_t, double, const Opac &) {}, stop);
     to.st.peel_rays += 1;
     to.st.peel_crossings += nc;
     double w = weight * std::exp(-tau);

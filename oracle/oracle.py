@@ -34,7 +34,8 @@ class OrcProblem(C.Structure):
                 ("forward_only", C.c_int), ("max_events", C.c_int64),
                 ("core_skip_tau", C.c_double), ("core_skip_frac", C.c_double), ("voigt_exact", C.c_int),
                 ("spec_kind", C.c_int), ("spec_p", C.c_double * 3),
-                ("spec_n", C.c_int), ("spec_lambda", C.c_void_p), ("spec_flux", C.c_void_p)]
+                ("spec_n", C.c_int), ("spec_lambda", C.c_void_p), ("spec_flux", C.c_void_p),
+                ("peel_tau_cut", C.c_double)]
 
 
 class OrcObserver(C.Structure):
@@ -114,7 +115,7 @@ def _line_struct(ln):
 class _Prob:
     """Keeps the numpy buffers alive for the lifetime of the C struct."""
 
-    def __init__(self, pb, forward_only=False, max_events=0, core_skip=None, voigt_exact=False):
+    def __init__(self, pb, forward_only=False, max_events=0, core_skip=None, voigt_exact=False, peel_tau_cut=0.0):
         m = pb.mesh
         self.level = np.ascontiguousarray(m.level, dtype=np.int8)
         self.ijk = np.ascontiguousarray(m.ijk, dtype=np.int32)
@@ -142,6 +143,7 @@ class _Prob:
         s.max_events = int(max_events)
         s.core_skip_tau, s.core_skip_frac = core_skip if core_skip else (0.0, 0.0)
         s.voigt_exact = int(bool(voigt_exact))
+        s.peel_tau_cut = float(peel_tau_cut)
         sp = getattr(pb, "spectrum", None)
         if sp and int(sp[0]) == 3:
             # tabulated continuum: (3, lambda[], F_lambda[])
@@ -268,15 +270,17 @@ def tau(pb, orig, dirs, x_ext, voigt_exact=False):
 
 
 def run(pb, seed, first=0, n=None, threads=0, forward_only=False, max_events=0, with_cubes=True,
-        core_skip=None, voigt_exact=False):
+        core_skip=None, voigt_exact=False, peel_tau_cut=0.0):
     """Forward transport of packets [first, first+n) of pb.sources.
     core_skip = (tau_skip, frac) turns core-skipping on (x_crit per cell:
     min(sqrt(ln(tau_cell / tau_skip)), frac (a tau_cell)^(1/3))).
     voigt_exact: H from its defining integral instead of the Tasitsiomi form.
+    peel_tau_cut > 0: peel-off rays stop once their optical depth reaches it
+    (746: exp(-tau) is exactly 0 beyond, the cubes do not change).
 
     Returns a dict with per-packet arrays (status, x, k, pos, n_scat, path),
     the observer cubes (list of [ny, nx, nbins] float64) and the stats."""
-    P = _Prob(pb, forward_only, max_events, core_skip, voigt_exact)
+    P = _Prob(pb, forward_only, max_events, core_skip, voigt_exact, peel_tau_cut)
     src = pb.sources
     pos = np.ascontiguousarray(src.pos, dtype=np.float64)
     dirs = None if src.dir is None else np.ascontiguousarray(src.dir, dtype=np.float64)

@@ -10,7 +10,8 @@
  * Everything is double precision and deliberately slow: frequencies are
  * carried in Hz, every per-cell line quantity is recomputed from T at each
  * use, the leaf holding a point is found by probing a (level,i,j,k) hash map
- * coarse to fine, and every peel-off ray is integrated to the domain edge.
+ * coarse to fine, and every peel-off ray is integrated to the domain edge
+ * (unless peel_tau_cut asks to stop where exp(-tau) has become zero).
  *
  * Units: positions in box units (the octree spans [0,1)^3, physical side
  * box_cm), densities in cm^-3, T in K, velocities in cm/s, dust opacity
@@ -74,6 +75,10 @@ typedef struct {
   int spec_n;              /* spec_kind 3, tabulated continuum: spec_n
                               wavelengths (A, increasing) and F_lambda > 0 */
   const double *spec_lambda, *spec_flux;
+  double peel_tau_cut;     /* >0: a peel-off ray stops integrating once its
+                              optical depth reaches this value (0: walked
+                              to the domain border).  From 746 on exp(-tau)
+                              is exactly 0 in double: deposits unchanged */
 } orc_problem;
 
 typedef struct {

@@ -365,3 +365,24 @@ def test_tabulated_continuum_source(orc, sigma0_oracle):
     z = (k - len(lam) * p) / np.sqrt(len(lam) * p * (1 - p))
     assert abs(z) < 4, z
     assert lam.min() >= 1200.0 * (1 - 1e-12) and lam.max() <= 1230.0 * (1 + 1e-12)
+
+
+def test_peel_tau_cut_leaves_the_cubes_unchanged(orc, sigma0_oracle):
+    # peel-off rays stopped once tau >= 746, where exp(-tau) rounds to exactly
+    # zero in double: every deposit, packet and count but the peel-off
+    # crossings is the same as with rays walked to the border
+    assert np.exp(-746.0) == 0.0 and np.exp(-745.0) > 0.0
+    pb = W.static_sphere(sigma0_oracle, 3e3, 1e4, 300, level=4, tau_dust=0.5)
+    pb.observers = [W.Observer((0.0, 0.0, 1.0), 16, 16, 30, (-0.5, 0.5, -0.5, 0.5), -30, 30),
+                    W.Observer((0.6, 0.0, 0.8), 8, 8, 20, (-0.5, 0.5, -0.5, 0.5), -30, 30)]
+    # one thread each, so that the deposits are added in the same order
+    a = orc.run(pb, 5, threads=1)
+    b = orc.run(pb, 5, threads=1, peel_tau_cut=746.0)
+    for k in ("status", "x", "k", "pos", "n_scat", "path"):
+        assert np.array_equal(a[k], b[k]), k
+    for ca, cb in zip(a["cubes"], b["cubes"]):
+        assert ca.sum() > 0 and np.array_equal(ca, cb)
+    for k in a["stats"]:
+        if k != "peel_crossings":
+            assert a["stats"][k] == b["stats"][k], k
+    assert b["stats"]["peel_crossings"] < 0.5 * a["stats"]["peel_crossings"]
