@@ -75,6 +75,18 @@ enum {
                                 order of the cube additions.                 */
   RMC_OPT_SLICE_ITERS = 7,   /* loop iterations (events or cell crossings)
                                 per lane in one transport launch            */
+  RMC_OPT_REGROUP = 9,       /* 1: the transport loop runs one rejection
+                                round of a line scattering's atom-velocity
+                                draw per pass; a rejected round leaves the
+                                event pending (the packet stays at its event
+                                point) and its next round runs at the next
+                                pass, in step with the other lanes' events,
+                                instead of the wave looping until its last
+                                lane accepts (the same draws, so the same
+                                packets); 0: the looping draw.  Default 1
+                                for RMC_FP64 contexts, 0 for RMC_FP32_BULK
+                                (the faster of the two on each path).
+                                Applies with RMC_OPT_PEEL_DEFER = 1.         */
   RMC_OPT_VOIGT = 8          /* Voigt function H(a,x) of the opacity:
                                 0 (default) the Tasitsiomi form the paper
                                 uses (Sect. 3.3.2; within ~1% for Lya at
@@ -117,10 +129,12 @@ typedef struct {
   uint64_t scatterings;       /* line scatterings                            */
   uint64_t dust_scatterings;
   uint64_t crossings;         /* transport ray-cell segments run to their end */
-  uint64_t peel_rays;         /* peel-off rays whose pixel and bin lie in a
-                                 cube (one per event and observer)            */
+  uint64_t peel_rays;         /* peel-off rays (one per emission or event and
+                                 observer)                                    */
   uint64_t peel_crossings;    /* ray-cell segments of peel-off rays           */
-  uint64_t peel_dropped;      /* peel-off deposits outside a cube             */
+  uint64_t peel_dropped;      /* peel-off deposits outside a cube (rays whose
+                                 optical depth reaches the exp(-tau) = 0 cut
+                                 in the leaf they start in are not binned)   */
   uint64_t peel_deferred;     /* peel-off rays handed from the transport
                                  launch to the ray-cast pass (whole launch;
                                  0 in per-problem reports)                    */
@@ -203,11 +217,20 @@ rmc_status rmc_set_source_table(rmc_ctx *ctx, int n, const double *lambda_A, con
  * node array on the host and uploads it. */
 rmc_status rmc_set_mesh(rmc_ctx *ctx, int64_t n_leaves, const int8_t *level,
                         const int32_t *ijk, double box_cm);
-/* Per-leaf gas (host arrays of n_leaves, v is [3n]): n_HI, T, bulk
- * velocity, dust opacity kappa_d (Sect. 3.1.2 tau_dust = int kappa_d dl).
- * Needs the mesh and the lines.  Non-finite or negative values: RMC_EINVAL. */
-rmc_status rmc_set_gas(rmc_ctx *ctx, const double *n_hi, const double *T_K,
-                       const double *v_cms, const double *kappa_d);
+/* Per-leaf gas (Sect. 4.1 cells: n_HI, T, bulk velocity; Sect. 3.1.2
+ * dust, tau_dust = int kappa_d dl): arrays of n_leaves elements (v_cms is
+ * [3n], x,y,z per leaf) of type dtype (RMC_F32 or RMC_F64), in host memory
+ * (mem = RMC_HOST) or device memory of the context's device (RMC_DEVICE:
+ * read in place on the context's stream, no copy through the host).  The
+ * values are checked and converted to double on the device and kept there;
+ * the leaf records the kernels read are built from them (again whenever the
+ * lines or the domain change).  Needs the mesh and the lines.  A
+ * non-finite or negative value, T <= 0 or a velocity component of 0.1 c or
+ * more gives RMC_EINVAL (the message names the first such leaf) and leaves
+ * the previous gas in place; an unknown dtype or mem gives RMC_EINVAL.
+ * Only a 16-byte status word returns to the host. */
+rmc_status rmc_set_gas(rmc_ctx *ctx, const void *n_hi, const void *T_K, const void *v_cms,
+                       const void *kappa_d, int dtype, int mem);
 /* Up to 4 lines; line 0 and T_ref define the x_ext unit. */
 rmc_status rmc_set_lines(rmc_ctx *ctx, int n_lines, const rmc_line *lines, double T_ref);
 /* Dust albedo (probability of scattering at a dust interaction) and HG
@@ -215,12 +238,16 @@ rmc_status rmc_set_lines(rmc_ctx *ctx, int n_lines, const rmc_line *lines, doubl
 rmc_status rmc_set_dust(rmc_ctx *ctx, double albedo, double g_hg);
 /* Computational domain (Sect. 4): BOX = the unit cube; SLAB_Z: params
  * (zc, half_z), periodic in x and y; SPHERE: (cx, cy, cz, R) inside the
- * unit cube. */
+ * unit cube.  A shell is a SPHERE domain whose gas is zero inside the inner
+ * radius: the inner radius bounds no packet (sources sit inside it), it is
+ * a density edge in the mesh. */
 rmc_status rmc_set_domain(rmc_ctx *ctx, int kind, const double params[4]);
 /* Packet initial conditions (the paper's PPIC lists, Sect. 2): pos[3n],
- * dir[3n] unit vectors or NULL for isotropic emission, x_ext[n].  Packet i
- * is identified by its index i, which keys its random numbers.  A
- * position outside the unit cube is rejected with RMC_EINVAL. */
+ * dir[3n] unit vectors or NULL for isotropic emission, x_ext[n], doubles in
+ * host (RMC_HOST) or device (RMC_DEVICE) memory.  Packet i is identified by
+ * its index i, which keys its random numbers.  A position outside the unit
+ * cube, a non-finite x or a direction with |k|^2 more than 1e-6 from 1 is
+ * rejected with RMC_EINVAL (device arrays are checked by a kernel). */
 rmc_status rmc_set_sources(rmc_ctx *ctx, int64_t n, const double *pos, const double *dir,
                            const double *x_ext, int mem);
 /* Peel-off observer (Sect. 5.1): direction k_obs (unit), image nx by ny
@@ -243,7 +270,9 @@ rmc_status rmc_run(rmc_ctx *ctx, uint64_t seed, int64_t first, int64_t n,
  * iterations per lane) in which every lane advances the packet it holds,
  * parks it in device memory if it is still alive, and idle lanes take new
  * packets from the queue.  step reports the work of that launch (emitted =
- * packets finished in it) and the packets not finished yet; end runs the
+ * packets finished in it = escaped + absorbed + stuck in it; peel_dropped
+ * counts the dropped deposits of those packets) and the packets not
+ * finished yet; end runs the
  * remaining launches and reports the totals of the range.  rmc_run is
  * begin + steps + end.  Results do not depend on how a run is sliced.
  * begin on a context whose stream is still open abandons that stream (its
@@ -285,11 +314,13 @@ rmc_status rmc_raycast_image(rmc_ctx *ctx, int id, int64_t n_rays, const double 
                              const double *x_ext, const double *w, double *image, int mem);
 /* Gradient of L = sum_p grad_image[p] image[p] with respect to per-leaf
  * n_HI, kappa_d and v_los = k_obs . v (cm/s), by replaying each ray:
- * outputs g_nhi, g_kd, g_vlos [n_leaves], overwritten. */
+ * outputs g_nhi, g_kd, g_vlos [n_leaves], overwritten, and, if g_v is not
+ * NULL, the gradient with respect to the leaf velocity vector, g_v[3n] =
+ * g_vlos k_obs (the chain rule through v_los; only v_los enters the image). */
 rmc_status rmc_raycast_image_backward(rmc_ctx *ctx, int id, int64_t n_rays, const double *orig,
                                       const double *x_ext, const double *w,
                                       const double *grad_image, double *g_nhi, double *g_kd,
-                                      double *g_vlos, int mem);
+                                      double *g_vlos, double *g_v, int mem);
 /* rmc_raycast_image that also keeps each ray's crossing list (leaf and
  * segment of every ray-cell crossing, in walk order; the tape) in device
  * memory of the context, for rmc_raycast_image_backward_tape.  The tape
@@ -308,7 +339,7 @@ rmc_status rmc_raycast_image_tape(rmc_ctx *ctx, int id, int64_t n_rays, const do
  * additions (and the float path's segments, kept as float).  RMC_ESTATE if
  * there is no tape for the current model. */
 rmc_status rmc_raycast_image_backward_tape(rmc_ctx *ctx, const double *grad_image, double *g_nhi,
-                                           double *g_kd, double *g_vlos, int mem);
+                                           double *g_kd, double *g_vlos, double *g_v, int mem);
 /* Ray-cell crossings and device time (ms) of the last image or image
  * adjoint call of this context (RMC_ESTATE if none since the last
  * transport run). */
@@ -350,7 +381,8 @@ rmc_status rmc_mesh_check(int64_t n_leaves, const int8_t *level, const int32_t *
  * dnu_D [Hz], a, sigma0 [cm^2]}. */
 rmc_status rmc_line_quantities(const rmc_line *line, double T_K, double out[5]);
 /* Version of this interface; it changes whenever a declaration or a struct
- * layout here changes (8: rmc_set_source_table). */
+ * layout here changes (8: rmc_set_source_table; 9: rmc_set_gas with dtype
+ * and mem, velocity-vector gradients, per-slice end counts). */
 int rmc_abi_version(void);
 
 #ifdef __cplusplus

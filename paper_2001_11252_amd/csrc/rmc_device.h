@@ -58,21 +58,30 @@ struct ObsK {
   void *cube;      // [ny][nx][nbins], float or double by precision
 };
 
-// A peel-off ray stopped where it leaves its first leaf, queued for the
-// ray-cast pass that follows each transport launch.
-struct PeelJob {
-  double p[3];              // point where the ray enters its next leaf
-  double tau;               // optical depth accumulated so far
+// A peel-off ray queued for the ray-cast pass that follows each transport
+// launch: cube element | observer << 40 | problem << 44 in dst.  Double
+// path: the point where the ray enters its next leaf (or its start), the
+// optical depth so far and the leaves crossed so far (64 B).  Float path:
+// the ray's start, its frequency and weight in float (40 B).
+template <class R> struct PeelJob;
+template <> struct PeelJob<double> {
+  double p[3];
+  double tau;
   double x;                 // x_ext of the ray (frequency toward the observer)
   double weight;            // phase-function weight of the deposit
-  unsigned long long dst;   // cube element | observer << 40 | problem << 44
-  uint32_t steps, pad;      // leaves crossed so far
+  unsigned long long dst;
+  uint32_t steps, pad;
+};
+template <> struct PeelJob<float> {
+  double p[3];
+  unsigned long long dst;
+  float x, weight;
 };
 constexpr int PQ_OBS_SHIFT = 40, PQ_PROB_SHIFT = 44;
 constexpr unsigned long long PQ_ELEM_MASK = (1ull << PQ_OBS_SHIFT) - 1ull;
 
 struct PeelQueue {
-  PeelJob *jobs;                  // [n_regions][cap]: one region per transport wave
+  void *jobs;                     // PeelJob<R> [n_regions][cap]: one region per transport wave
   uint32_t *counts;               // [n_regions]: pushes of each region in the last launch
   unsigned long long cap;         // jobs per region (a wave stops its slice before it)
   unsigned long long n_regions;
@@ -385,6 +394,7 @@ template <class R> __device__ __forceinline__ R voigt_dhdx(R a, R x) {
 // two-piece Lorentzian envelope split at u0(x, log10 a) (the paper's fit,
 // clamped at 0 where it goes negative); |x| >= 8: Gaussian of variance 1/2
 // centred at 1/x; negative x by symmetry.
+#pragma clang fp contract(on)
 template <class R> __device__ __forceinline__ R u0_fit(R x, R la) {
   const R c0 = R(2.648963) + la * (R(2.014446) + la * R(0.351479));
   const R c1 = R(-4.058673) + la * (R(-3.675859) + la * R(-0.640003));
@@ -399,61 +409,106 @@ template <class R> __device__ __forceinline__ R u0_fit(R x, R la) {
 // with status stuck (never reached for finite x and a > 0).
 constexpr uint32_t MAX_REJECT = 1u << 20;
 
-template <class R>
-__device__ __forceinline__ bool sample_upar(R x, R a, EventRng<R> &rng, uint32_t *iters, R *out) {
-  if (fabs(x) >= R(8)) {
-    R s, c;
-    M<R>::sincos2pi(rng.u(J_GAUSS2), &s, &c);
-    *out = M<R>::div(R(1), x) + M<R>::sqrt(-M<R>::log(rng.u(J_GAUSS1))) * c;
-    return true;
-  }
-  const R sg = x < R(0) ? R(-1) : R(1);
-  const R xa = fabs(x);
-  R u0 = u0_fit(xa, M<R>::log10(a));
+// The draw's envelope at (x, a), then single rounds of it.  Contraction
+// within a statement only (from u0_fit on), so that the same expressions
+// give the same values wherever the functions are inlined (the
+// one-round-per-pass transport and the looping sampler then draw identical
+// velocities).
+template <class R> struct UparEnv {
+  R sg, xa, th0, u02, p1, s1, s2;
+};
+
+template <class R> __device__ __forceinline__ UparEnv<R> upar_env(R x, R a) {
+  UparEnv<R> e;
+  e.sg = x < R(0) ? R(-1) : R(1);
+  e.xa = fabs(x);
+  R u0 = u0_fit(e.xa, M<R>::log10(a));
   u0 = u0 < R(0) ? R(0) : u0;
-  const R th0 = M<R>::atan(M<R>::div(u0 - xa, a));
+  e.th0 = M<R>::atan(M<R>::div(u0 - e.xa, a));
   const R e0 = M<R>::exp(-u0 * u0);
   const R hp = R(0.5 * PI_D);
-  const R p1 = M<R>::div(th0 + hp, (R(1) - e0) * th0 + (R(1) + e0) * hp);
-  const R u02 = u0 * u0;
+  e.p1 = M<R>::div(e.th0 + hp, (R(1) - e0) * e.th0 + (R(1) + e0) * hp);
+  e.u02 = u0 * u0;
   // float: one uniform picks the piece and, rescaled within it, the angle
   // (the same distribution with two uniforms per round, so that an event
   // with one round fits in two Philox blocks); double: three per round
-  const R s1 = p1 > R(0) ? M<R>::div(th0 + hp, p1) : R(0);
-  const R s2 = p1 < R(1) ? M<R>::div(hp - th0, R(1) - p1) : R(0);
-  for (uint32_t it = 0; it < MAX_REJECT; ++it) {
-    R th, lim, r3;
-    if constexpr (sizeof(R) == 4) {
-      const R r1 = rng.u(J_REJ + 2 * it);
-      r3 = rng.u(J_REJ + 2 * it + 1);
-      if (r1 < p1) {
-        th = -hp + r1 * s1;
-        lim = R(0);
-      } else {
-        th = th0 + (r1 - p1) * s2;
-        lim = u02;
-      }
+  e.s1 = e.p1 > R(0) ? M<R>::div(e.th0 + hp, e.p1) : R(0);
+  e.s2 = e.p1 < R(1) ? M<R>::div(hp - e.th0, R(1) - e.p1) : R(0);
+  return e;
+}
+
+// Round `it` of the rejection draw (|x| < 8): true when it accepts, with
+// the velocity in *out.
+template <class R>
+__device__ __forceinline__ bool upar_try(const UparEnv<R> &e, R a, EventRng<R> &rng, uint32_t it, R *out) {
+  const R hp = R(0.5 * PI_D);
+  R th, lim, r3;
+  if constexpr (sizeof(R) == 4) {
+    const R r1 = rng.u(J_REJ + 2 * it);
+    r3 = rng.u(J_REJ + 2 * it + 1);
+    if (r1 < e.p1) {
+      th = -hp + r1 * e.s1;
+      lim = R(0);
     } else {
-      const R r1 = rng.u(J_REJ + 3 * it);
-      const R r2 = rng.u(J_REJ + 3 * it + 1);
-      r3 = rng.u(J_REJ + 3 * it + 2);
-      if (r1 < p1) {
-        th = -hp + r2 * (th0 + hp);
-        lim = R(0);
-      } else {
-        th = th0 + r2 * (hp - th0);
-        lim = u02;
-      }
+      th = e.th0 + (r1 - e.p1) * e.s2;
+      lim = e.u02;
     }
-    const R u = xa + a * M<R>::tan(th);
-    if (r3 < M<R>::exp(lim - u * u)) {
+  } else {
+    const R r1 = rng.u(J_REJ + 3 * it);
+    const R r2 = rng.u(J_REJ + 3 * it + 1);
+    r3 = rng.u(J_REJ + 3 * it + 2);
+    if (r1 < e.p1) {
+      th = -hp + r2 * (e.th0 + hp);
+      lim = R(0);
+    } else {
+      th = e.th0 + r2 * (hp - e.th0);
+      lim = e.u02;
+    }
+  }
+  const R u = e.xa + a * M<R>::tan(th);
+  *out = e.sg * u;
+  return r3 < M<R>::exp(lim - u * u);
+}
+
+// The |x| >= 8 branch: Gaussian of variance 1/2 centred at 1/x.
+template <class R> __device__ __forceinline__ R upar_gauss(R x, EventRng<R> &rng) {
+  R s, c;
+  M<R>::sincos2pi(rng.u(J_GAUSS2), &s, &c);
+  return M<R>::div(R(1), x) + M<R>::sqrt(-M<R>::log(rng.u(J_GAUSS1))) * c;
+}
+#pragma clang fp contract(fast)
+
+template <class R>
+__device__ __forceinline__ bool sample_upar(R x, R a, EventRng<R> &rng, uint32_t *iters, R *out) {
+  if (fabs(x) >= R(8)) {
+    *out = upar_gauss(x, rng);
+    return true;
+  }
+  const UparEnv<R> e = upar_env(x, a);
+  for (uint32_t it = 0; it < MAX_REJECT; ++it) {
+    if (upar_try(e, a, rng, it, out)) {
       *iters += it + 1;
-      *out = sg * u;
       return true;
     }
   }
   *out = R(0);
   return false;
+}
+
+// Round `it` alone of the same draw, the envelope rebuilt from x and a
+// (exact functions of the packet's state): true and *out when round `it`
+// accepts (the |x| >= 8 Gaussian accepts at round 0).  Running rounds 0, 1,
+// 2, ... one per call gives sample_upar's result with the same draws, so a
+// lane whose round is rejected can take its next round at a later pass of
+// the transport loop, together with the first rounds of other lanes,
+// instead of holding its wave in a loop of its own.
+template <class R>
+__device__ __forceinline__ bool upar_round(R x, R a, EventRng<R> &rng, uint32_t it, R *out) {
+  if (fabs(x) >= R(8)) {
+    *out = upar_gauss(x, rng);
+    return true;
+  }
+  return upar_try(upar_env(x, a), a, rng, it, out);
 }
 
 // Sect. 3.3.1 inverse CDFs.

@@ -171,54 +171,50 @@ template <class R> struct PeelSrc {
 // of the queue and the region's fill count, kept in LDS (one per wave, so
 // no global atomics).  The wave stops taking events before the region
 // could overflow, so a push always finds room.
-struct PeelSink {
-  PeelJob *region;
+template <class R> struct PeelSink {
+  PeelJob<R> *region;
   int *count;
   uint32_t cap;
   unsigned long long *lost;   // pushes that found no room (never expected)
 };
 
-// Deferred peel-off ray toward observer oi from p: the scattering's own leaf
-// (its record is in the lane's registers) ends most rays, whose optical
-// depth to the nearest face, or to the exit face along k_obs, already
-// reaches the cut (exp(-tau) is zero, no deposit).  Any other ray is queued
-// for the ray-cast pass, which does every deposit: the float path queues it
-// from its start (the pass walks the first leaf again, which keeps this
-// kernel's registers low enough for four waves per SIMD), the double path
-// from the point where it leaves the first leaf, with the optical depth so
-// far.  Rays from a leaf the domain border may cut, and emission rays (sc
-// null: no leaf located yet), are queued from the start.
-template <class R, int NL>
-__device__ __forceinline__ void peel_defer(const ProblemK &pb, const double p[3], const ObsK &ob, const R ko[3],
-                                           R xo, R weight, size_t elem, int oi, LaneCount &cnt,
-                                           const PeelSink &snk, const StartCell<R> *sc) {
-  bool ends = false;
-  double q[3] = {p[0], p[1], p[2]}, qtau = 0.0;
-  uint32_t qsteps = 0;
-  if (sc && sc->lf->bnd == R(0)) {
-    Opac<R, NL> o;
-    opacity(pb, *sc->lf, (double)xo, ko, o);
-    const double kt = (double)o.ktot;
-    ends = kt * inner_dist(*sc->c, pb.L, p) >= TauCut<R>::v;
-    if (!ends) {
-      double face[3], lo[3], hi[3];
-      int em;
-      const double te = exit_dist(*sc->c, pb.L, p, ob.k, face, lo, hi, &em, sizeof(R) == 4 ? ob.kinv : nullptr);
-      const double t1 = kt * te;
-      ends = t1 >= TauCut<R>::v;
-      if constexpr (sizeof(R) == 8) {
-        if (!ends) {
-          exit_point(te, em, p, ob.k, face, lo, hi, q);
-          wrap_slab(pb.domain, q, ob.k);
-          qtau = t1;
-          qsteps = 1;
-        }
-      }
-    }
+// First-leaf test of a peel-off ray toward observer ob from p, in the
+// scattering's own leaf (its record is in the lane's registers; the leaf
+// lies strictly inside the domain): true if the optical depth to the
+// nearest face, or to the exit face along k_obs, already reaches the cut,
+// where exp(-tau) is zero and no deposit changes.  With EXIT (double path,
+// deferred rays) a ray that goes on gets where it leaves the leaf (q,
+// wrapped through periodic borders) and the optical depth so far.
+template <class R, int NL, bool EXIT>
+__device__ __forceinline__ bool peel_first_leaf(const ProblemK &pb, const double p[3], const ObsK &ob,
+                                                const R ko[3], R xo, const StartCell<R> *sc, double q[3],
+                                                double *qtau) {
+  Opac<R, NL> o;
+  opacity(pb, *sc->lf, (double)xo, ko, o);
+  const double kt = (double)o.ktot;
+  if (kt * inner_dist(*sc->c, pb.L, p) >= TauCut<R>::v) return true;
+  double face[3], lo[3], hi[3];
+  int em;
+  const double te = exit_dist(*sc->c, pb.L, p, ob.k, face, lo, hi, &em, sizeof(R) == 4 ? ob.kinv : nullptr);
+  const double t1 = kt * te;
+  if (t1 >= TauCut<R>::v) return true;
+  if constexpr (EXIT) {
+    exit_point(te, em, p, ob.k, face, lo, hi, q);
+    wrap_slab(pb.domain, q, ob.k);
+    *qtau = t1;
   }
-  if (ends || qsteps) ++cnt.peel_cross;
-  if (ends) return;
-  // one LDS atomic per wave reserves the slots of the lanes pushing here
+  return false;
+}
+
+// Queue a peel-off ray for the ray-cast pass, which makes every deposit:
+// the float path queues it from its start (the pass walks the first leaf
+// again, which keeps this kernel's registers low enough for four waves per
+// SIMD), the double path, when its first leaf was tested, from where it
+// leaves that leaf with the optical depth so far (qsteps = 1).  One LDS
+// atomic per wave reserves the slots of the lanes pushing here.
+template <class R>
+__device__ __forceinline__ void peel_push(const ProblemK &pb, const double q[3], double qtau, uint32_t qsteps,
+                                          R xo, R weight, size_t elem, int oi, const PeelSink<R> &snk) {
   const unsigned long long m = __ballot(true);
   const int lane = __lane_id();
   const int leader = __ffsll((long long)m) - 1;
@@ -227,45 +223,48 @@ __device__ __forceinline__ void peel_defer(const ProblemK &pb, const double p[3]
   base = __shfl(base, leader);
   const uint32_t slot = (uint32_t)base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
   if (slot < snk.cap) {
-    PeelJob &j = snk.region[slot];
+    PeelJob<R> &j = snk.region[slot];
     j.p[0] = q[0]; j.p[1] = q[1]; j.p[2] = q[2];
-    j.tau = qtau;
-    j.x = (double)xo;
-    j.weight = (double)weight;
+    j.x = xo;
+    j.weight = weight;
     j.dst = (unsigned long long)elem | ((unsigned long long)oi << PQ_OBS_SHIFT) |
             ((unsigned long long)pb.index << PQ_PROB_SHIFT);
-    j.steps = qsteps;
+    if constexpr (sizeof(R) == 8) {
+      j.tau = qtau;
+      j.steps = qsteps;
+    }
   } else {
     atomicAdd(snk.lost, 1ull);
   }
 }
 
-// Peel-off of one event toward every observer (Sect. 5.1).  DEFER: each ray
-// is decided in the scattering's own leaf or queued for the ray-cast pass
-// (peel_defer).  Otherwise the whole ray is walked here.
+// Peel-off of one event toward every observer (Sect. 5.1).  A ray from a
+// leaf strictly inside the domain is first tested in that leaf, before its
+// weight, pixel and bin are computed: most rays from optically thick gas
+// end there with no deposit.  A ray that goes on is binned (deposits
+// outside the cube are dropped and counted) and, with DEFER, queued for the
+// ray-cast pass (peel_push), else walked here.  Emission rays (sc null: no
+// leaf located yet) and rays from leaves the domain border may cut skip the
+// first-leaf test.
 template <class R, bool DEFER, int NL>
 __device__ void peel_all(const ProblemK &pb, const double p[3], const PeelSrc<R> &s, int *stk,
-                         int stride, LaneCount &cnt, const PeelSink &snk, const StartCell<R> *sc = nullptr) {
+                         int stride, LaneCount &cnt, const PeelSink<R> &snk, const StartCell<R> *sc = nullptr) {
   for (int oi = 0; oi < pb.n_obs; ++oi) {
     const ObsK &ob = pb.obs[oi];
     const R ko[3] = {(R)ob.k[0], (R)ob.k[1], (R)ob.k[2]};
-    R weight, xo;
+    R xo, mu = R(0);
     if (s.kind == 0) {
-      weight = R(1.0 / (4.0 * PI_D));
       xo = s.x;
     } else if (NL > 1 && s.kind == 3) {
       // fluorescent re-emission: isotropic, at the channel's rest frequency
       // in the atom frame, then through the cell's velocity
       const LineK &ln = pb.lines[s.line];
-      weight = R(1.0 / (4.0 * PI_D));
       const R ba = s.bc * (ko[0] * s.U[0] + ko[1] * s.U[1] + ko[2] * s.U[2]);
       const R bw = R(pb.b_ref) * (ko[0] * s.ux + ko[1] * s.uy + ko[2] * s.uz);
       xo = R(ln.xf0[s.core]) + M<R>::div(R(ln.sf[s.core]) * (ba + bw + ba * bw), R(pb.b_ref));
     } else if (s.kind == 1) {
       const LineK &ln = pb.lines[s.line];
-      const R mu = s.kin[0] * ko[0] + s.kin[1] * ko[1] + s.kin[2] * ko[2];
-      const R P = ln.phase == PHASE_ISO ? R(0.5) : (s.core ? p_core(mu) : p_wing(mu));
-      weight = P * R(1.0 / (2.0 * PI_D));
+      mu = s.kin[0] * ko[0] + s.kin[1] * ko[1] + s.kin[2] * ko[2];
       const R dkU = (ko[0] - s.kin[0]) * s.U[0] + (ko[1] - s.kin[1]) * s.U[1] + (ko[2] - s.kin[2]) * s.U[2];
       const R g1 = R(1) + s.bc * s.x;
       const R Rr = ln.recoil ? (R(1) - mu) * R(ln.rec) * g1 : R(0);
@@ -273,11 +272,31 @@ __device__ void peel_all(const ProblemK &pb, const double p[3], const PeelSrc<R>
       const R wo = ko[0] * s.ux + ko[1] * s.uy + ko[2] * s.uz;
       xo = (R(-ln.delta) + R(ln.mu) * s.rho * xc * (R(1) + R(pb.b_ref) * wo) + wo) * R(ln.inv_s);
     } else {
-      const R mu = s.kin[0] * ko[0] + s.kin[1] * ko[1] + s.kin[2] * ko[2];
-      weight = p_hg(mu, R(pb.g_hg)) * R(1.0 / (2.0 * PI_D));
+      mu = s.kin[0] * ko[0] + s.kin[1] * ko[1] + s.kin[2] * ko[2];
       const R wo = ko[0] * s.ux + ko[1] * s.uy + ko[2] * s.uz;
       const R b = R(pb.b_ref);
       xo = M<R>::div(s.x + wo + b * s.x * wo - s.w, R(1) + b * s.w);
+    }
+    ++cnt.peel_rays;
+    constexpr bool EXIT = DEFER && sizeof(R) == 8;
+    double q[3] = {p[0], p[1], p[2]}, qtau = 0.0;
+    uint32_t qsteps = 0;
+    if (sc && sc->lf->bnd == R(0)) {
+      if (peel_first_leaf<R, NL, EXIT>(pb, p, ob, ko, xo, sc, q, &qtau)) {
+        ++cnt.peel_cross;
+        continue;
+      }
+      qsteps = EXIT ? 1u : 0u;
+    }
+    R weight;
+    if (s.kind == 0 || (NL > 1 && s.kind == 3)) {
+      weight = R(1.0 / (4.0 * PI_D));
+    } else if (s.kind == 1) {
+      const LineK &ln = pb.lines[s.line];
+      const R P = ln.phase == PHASE_ISO ? R(0.5) : (s.core ? p_core(mu) : p_wing(mu));
+      weight = P * R(1.0 / (2.0 * PI_D));
+    } else {
+      weight = p_hg(mu, R(pb.g_hg)) * R(1.0 / (2.0 * PI_D));
     }
     const int pix = pixel_of<sizeof(R) == 4>(ob, p);
     const int bin = bin_of<sizeof(R) == 4>(ob, (double)xo);
@@ -285,10 +304,10 @@ __device__ void peel_all(const ProblemK &pb, const double p[3], const PeelSrc<R>
       ++cnt.peel_drop;
       continue;
     }
-    ++cnt.peel_rays;
     const size_t elem = (size_t)pix * ob.nbins + bin;
     if constexpr (DEFER) {
-      peel_defer<R, NL>(pb, p, ob, ko, xo, weight, elem, oi, cnt, snk, sc);
+      if (qsteps) ++cnt.peel_cross;
+      peel_push<R>(pb, q, qtau, qsteps, xo, weight, elem, oi, snk);
     } else {
       uint32_t nc = 0;
       const double tau = ray_tau<R, NL>(pb, p, ob.k, (double)xo, TauCut<R>::v, stk, stride, &nc, sc,
@@ -308,6 +327,8 @@ template <class R> struct Lane {
   R x;
   double tau, path;
   uint32_t event, upar_iters;
+  uint32_t rej;    // regrouped loop: rejection rounds already run by the pending
+                   // line scattering at p (0: none pending)
   int32_t nscat;
   Cell c;
   LeafRec<R> lf;
@@ -329,8 +350,12 @@ template <class R> __device__ __forceinline__ void set_geom_dir(Lane<R> &s) {
   }
 }
 
+// Record a packet that ended (escaped, absorbed or stuck): its outputs, its
+// counts in the problem's totals, and, in the launch's slice counters, the
+// packet and its status (its dropped peel-off deposits are reported in the
+// slice where it ends).
 template <class R>
-__device__ void finish(const ProblemK &pb, Lane<R> &s, int status) {
+__device__ void finish(const ProblemK &pb, Lane<R> &s, int status, unsigned long long *slice) {
   const int64_t i = s.pid - pb.first;
   pb.status[i] = status;
   pb.x_out[i] = (double)s.x;
@@ -351,6 +376,10 @@ __device__ void finish(const ProblemK &pb, Lane<R> &s, int status) {
   if (s.cnt.peel_rays) atomicAdd(st + S_PEEL_RAYS, (unsigned long long)s.cnt.peel_rays);
   if (s.cnt.peel_cross) atomicAdd(st + S_PEEL_CROSS, (unsigned long long)s.cnt.peel_cross);
   if (s.cnt.peel_drop) atomicAdd(st + S_PEEL_DROPPED, (unsigned long long)s.cnt.peel_drop);
+  const int sk = status == ST_ESCAPED ? S_ESCAPED : (status == ST_ABSORBED ? S_ABSORBED : S_STUCK);
+  atomicAdd(slice + S_EMITTED, 1ull);
+  atomicAdd(slice + sk, 1ull);
+  if (s.cnt.peel_drop) atomicAdd(slice + S_PEEL_DROPPED, (unsigned long long)s.cnt.peel_drop);
 }
 
 // Emission (Sect. 2): position and frequency from the source list,
@@ -423,7 +452,7 @@ hipError_t launch_source_x(bool f32, const ProblemK &pb, const double *src_x, do
 
 template <class R, bool DEFER, int NL>
 __device__ void emit(const ProblemK &pb, int64_t pid, Lane<R> &s, int *stk, int *pstk, int stride,
-                     const PeelSink &snk) {
+                     const PeelSink<R> &snk) {
   s.pid = pid;
   s.p[0] = pb.src_pos[3 * pid];
   s.p[1] = pb.src_pos[3 * pid + 1];
@@ -449,6 +478,7 @@ __device__ void emit(const ProblemK &pb, int64_t pid, Lane<R> &s, int *stk, int 
   s.event = 0;
   s.nscat = 0;
   s.upar_iters = 0;
+  s.rej = 0;
   s.cnt = LaneCount{0, 0, 0, 0, 0};
   if (pb.n_obs) {
     PeelSrc<R> ps;
@@ -460,12 +490,18 @@ __device__ void emit(const ProblemK &pb, int64_t pid, Lane<R> &s, int *stk, int 
 
 // Interaction at the current position (Sect. 3.2).  Returns the packet's
 // status (ST_NONE while it lives).
-template <class R, bool DEFER, int NL>
+// With REGROUP a line scattering runs one rejection round of its u_par
+// draw per call: a rejected round leaves the event pending (s.rej rounds
+// run) and the packet where it is, and the next pass of the transport loop
+// calls again for the next round (the same draws as the looping sampler).
+template <class R, bool DEFER, int NL, bool REGROUP = false>
 __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R, NL> &o, int *pstk, const int *stk,
-                        const PeelSink &snk, int stride) {
+                        const PeelSink<R> &snk, int stride) {
   const StartCell<R> sc{&s.c, &s.lf, stk};
-  ++s.event;
-  if (pb.max_events > 0 && (int64_t)s.event >= pb.max_events) return ST_STUCK;
+  if (!REGROUP || s.rej == 0) {
+    ++s.event;
+    if (pb.max_events > 0 && (int64_t)s.event >= pb.max_events) return ST_STUCK;
+  }
   EventRng<R> rng(pb.seed, (uint64_t)s.pid, s.event);
   // kappa_d / kappa reaches ~1e-8 in optically thick line cores
   R r = rng.u_small(J_CHANNEL) * o.ktot;
@@ -521,7 +557,16 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R, NL> &o, in
     const LineK &ln = pb.lines[i];
     const R a = R(ln.alpha) * s.lf.irho;
     R upar;
-    if (!sample_upar<R>(x, a, rng, &s.upar_iters, &upar)) return ST_STUCK;
+    if constexpr (REGROUP) {
+      if (!upar_round<R>(x, a, rng, s.rej, &upar)) {
+        if (++s.rej >= MAX_REJECT) return ST_STUCK;
+        return ST_NONE;
+      }
+      s.upar_iters += s.rej + 1;
+      s.rej = 0;
+    } else {
+      if (!sample_upar<R>(x, a, rng, &s.upar_iters, &upar)) return ST_STUCK;
+    }
     // Gaussian u_perp (Box-Muller), restricted to |u_perp| >= x_crit while
     // core-skipping applies
     const R xc2 = pb.skip_tau > 0.0 ? core_skip_x2<R>(pb, ln, s.lf, s.c.level, a, x) : R(0);
@@ -611,7 +656,7 @@ struct SlotState {
   int32_t prob, active, event, nscat;
   int32_t leaf, level, ox, oy, oz;
   uint32_t dust, cross, peel_rays, peel_cross, peel_drop, iters;
-  int32_t pad;
+  uint32_t rej;
 };
 
 template <class R>
@@ -622,6 +667,7 @@ __device__ __forceinline__ void save_slot(SlotState &q, const Lane<R> &s, int pr
   q.leaf = s.c.leaf; q.level = s.c.level; q.ox = s.c.ox; q.oy = s.c.oy; q.oz = s.c.oz;
   q.dust = s.cnt.dust_scat; q.cross = s.cnt.cross; q.peel_rays = s.cnt.peel_rays;
   q.peel_cross = s.cnt.peel_cross; q.peel_drop = s.cnt.peel_drop; q.iters = s.upar_iters;
+  q.rej = s.rej;
 }
 
 template <class R>
@@ -632,12 +678,14 @@ __device__ __forceinline__ void load_slot(const SlotState &q, Lane<R> &s, int *p
   s.c.leaf = q.leaf; s.c.level = q.level; s.c.ox = q.ox; s.c.oy = q.oy; s.c.oz = q.oz;
   s.cnt.dust_scat = q.dust; s.cnt.cross = q.cross; s.cnt.peel_rays = q.peel_rays;
   s.cnt.peel_cross = q.peel_cross; s.cnt.peel_drop = q.peel_drop; s.upar_iters = q.iters;
+  s.rej = q.rej;
   set_geom_dir(s);
 }
 
-// Counters of work done inside one launch.
+// Counters of work done inside one launch (packets that end in it are
+// counted by finish).
 struct SliceCount {
-  uint32_t scat, dust, cross, peel_rays, peel_cross, finished;
+  uint32_t scat, dust, cross, peel_rays, peel_cross;
 };
 
 template <class R>
@@ -672,7 +720,11 @@ template <bool BATCH, bool DEFER, int NL> struct WavesPerEU<double, BATCH, DEFER
   static constexpr int v = RMC_WAVES_F64;
 };
 
-template <class R, bool BATCH, bool DEFER, int NL>
+// REGROUP: a line scattering whose rejection round fails stays pending and
+// takes its next round at the next pass of the loop, where it runs in step
+// with the other lanes' events (upar_round), instead of the wave looping
+// until its last lane accepts.
+template <class R, bool BATCH, bool DEFER, int NL, bool REGROUP = false>
 __global__ void __launch_bounds__(256)
     __attribute__((amdgpu_waves_per_eu(WavesPerEU<R, BATCH, DEFER, NL>::v, WavesPerEU<R, BATCH, DEFER, NL>::v)))
     k_transport(const ProblemK *__restrict__ probs,
@@ -695,9 +747,9 @@ __global__ void __launch_bounds__(256)
   PeelQueue *const pq = DEFER ? probs[0].pq : nullptr;
   const bool queue = DEFER && pq != nullptr;
   const int64_t wave = gid >> 6;
-  PeelSink snk;
+  PeelSink<R> snk;
   snk.count = lds + 2 * stack_levels * stride + (threadIdx.x >> 6);
-  snk.region = queue ? pq->jobs + (size_t)wave * pq->cap : nullptr;
+  snk.region = queue ? (PeelJob<R> *)pq->jobs + (size_t)wave * pq->cap : nullptr;
   snk.cap = queue ? (uint32_t)pq->cap : 0u;
   snk.lost = queue ? &pq->lost : nullptr;
   const int room = queue ? (int)pq->cap - 2 * 64 * MAX_OBS : 0x7fffffff;
@@ -705,7 +757,7 @@ __global__ void __launch_bounds__(256)
 
   Lane<R> s;
   Lane<R> z;            // counters when this slice took the packet over
-  SliceCount acc{0, 0, 0, 0, 0, 0};
+  SliceCount acc{0, 0, 0, 0, 0};
   int prob = 0;
   bool active = false;
   bool drained = false;
@@ -758,8 +810,7 @@ __global__ void __launch_bounds__(256)
               active = true;
             } else {
               add_delta(acc, s, z);
-              ++acc.finished;
-              finish<R>(pb, s, ST_ESCAPED);
+              finish<R>(pb, s, ST_ESCAPED, slice);
             }
           }
         }
@@ -778,10 +829,12 @@ __global__ void __launch_bounds__(256)
     double face[3], lo[3], hi[3];
     int em = 0;
     double te = 0.0, td = 0.0, lmax = 0.0, tseg = 0.0;
+    // a pending line scattering (REGROUP) is already at its event point
+    const bool pend = REGROUP && s.rej != 0;
     // An event closer than the nearest face of a leaf inside the domain
     // happens in this leaf whatever the exit distance; only a packet that
     // may leave needs it (the decision is the one tau < tseg would take).
-    bool here = s.lf.bnd == R(0) && s.tau < (double)o.ktot * inner_dist(s.c, pb.L, s.p);
+    bool here = pend || (s.lf.bnd == R(0) && s.tau < (double)o.ktot * inner_dist(s.c, pb.L, s.p));
     if (here) {
       cell_bounds(s.c, pb.L, lo, hi);
     } else {
@@ -796,12 +849,14 @@ __global__ void __launch_bounds__(256)
       // the event happens inside this leaf (float path: kappa is a float
       // and tau_event came from a float logarithm, so a float reciprocal
       // of kappa loses nothing the path keeps)
-      const double dist = sizeof(R) == 4 ? s.tau * (double)__builtin_amdgcn_rcpf((float)o.ktot)
-                                         : s.tau / (double)o.ktot;
+      // (a pending event moves by 0: p stays, clamped into its own leaf)
+      const double dist = pend ? 0.0
+                               : (sizeof(R) == 4 ? s.tau * (double)__builtin_amdgcn_rcpf((float)o.ktot)
+                                                 : s.tau / (double)o.ktot);
 #pragma unroll
       for (int d = 0; d < 3; ++d) s.p[d] = fmin(fmax(fma(dist, kd[d], s.p[d]), lo[d]), hi[d]);
       s.path += dist;
-      st = interact<R, DEFER, NL>(pb, s, o, pstk, stk, snk, stride);
+      st = interact<R, DEFER, NL, REGROUP>(pb, s, o, pstk, stk, snk, stride);
     } else {
       s.tau -= tseg;
       s.path += lmax;
@@ -828,8 +883,7 @@ __global__ void __launch_bounds__(256)
     }
     if (st != ST_NONE) {
       add_delta(acc, s, z);
-      ++acc.finished;
-      finish<R>(pb, s, st);
+      finish<R>(pb, s, st, slice);
       active = false;
     }
   }
@@ -849,10 +903,10 @@ __global__ void __launch_bounds__(256)
       atomicMax(&pq->max_region, (unsigned long long)nq);
     }
   }
-  unsigned long long v[6] = {acc.scat, acc.dust, acc.cross, acc.peel_rays, acc.peel_cross, acc.finished};
-  const int idx[6] = {S_SCAT, S_DUST_SCAT, S_CROSS, S_PEEL_RAYS, S_PEEL_CROSS, S_EMITTED};
+  unsigned long long v[5] = {acc.scat, acc.dust, acc.cross, acc.peel_rays, acc.peel_cross};
+  const int idx[5] = {S_SCAT, S_DUST_SCAT, S_CROSS, S_PEEL_RAYS, S_PEEL_CROSS};
 #pragma unroll
-  for (int j = 0; j < 6; ++j) {
+  for (int j = 0; j < 5; ++j) {
     unsigned long long x = v[j];
     for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off);
     if (lane == 0 && x) atomicAdd(slice + idx[j], x);
@@ -897,7 +951,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DrainW
   int *stk = lds + threadIdx.x;
   const int lane = __lane_id();
   const unsigned long long n_regions = pq->n_regions, cap = pq->cap;
-  const PeelJob *__restrict__ jobs = pq->jobs;
+  const PeelJob<R> *__restrict__ jobs = (const PeelJob<R> *)pq->jobs;
   const uint32_t *__restrict__ counts = pq->counts;
   const double cut = TauCut<R>::v;
   // wave-uniform: current region, next job in it, jobs in it
@@ -933,7 +987,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DrainW
       const uint32_t rank = (uint32_t)__popcll(idle & ((1ull << lane) - 1ull));
       const bool mine = ((idle >> lane) & 1ull) && rank < avail;
       if (mine) {
-        const PeelJob j = jobs[reg * cap + r_next + rank];
+        const PeelJob<R> j = jobs[reg * cap + r_next + rank];
         const int jp = BATCH ? (int)(j.dst >> PQ_PROB_SHIFT) : 0;
         if (BATCH && jp != acc_prob) {
           if (nc_prob) atomicAdd(probs[acc_prob].stats + S_PEEL_CROSS, nc_prob);
@@ -948,10 +1002,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DrainW
         k[0] = ob.k[0]; k[1] = ob.k[1]; k[2] = ob.k[2];
         kr[0] = (R)k[0]; kr[1] = (R)k[1]; kr[2] = (R)k[2];
         p[0] = j.p[0]; p[1] = j.p[1]; p[2] = j.p[2];
-        tau = j.tau;
-        x = j.x;
+        if constexpr (sizeof(R) == 8) {
+          tau = j.tau;
+          steps = j.steps;
+        } else {
+          tau = 0.0;
+          steps = 0;
+        }
+        x = (double)j.x;
         weight = (R)j.weight;
-        steps = j.steps;
         int X[3];
         if (steps < MAX_CROSS && int_coords(pb.L, p, k, X)) {
           descend(pb.nodes, pb.L, 0, 0, X, stk, stride, c);
@@ -1408,6 +1467,107 @@ __global__ void __launch_bounds__(256) k_image_bwd_tape(ProblemK pb, int obs, in
   if (lane == 0 && v) atomicAdd(ncross, v);
 }
 
+// ----------------------------------------------------- gas and sources in
+// Gas fields as given (float or double; v is [3n]) checked and copied into
+// the raw per-leaf array raw[8n] = {n_HI, T, vx, vy, vz, kappa_d, 0, 0} in
+// double.  bad[0] receives the smallest leaf with a non-finite or negative
+// value (or T <= 0), bad[1] the smallest with a velocity component of at
+// least 0.1 c; both start at ~0 (set by the caller).
+template <class T>
+__global__ void k_stage_gas(int64_t n, const T *__restrict__ nh, const T *__restrict__ tk,
+                            const T *__restrict__ v, const T *__restrict__ kd, double *__restrict__ raw,
+                            unsigned long long *__restrict__ bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double a = (double)nh[i], t = (double)tk[i], k = (double)kd[i];
+  const double vx = (double)v[3 * i], vy = (double)v[3 * i + 1], vz = (double)v[3 * i + 2];
+  const bool ok = isfinite(a) && a >= 0.0 && isfinite(t) && t > 0.0 && isfinite(k) && k >= 0.0 && isfinite(vx) &&
+                  isfinite(vy) && isfinite(vz);
+  const double vmax = 0.1 * 2.99792458e10;
+  if (!ok) atomicMin(bad, (unsigned long long)i);
+  else if (fabs(vx) >= vmax || fabs(vy) >= vmax || fabs(vz) >= vmax) atomicMin(bad + 1, (unsigned long long)i);
+  double *r = raw + 8 * i;
+  r[0] = a; r[1] = t; r[2] = vx; r[3] = vy; r[4] = vz; r[5] = k; r[6] = 0.0; r[7] = 0.0;
+}
+
+// Leaf records (see rmc_device.h) from the raw gas: nl = n_HI box irho,
+// irho = sqrt(T_ref / T), kd = kappa_d box, u = v / v_th,ref, and the
+// domain-border flag of the leaf (level lv, integer coordinates ijk at its
+// level): box -- touches a face of the cube; slab -- not strictly inside
+// the slab; sphere -- some corner outside R (1 - 1e-9).  Plain IEEE double
+// arithmetic, uncontracted, so the records are exact functions of the
+// inputs; the float path rounds them once.
+#pragma clang fp contract(off)
+template <class R>
+__global__ void k_leaf_records(int64_t n, const double *__restrict__ raw, const int8_t *__restrict__ lv,
+                               const int32_t *__restrict__ ijk, double T_ref, double vth_ref, double box,
+                               int domain, double d0, double d1, double d2, double d3, R *__restrict__ leaves) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double *g = raw + 8 * i;
+  const double irho = sqrt(T_ref / g[1]);
+  const int l = lv[i];
+  const double h = ldexp(1.0, -l);
+  double lo[3], hi[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = (double)ijk[3 * i + d] * h;
+    hi[d] = (double)(ijk[3 * i + d] + 1) * h;
+  }
+  bool border;
+  if (domain == DOM_BOX) {
+    border = lo[0] <= 0.0 || hi[0] >= 1.0 || lo[1] <= 0.0 || hi[1] >= 1.0 || lo[2] <= 0.0 || hi[2] >= 1.0;
+  } else if (domain == DOM_SLAB_Z) {
+    border = !(lo[2] > d0 - d1 && hi[2] < d0 + d1);
+  } else {
+    const double Rr = d3 * (1.0 - 1e-9);
+    const double c[3] = {d0, d1, d2};
+    double far2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double a = fabs(lo[d] - c[d]), b = fabs(hi[d] - c[d]);
+      const double m = a > b ? a : b;
+      far2 += m * m;
+    }
+    border = !(far2 < Rr * Rr);
+  }
+  const double rec[8] = {g[0] * box * irho, irho, g[5] * box, g[2] / vth_ref, g[3] / vth_ref, g[4] / vth_ref,
+                         border ? 1.0 : 0.0, 0.0};
+  R *o = leaves + (size_t)i * LEAF_STRIDE;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) o[q] = (R)rec[q];
+}
+
+// Device-resident sources checked as the host path checks them: positions
+// in [0,1], finite x, unit directions (|k|^2 within 1e-6 of 1).  bad[0]
+// receives the smallest failing source.
+__global__ void k_check_sources(int64_t n, const double *__restrict__ pos, const double *__restrict__ dir,
+                                const double *__restrict__ x, unsigned long long *__restrict__ bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  bool ok = isfinite(x[i]);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) ok = ok && pos[3 * i + d] >= 0.0 && pos[3 * i + d] <= 1.0;
+  if (dir) {
+    const double nn = dir[3 * i] * dir[3 * i] + dir[3 * i + 1] * dir[3 * i + 1] + dir[3 * i + 2] * dir[3 * i + 2];
+    ok = ok && fabs(nn - 1.0) < 1e-6;
+  }
+  if (!ok) atomicMin(bad, (unsigned long long)i);
+}
+
+// Gradient with respect to the cell velocity vector from the one with
+// respect to v_los = k_obs . v (chain rule): g_v[3i + d] = g_vlos[i] k_d.
+__global__ void k_vlos_to_v(int64_t n, const double *__restrict__ g_vlos, double k0, double k1, double k2,
+                            double *__restrict__ g_v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double g = g_vlos[i];
+  g_v[3 * i] = g * k0;
+  g_v[3 * i + 1] = g * k1;
+  g_v[3 * i + 2] = g * k2;
+}
+#pragma clang fp contract(fast)
+
 // --------------------------------------------------------------- helpers
 __global__ void k_hist(int64_t n, const int32_t *__restrict__ status, const double *__restrict__ x,
                        int nbins, double x_min, double span, unsigned long long *__restrict__ h) {
@@ -1453,26 +1613,36 @@ static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b -
 using TransportFn = void (*)(const ProblemK *, const int64_t *, int, unsigned long long *, int, int, SlotState *,
                             int, unsigned long long *);
 
+// The one-round-per-pass form (regroup) is built for the deferred
+// peel-off kernels only (the default).
 template <class R, int NL>
-static TransportFn transport_fn(bool batch, bool defer) {
-  if (batch) return defer ? k_transport<R, true, true, NL> : k_transport<R, true, false, NL>;
-  return defer ? k_transport<R, false, true, NL> : k_transport<R, false, false, NL>;
+static TransportFn transport_fn(bool batch, bool defer, bool regroup) {
+  if (batch) {
+    if (!defer) return k_transport<R, true, false, NL>;
+    return regroup ? k_transport<R, true, true, NL, true> : k_transport<R, true, true, NL>;
+  }
+  if (!defer) return k_transport<R, false, false, NL>;
+  return regroup ? k_transport<R, false, true, NL, true> : k_transport<R, false, true, NL>;
 }
 
-static TransportFn transport_fn(bool fp32, bool batch, bool defer, bool one_line) {
-  if (fp32) return one_line ? transport_fn<float, 1>(batch, defer) : transport_fn<float, MAX_LINES>(batch, defer);
-  return one_line ? transport_fn<double, 1>(batch, defer) : transport_fn<double, MAX_LINES>(batch, defer);
+static TransportFn transport_fn(bool fp32, bool batch, bool defer, bool one_line, bool regroup) {
+  if (fp32)
+    return one_line ? transport_fn<float, 1>(batch, defer, regroup)
+                    : transport_fn<float, MAX_LINES>(batch, defer, regroup);
+  return one_line ? transport_fn<double, 1>(batch, defer, regroup)
+                  : transport_fn<double, MAX_LINES>(batch, defer, regroup);
 }
 
 static size_t transport_lds(int stack_levels, int block) {
   return ((size_t)2 * stack_levels * block + block / 64) * sizeof(int);
 }
 
-hipError_t launch_transport(bool fp32, bool batch, bool defer, bool one_line, const ProblemK *d_probs,
+hipError_t launch_transport(bool fp32, bool batch, bool defer, bool one_line, bool regroup, const ProblemK *d_probs,
                             const int64_t *d_starts, int n_probs, unsigned long long *d_next, int refill_min,
                             int stack_levels, int grid, int block, void *slots, int budget,
                             unsigned long long *slice, hipStream_t st) {
-  hipLaunchKernelGGL(transport_fn(fp32, batch, defer, one_line), dim3(grid), dim3(block), transport_lds(stack_levels, block), st,
+  hipLaunchKernelGGL(transport_fn(fp32, batch, defer, one_line, regroup), dim3(grid), dim3(block),
+                     transport_lds(stack_levels, block), st,
                      d_probs, d_starts, n_probs, d_next, refill_min, stack_levels, (SlotState *)slots, budget, slice);
   return hipGetLastError();
 }
@@ -1507,14 +1677,16 @@ int peel_drain_blocks_per_cu(bool fp32, bool batch, bool one_line, int stack_lev
   return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
-size_t peel_job_bytes() { return sizeof(PeelJob); }
+size_t peel_job_bytes(bool fp32) { return fp32 ? sizeof(PeelJob<float>) : sizeof(PeelJob<double>); }
 size_t peel_queue_bytes() { return sizeof(PeelQueue); }
 
 size_t slot_bytes() { return sizeof(SlotState); }
 
-int transport_blocks_per_cu(bool fp32, bool batch, bool defer, bool one_line, int block, int stack_levels) {
+int transport_blocks_per_cu(bool fp32, bool batch, bool defer, bool one_line, bool regroup, int block,
+                            int stack_levels) {
   int nb = 0;
-  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, transport_fn(fp32, batch, defer, one_line),
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb,
+                                                                    transport_fn(fp32, batch, defer, one_line, regroup),
                                                                     block,
                                                                     transport_lds(stack_levels, block));
   return (e == hipSuccess && nb > 0) ? nb : 1;
@@ -1606,6 +1778,44 @@ hipError_t launch_image_bwd_tape(bool fp32, const ProblemK &pb, int obs, int64_t
   else
     hipLaunchKernelGGL(k_image_bwd_tape<double>, dim3(blocks_for(n, b)), dim3(b), 0, st, pb, obs, n, tp, G,
                        inv_vth_ref, gn, gk, gv, ncross);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage_gas(bool f32_in, int64_t n, const void *nh, const void *tk, const void *v, const void *kd,
+                           double *raw, unsigned long long *bad, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  if (f32_in)
+    hipLaunchKernelGGL(k_stage_gas<float>, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, (const float *)nh,
+                       (const float *)tk, (const float *)v, (const float *)kd, raw, bad);
+  else
+    hipLaunchKernelGGL(k_stage_gas<double>, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, (const double *)nh,
+                       (const double *)tk, (const double *)v, (const double *)kd, raw, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_leaf_records(bool fp32, int64_t n, const double *raw, const int8_t *lv, const int32_t *ijk,
+                               double T_ref, double vth_ref, double box, int domain, const double dom[4],
+                               void *leaves, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  if (fp32)
+    hipLaunchKernelGGL(k_leaf_records<float>, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, raw, lv, ijk, T_ref,
+                       vth_ref, box, domain, dom[0], dom[1], dom[2], dom[3], (float *)leaves);
+  else
+    hipLaunchKernelGGL(k_leaf_records<double>, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, raw, lv, ijk, T_ref,
+                       vth_ref, box, domain, dom[0], dom[1], dom[2], dom[3], (double *)leaves);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_sources(int64_t n, const double *pos, const double *dir, const double *x,
+                                unsigned long long *bad, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_check_sources, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, pos, dir, x, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_vlos_to_v(int64_t n, const double *g_vlos, const double k[3], double *g_v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_vlos_to_v, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, g_vlos, k[0], k[1], k[2], g_v);
   return hipGetLastError();
 }
 

@@ -10,7 +10,9 @@ namespace rmc {
 // defer: peel-off rays past their first leaf go to the queue of
 // d_probs[0].pq (then launch_peel_drain must follow).  one_line: every
 // problem of the launch has a single line (a kernel specialised for it).
-hipError_t launch_transport(bool fp32, bool batch, bool defer, bool one_line, const ProblemK *d_probs,
+// regroup (with defer): one rejection round of a line scattering per pass
+// of the loop, a rejected round leaving the event pending for the next.
+hipError_t launch_transport(bool fp32, bool batch, bool defer, bool one_line, bool regroup, const ProblemK *d_probs,
                             const int64_t *d_starts, int n_probs, unsigned long long *d_next, int refill_min,
                             int stack_levels, int grid, int block, void *slots, int budget,
                             unsigned long long *slice, hipStream_t st);
@@ -20,9 +22,10 @@ size_t slot_bytes();
 hipError_t launch_peel_drain(bool fp32, bool batch, bool one_line, const ProblemK *d_probs, void *pq,
                              int stack_levels, int grid, unsigned long long *slice, hipStream_t st);
 int peel_drain_blocks_per_cu(bool fp32, bool batch, bool one_line, int stack_levels);
-size_t peel_job_bytes();
+size_t peel_job_bytes(bool fp32);
 size_t peel_queue_bytes();
-int transport_blocks_per_cu(bool fp32, bool batch, bool defer, bool one_line, int block, int stack_levels);
+int transport_blocks_per_cu(bool fp32, bool batch, bool defer, bool one_line, bool regroup, int block,
+                            int stack_levels);
 hipError_t launch_clear_slots(void *slots, int64_t n, hipStream_t st);
 hipError_t launch_count_live(const void *slots, int64_t n, unsigned long long *out, hipStream_t st);
 hipError_t launch_trace(const ProblemK &pb, int64_t n, const double *orig, const double *dir,
@@ -44,6 +47,22 @@ hipError_t launch_image_fwd_tape(bool fp32, const ProblemK &pb, int obs, int64_t
 hipError_t launch_image_bwd_tape(bool fp32, const ProblemK &pb, int obs, int64_t n, const TapeK &tp,
                                  const double *G, double inv_vth_ref, double *gn, double *gk, double *gv,
                                  unsigned long long *ncross, hipStream_t st);
+// Gas given as float (f32_in) or double arrays on the device, checked and
+// copied into raw[8n] (bad[0]: first invalid leaf, bad[1]: first leaf with
+// |v_d| >= 0.1 c; both must start at ~0).
+hipError_t launch_stage_gas(bool f32_in, int64_t n, const void *nh, const void *tk, const void *v, const void *kd,
+                           double *raw, unsigned long long *bad, hipStream_t st);
+// Leaf records (float when fp32) from raw gas and the leaves' levels and
+// integer coordinates.
+hipError_t launch_leaf_records(bool fp32, int64_t n, const double *raw, const int8_t *lv, const int32_t *ijk,
+                               double T_ref, double vth_ref, double box, int domain, const double dom[4],
+                               void *leaves, hipStream_t st);
+// bad[0]: first source outside the box, with non-finite x or a non-unit
+// direction (dir may be null); must start at ~0.
+hipError_t launch_check_sources(int64_t n, const double *pos, const double *dir, const double *x,
+                                unsigned long long *bad, hipStream_t st);
+// g_v[3n] = g_vlos[n] k (velocity-vector gradient from the line-of-sight one)
+hipError_t launch_vlos_to_v(int64_t n, const double *g_vlos, const double k[3], double *g_v, hipStream_t st);
 hipError_t launch_hist(int64_t n, const int32_t *status, const double *x, int nbins, double x_min, double span,
                        unsigned long long *h, hipStream_t st);
 hipError_t launch_batch_reset(const ProblemK *d_probs, int n, unsigned long long *d_next, hipStream_t st);

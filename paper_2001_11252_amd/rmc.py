@@ -24,6 +24,7 @@ F32, F64 = 0, 1
 OPT_FORWARD_ONLY, OPT_MAX_EVENTS, OPT_BLOCK, OPT_WAVES_PER_CU, OPT_REFILL, OPT_PEEL_DEFER = 1, 2, 3, 4, 5, 6
 OPT_SLICE_ITERS = 7
 OPT_VOIGT = 8
+OPT_REGROUP = 9
 ST_NONE, ST_ESCAPED, ST_ABSORBED, ST_STUCK = 0, 1, 2, 3
 _NAMES = {EINVAL: "RMC_EINVAL", ENOMEM: "RMC_ENOMEM", EDEVICE: "RMC_EDEVICE", EMESH: "RMC_EMESH",
           ESTATE: "RMC_ESTATE", EUNSUPPORTED: "RMC_EUNSUPPORTED"}
@@ -77,7 +78,7 @@ _sig = {
     "rmc_set_source_spectrum": (C.c_int, [_P, C.c_int, _P]),
     "rmc_set_source_table": (C.c_int, [_P, C.c_int, _P, _P]),
     "rmc_set_mesh": (C.c_int, [_P, _i64, _P, _P, C.c_double]),
-    "rmc_set_gas": (C.c_int, [_P, _P, _P, _P, _P]),
+    "rmc_set_gas": (C.c_int, [_P, _P, _P, _P, _P, C.c_int, C.c_int]),
     "rmc_set_lines": (C.c_int, [_P, C.c_int, _P, C.c_double]),
     "rmc_set_dust": (C.c_int, [_P, C.c_double, C.c_double]),
     "rmc_set_domain": (C.c_int, [_P, C.c_int, _P]),
@@ -95,9 +96,9 @@ _sig = {
     "rmc_trace_cells": (C.c_int, [_P, _i64, _P, _P, C.c_int32, _P, _P, _P, C.c_int]),
     "rmc_tau": (C.c_int, [_P, _i64, _P, _P, _P, _P, C.c_int]),
     "rmc_raycast_image": (C.c_int, [_P, C.c_int, _i64, _P, _P, _P, _P, C.c_int]),
-    "rmc_raycast_image_backward": (C.c_int, [_P, C.c_int, _i64, _P, _P, _P, _P, _P, _P, _P, C.c_int]),
+    "rmc_raycast_image_backward": (C.c_int, [_P, C.c_int, _i64, _P, _P, _P, _P, _P, _P, _P, _P, C.c_int]),
     "rmc_raycast_image_tape": (C.c_int, [_P, C.c_int, _i64, _P, _P, _P, _P, C.c_int]),
-    "rmc_raycast_image_backward_tape": (C.c_int, [_P, _P, _P, _P, _P, C.c_int]),
+    "rmc_raycast_image_backward_tape": (C.c_int, [_P, _P, _P, _P, _P, _P, C.c_int]),
     "rmc_image_stats": (C.c_int, [_P, C.POINTER(C.c_uint64), C.POINTER(C.c_double)]),
     "rmc_batch_run": (C.c_int, [_P, C.c_int, _P, _P, C.POINTER(RmcRunStats), C.POINTER(RmcRunStats)]),
     "rmc_batch_begin": (C.c_int, [_P, C.c_int, _P, _P]),
@@ -131,6 +132,29 @@ def _ptr(a):
 
 def _host(a, dtype):
     return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _dev(a, name, device, dtypes, numel):
+    """A device tensor handed to the library in place: checked to be on the
+    context's device, of an accepted dtype, contiguous and of the expected
+    size (the kernels read numel elements from its pointer)."""
+    import torch
+    if not _is_dev(a):
+        raise TypeError(f"{name}: expected a torch tensor on the GPU (the other arguments are)")
+    if a.device != device:
+        raise ValueError(f"{name}: on {a.device}, expected {device}")
+    if a.dtype not in dtypes:
+        raise TypeError(f"{name}: dtype {a.dtype}, expected one of {dtypes}")
+    if not a.is_contiguous():
+        raise ValueError(f"{name}: not contiguous")
+    if a.numel() != numel:
+        raise ValueError(f"{name}: {a.numel()} elements, expected {numel}")
+    return a
+
+
+def _f64():
+    import torch
+    return (torch.float64,)
 
 
 def _line(ln):
@@ -235,9 +259,26 @@ class Context:
         self._chk(_L.rmc_set_lines(self._h, len(lines), arr, float(T_ref)), "set_lines")
 
     def set_gas(self, n_hi, T, v, kappa_d):
+        """Per-leaf gas: numpy arrays (host), or torch tensors on the GPU, all
+        float32 or all float64 (read in place on the device, no host copy)."""
+        n = self.n_leaves
+        if _is_dev(n_hi):
+            import torch
+            dt = n_hi.dtype
+            if dt not in (torch.float32, torch.float64):
+                raise TypeError(f"n_hi: dtype {dt}, expected float32 or float64")
+            a = _dev(n_hi, "n_hi", n_hi.device, (dt,), n)
+            b = _dev(T, "T", n_hi.device, (dt,), n)
+            c = _dev(v, "v", n_hi.device, (dt,), 3 * n)
+            d = _dev(kappa_d, "kappa_d", n_hi.device, (dt,), n)
+            self._chk(_L.rmc_set_gas(self._h, _ptr(a), _ptr(b), _ptr(c), _ptr(d),
+                                     F32 if dt == torch.float32 else F64, DEVICE), "set_gas")
+            return
         a, b, c, d = (_host(n_hi, np.float64), _host(T, np.float64), _host(v, np.float64),
                       _host(kappa_d, np.float64))
-        self._chk(_L.rmc_set_gas(self._h, _ptr(a), _ptr(b), _ptr(c), _ptr(d)), "set_gas")
+        if not (len(a) == len(b) == len(d) == n and c.size == 3 * n):
+            raise ValueError(f"gas arrays must hold {n} leaves (v: {3 * n} values)")
+        self._chk(_L.rmc_set_gas(self._h, _ptr(a), _ptr(b), _ptr(c), _ptr(d), F64, HOST), "set_gas")
 
     def set_dust(self, albedo, g):
         self._chk(_L.rmc_set_dust(self._h, float(albedo), float(g)), "set_dust")
@@ -248,8 +289,12 @@ class Context:
 
     def set_sources(self, pos, x, dirs=None):
         if _is_dev(pos):
-            self._chk(_L.rmc_set_sources(self._h, pos.shape[0], _ptr(pos), _ptr(dirs), _ptr(x), DEVICE),
-                      "set_sources")
+            n = pos.shape[0]
+            _dev(pos, "pos", pos.device, _f64(), 3 * n)
+            _dev(x, "x", pos.device, _f64(), n)
+            if dirs is not None:
+                _dev(dirs, "dirs", pos.device, _f64(), 3 * n)
+            self._chk(_L.rmc_set_sources(self._h, n, _ptr(pos), _ptr(dirs), _ptr(x), DEVICE), "set_sources")
             return
         p = _host(pos, np.float64)
         xx = _host(x, np.float64)
@@ -332,10 +377,18 @@ class Context:
         return t
 
     # ----------------------------------------------------- image/adjoint
+    def _rays_dev(self, orig, x_ext, w):
+        n = orig.shape[0]
+        _dev(orig, "orig", orig.device, _f64(), 3 * n)
+        _dev(x_ext, "x_ext", orig.device, _f64(), n)
+        _dev(w, "w", orig.device, _f64(), n)
+        return n
+
     def raycast_image(self, oid, orig, x_ext, w):
         ny, nx, _ = self.observers[oid]
         if _is_dev(orig):
             import torch
+            self._rays_dev(orig, x_ext, w)
             img = torch.zeros((ny, nx), dtype=torch.float64, device=orig.device)
             self._chk(_L.rmc_raycast_image(self._h, oid, orig.shape[0], _ptr(orig), _ptr(x_ext), _ptr(w), _ptr(img),
                                            DEVICE), "raycast_image")
@@ -346,22 +399,30 @@ class Context:
                   "raycast_image")
         return img
 
-    def raycast_image_backward(self, oid, orig, x_ext, w, grad_image):
+    def raycast_image_backward(self, oid, orig, x_ext, w, grad_image, with_v=False):
+        """(g_nhi, g_kd, g_vlos) per leaf of sum(grad_image * image); with_v
+        adds g_v [n, 3], the gradient with respect to the velocity vector."""
+        ny, nx, _ = self.observers[oid]
+        n = self.n_leaves
         if _is_dev(orig):
             import torch
-            n = self.n_leaves
+            self._rays_dev(orig, x_ext, w)
             gn, gk, gv = (torch.zeros(n, dtype=torch.float64, device=orig.device) for _ in range(3))
-            G = grad_image.contiguous().to(torch.float64)
+            g3 = torch.zeros((n, 3), dtype=torch.float64, device=orig.device) if with_v else None
+            G = _dev(grad_image.contiguous().to(torch.float64), "grad_image", orig.device, _f64(), ny * nx)
             self._chk(_L.rmc_raycast_image_backward(self._h, oid, orig.shape[0], _ptr(orig), _ptr(x_ext), _ptr(w),
-                                                    _ptr(G), _ptr(gn), _ptr(gk), _ptr(gv), DEVICE),
+                                                    _ptr(G), _ptr(gn), _ptr(gk), _ptr(gv), _ptr(g3), DEVICE),
                       "raycast_image_backward")
-            return gn, gk, gv
+            return (gn, gk, gv, g3) if with_v else (gn, gk, gv)
         o, x, ww = _host(orig, np.float64), _host(x_ext, np.float64), _host(w, np.float64)
         G = _host(grad_image, np.float64)
-        gn, gk, gv = np.zeros(self.n_leaves), np.zeros(self.n_leaves), np.zeros(self.n_leaves)
+        if G.size != ny * nx or o.size != 3 * len(x) or len(ww) != len(x):
+            raise ValueError("ray arrays or grad_image of the wrong size")
+        gn, gk, gv = np.zeros(n), np.zeros(n), np.zeros(n)
+        g3 = np.zeros((n, 3)) if with_v else None
         self._chk(_L.rmc_raycast_image_backward(self._h, oid, len(x), _ptr(o), _ptr(x), _ptr(ww), _ptr(G), _ptr(gn),
-                                                _ptr(gk), _ptr(gv), HOST), "raycast_image_backward")
-        return gn, gk, gv
+                                                _ptr(gk), _ptr(gv), _ptr(g3), HOST), "raycast_image_backward")
+        return (gn, gk, gv, g3) if with_v else (gn, gk, gv)
 
     def raycast_image_tape(self, oid, orig, x_ext, w):
         """raycast_image that keeps the rays' crossing lists on the device
@@ -369,6 +430,7 @@ class Context:
         ny, nx, _ = self.observers[oid]
         if _is_dev(orig):
             import torch
+            self._rays_dev(orig, x_ext, w)
             img = torch.zeros((ny, nx), dtype=torch.float64, device=orig.device)
             self._chk(_L.rmc_raycast_image_tape(self._h, oid, orig.shape[0], _ptr(orig), _ptr(x_ext), _ptr(w),
                                                 _ptr(img), DEVICE), "raycast_image_tape")
@@ -380,22 +442,25 @@ class Context:
         self.tape_serial = getattr(self, "tape_serial", 0) + 1
         return img
 
-    def raycast_image_backward_tape(self, grad_image):
+    def raycast_image_backward_tape(self, grad_image, with_v=False):
         """(g_nhi, g_kd, g_vlos) per leaf of sum(grad_image * image) for the
-        rays of the last raycast_image_tape call, read from its tape."""
+        rays of the last raycast_image_tape call, read from its tape; with_v
+        adds g_v [n, 3] (velocity-vector gradient)."""
         n = self.n_leaves
         if _is_dev(grad_image):
             import torch
             gn, gk, gv = (torch.zeros(n, dtype=torch.float64, device=grad_image.device) for _ in range(3))
+            g3 = torch.zeros((n, 3), dtype=torch.float64, device=grad_image.device) if with_v else None
             G = grad_image.contiguous().to(torch.float64)
-            self._chk(_L.rmc_raycast_image_backward_tape(self._h, _ptr(G), _ptr(gn), _ptr(gk), _ptr(gv), DEVICE),
-                      "raycast_image_backward_tape")
-            return gn, gk, gv
+            self._chk(_L.rmc_raycast_image_backward_tape(self._h, _ptr(G), _ptr(gn), _ptr(gk), _ptr(gv), _ptr(g3),
+                                                         DEVICE), "raycast_image_backward_tape")
+            return (gn, gk, gv, g3) if with_v else (gn, gk, gv)
         G = _host(grad_image, np.float64)
         gn, gk, gv = np.zeros(n), np.zeros(n), np.zeros(n)
-        self._chk(_L.rmc_raycast_image_backward_tape(self._h, _ptr(G), _ptr(gn), _ptr(gk), _ptr(gv), HOST),
+        g3 = np.zeros((n, 3)) if with_v else None
+        self._chk(_L.rmc_raycast_image_backward_tape(self._h, _ptr(G), _ptr(gn), _ptr(gk), _ptr(gv), _ptr(g3), HOST),
                   "raycast_image_backward_tape")
-        return gn, gk, gv
+        return (gn, gk, gv, g3) if with_v else (gn, gk, gv)
 
     def image_stats(self):
         """(ray-cell crossings, device ms) of the last image call."""
@@ -480,38 +545,47 @@ def _make_raycast_fn():
 
     class RayCastImage(torch.autograd.Function):
         """Peel-off image of fixed rays as a differentiable function of the
-        per-leaf gas: image = f(n_HI, kappa_d, v).  The forward pass keeps
-        the rays' crossing lists (rmc_raycast_image_tape) and the backward
-        pass reads them (rmc_raycast_image_backward_tape); if the context has
-        recorded another tape since, the backward sets this call's gas again
-        and replays the rays (rmc_raycast_image_backward).  The gradient with
-        respect to v is dL/dv_los times the observer direction."""
+        per-leaf gas: image = f(n_HI, kappa_d, v).  The gas tensors (float32
+        or float64, on the context's GPU) go to the library in place
+        (rmc_set_gas with RMC_DEVICE).  The forward pass keeps the rays'
+        crossing lists (rmc_raycast_image_tape) and the backward pass reads
+        them (rmc_raycast_image_backward_tape); if the context has recorded
+        another tape since, the backward sets this call's gas again and
+        replays the rays (rmc_raycast_image_backward).  The library returns
+        the gradient with respect to the velocity vector directly."""
 
         @staticmethod
         def _set_gas(rmc_ctx, n_hi, kappa_d, v, T):
-            rmc_ctx.set_gas(n_hi.detach().cpu().numpy(), T, v.detach().cpu().numpy(),
-                            kappa_d.detach().cpu().numpy())
+            n_hi, kappa_d, v = n_hi.detach(), kappa_d.detach(), v.detach()
+            if _is_dev(n_hi):
+                T = torch.as_tensor(T, dtype=n_hi.dtype, device=n_hi.device)
+                if T.numel() == 1:
+                    T = T.expand(n_hi.numel())
+                rmc_ctx.set_gas(n_hi.contiguous(), T.contiguous(), v.contiguous(), kappa_d.contiguous())
+            else:
+                rmc_ctx.set_gas(n_hi.numpy(), T, v.numpy(), kappa_d.numpy())
 
         @staticmethod
-        def forward(ctx, n_hi, kappa_d, v, rmc_ctx, T, oid, orig, x_ext, w, k_obs):
+        def forward(ctx, n_hi, kappa_d, v, rmc_ctx, T, oid, orig, x_ext, w):
             RayCastImage._set_gas(rmc_ctx, n_hi, kappa_d, v, T)
             img = rmc_ctx.raycast_image_tape(oid, orig, x_ext, w)
             # this call's gas, kept by reference for the replay fallback
             ctx.save_for_backward(n_hi, kappa_d, v)
-            ctx.rmc = (rmc_ctx, oid, orig, x_ext, w, k_obs, T, rmc_ctx.tape_serial)
+            ctx.rmc = (rmc_ctx, oid, orig, x_ext, w, T, rmc_ctx.tape_serial)
             return img
 
         @staticmethod
         def backward(ctx, grad_image):
-            rmc_ctx, oid, orig, x_ext, w, k_obs, T, serial = ctx.rmc
+            rmc_ctx, oid, orig, x_ext, w, T, serial = ctx.rmc
             if rmc_ctx.tape_serial == serial:
-                gn, gk, gv = rmc_ctx.raycast_image_backward_tape(grad_image)
+                gn, gk, _, g3 = rmc_ctx.raycast_image_backward_tape(grad_image, with_v=True)
             else:
                 n_hi, kappa_d, v = ctx.saved_tensors
                 RayCastImage._set_gas(rmc_ctx, n_hi, kappa_d, v, T)
-                gn, gk, gv = rmc_ctx.raycast_image_backward(oid, orig, x_ext, w, grad_image)
-            kv = torch.as_tensor(k_obs, dtype=gv.dtype, device=gv.device)
-            return gn, gk, gv[:, None] * kv[None, :], None, None, None, None, None, None, None
+                gn, gk, _, g3 = rmc_ctx.raycast_image_backward(oid, orig, x_ext, w, grad_image, with_v=True)
+            n_hi, kappa_d, v = ctx.saved_tensors
+            return (gn.to(n_hi.dtype), gk.to(kappa_d.dtype), g3.reshape(v.shape).to(v.dtype),
+                    None, None, None, None, None, None)
 
     return RayCastImage
 

@@ -24,7 +24,7 @@ def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(rmc.LIB_PATH)
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
-    assert rmc.lib().rmc_abi_version() == 8
+    assert rmc.lib().rmc_abi_version() == 9
 
 
 def test_host_line_quantities_match_oracle(orc):

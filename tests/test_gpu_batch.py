@@ -56,7 +56,7 @@ def test_batch_matches_oracle(orc):
         o = orc.run(p, p.seed)
         xg = g["x"][g["status"] == 1]
         xo = o["x"][o["status"] == 1]
-        assert stats.ks_2samp(xg, xo).pvalue > 1e-3, (p.name, p.meta)
+        assert stats.ks_2samp(xg, xo).pvalue > 0.01, (p.name, p.meta)
         se = np.sqrt(g["n_scat"].var() / n + o["n_scat"].var() / n)
         assert abs(g["n_scat"].mean() - o["n_scat"].mean()) < 4 * se + 1e-9, p.name
 
@@ -143,3 +143,31 @@ def test_batch_with_observers_equals_single_runs(orc, prec):
             ca, cb = c.get_cube(o), single.get_cube(o)
             assert ca.sum() > 0
             assert np.allclose(ca, cb, rtol=1e-5 if prec == "fp32" else 1e-12, atol=0), (p.name, o)
+
+
+def test_batch_autotune_leaves_the_cubes_alone(orc):
+    # the tuner's trial launches deposit peel-off rays; it puts every
+    # member's cubes back, so a later run adds to what they held before
+    from paper_2001_11252_amd import rmc
+    s0 = lambda ln, T: orc.line_quantities(ln, T)["sigma0"]
+    probs = []
+    for i, tau0 in enumerate((2e3, 5e3, 1e3)):
+        pb = W.static_sphere(s0, tau0, 1e4, 1200, level=3, tau_dust=0.3)
+        pb.observers = [W.Observer((0.0, 0.6, 0.8), 8, 8, 10, (-0.5, 0.5, -0.5, 0.5), -25, 25)]
+        pb.seed = 300 + i
+        probs.append(pb)
+    npk = [len(p.sources.x) for p in probs]
+    seeds = [p.seed for p in probs]
+    a = [rmc.Context.from_problem(p, "fp64") for p in probs]
+    rmc.batch_run(a, seeds, npk)
+    before = [c.get_cube(0) for c in a]
+    rmc.batch_autotune(a, seeds, npk, trial_slices=1)
+    for c, cb in zip(a, before):
+        assert np.array_equal(c.get_cube(0), cb)
+    rmc.batch_run(a, seeds, npk)
+    b = [rmc.Context.from_problem(p, "fp64") for p in probs]
+    rmc.batch_run(b, seeds, npk)
+    rmc.batch_run(b, seeds, npk)
+    for ca, cb in zip(a, b):
+        x, y = ca.get_cube(0), cb.get_cube(0)
+        assert x.sum() > 0 and np.allclose(x, y, rtol=1e-12, atol=0)

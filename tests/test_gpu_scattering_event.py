@@ -1,0 +1,91 @@
+"""One resonant scattering on the GPU (Sect. 3.2.1), from packets stopped
+at their second interaction (RMC_OPT_MAX_EVENTS = 2), in both precisions:
+the recoil denominator of the outgoing-frequency relation per event, and
+the Lya core/wing switch at 0.2 Doppler widths in the atom frame against
+the probability the u_par density gives.  The expected values are the ones
+the oracle's pins use (tests/test_oracle_scattering_event.py), computed
+from the paper's definitions."""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+from paper_2001_11252_amd import workloads as W
+from tests.test_oracle_scattering_event import (C, H_PL, J_MU, _cdf_core, _cdf_wing, _core_probability,
+                                                _invert, _line_consts)
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_first_scatterings(orc, prec, x_in, T, n, seed, phase, recoil):
+    from paper_2001_11252_amd import rmc
+    s0 = lambda ln, TT: orc.line_quantities(ln, TT)["sigma0"]
+    line = replace(W.LYA, phase=phase, recoil=int(recoil))
+    pb = W.static_sphere(s0, 1e10, T, n, level=0, line=line)
+    rng = np.random.default_rng(seed)
+    d = rng.standard_normal((n, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    if prec == "fp32":
+        # float-representable directions, renormalised in double on the device
+        d = d.astype(np.float32).astype(np.float64)
+        d /= np.linalg.norm(d, axis=1)[:, None]
+    pb.sources.dir = d
+    pb.sources.x[:] = x_in
+    ctx = rmc.Context.from_problem(pb, prec, observers=False)
+    ctx.set_option(rmc.OPT_MAX_EVENTS, 2)
+    ctx.run(seed, 0, n)
+    out = ctx.get_packets()
+    assert np.all(out["status"] == rmc.ST_STUCK) and np.all(out["n_scat"] == 1)
+    return d, out["k"], out["x"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("phase,x_in", [(W.PHASE_ISO, 0.0), (W.PHASE_LYA, 0.7)])
+def test_gpu_recoil_follows_the_outgoing_frequency_relation(orc, prec, phase, x_in):
+    T, n, seed = 1e4, 20000, 31
+    kin, k1, x1 = _gpu_first_scatterings(orc, prec, x_in, T, n, seed, phase, True)
+    _, k0, x0 = _gpu_first_scatterings(orc, prec, x_in, T, n, seed, phase, False)
+    assert np.array_equal(k1, k0)
+    mu = np.sum(kin * k1, axis=1)
+    nu0, vth, dnu, m = _line_consts(W.LYA, T)
+    nu_in = nu0 + x_in * dnu
+    r = (1 - mu) * H_PL * nu_in / (m * C * C)
+    x_pred = (x0 - r * nu0 / dnu) / (1 + r)
+    # float path: x in float (the 2.5e-4 shift resolved to ~1%)
+    tol = 1e-10 if prec == "fp64" else 2e-6
+    assert np.max(np.abs(x1 - x_pred)) < tol
+    g_r = H_PL * nu0 / (m * C * vth)
+    shift = x1 - x0
+    assert abs(shift.mean() + g_r * (nu_in / nu0) * np.mean(1 - mu)) < (1e-4 if prec == "fp64" else 1e-2) * g_r
+
+
+def _float_uniform(orc, seed, pid, event, j):
+    # the float path's draw j: word j % 4 of Philox block j / 4, top 23 bits
+    ctr = [pid & 0xFFFFFFFF, pid >> 32, event, j >> 2]
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    w = int(orc.philox(ctr, key)[j & 3])
+    return (2 * (w >> 9) + 1) * 2.0 ** -24
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("T,x_in", [(1e4, 3.0), (10.0, 1.0), (10.0, 2.0)])
+def test_gpu_lya_core_wing_switch(orc, prec, T, x_in):
+    n, seed = 40000, 53 + int(10 * x_in) + int(T)
+    kin, k1, _ = _gpu_first_scatterings(orc, prec, x_in, T, n, seed, W.PHASE_LYA, False)
+    mu = np.sum(kin * k1, axis=1)
+    if prec == "fp64":
+        ru = np.array([orc.uniform(seed, i, 1, J_MU) for i in range(n)])
+        tol = 1e-12
+    else:
+        ru = np.array([_float_uniform(orc, seed, i, 1, J_MU) for i in range(n)])
+        tol = 2e-5
+    mc, mw = _invert(_cdf_core, ru), _invert(_cdf_wing, ru)
+    dc, dw = np.abs(mu - mc), np.abs(mu - mw)
+    ok = np.abs(mc - mw) > 10 * tol
+    assert np.all(np.minimum(dc, dw)[ok] < tol)
+    core = (dc < dw)[ok]
+    nu0, vth, dnu, m = _line_consts(W.LYA, T)
+    a = orc.line_quantities(W.LYA, T)["a"]
+    p = _core_probability(x_in, a, vth / C)
+    f = core.mean()
+    assert abs(f - p) < 3 * np.sqrt(p * (1 - p) / core.size) + 1e-5, (f, p)

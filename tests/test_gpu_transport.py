@@ -288,13 +288,20 @@ def test_slicing_does_not_change_results(rmc, orc, prec):
     b.set_option(rmc.OPT_SLICE_ITERS, 7)
     b.stream_begin(9, 0, 5000)
     steps, work = 0, 0
+    ends = {k: 0 for k in ("emitted", "escaped", "absorbed", "stuck", "peel_dropped")}
     while True:
         sl, rem = b.stream_step()
         steps += 1
         work += sl["scatterings"]
+        # every slice accounts for the packets that ended in it
+        assert sl["escaped"] + sl["absorbed"] + sl["stuck"] == sl["emitted"]
+        for k in ends:
+            ends[k] += sl[k]
         if rem == 0:
             break
     sb = b.stream_end()
+    for k in ends:
+        assert ends[k] == sb[k], k
     pbk = b.get_packets()
     assert steps > 20
     for k in pa:
@@ -482,3 +489,38 @@ def test_error_paths(rmc, orc):
     check_conservation(st, 500)
     assert st["stuck"] > 400
     assert c2.get_packets()["n_scat"].max() <= 49
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_regrouped_rejection_rounds_give_the_same_packets(rmc, orc, prec):
+    # RMC_OPT_REGROUP: one rejection round of the atom-velocity draw per pass
+    # of the transport loop, a rejected round leaving the event pending; the
+    # draws are the same, so every packet, count and deposit is the looping
+    # kernel's.  Lya at 100 K with flows (many wing scatterings, where the
+    # draw takes several rounds), sliced finely so that pending events are
+    # parked between launches, a dusty medium and two observers.
+    pb = W.static_sphere(s0(orc), 3e4, 100.0, 6000, level=4, tau_dust=0.5)
+    pb.gas.v[:] = np.random.default_rng(9).standard_normal((pb.mesh.n, 3)) * 15e5
+    pb.observers = [W.Observer((0.0, 0.0, 1.0), 8, 8, 12, (-0.5, 0.5, -0.5, 0.5), -40, 40),
+                    W.Observer((0.6, 0.0, 0.8), 8, 8, 12, (-0.5, 0.5, -0.5, 0.5), -40, 40)]
+    a = rmc.Context.from_problem(pb, prec)
+    a.set_option(rmc.OPT_REGROUP, 0)
+    a.set_option(rmc.OPT_SLICE_ITERS, 97)
+    sa = a.run(13, 0, 6000)
+    b = rmc.Context.from_problem(pb, prec)
+    b.set_option(rmc.OPT_REGROUP, 1)
+    b.set_option(rmc.OPT_SLICE_ITERS, 97)
+    sb = b.run(13, 0, 6000)
+    pa, pbk = a.get_packets(), b.get_packets()
+    for k in pa:
+        assert np.array_equal(pa[k], pbk[k]), k
+    for k in ("emitted", "escaped", "absorbed", "stuck", "scatterings", "dust_scatterings", "crossings",
+              "peel_rays", "peel_crossings", "peel_dropped"):
+        assert sa[k] == sb[k], k
+    assert sa["scatterings"] > 1e6
+    for o in range(2):
+        ca, cb = a.get_cube(o), b.get_cube(o)
+        assert ca.sum() > 0
+        assert np.allclose(ca, cb, rtol=1e-5 if prec == "fp32" else 1e-12, atol=0)
+    with pytest.raises(rmc.RmcError):
+        b.set_option(rmc.OPT_REGROUP, 2)
