@@ -72,6 +72,36 @@ def measured_traffic(prec):
     return e["bytes_per_launch"]
 
 
+def host_cores():
+    """Host cores this process may run on: the CPU affinity mask, reduced
+    to the cgroup CPU quota when one is set (a container's share of the
+    host), with what nproc, os.cpu_count() and lscpu report."""
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    quota = None
+    try:
+        q, per = open("/sys/fs/cgroup/cpu.max").read().split()[:2]
+        if q != "max":
+            quota = float(q) / float(per)
+    except (OSError, ValueError):
+        pass
+    n = max(1, min(aff, int(quota)) if quota else aff)
+    model = None
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    import subprocess
+    try:
+        nproc = int(subprocess.run(["nproc"], capture_output=True, text=True).stdout.strip())
+    except (OSError, ValueError):
+        nproc = None
+    return n, {"threads": n, "nproc": nproc, "os_cpu_count": os.cpu_count(), "affinity": aff,
+               "cgroup_cpu_quota": quota, "model": model}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,7 +114,15 @@ def parse():
                     help="launches of the untimed FP32/FP64 comparison sample (0: skip)")
     ap.add_argument("--tau0", type=float, default=1e6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-packets", type=int, default=0, help="oracle packets (0: eight per core)")
+    ap.add_argument("--cpu-packets", type=int, default=0,
+                    help="oracle packets, full peel-off rays (0: six per core)")
+    ap.add_argument("--cpu-packets-cut", type=int, default=0,
+                    help="oracle packets with the exp(-tau) = 0 cut (0: 24 per core)")
+    ap.add_argument("--regroup", type=int, default=None, choices=[0, 1],
+                    help="transport loop with one rejection round per pass (1) or the looping draw (0); "
+                         "default: the library's default")
+    ap.add_argument("--complete-run", type=int, default=1,
+                    help="dusty_sphere: also time one complete FP32 run of all queued packets (1) or not (0)")
     ap.add_argument("--only", choices=["fp32", "fp64", "both"], default="both")
     ap.add_argument("--copy-gib", type=float, default=1.0, help="size of the copy used to measure HBM bandwidth")
     ap.add_argument("--workload", choices=["dusty_sphere", "shell", "batch", "adjoint", "core_skip",
@@ -97,6 +135,7 @@ def parse():
     ap.add_argument("--vmax", type=float, default=200.0, help="shell: outflow speed at R (km/s)")
     ap.add_argument("--leaves", type=float, default=2e7, help="adjoint: target leaf count")
     ap.add_argument("--sources", type=int, default=100_000, help="adjoint: sources (100 rays each)")
+    ap.add_argument("--galaxy-cache", default=None, help="adjoint: .npz file holding the generated galaxy")
     return ap.parse_args()
 
 
@@ -134,7 +173,7 @@ def oracle_transport_baseline(a, probs, packets_each, max_events):
     if a.no_cpu_baseline:
         return None
     from oracle import oracle as O
-    cores = max(1, min(16, os.cpu_count() or 1))
+    cores = host_cores()[0]
     scat, dt, setup = 0, 0.0, 0.0
     for p in probs:
         n = min(packets_each, len(p.sources.x))
@@ -176,7 +215,7 @@ def bench_shell(a, rmc, W):
     ctx.stream_begin(pb.seed, 0, 10_000_000)
     wall, tot, kms = stream_rate(ctx, a.steps, a.warmup, "shell fp32")
     ctx.close()
-    cpu = oracle_transport_baseline(a, [pb], 8 * max(1, min(16, os.cpu_count() or 1)), 20000)
+    cpu = oracle_transport_baseline(a, [pb], 8 * host_cores()[0], 20000)
     return _line("scatterings/s + ray-cell crossings/s (1 GPU), FP32", tot["scatterings"] / wall, "scatterings/s",
                  a.steps, a.warmup, 1e3 * wall / a.steps, "f32",
                  {"workload": f"outflowing_shell_vmax{int(a.vmax)}_tau1e7_{pb.mesh.n}_leaves_3x256x256x200",
@@ -254,7 +293,7 @@ def bench_core_skip(a, rmc, W):
     cpu = None
     if not a.no_cpu_baseline:
         from oracle import oracle as O
-        cores = max(1, min(16, os.cpu_count() or 1))
+        cores = host_cores()[0]
         m = 8 * cores
         t0 = time.perf_counter()
         r = O.run(pb, pb.seed, first=0, n=m, threads=cores, core_skip=(1.0, 0.2))
@@ -345,7 +384,7 @@ def bench_voigt_accuracy(a, rmc, W):
 def oracle_voigt_baseline(pb):
     """The oracle with the accurate H on a bounded sample of the same slab."""
     from oracle import oracle as O
-    cores = max(1, min(16, os.cpu_count() or 1))
+    cores = host_cores()[0]
     m, ev = 2 * cores, 20000
     t0 = time.perf_counter()
     r = O.run(pb, pb.seed, first=0, n=m, threads=cores, max_events=ev, with_cubes=False, voigt_exact=True)
@@ -388,7 +427,7 @@ def bench_multi_species(a, rmc, W):
     cpu = None
     if not a.no_cpu_baseline:
         from oracle import oracle as O
-        cores = max(1, min(16, os.cpu_count() or 1))
+        cores = host_cores()[0]
         m = 250000 * cores     # a few seconds of the oracle
         pw = W.feii_wind(rmc.sigma0, m)
         t1 = time.perf_counter()
@@ -437,7 +476,7 @@ def bench_c1_slab(a, rmc, W):
     wall = time.perf_counter() - t0
     out = ctx.get_packets()
     ctx.close()
-    cores = max(1, min(16, os.cpu_count() or 1))
+    cores = host_cores()[0]
     t1 = time.perf_counter()
     ref = O.run(pb, pb.seed, threads=cores, with_cubes=False)
     dt = time.perf_counter() - t1
@@ -518,6 +557,31 @@ def bench_upar_cost(a, rmc, W):
                                "sample": "20,000 u_parallel draws per grid point on one core (geometric mean)"})
 
 
+def galaxy_problem(a, rmc, W):
+    """The C5 galaxy (a few minutes to generate at full size); with
+    --galaxy-cache PATH it is read from / written to an .npz file, so that
+    several profiler passes of one session generate it once."""
+    import numpy as np
+    if a.galaxy_cache and os.path.exists(a.galaxy_cache):
+        z = np.load(a.galaxy_cache)
+        mesh = W.Mesh(z["level"], z["ijk"])
+        gas = W.Gas(z["n_hi"], z["T"], z["v"], z["kappa_d"])
+        nx = int(z["nx"])
+        obs = [W.Observer((0.0, 0.0, 1.0), nx, nx, 1, (-0.5, 0.5, -0.5, 0.5), -1e30, 1e30)]
+        pb = W.Problem("c5_galaxy", mesh, gas, W.Domain(W.DOM_BOX, (0.0, 0.0, 0.0, 0.0)), [W.LYA], 1e4,
+                       W.Dust(0.32, 0.73), W.Sources(z["src"], np.zeros(len(z["src"]))), obs)
+        pb.meta.update(rays=dict(orig=z["orig"], x_ext=z["x_ext"], w=z["w"]), grad_image=z["G"])
+        return pb
+    pb = W.c5_galaxy(rmc.sigma0, target_leaves=a.leaves, n_sources=a.sources,
+                     log=lambda m: print("# " + m, file=sys.stderr, flush=True))
+    if a.galaxy_cache:
+        r = pb.meta["rays"]
+        np.savez(a.galaxy_cache, level=pb.mesh.level, ijk=pb.mesh.ijk, n_hi=pb.gas.n_hi, T=pb.gas.T, v=pb.gas.v,
+                 kappa_d=pb.gas.kappa_d, src=pb.sources.pos, orig=r["orig"], x_ext=r["x_ext"], w=r["w"],
+                 G=pb.meta["grad_image"], nx=pb.observers[0].nx)
+    return pb
+
+
 def bench_adjoint(a, rmc, W):
     """C5: galaxy-like adaptive mesh (~2e7 leaves), 1e7 fixed rays toward
     +z, 512^2 image; one forward image and one backward (gradients per
@@ -525,8 +589,7 @@ def bench_adjoint(a, rmc, W):
     crossing lists (the replaying backward is measured beside it)."""
     import torch
     t0 = time.perf_counter()
-    pb = W.c5_galaxy(rmc.sigma0, target_leaves=a.leaves, n_sources=a.sources,
-                     log=lambda m: print("# " + m, file=sys.stderr, flush=True))
+    pb = galaxy_problem(a, rmc, W)
     r = pb.meta["rays"]
     print(f"# adjoint: {pb.mesh.n} leaves, {len(r['x_ext'])} rays, generated in {time.perf_counter() - t0:.0f} s",
           file=sys.stderr, flush=True)
@@ -593,7 +656,7 @@ def bench_adjoint(a, rmc, W):
         # subtracted
         from oracle import oracle as O
         import numpy as np
-        cores = max(1, min(16, os.cpu_count() or 1))
+        cores = host_cores()[0]
         ns = 2_000_000
         ob = pb.observers[0]
         t0 = time.perf_counter()
@@ -618,6 +681,117 @@ def bench_adjoint(a, rmc, W):
                  replay={"crossings_per_s": 2.0 * rf * n / t_rep, "ms_per_step": 1e3 * t_rep / n,
                          "forward_ms": rmf, "backward_ms": rmb, "forward_GBps_algorithmic": gbs_rf},
                  cpu_baseline=cpu)
+
+
+def complete_run(pb, P, rmc, torch, regroup=None):
+    """One complete FP32 run of all P queued packets (every walk to its end,
+    the tail of the longest walks included), timed by the wall clock and by
+    the library's events; its outputs feed the comparison with the oracle."""
+    ctx = rmc.Context.from_problem(pb, "fp32")
+    ctx.set_stream(torch.cuda.current_stream())
+    if regroup is not None:
+        ctx.set_option(rmc.OPT_REGROUP, regroup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = ctx.run(pb.seed, 0, P)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out = ctx.get_packets()
+    out["cube"] = ctx.get_cube(0)
+    ctx.close()
+    print(f"# complete fp32 run: {P} packets in {wall:.2f} s, {st}", file=sys.stderr, flush=True)
+    rec = {"packets": P, "seconds": wall, "scatterings": st["scatterings"],
+           "scatterings_per_s": st["scatterings"] / wall,
+           "crossings_per_s": (st["crossings"] + st["peel_crossings"]) / wall,
+           "device_ms": {"transport": st["kernel_ms"], "ray_cast_pass": st["peel_pass_ms"]},
+           "escaped": st["escaped"], "absorbed": st["absorbed"], "stuck": st["stuck"]}
+    return rec, out
+
+
+def fp32_against_oracle(g, o, pb):
+    """Each output of the complete FP32 run against the oracle's packets
+    (a prefix of the same packet list, FP64): the value on each side, the
+    relative difference and its z from the two sides' Monte Carlo errors
+    (the oracle's, from 8 equal slices of its sample, dominates)."""
+    import numpy as np
+    from scipy import stats
+    n_o = len(o["status"])
+    k = len(o["cube_slices"])
+    edges = np.linspace(0, n_o, k + 1).astype(int)
+    sl = [np.arange(lo, hi) for lo, hi in zip(edges[:-1], edges[1:])]
+    res = {"oracle_packets": n_o, "gpu_packets": len(g["status"])}
+
+    def entry(vg, vo_slices, vg_se=0.0):
+        vo_slices = np.asarray(vo_slices, dtype=float)
+        vo = vo_slices.mean()
+        se = np.sqrt(vo_slices.var(ddof=1) / k + vg_se ** 2)
+        return {"fp32": float(vg), "oracle": float(vo), "rel_diff": float(vg / vo - 1) if vo else None,
+                "z": float((vg - vo) / se) if se > 0 else None}
+
+    eg = g["status"] == 1
+    res["escape_fraction"] = entry(eg.mean(), [(o["status"][i] == 1).mean() for i in sl],
+                                   np.sqrt(eg.mean() * (1 - eg.mean()) / len(eg)))
+    res["absorbed_fraction"] = entry((g["status"] == 2).mean(), [(o["status"][i] == 2).mean() for i in sl])
+    res["mean_line_scatterings"] = entry(g["n_scat"].mean(), [o["n_scat"][i].mean() for i in sl],
+                                         g["n_scat"].std() / np.sqrt(len(eg)))
+    xg, xo = g["x"][eg], o["x"][o["status"] == 1]
+    if len(xo) >= 20:
+        res["escaped_x_ks_p"] = float(stats.ks_2samp(xg, xo).pvalue)
+        res["escaped_x_mean"] = entry(xg.mean(), [o["x"][i][o["status"][i] == 1].mean() for i in sl])
+        res["escaped_abs_x_mean"] = entry(np.abs(xg).mean(),
+                                          [np.abs(o["x"][i][o["status"][i] == 1]).mean() for i in sl])
+    # the peel-off cube per emitted packet: total, spectrum and image
+    # moments, against the oracle's per-slice cubes
+    res["cube"] = cube_moments(g["cube"] / len(g["status"]), o, pb)
+    return res
+
+
+def oracle_slices(O, pb, n, cores, k):
+    """The oracle on packets [0, n) in k consecutive slices (peel-off rays
+    stopped where exp(-tau) = 0): packet records, per-slice cubes per
+    packet, summed stats and the transport time (each call's set-up, the
+    leaf hash map, measured with a one-event call and subtracted)."""
+    import numpy as np
+    t0 = time.perf_counter()
+    O.run(pb, pb.seed, first=0, n=1, threads=1, max_events=1, with_cubes=False)
+    t_set = time.perf_counter() - t0
+    edges = np.linspace(0, n, k + 1).astype(int)
+    recs, cubes, stats, secs = [], [], {}, 0.0
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        t0 = time.perf_counter()
+        r = O.run(pb, pb.seed, first=int(lo), n=int(hi - lo), threads=cores, peel_tau_cut=746.0)
+        secs += max(time.perf_counter() - t0 - t_set, 1e-9)
+        recs.append(r)
+        cubes.append(r["cubes"][0] / (hi - lo))
+        for key, v in r["stats"].items():
+            stats[key] = stats.get(key, 0) + v
+    out = {key: np.concatenate([r[key] for r in recs]) for key in ("status", "x", "n_scat")}
+    out.update(cube_slices=cubes, stats=stats, seconds=secs)
+    return out
+
+
+def cube_moments(cg, o, pb):
+    """Per-packet cube totals and the mean |x| and mean projected radius of
+    the peel-off flux, GPU (complete run) against the oracle slices."""
+    import numpy as np
+    ob = pb.observers[0]
+    xs = ob.x_min + (np.arange(ob.nbins) + 0.5) * (ob.x_max - ob.x_min) / ob.nbins
+    yy, xx = np.mgrid[0:ob.ny, 0:ob.nx]
+    r = np.hypot((xx + 0.5) / ob.nx - 0.5, (yy + 0.5) / ob.ny - 0.5)
+
+    def mom(c):
+        t = c.sum()
+        return t, (c.sum(axis=(0, 1)) * np.abs(xs)).sum() / t, (c.sum(axis=2) * r).sum() / t
+
+    g = mom(cg)
+    vals = np.array([mom(oc) for oc in o["cube_slices"]])
+    out = {}
+    for j, name in enumerate(("total_per_packet", "mean_abs_x", "mean_projected_radius")):
+        v = vals[:, j]
+        se = np.sqrt(v.var(ddof=1) / len(v))
+        out[name] = {"fp32": float(g[j]), "oracle": float(v.mean()), "rel_diff": float(g[j] / v.mean() - 1),
+                     "z": float((g[j] - v.mean()) / se) if se > 0 else None}
+    return out
 
 
 def matched_spectra(early, launches):
@@ -682,6 +856,8 @@ def main():
         setup[prec] = time.perf_counter() - t0
         ctx.set_stream(torch.cuda.current_stream())
         ctx.set_option(rmc.OPT_SLICE_ITERS, a.slice)
+        if a.regroup is not None:
+            ctx.set_option(rmc.OPT_REGROUP, a.regroup)
         # a first stream, abandoned after two launches, lets the peel-off
         # queue grow to its working size (it grows after a launch in which
         # a wave ended its slice early for room) before the measured stream
@@ -741,8 +917,11 @@ def main():
     print(f"# copy: {copy_GBps:.1f} GB/s (read+write of {a.copy_gib} GiB)", file=sys.stderr, flush=True)
 
     res = {}
+    full = full_out = None
     if a.only in ("fp32", "both"):
         res["fp32"] = measure("fp32", steps)
+        if a.complete_run:
+            full, full_out = complete_run(pb, P, rmc, torch, a.regroup)
     if a.only in ("fp64", "both"):
         res["fp64"] = measure("fp64", a.fp64_steps if a.only == "both" else steps)
     head = "fp32" if "fp32" in res else "fp64"
@@ -757,15 +936,21 @@ def main():
     # device duration; the rest of the peel-off rays is the ray-cast pass
     avg_ms = sum(kms) / nsteps
     traffic = measured_traffic(head)
-    # the same launch against the HBM roof: algorithmic bytes (a leaf record
-    # and a node entry per transport segment; events inside a leaf and the
-    # peel-off tests use the record the lane holds) and, when the profiler's
-    # counters match these sources, the bytes moved
-    alg_bytes = tot["crossings"] * BYTES_PER_CROSSING[head] / nsteps
-    hbm = {"peak_GBps": 8000.0, "algorithmic_GBps": alg_bytes / (avg_ms * 1e-3) / 1e9,
-           "measured_GBps": None if traffic is None else traffic / (avg_ms * 1e-3) / 1e9}
+    # the step against the HBM roof, one definition: algorithmic bytes = a
+    # leaf record and a node entry per ray-cell crossing, transport and
+    # peel-off alike (28 B float, 52 B double); events inside a leaf use the
+    # record the lane holds (0 B); over the step's wall time.  Beside it,
+    # when the profiler's counters match these sources, the bytes the
+    # transport launch moved over its own duration.
+    alg_bytes = cross * BYTES_PER_CROSSING[head] / nsteps
+    hbm = {"peak_GBps": 8000.0,
+           "definition": "ray-cell crossings (transport + peel-off) x (leaf record + node entry) per step "
+                         "wall time; scatterings use the register-held record",
+           "algorithmic_bytes_per_step": alg_bytes,
+           "algorithmic_GBps": alg_bytes / (wall / nsteps) / 1e9,
+           "transport_launch_measured_GBps": None if traffic is None else traffic / (avg_ms * 1e-3) / 1e9}
     hbm["frac_algorithmic"] = hbm["algorithmic_GBps"] / 8000.0
-    hbm["frac_measured"] = None if traffic is None else hbm["measured_GBps"] / 8000.0
+    hbm["frac_measured"] = None if traffic is None else hbm["transport_launch_measured_GBps"] / 8000.0
     transport_cross = tot["crossings"] + tot["peel_rays"]
     flops_per_launch = (FLOP_PER_SCATTERING * tot["scatterings"] + FLOP_PER_CROSSING * transport_cross) / nsteps
     achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
@@ -781,7 +966,7 @@ def main():
                       "slices_cut": t["slices_cut"],
                       "peel_pass_crossings_per_s": pass_cross / max(t["peel_pass_ms"] * 1e-3, 1e-30),
                       "hbm_GBps_algorithmic": (t["crossings"] + t["peel_crossings"]) * BYTES_PER_CROSSING[prec]
-                      / ((sum(k) + t["peel_pass_ms"]) * 1e-3) / 1e9,
+                      / w / 1e9,
                       "packets_finished": t["emitted"]}
     line = {
         "metric": "scatterings/s + ray-cell crossings/s (1 GPU), FP32 vs FP64 at matched spectra",
@@ -799,7 +984,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "dusty_sphere_tau1e6_T1e4_287k_leaves_peel_128x128x100",
                    "tau0": a.tau0, "packets_queued": P, "iterations_per_lane_per_step": a.slice,
-                   "leaves": int(pb.mesh.n), "observer": "+z 128x128x100", "parallelism": "none"},
+                   "leaves": int(pb.mesh.n), "observer": "+z 128x128x100", "parallelism": "none",
+                   "regroup": a.regroup},
         "precisions": side,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK[head], "unit": "TFLOP/s",
                      "frac": achieved / PEAK[head], "traffic": traffic,
@@ -812,17 +998,36 @@ def main():
     }
     if len(early) == 2:
         line["matched_spectra"] = matched_spectra(early, a.match_launches)
+    if full is not None:
+        line["complete_run"] = full
     if not a.no_cpu_baseline:
         from oracle import oracle as O
-        cores = max(1, min(16, os.cpu_count() or 1))
-        n_cpu = a.cpu_packets or 12 * cores
+        cores, host = host_cores()
+        # the oracle as it stands: every peel-off ray walked to the border
+        n_cpu = a.cpu_packets or 6 * cores
         t0 = time.perf_counter()
         r = O.run(pb, pb.seed, first=0, n=n_cpu, threads=cores)
         dt = time.perf_counter() - t0
-        line["cpu_baseline"] = {"value": r["stats"]["scatterings"] / dt, "unit": "scatterings/s", "cores": cores,
-                                "kind": "oracle",
-                                "sample": f"{n_cpu} packets of the same workload (FP64 oracle, full peel-off rays), "
-                                          f"{r['stats']['scatterings']} scatterings in {dt:.1f} s"}
+        st = r["stats"]
+        # like for like: peel-off rays stopped where exp(-tau) is exactly 0,
+        # as the GPU stops them (the same deposits); its packets are also
+        # the oracle sample the FP32 outputs are compared with
+        n_cut = a.cpu_packets_cut or 24 * cores
+        rc = oracle_slices(O, pb, n_cut, cores, 8)
+        dc, sc = rc["seconds"], rc["stats"]
+        line["cpu_baseline"] = {
+            "value": st["scatterings"] / dt, "unit": "scatterings/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n_cpu} packets of the same workload (FP64 oracle, every peel-off ray walked to the "
+                      f"border), {st['scatterings']} scatterings in {dt:.1f} s",
+            "crossings_per_s": (st["crossings"] + st["peel_crossings"]) / dt,
+            "like_for_like": {"scatterings_per_s": sc["scatterings"] / dc,
+                              "crossings_per_s": (sc["crossings"] + sc["peel_crossings"]) / dc,
+                              "sample": f"{n_cut} packets, peel-off rays stopped once tau >= 746 "
+                                        f"(exp(-tau) = 0 in double, deposits unchanged), "
+                                        f"{sc['scatterings']} scatterings in {dc:.1f} s"},
+            "host": host}
+        if full_out is not None:
+            line["fp32_vs_oracle"] = fp32_against_oracle(full_out, rc, pb)
     print(json.dumps(line), flush=True)
 
 
