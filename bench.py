@@ -57,12 +57,12 @@ def kernel_source_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(prec):
-    """HBM bytes per transport launch from the profiler's FETCH_SIZE and
-    WRITE_SIZE counters (profiles/transport_traffic.json), or None if the
-    kernel sources changed since they were taken."""
+def measured_traffic(prec, name="transport_traffic.json"):
+    """HBM bytes per launch of a kernel from the profiler's FETCH_SIZE and
+    WRITE_SIZE counters (profiles/<name>, entry prec), or None if the kernel
+    sources changed since they were taken."""
     import json as _j
-    f = os.path.join(ROOT, "profiles", "transport_traffic.json")
+    f = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(f):
         return None
     d = _j.load(open(f))
@@ -557,6 +557,28 @@ def bench_upar_cost(a, rmc, W):
                                "sample": "20,000 u_parallel draws per grid point on one core (geometric mean)"})
 
 
+def measure_copy(a):
+    """Achievable HBM bandwidth: a plain device copy (read + write) of known
+    size; the same kernel calibrates the profiler's traffic counters."""
+    import torch
+    n_el = int(a.copy_gib * (1 << 30)) // 4
+    src = torch.ones(n_el, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbps = 5 * 2 * n_el * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    print(f"# copy: {gbps:.1f} GB/s (read+write of {a.copy_gib} GiB)", file=sys.stderr, flush=True)
+    return gbps
+
+
 def galaxy_problem(a, rmc, W):
     """The C5 galaxy (a few minutes to generate at full size); with
     --galaxy-cache PATH it is read from / written to an .npz file, so that
@@ -588,6 +610,7 @@ def bench_adjoint(a, rmc, W):
     leaf) per step, FP32 leaf records; the backward reads the forward's
     crossing lists (the replaying backward is measured beside it)."""
     import torch
+    copy_GBps = measure_copy(a)
     t0 = time.perf_counter()
     pb = galaxy_problem(a, rmc, W)
     r = pb.meta["rays"]
@@ -640,12 +663,14 @@ def bench_adjoint(a, rmc, W):
     gbs_tf = tf * (28.0 + 8.0) / (tmf * 1e-3) / 1e9
     gbs_tb = tb * (8.0 + 24.0 + 48.0) / (tmb * 1e-3) / 1e9
     gbs_rf = rf * 28.0 / (rmf * 1e-3) / 1e9
+    tr_f = measured_traffic("k_image_fwd_tape", "adjoint_traffic.json")
+    tr_b = measured_traffic("k_image_bwd_tape", "adjoint_traffic.json")
     if tmf >= tmb:
         roof = {"bound": "hbm", "achieved": gbs_tf, "peak": 8000.0, "unit": "GB/s", "frac": gbs_tf / 8000.0,
-                "traffic": None, "kernel": "k_image_fwd_tape<float>"}
+                "traffic": tr_f, "kernel": "k_image_fwd_tape<float>"}
     else:
         roof = {"bound": "hbm", "achieved": gbs_tb, "peak": 8000.0, "unit": "GB/s", "frac": gbs_tb / 8000.0,
-                "traffic": None, "kernel": "k_image_bwd_tape<float>"}
+                "traffic": tr_b, "kernel": "k_image_bwd_tape<float>"}
     ctx.close()
     cpu = None
     if not a.no_cpu_baseline:
@@ -676,8 +701,11 @@ def bench_adjoint(a, rmc, W):
                  {"workload": f"galaxy_{pb.mesh.n}_leaves_{len(r['x_ext'])}_rays_512x512", "parallelism": "none",
                   "backward": "tape"},
                  roof,
-                 forward={"crossings_per_launch": tf, "ms": tmf, "GBps_algorithmic": gbs_tf},
-                 backward={"crossings_per_launch": tb, "ms": tmb, "GBps_algorithmic": gbs_tb},
+                 forward={"crossings_per_launch": tf, "ms": tmf, "GBps_algorithmic": gbs_tf,
+                          "GBps_measured": None if tr_f is None else tr_f / (tmf * 1e-3) / 1e9},
+                 backward={"crossings_per_launch": tb, "ms": tmb, "GBps_algorithmic": gbs_tb,
+                           "GBps_measured": None if tr_b is None else tr_b / (tmb * 1e-3) / 1e9},
+                 hbm_copy_GBps=copy_GBps,
                  replay={"crossings_per_s": 2.0 * rf * n / t_rep, "ms_per_step": 1e3 * t_rep / n,
                          "forward_ms": rmf, "backward_ms": rmb, "forward_GBps_algorithmic": gbs_rf},
                  cpu_baseline=cpu)
@@ -887,6 +915,9 @@ def main():
             # walks first); launches short enough that no wave runs out of
             # queue room, which would end its slice early
             ctx.set_option(rmc.OPT_SLICE_ITERS, MATCH_SLICE)
+            # the same loop in both precisions, so that equal iterations
+            # select the packets alike
+            ctx.set_option(rmc.OPT_REGROUP, 0)
             ctx.stream_begin(pb.seed, 0, P)
             cut = 0
             for _ in range(a.match_launches):
@@ -898,23 +929,7 @@ def main():
         ctx.close()
         return wall, tot, kms
 
-    # achievable HBM bandwidth: a plain device copy (read + write) of known
-    # size; the same kernel calibrates the profiler's traffic counters
-    n_el = int(a.copy_gib * (1 << 30)) // 4
-    src = torch.ones(n_el, dtype=torch.float32, device="cuda")
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(5):
-        dst.copy_(src)
-    e1.record()
-    torch.cuda.synchronize()
-    copy_GBps = 5 * 2 * n_el * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del src, dst
-    torch.cuda.empty_cache()
-    print(f"# copy: {copy_GBps:.1f} GB/s (read+write of {a.copy_gib} GiB)", file=sys.stderr, flush=True)
+    copy_GBps = measure_copy(a)
 
     res = {}
     full = full_out = None

@@ -62,6 +62,10 @@ def test_fp32_matches_fp64_at_full_size(orc, sphere):
     for prec in ("fp32", "fp64"):
         c = rmc.Context.from_problem(pb, prec)
         c.set_option(rmc.OPT_SLICE_ITERS, 1024)
+        # the same loop in both precisions (a pending rejection round takes
+        # a loop iteration with RMC_OPT_REGROUP, which would select other
+        # packets into the sample below)
+        c.set_option(rmc.OPT_REGROUP, 0)
         # a first stream, abandoned after two launches, grows the peel-off
         # queue to its working size (the first launch of a fresh context can
         # end slices early for room)
