@@ -290,6 +290,17 @@ rmc_status rmc_get_packets(rmc_ctx *ctx, int32_t *status, double *x_out, double 
 /* Histogram (counts) of x_ext of the escaped packets of the last run. */
 rmc_status rmc_get_spectrum(rmc_ctx *ctx, int nbins, double x_min, double x_max, double *hist,
                             int mem);
+/* rmc_get_spectrum for callers that cannot allocate device memory (code
+ * that runs between graph replays, tight serving loops, harnesses that
+ * forbid hipMalloc): the same counts, written as doubles to hist, a device
+ * pointer to nbins doubles on the context's device, on the context's
+ * stream.  The counting goes through a fixed array of 65536 64-bit counters
+ * that each device holds for the life of the process, so nbins is at most
+ * 65536 (RMC_EINVAL beyond); the call allocates and frees nothing.  Every
+ * call on one device shares that array and clears it first: calls that
+ * overlap on one GPU (other threads, or contexts on other streams) race,
+ * and the caller must order them.  Returns once hist is written. */
+rmc_status rmc_get_spectrum_noalloc(rmc_ctx *ctx, int nbins, double x_min, double x_max, double *hist);
 /* Peel-off cube of observer `id`, [ny][nx][nbins], as RMC_F32 or RMC_F64. */
 rmc_status rmc_get_cube(rmc_ctx *ctx, int id, void *out, int dtype, int mem);
 

@@ -131,6 +131,7 @@ struct rmc_ctx {
   ProblemK pb_host;
   int64_t starts_host[2];
   int num_cus = 0;
+  unsigned long long *scratch = nullptr;   // this device's fixed counters (no-allocation spectrum)
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
   // batch launches
   DevBuf b_probs, b_starts;
@@ -556,6 +557,7 @@ rmc_status rmc_create(rmc_ctx **out, int device, int precision) {
   c->regroup = precision == RMC_FP64 ? 1 : 0;
   if (hipSetDevice(device) != hipSuccess ||
       hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+      scratch_address(device, &c->scratch) != hipSuccess ||
       hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
       hipEventCreate(&c->ev2) != hipSuccess) {
     for (hipEvent_t e : {c->ev0, c->ev1, c->ev2})
@@ -1249,6 +1251,23 @@ rmc_status rmc_get_spectrum(rmc_ctx *c, int nbins, double x_min, double x_max, d
   HIPCHK(c, launch_u64_to_f64(c->tmp1.as<unsigned long long>(), dst, nbins, c->stream));
   if (mem != RMC_DEVICE)
     HIPCHK(c, hipMemcpyAsync(hist, c->tmp2.p, (size_t)nbins * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return RMC_OK;
+}
+
+rmc_status rmc_get_spectrum_noalloc(rmc_ctx *c, int nbins, double x_min, double x_max, double *hist) {
+  rmc_status r = enter(c);
+  if (r) return r;
+  if (nbins <= 0 || nbins > NOALLOC_MAX_BINS)
+    return fail(c, RMC_EINVAL, "nbins %d outside [1, %d], the fixed counter array of this call", nbins,
+                NOALLOC_MAX_BINS);
+  if (!(x_max > x_min) || !hist) return fail(c, RMC_EINVAL, "bad histogram");
+  if (c->last_n <= 0) return fail(c, RMC_ESTATE, "no run yet");
+  // the counters keep the last call's values: cleared by a fill kernel
+  HIPCHK(c, launch_fill_u64(c->scratch, nbins, 0ull, c->stream));
+  HIPCHK(c, launch_hist(c->last_n, c->o_status.as<int32_t>(), c->o_x.as<double>(), nbins, x_min, x_max - x_min,
+                        c->scratch, c->stream));
+  HIPCHK(c, launch_u64_to_f64(c->scratch, hist, nbins, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return RMC_OK;
 }

@@ -15,6 +15,8 @@
 // k_image_fwd   peel-off image of fixed rays
 // k_image_bwd   its adjoint with respect to per-leaf n_HI, kappa_d, v_los
 // k_hist        spectrum of escaped packets
+#include <mutex>
+
 #include "rmc_device.h"
 #include "rmc_launch.h"
 
@@ -1605,6 +1607,29 @@ __global__ void k_f32_to_f64(const float *a, double *b, int64_t n) {
 __global__ void k_f64_to_f32(const double *a, float *b, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) b[i] = (float)a[i];
+}
+
+// ------------------------------------------ fixed scratch (no allocation)
+// Histogram counts of rmc_get_spectrum_noalloc: a file-scope device array
+// of NOALLOC_MAX_BINS counters (each device the library runs on holds its
+// own copy until the process ends).  Host code never uses the array's name
+// as an address: scratch_address() asks the runtime for the current
+// device's copy once and keeps it.
+static __device__ __align__(256) unsigned long long scratch[NOALLOC_MAX_BINS];
+
+hipError_t scratch_address(int device, unsigned long long **out) {
+  static std::mutex mu;
+  static unsigned long long *addr[256] = {};
+  if (device < 0 || device >= 256) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = (unsigned long long *)p;
+  }
+  *out = addr[device];
+  return hipSuccess;
 }
 
 // ------------------------------------------------------------- launchers

@@ -63,6 +63,11 @@ hipError_t launch_check_sources(int64_t n, const double *pos, const double *dir,
                                 unsigned long long *bad, hipStream_t st);
 // g_v[3n] = g_vlos[n] k (velocity-vector gradient from the line-of-sight one)
 hipError_t launch_vlos_to_v(int64_t n, const double *g_vlos, const double k[3], double *g_v, hipStream_t st);
+// Counters the allocation-free spectrum call uses: the current device's
+// copy of a fixed array of NOALLOC_MAX_BINS unsigned 64-bit counters
+// (hipGetSymbolAddress, once per device; call with that device current).
+constexpr int NOALLOC_MAX_BINS = 1 << 16;
+hipError_t scratch_address(int device, unsigned long long **out);
 hipError_t launch_hist(int64_t n, const int32_t *status, const double *x, int nbins, double x_min, double span,
                        unsigned long long *h, hipStream_t st);
 hipError_t launch_batch_reset(const ProblemK *d_probs, int n, unsigned long long *d_next, hipStream_t st);

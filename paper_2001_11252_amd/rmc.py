@@ -92,6 +92,7 @@ _sig = {
     "rmc_stream_end": (C.c_int, [_P, C.POINTER(RmcRunStats)]),
     "rmc_get_packets": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, C.c_int]),
     "rmc_get_spectrum": (C.c_int, [_P, C.c_int, C.c_double, C.c_double, _P, C.c_int]),
+    "rmc_get_spectrum_noalloc": (C.c_int, [_P, C.c_int, C.c_double, C.c_double, _P]),
     "rmc_get_cube": (C.c_int, [_P, C.c_int, _P, C.c_int, C.c_int]),
     "rmc_trace_cells": (C.c_int, [_P, _i64, _P, _P, C.c_int32, _P, _P, _P, C.c_int]),
     "rmc_tau": (C.c_int, [_P, _i64, _P, _P, _P, _P, C.c_int]),
