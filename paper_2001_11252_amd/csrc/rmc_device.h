@@ -182,7 +182,8 @@ enum {
 
 // Uniforms of one event.  Double: draw j uses the word pair (2(j%2),
 // 2(j%2)+1) of block j/2 and returns (2m+1) 2^-53 with m the top 52 bits.
-// Float: draw j uses word j%4 of block j/4 and returns (2m+1) 2^-24 with m
+// Float: draw j uses word p%4 of block p/4, p = float_word(j) (below), and
+// returns (2m+1) 2^-24 with m
 // the top 23 bits.  Both lie strictly inside (0,1).
 template <class R> struct EventRng;
 
@@ -209,6 +210,16 @@ template <> struct EventRng<double> {
   __device__ double u_small(uint32_t j) { return u(j); }
 };
 
+// Float: the slots of the first two blocks are placed by when an event
+// uses them, so that with one block kept each block of an event is
+// computed once: block 0 holds the channel, tau_event and the first
+// rejection round (or the albedo test, or the |x| >= 8 Gaussian pair),
+// block 1 the perpendicular velocities and the new direction; slot j sits
+// at word float_word(j) (nibble j of 0x32541760 for j < 8, j beyond).
+__device__ __forceinline__ uint32_t float_word(uint32_t j) {
+  return j < 8u ? (0x32541760u >> (4u * j)) & 15u : j;
+}
+
 template <> struct EventRng<float> {
   uint2 key;
   uint32_t plo, phi, ev;
@@ -217,30 +228,22 @@ template <> struct EventRng<float> {
   __device__ EventRng(uint64_t seed, uint64_t pid, uint32_t event)
       : key(make_uint2((uint32_t)seed, (uint32_t)(seed >> 32))), plo((uint32_t)pid),
         phi((uint32_t)(pid >> 32)), ev(event), cur(0xffffffffu) {}
-  __device__ float u(uint32_t j) {
-    const uint32_t b = j >> 2;
+  __device__ uint32_t word(uint32_t j) {
+    const uint32_t p = float_word(j);
+    const uint32_t b = p >> 2;
     if (b != cur) {
       w = philox4x32_10(make_uint4(plo, phi, ev, b), key);
       cur = b;
     }
-    const uint32_t q = j & 3;
-    const uint32_t x = q == 0 ? w.x : (q == 1 ? w.y : (q == 2 ? w.z : w.w));
-    return (float)(2u * (x >> 9) + 1u) * 0x1p-24f;
+    const uint32_t q = p & 3;
+    return q == 0 ? w.x : (q == 1 ? w.y : (q == 2 ? w.z : w.w));
   }
+  __device__ float u(uint32_t j) { return (float)(2u * (word(j) >> 9) + 1u) * 0x1p-24f; }
   // Draw j for a comparison with a probability that may be far below the
   // 2^-23 spacing of u (kappa_d / kappa in an optically thick line core):
   // the whole 32-bit word, whose conversion is exact below 2^24, so near
   // zero the draw is resolved to 2^-32.  Lies in [0, 1].
-  __device__ float u_small(uint32_t j) {
-    const uint32_t b = j >> 2;
-    if (b != cur) {
-      w = philox4x32_10(make_uint4(plo, phi, ev, b), key);
-      cur = b;
-    }
-    const uint32_t q = j & 3;
-    const uint32_t x = q == 0 ? w.x : (q == 1 ? w.y : (q == 2 ? w.z : w.w));
-    return (float)x * 0x1p-32f;
-  }
+  __device__ float u_small(uint32_t j) { return (float)word(j) * 0x1p-32f; }
 };
 
 // ------------------------------------------------------------ math policy

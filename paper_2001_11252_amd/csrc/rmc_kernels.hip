@@ -507,6 +507,13 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R, NL> &o, in
   EventRng<R> rng(pb.seed, (uint64_t)s.pid, s.event);
   // kappa_d / kappa reaches ~1e-8 in optically thick line cores
   R r = rng.u_small(J_CHANNEL) * o.ktot;
+  // the generator keeps one Philox block: the draw of the channel's block
+  // that the event uses last is taken now, so that no block of the event is
+  // computed twice (tau_event in the float layout, the scattering angle in
+  // the double one)
+  const R r_late = rng.u(sizeof(R) == 4 ? J_TAU : J_MU);
+  auto u_mu = [&]() { return sizeof(R) == 8 ? r_late : rng.u(J_MU); };
+  auto u_tau = [&]() { return sizeof(R) == 4 ? r_late : rng.u(J_TAU); };
   const R kin[3] = {s.k[0], s.k[1], s.k[2]};
   R e1[3], e2[3];
   perp_basis(kin, e1, e2);
@@ -524,7 +531,7 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R, NL> &o, in
       peel_all<R, DEFER, NL>(pb, s.p, ps, pstk, stride, s.cnt, snk, &sc);
     }
     if (!pb.forward_only) {
-      const R mu = mu_hg(rng.u(J_MU), R(pb.g_hg));
+      const R mu = mu_hg(u_mu(), R(pb.g_hg));
       R sp, cp;
       M<R>::sincos2pi(rng.u(J_PHI), &sp, &cp);
       const R st = M<R>::sqrt(fmax(R(0), R(1) - mu * mu));
@@ -604,7 +611,7 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R, NL> &o, in
         ps.core = fch;
         peel_all<R, DEFER, NL>(pb, s.p, ps, pstk, stride, s.cnt, snk, &sc);
       }
-      const R mu = R(2) * rng.u(J_MU) - R(1);
+      const R mu = R(2) * u_mu() - R(1);
       M<R>::sincos2pi(rng.u(J_PHI), &sp, &cp);
       const R st = M<R>::sqrt(fmax(R(0), R(1) - mu * mu));
 #pragma unroll
@@ -613,7 +620,7 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R, NL> &o, in
       const R ba = bc * (s.k[0] * U[0] + s.k[1] * U[1] + s.k[2] * U[2]);
       const R bw = R(pb.b_ref) * (s.k[0] * s.lf.ux + s.k[1] * s.lf.uy + s.k[2] * s.lf.uz);
       s.x = R(ln.xf0[fch]) + M<R>::div(R(ln.sf[fch]) * (ba + bw + ba * bw), R(pb.b_ref));
-      s.tau = -(double)M<R>::log(rng.u(J_TAU));
+      s.tau = -(double)M<R>::log(u_tau());
       return ST_NONE;
     }
     if (pb.n_obs) {
@@ -627,7 +634,7 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R, NL> &o, in
       peel_all<R, DEFER, NL>(pb, s.p, ps, pstk, stride, s.cnt, snk, &sc);
     }
     if (!pb.forward_only) {
-      const R ru = rng.u(J_MU);
+      const R ru = u_mu();
       const R mu = ln.phase == PHASE_ISO ? R(2) * ru - R(1) : (core ? mu_core(ru) : mu_wing(ru));
       M<R>::sincos2pi(rng.u(J_PHI), &sp, &cp);
       const R st = M<R>::sqrt(fmax(R(0), R(1) - mu * mu));
@@ -643,7 +650,7 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R, NL> &o, in
       s.x = (R(-ln.delta) + R(ln.mu) * rho * xc * (R(1) + R(pb.b_ref) * wn) + wn) * R(ln.inv_s);
     }
   }
-  s.tau = -(double)M<R>::log(rng.u(J_TAU));
+  s.tau = -(double)M<R>::log(u_tau());
   return ST_NONE;
 }
 

@@ -60,10 +60,14 @@ def test_gpu_recoil_follows_the_outgoing_frequency_relation(orc, prec, phase, x_
 
 
 def _float_uniform(orc, seed, pid, event, j):
-    # the float path's draw j: word j % 4 of Philox block j / 4, top 23 bits
-    ctr = [pid & 0xFFFFFFFF, pid >> 32, event, j >> 2]
+    # the float path's draw j: word p % 4 of Philox block p / 4, top 23 bits,
+    # with p the slot's place in the float layout (slots 0..7 at words 0, 6,
+    # 7, 1, 4, 5, 2, 3: the channel, tau_event and the first rejection round
+    # in block 0, the perpendicular velocities and the direction in block 1)
+    p = (0, 6, 7, 1, 4, 5, 2, 3)[j] if j < 8 else j
+    ctr = [pid & 0xFFFFFFFF, pid >> 32, event, p >> 2]
     key = [seed & 0xFFFFFFFF, seed >> 32]
-    w = int(orc.philox(ctr, key)[j & 3])
+    w = int(orc.philox(ctr, key)[p & 3])
     return (2 * (w >> 9) + 1) * 2.0 ** -24
 
 
