@@ -721,19 +721,38 @@ def complete_run(pb, P, rmc, torch, regroup=None):
     ctx.set_stream(torch.cuda.current_stream())
     if regroup is not None:
         ctx.set_option(rmc.OPT_REGROUP, regroup)
+    ctx.set_option(rmc.OPT_SLICE_ITERS, 8192)
+    # streamed launch by launch (the same packets as rmc_run), so that the
+    # bulk, while every lane holds a packet, and the tail, while the last
+    # walks finish, can be told apart
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st = ctx.run(pb.seed, 0, P)
+    ctx.stream_begin(pb.seed, 0, P)
+    hist = []
+    rem = P
+    while rem > 0:
+        sl, rem = ctx.stream_step()
+        hist.append((time.perf_counter() - t0, rem, sl["scatterings"]))
+    st = ctx.stream_end()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     out = ctx.get_packets()
     out["cube"] = ctx.get_cube(0)
     ctx.close()
     print(f"# complete fp32 run: {P} packets in {wall:.2f} s, {st}", file=sys.stderr, flush=True)
+    # the tail: launches after the one in which 90% of the packets had ended
+    k90 = next(i for i, (_, r, _) in enumerate(hist) if r <= 0.1 * P)
+    t90 = hist[k90][0]
+    scat_tail = sum(h[2] for h in hist[k90 + 1:])
     rec = {"packets": P, "seconds": wall, "scatterings": st["scatterings"],
            "scatterings_per_s": st["scatterings"] / wall,
            "crossings_per_s": (st["crossings"] + st["peel_crossings"]) / wall,
            "device_ms": {"transport": st["kernel_ms"], "ray_cast_pass": st["peel_pass_ms"]},
+           "launches": len(hist),
+           "tail": {"seconds_to_90pct_ended": t90, "seconds_after": wall - t90,
+                    "scatterings_after": scat_tail,
+                    "note": "the last 10% of the packets are the longest walks; they run on a "
+                            "shrinking number of lanes"},
            "escaped": st["escaped"], "absorbed": st["absorbed"], "stuck": st["stuck"]}
     return rec, out
 
