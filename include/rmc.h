@@ -271,8 +271,10 @@ rmc_status rmc_run(rmc_ctx *ctx, uint64_t seed, int64_t first, int64_t n,
  * parks it in device memory if it is still alive, and idle lanes take new
  * packets from the queue.  step reports the work of that launch (emitted =
  * packets finished in it = escaped + absorbed + stuck in it; peel_dropped
- * counts the dropped deposits of those packets) and the packets not
- * finished yet; end runs the
+ * counts the dropped deposits of those packets, except in FP32 contexts
+ * with deferred peel-off, where the launch's ray-cast pass bins the rays
+ * and peel_dropped counts those it found outside the cube) and the packets
+ * not finished yet; end runs the
  * remaining launches and reports the totals of the range.  rmc_run is
  * begin + steps + end.  Results do not depend on how a run is sliced.
  * begin on a context whose stream is still open abandons that stream (its

@@ -62,7 +62,8 @@ struct ObsK {
 // launch: cube element | observer << 40 | problem << 44 in dst.  Double
 // path: the point where the ray enters its next leaf (or its start), the
 // optical depth so far and the leaves crossed so far (64 B).  Float path:
-// the ray's start, its frequency and weight in float (40 B).
+// the ray's start, its frequency and weight in float (40 B); its cube
+// element is left 0 and found by the pass from the start and frequency.
 template <class R> struct PeelJob;
 template <> struct PeelJob<double> {
   double p[3];
@@ -148,12 +149,17 @@ struct ProblemK {
 };
 
 // ------------------------------------------------------------------ Philox
-// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).  Each round's two
+// 32x32-bit products are taken whole as 64-bit products: one
+// v_mad_u64_u32 gives both halves, where separate high and low multiplies
+// cost two multi-pass instructions.
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
     c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
     k.x += 0x9E3779B9u;
     k.y += 0xBB67AE85u;
@@ -514,15 +520,13 @@ __device__ __forceinline__ bool upar_round(R x, R a, EventRng<R> &rng, uint32_t 
   return upar_try(upar_env(x, a), a, rng, it, out);
 }
 
-// Sect. 3.3.1 inverse CDFs.
-template <class R> __device__ __forceinline__ R mu_core(R r) {
-  const R B = R(6) * (R(2) * r - R(1));
-  const R A = M<R>::sqrt(B * B + R(11.0 * 11.0 * 11.0 / 27.0));
-  return M<R>::cbrt_pos(A + B) - M<R>::cbrt_pos(A - B);
-}
-template <class R> __device__ __forceinline__ R mu_wing(R r) {
-  const R B = R(4) * r - R(2);
-  const R A = M<R>::sqrt(B * B + R(1));
+// Sect. 3.3.1 inverse CDFs.  Both are cbrt(A + B) - cbrt(A - B) with
+// A = sqrt(B^2 + C): core B = 6 (2r - 1), C = 11^3/27; wing B = 2 (2r - 1)
+// (= 4r - 2 exactly), C = 1.  One evaluation with the lane's constants, so
+// that a wave holding core and wing scatterings runs the cube roots once.
+template <class R> __device__ __forceinline__ R mu_dipole(R r, bool core) {
+  const R B = (core ? R(6) : R(2)) * (R(2) * r - R(1));
+  const R A = M<R>::sqrt(B * B + (core ? R(11.0 * 11.0 * 11.0 / 27.0) : R(1)));
   return M<R>::cbrt_pos(A + B) - M<R>::cbrt_pos(A - B);
 }
 // Henyey-Greenstein inverse, with the square of the exact inverse.
@@ -607,18 +611,16 @@ __device__ __forceinline__ void cell_bounds(const Cell &c, int L, double lo[3], 
 // 2^-40: no ray from p leaves the cell sooner than this, whatever its
 // direction, with exit_dist's rounding (which divides the same face - p
 // differences by |k_d| <= 1 + 2^-52) included.
-__device__ __forceinline__ double inner_dist(const Cell &c, int L, const double p[3]) {
-  const double inv = ldexp(1.0, -L);
-  const int s = 1 << (L - c.level);
-  const int o[3] = {c.ox, c.oy, c.oz};
+__device__ __forceinline__ double inner_dist(const double lo[3], const double hi[3], const double p[3]) {
   double m = __builtin_inf();
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const double lo = (double)o[d] * inv;
-    const double hi = (double)(o[d] + s) * inv;
-    m = fmin(m, fmin(p[d] - lo, hi - p[d]));
-  }
+  for (int d = 0; d < 3; ++d) m = fmin(m, fmin(p[d] - lo[d], hi[d] - p[d]));
   return fmax(m, 0.0) * (1.0 - 0x1p-40);
+}
+__device__ __forceinline__ double inner_dist(const Cell &c, int L, const double p[3]) {
+  double lo[3], hi[3];
+  cell_bounds(c, L, lo, hi);
+  return inner_dist(lo, hi, p);
 }
 
 // The point where the packet leaves: exit axes snapped onto the face, the

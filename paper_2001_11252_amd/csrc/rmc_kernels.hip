@@ -182,10 +182,11 @@ template <class R> struct PeelSink {
 
 // First-leaf test of a peel-off ray toward observer ob from p, in the
 // scattering's own leaf (its record is in the lane's registers; the leaf
-// lies strictly inside the domain): true if the optical depth to the
-// nearest face, or to the exit face along k_obs, already reaches the cut,
-// where exp(-tau) is zero and no deposit changes.  With EXIT (double path,
-// deferred rays) a ray that goes on gets where it leaves the leaf (q,
+// lies strictly inside the domain): true if the optical depth to the exit
+// face along k_obs already reaches the cut, where exp(-tau) is zero and no
+// deposit changes.  Without EXIT (float path) that distance alone is
+// computed; with EXIT (double path, deferred rays) the nearest face is
+// tried first, and a ray that goes on gets where it leaves the leaf (q,
 // wrapped through periodic borders) and the optical depth so far.
 template <class R, int NL, bool EXIT>
 __device__ __forceinline__ bool peel_first_leaf(const ProblemK &pb, const double p[3], const ObsK &ob,
@@ -194,6 +195,23 @@ __device__ __forceinline__ bool peel_first_leaf(const ProblemK &pb, const double
   Opac<R, NL> o;
   opacity(pb, *sc->lf, (double)xo, ko, o);
   const double kt = (double)o.ktot;
+  if constexpr (!EXIT) {
+    // the distance to the leaf's face ahead along k_obs, as exit_dist
+    // computes it (the observer's direction is uniform across the wave)
+    const double inv = ldexp(1.0, -pb.L);
+    const int sz = 1 << (pb.L - sc->c->level);
+    const int o3[3] = {sc->c->ox, sc->c->oy, sc->c->oz};
+    double te = __builtin_inf();
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      if (ob.k[d] != 0.0) {
+        const double f = (double)(ob.k[d] > 0.0 ? o3[d] + sz : o3[d]) * inv;
+        const double t = (f - p[d]) * ob.kinv[d];
+        te = t < te ? t : te;
+      }
+    }
+    return kt * (te < 0.0 ? 0.0 : te) >= TauCut<R>::v;
+  }
   if (kt * inner_dist(*sc->c, pb.L, p) >= TauCut<R>::v) return true;
   double face[3], lo[3], hi[3];
   int em;
@@ -245,7 +263,8 @@ __device__ __forceinline__ void peel_push(const ProblemK &pb, const double q[3],
 // weight, pixel and bin are computed: most rays from optically thick gas
 // end there with no deposit.  A ray that goes on is binned (deposits
 // outside the cube are dropped and counted) and, with DEFER, queued for the
-// ray-cast pass (peel_push), else walked here.  Emission rays (sc null: no
+// ray-cast pass (peel_push), else walked here; the float path queues it
+// unbinned, and the pass bins it.  Emission rays (sc null: no
 // leaf located yet) and rays from leaves the domain border may cut skip the
 // first-leaf test.
 template <class R, bool DEFER, int NL>
@@ -299,6 +318,12 @@ __device__ void peel_all(const ProblemK &pb, const double p[3], const PeelSrc<R>
       weight = P * R(1.0 / (2.0 * PI_D));
     } else {
       weight = p_hg(mu, R(pb.g_hg)) * R(1.0 / (2.0 * PI_D));
+    }
+    if constexpr (DEFER && sizeof(R) == 4) {
+      // the float ray-cast pass bins the ray from its start (and counts
+      // the deposits outside the cube)
+      peel_push<R>(pb, q, 0.0, 0u, xo, weight, 0, oi, snk);
+      continue;
     }
     const int pix = pixel_of<sizeof(R) == 4>(ob, p);
     const int bin = bin_of<sizeof(R) == 4>(ob, (double)xo);
@@ -635,7 +660,7 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R, NL> &o, in
     }
     if (!pb.forward_only) {
       const R ru = u_mu();
-      const R mu = ln.phase == PHASE_ISO ? R(2) * ru - R(1) : (core ? mu_core(ru) : mu_wing(ru));
+      const R mu = ln.phase == PHASE_ISO ? R(2) * ru - R(1) : mu_dipole(ru, core != 0);
       M<R>::sincos2pi(rng.u(J_PHI), &sp, &cp);
       const R st = M<R>::sqrt(fmax(R(0), R(1) - mu * mu));
 #pragma unroll
@@ -976,6 +1001,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DrainW
   uint32_t steps = 0;
   Cell c;
   unsigned long long nc_prob = 0, nc_all = 0;
+  unsigned long long nd_prob = 0, nd_all = 0;   // float jobs outside the cube
   while (true) {
     unsigned long long idle = __ballot(!active);
     while (idle && !drained) {
@@ -1000,32 +1026,46 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DrainW
         const int jp = BATCH ? (int)(j.dst >> PQ_PROB_SHIFT) : 0;
         if (BATCH && jp != acc_prob) {
           if (nc_prob) atomicAdd(probs[acc_prob].stats + S_PEEL_CROSS, nc_prob);
+          if (nd_prob) atomicAdd(probs[acc_prob].stats + S_PEEL_DROPPED, nd_prob);
           nc_prob = 0;
+          nd_prob = 0;
           acc_prob = jp;
         }
         prob = jp;
         const ProblemK &pb = probs[prob];
         oi = (int)((j.dst >> PQ_OBS_SHIFT) & 15ull);
-        elem = j.dst & PQ_ELEM_MASK;
         const ObsK &ob = pb.obs[oi];
         k[0] = ob.k[0]; k[1] = ob.k[1]; k[2] = ob.k[2];
         kr[0] = (R)k[0]; kr[1] = (R)k[1]; kr[2] = (R)k[2];
         p[0] = j.p[0]; p[1] = j.p[1]; p[2] = j.p[2];
+        x = (double)j.x;
+        weight = (R)j.weight;
+        bool binned = true;
         if constexpr (sizeof(R) == 8) {
           tau = j.tau;
           steps = j.steps;
+          elem = j.dst & PQ_ELEM_MASK;
         } else {
+          // float jobs come unbinned, from the ray's start
           tau = 0.0;
           steps = 0;
+          const int pix = pixel_of<true>(ob, p);
+          const int bin = bin_of<true>(ob, x);
+          binned = pix >= 0 && bin >= 0;
+          elem = binned ? (unsigned long long)pix * ob.nbins + bin : 0ull;
+          if (!binned) {
+            ++nd_prob;
+            ++nd_all;
+          }
         }
-        x = (double)j.x;
-        weight = (R)j.weight;
         int X[3];
-        if (steps < MAX_CROSS && int_coords(pb.L, p, k, X)) {
-          descend(pb.nodes, pb.L, 0, 0, X, stk, stride, c);
-          active = true;
-        } else if (tau < cut) {
-          atomic_add_real((R *)ob.cube + elem, weight * M<R>::exp((R)(-tau)));
+        if (binned) {
+          if (steps < MAX_CROSS && int_coords(pb.L, p, k, X)) {
+            descend(pb.nodes, pb.L, 0, 0, X, stk, stride, c);
+            active = true;
+          } else if (tau < cut) {
+            atomic_add_real((R *)ob.cube + elem, weight * M<R>::exp((R)(-tau)));
+          }
         }
       }
       const uint32_t n_idle = (uint32_t)__popcll(idle);
@@ -1075,17 +1115,27 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DrainW
       active = false;
     }
   }
-  // crossings: per problem, and for the launch's slice counters
+  // crossings and dropped deposits: per problem, and for the launch's
+  // slice counters
   if (BATCH) {
     if (nc_prob) atomicAdd(probs[acc_prob].stats + S_PEEL_CROSS, nc_prob);
+    if (nd_prob) atomicAdd(probs[acc_prob].stats + S_PEEL_DROPPED, nd_prob);
   } else {
-    unsigned long long v = nc_prob;
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+    unsigned long long v = nc_prob, d = nd_prob;
+    for (int off = 32; off > 0; off >>= 1) {
+      v += __shfl_down(v, off);
+      d += __shfl_down(d, off);
+    }
     if (lane == 0 && v) atomicAdd(probs[0].stats + S_PEEL_CROSS, v);
+    if (lane == 0 && d) atomicAdd(probs[0].stats + S_PEEL_DROPPED, d);
   }
-  unsigned long long v = nc_all;
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+  unsigned long long v = nc_all, d = nd_all;
+  for (int off = 32; off > 0; off >>= 1) {
+    v += __shfl_down(v, off);
+    d += __shfl_down(d, off);
+  }
   if (lane == 0 && v) atomicAdd(slice + S_PEEL_CROSS, v);
+  if (lane == 0 && d) atomicAdd(slice + S_PEEL_DROPPED, d);
 }
 
 // After the ray-cast pass: report the launch's pushes, largest region and
