@@ -121,6 +121,8 @@ def parse():
     ap.add_argument("--regroup", type=int, default=None, choices=[0, 1],
                     help="transport loop with one rejection round per pass (1) or the looping draw (0); "
                          "default: the library's default")
+    ap.add_argument("--compact", type=int, default=None, choices=[0, 1],
+                    help="complete run: gather the last packets into fewer waves (library default 1)")
     ap.add_argument("--complete-run", type=int, default=1,
                     help="dusty_sphere: also time one complete FP32 run of all queued packets (1) or not (0)")
     ap.add_argument("--only", choices=["fp32", "fp64", "both"], default="both")
@@ -713,7 +715,7 @@ def bench_adjoint(a, rmc, W):
                  cpu_baseline=cpu)
 
 
-def complete_run(pb, P, rmc, torch, regroup=None):
+def complete_run(pb, P, rmc, torch, regroup=None, compact=None):
     """One complete FP32 run of all P queued packets (every walk to its end,
     the tail of the longest walks included), timed by the wall clock and by
     the library's events; its outputs feed the comparison with the oracle."""
@@ -721,6 +723,8 @@ def complete_run(pb, P, rmc, torch, regroup=None):
     ctx.set_stream(torch.cuda.current_stream())
     if regroup is not None:
         ctx.set_option(rmc.OPT_REGROUP, regroup)
+    if compact is not None:
+        ctx.set_option(rmc.OPT_COMPACT, compact)
     ctx.set_option(rmc.OPT_SLICE_ITERS, 8192)
     # streamed launch by launch (the same packets as rmc_run), so that the
     # bulk, while every lane holds a packet, and the tail, while the last
@@ -751,8 +755,10 @@ def complete_run(pb, P, rmc, torch, regroup=None):
            "launches": len(hist),
            "tail": {"seconds_to_90pct_ended": t90, "seconds_after": wall - t90,
                     "scatterings_after": scat_tail,
+                    "gathered": 1 if compact is None else compact,
                     "note": "the last 10% of the packets are the longest walks; they run on a "
-                            "shrinking number of lanes"},
+                            "shrinking number of lanes (gathered: into the waves they fill, "
+                            "RMC_OPT_COMPACT)"},
            "escaped": st["escaped"], "absorbed": st["absorbed"], "stuck": st["stuck"]}
     return rec, out
 
@@ -957,7 +963,7 @@ def main():
     if a.only in ("fp32", "both"):
         res["fp32"] = measure("fp32", steps)
         if a.complete_run:
-            full, full_out = complete_run(pb, P, rmc, torch, a.regroup)
+            full, full_out = complete_run(pb, P, rmc, torch, a.regroup, a.compact)
     if a.only in ("fp64", "both"):
         res["fp64"] = measure("fp64", a.fp64_steps if a.only == "both" else steps)
     head = "fp32" if "fp32" in res else "fp64"

@@ -87,6 +87,15 @@ enum {
                                 for RMC_FP64 contexts, 0 for RMC_FP32_BULK
                                 (the faster of the two on each path).
                                 Applies with RMC_OPT_PEEL_DEFER = 1.         */
+  RMC_OPT_COMPACT = 10,      /* 1 (default): once every packet of a run has
+                                started, the packets still walking are
+                                gathered into the first lanes after each
+                                launch that leaves at most three quarters of
+                                its lanes busy, and the next launches use
+                                only the waves they fill (the last, longest
+                                walks then run faster per wave); 0: every
+                                launch keeps the full grid.  The same packets
+                                either way.                                  */
   RMC_OPT_VOIGT = 8          /* Voigt function H(a,x) of the opacity:
                                 0 (default) the Tasitsiomi form the paper
                                 uses (Sect. 3.3.2; within ~1% for Lya at

@@ -94,6 +94,7 @@ struct rmc_ctx {
   int slice_iters = 2048;
   int regroup = 0;         // one rejection round per pass of the transport loop
                            // (default 1 for RMC_FP64 contexts, set in rmc_create)
+  int compact = 1;         // gather the last packets of a stream into fewer waves
   // mesh
   bool has_mesh = false;
   int64_t n_leaves = 0;
@@ -139,6 +140,8 @@ struct rmc_ctx {
   std::vector<int64_t> b_starts_host;
   // streaming state (single problem or a batch led by this context)
   DevBuf slots, d_slice;
+  DevBuf slots2, d_live;     // gathered slots (tail of a stream) and their count
+  int s_tail_grid = 0;       // >0: blocks of the launches on gathered slots
   int64_t s_total = 0, s_done = 0;
   int s_grid = 0, s_levels = 1, s_nprobs = 0;
   bool s_open = false, s_batch = false;
@@ -407,6 +410,7 @@ void make_problem(rmc_ctx *c, int64_t first, int64_t n, uint64_t seed, ProblemK 
     k.mu = std::sqrt(c->lines[0].mass_amu / ln.mass_amu);
     k.inv_mu = std::sqrt(ln.mass_amu / c->lines[0].mass_amu);
     k.alpha = q.a;
+    k.lalpha = std::log10(q.a);
     k.kfac = ln.abundance * q.sigma0;
     k.rec = H_PLANCK * q.nu0 / (ln.mass_amu * AMU_G * C_LIGHT * C_LIGHT);
     k.phase = ln.phase;
@@ -582,7 +586,7 @@ void rmc_destroy(rmc_ctx *c) {
                     &c->slots, &c->d_slice, &c->pq_ctl, &c->pq_jobs, &c->pq_counts, &c->tp_leaf,
                     &c->tp_seg, &c->tp_next, &c->tp_first, &c->tp_count, &c->tp_pix, &c->tp_wt, &c->tp_x,
                     &c->tp_ctl, &c->sx_eff, &c->tab, &c->g_raw, &c->g_stage, &c->g_in, &c->d_bad,
-                    &c->m_lv, &c->m_ijk};
+                    &c->m_lv, &c->m_ijk, &c->slots2, &c->d_live};
   for (DevBuf *b : bufs) b->release();
   for (auto &o : c->obs) o.cube.release();
   if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -632,6 +636,10 @@ rmc_status rmc_set_option(rmc_ctx *c, int opt, int64_t v) {
     case RMC_OPT_REGROUP:
       if (v != 0 && v != 1) return fail(c, RMC_EINVAL, "regroup is 0 or 1");
       c->regroup = (int)v;
+      break;
+    case RMC_OPT_COMPACT:
+      if (v != 0 && v != 1) return fail(c, RMC_EINVAL, "compact is 0 or 1");
+      c->compact = (int)v;
       break;
     case RMC_OPT_VOIGT:
       if (v != 0 && v != 1) return fail(c, RMC_EINVAL, "voigt is 0 (Tasitsiomi) or 1 (accurate)");
@@ -1029,6 +1037,7 @@ rmc_status stream_open(rmc_ctx *c, int64_t total, int n_probs, int levels, bool 
   c->s_levels = std::max(levels, 1);
   c->s_batch = batch;
   c->s_grid = grid_for(c, total, batch, levels);
+  c->s_tail_grid = 0;
   const int64_t n_slots = (int64_t)c->s_grid * c->block;
   HIPCHK(c, c->slots.ensure((size_t)n_slots * slot_bytes()));
   HIPCHK(c, c->d_slice.ensure((N_STATS + 3) * 8));
@@ -1091,6 +1100,39 @@ rmc_status stream_open(rmc_ctx *c, int64_t total, int n_probs, int levels, bool 
   return RMC_OK;
 }
 
+// Once every packet of the stream has started (the queue is drained), the
+// live packets are total - done, all parked in slots.  When they fill at
+// most three quarters of the lanes launched, gather them to the front
+// (through slots2) and run the next launches with the blocks they fill:
+// the last, longest walks then share the SIMDs with fewer waves, and each
+// wave issues its instructions faster.  Which lane runs a packet does not
+// change its walk, so results are those of the full grid (cube additions
+// aside, whose order differs).
+rmc_status gather_tail(rmc_ctx *c) {
+  const int64_t live = c->s_total - c->s_done;
+  const int grid = c->s_tail_grid > 0 ? c->s_tail_grid : c->s_grid;
+  const int64_t lanes = (int64_t)grid * c->block;
+  if (live > lanes * 3 / 4) return RMC_OK;
+  const int new_grid = (int)((live + c->block - 1) / c->block);
+  const int64_t n_new = (int64_t)new_grid * c->block;
+  HIPCHK(c, c->slots2.ensure((size_t)n_new * slot_bytes()));
+  HIPCHK(c, c->d_live.ensure(8));
+  HIPCHK(c, launch_clear_slots(c->slots2.p, n_new, c->stream));
+  HIPCHK(c, launch_fill_u64(c->d_live.as<unsigned long long>(), 1, 0ull, c->stream));
+  HIPCHK(c, launch_compact_slots(c->slots.p, lanes, c->slots2.p, c->d_live.as<unsigned long long>(), c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->slots.p, c->slots2.p, (size_t)n_new * slot_bytes(), hipMemcpyDeviceToDevice,
+                           c->stream));
+  unsigned long long got = 0;
+  HIPCHK(c, hipMemcpyAsync(&got, c->d_live.p, 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if ((int64_t)got != live) {
+    c->s_open = false;
+    return fail(c, RMC_EDEVICE, "gathering the last packets: %llu parked, %lld expected", got, (long long)live);
+  }
+  c->s_tail_grid = new_grid;
+  return RMC_OK;
+}
+
 rmc_status stream_step(rmc_ctx *c, rmc_run_stats *slice, int64_t *remaining) {
   if (!c->s_open) return fail(c, RMC_ESTATE, "no open stream (rmc_stream_begin)");
   rmc_run_stats z;
@@ -1101,12 +1143,31 @@ rmc_status stream_step(rmc_ctx *c, rmc_run_stats *slice, int64_t *remaining) {
     return RMC_OK;
   }
   HIPCHK(c, hipEventRecord(c->ev0, c->stream));
-  HIPCHK(c, hipGraphLaunch(c->s_graph, c->stream));
-  HIPCHK(c, hipEventRecord(c->ev1, c->stream));
-  if (c->s_pq) HIPCHK(c, hipGraphLaunch(c->s_graph2, c->stream));
+  if (c->s_tail_grid > 0) {
+    // the captured launches with the grid of the gathered slots
+    const bool f32 = c->precision == RMC_FP32_BULK;
+    HIPCHK(c, launch_fill_u64(c->d_slice.as<unsigned long long>(), N_STATS + 3, 0ull, c->stream));
+    // regions of waves not launched must read empty in the pass
+    if (c->s_pq) HIPCHK(c, launch_fill_u32(c->pq_counts.as<uint32_t>(), (int64_t)c->pq_regions, 0u, c->stream));
+    HIPCHK(c, launch_transport(f32, c->s_batch, c->s_defer, c->s_one_line, c->regroup != 0, c->s_probs,
+                               c->s_starts, c->s_nprobs, c->d_next.as<unsigned long long>(), c->refill,
+                               c->s_levels, c->s_tail_grid, c->block, c->slots.p, c->slice_iters,
+                               c->d_slice.as<unsigned long long>(), c->stream));
+    HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+    if (c->s_pq) {
+      const int grid = c->num_cus * peel_drain_blocks_per_cu(f32, c->s_batch, c->s_one_line, c->s_levels);
+      HIPCHK(c, launch_peel_drain(f32, c->s_batch, c->s_one_line, c->s_probs, c->s_pq, c->s_levels, grid,
+                                  c->d_slice.as<unsigned long long>(), c->stream));
+    }
+  } else {
+    HIPCHK(c, hipGraphLaunch(c->s_graph, c->stream));
+    HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+    if (c->s_pq) HIPCHK(c, hipGraphLaunch(c->s_graph2, c->stream));
+  }
   HIPCHK(c, hipEventRecord(c->ev2, c->stream));
-  unsigned long long h[N_STATS + 3];
+  unsigned long long h[N_STATS + 3], next = 0;
   HIPCHK(c, hipMemcpyAsync(h, c->d_slice.p, sizeof h, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(&next, c->d_next.p, 8, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   float ms = 0.f, ms2 = 0.f;
   HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
@@ -1127,6 +1188,10 @@ rmc_status stream_step(rmc_ctx *c, rmc_run_stats *slice, int64_t *remaining) {
   add_run_stats(c->s_acc, z);
   if (slice) *slice = z;
   if (remaining) *remaining = c->s_total - c->s_done;
+  if (c->compact && (int64_t)next >= c->s_total && c->s_done < c->s_total) {
+    rmc_status r = gather_tail(c);
+    if (r) return r;
+  }
   return RMC_OK;
 }
 

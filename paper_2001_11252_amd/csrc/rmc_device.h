@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "rmc_math.h"
+
 namespace rmc {
 
 constexpr int MAX_LEVEL = 16;
@@ -38,6 +40,7 @@ enum {
 
 struct LineK {
   double delta, s, inv_s, inv_mu, mu, alpha, kfac;
+  double lalpha;   // log10 alpha
   double rec;      // h nu_i / (m_i c^2)
   int phase, recoil;
   // fluorescent channels: decay through channel j when the draw u lies at
@@ -255,16 +258,16 @@ template <> struct EventRng<float> {
 // ------------------------------------------------------------ math policy
 template <class R> struct M;
 template <> struct M<double> {
-  static __device__ __forceinline__ double exp(double x) { return ::exp(x); }
-  static __device__ __forceinline__ double log(double x) { return ::log(x); }
+  static __device__ __forceinline__ double exp(double x) { return exp_any(x); }
+  static __device__ __forceinline__ double log(double x) { return log_pos(x); }
   static __device__ __forceinline__ double log10(double x) { return ::log10(x); }
   static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
   static __device__ __forceinline__ double cbrt(double x) { return ::cbrt(x); }
-  static __device__ __forceinline__ double atan(double x) { return ::atan(x); }
-  static __device__ __forceinline__ double tan(double x) { return ::tan(x); }
-  static __device__ __forceinline__ void sincos2pi(double r, double *s, double *c) {
-    ::sincospi(2.0 * r, s, c);
-  }
+  // exp, log, the draw's arctangent and its tangent of |th| <= pi/2, and
+  // the sine and cosine of 2 pi r: the forms of rmc_math.h
+  static __device__ __forceinline__ double atan(double x) { return atan_any(x); }
+  static __device__ __forceinline__ double tan(double x) { return tan_halfpi(x); }
+  static __device__ __forceinline__ void sincos2pi(double r, double *s, double *c) { sincos_turns(r, s, c); }
   static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
   static __device__ __forceinline__ double div(double a, double b) { return a / b; }
   static __device__ __forceinline__ double cbrt_pos(double x) { return ::cbrt(x); }
@@ -427,11 +430,11 @@ template <class R> struct UparEnv {
   R sg, xa, th0, u02, p1, s1, s2;
 };
 
-template <class R> __device__ __forceinline__ UparEnv<R> upar_env(R x, R a) {
+template <class R> __device__ __forceinline__ UparEnv<R> upar_env(R x, R a, R la) {
   UparEnv<R> e;
   e.sg = x < R(0) ? R(-1) : R(1);
   e.xa = fabs(x);
-  R u0 = u0_fit(e.xa, M<R>::log10(a));
+  R u0 = u0_fit(e.xa, la);
   u0 = u0 < R(0) ? R(0) : u0;
   e.th0 = M<R>::atan(M<R>::div(u0 - e.xa, a));
   const R e0 = M<R>::exp(-u0 * u0);
@@ -488,12 +491,12 @@ template <class R> __device__ __forceinline__ R upar_gauss(R x, EventRng<R> &rng
 #pragma clang fp contract(fast)
 
 template <class R>
-__device__ __forceinline__ bool sample_upar(R x, R a, EventRng<R> &rng, uint32_t *iters, R *out) {
+__device__ __forceinline__ bool sample_upar(R x, R a, R la, EventRng<R> &rng, uint32_t *iters, R *out) {
   if (fabs(x) >= R(8)) {
     *out = upar_gauss(x, rng);
     return true;
   }
-  const UparEnv<R> e = upar_env(x, a);
+  const UparEnv<R> e = upar_env(x, a, la);
   for (uint32_t it = 0; it < MAX_REJECT; ++it) {
     if (upar_try(e, a, rng, it, out)) {
       *iters += it + 1;
@@ -512,12 +515,12 @@ __device__ __forceinline__ bool sample_upar(R x, R a, EventRng<R> &rng, uint32_t
 // the transport loop, together with the first rounds of other lanes,
 // instead of holding its wave in a loop of its own.
 template <class R>
-__device__ __forceinline__ bool upar_round(R x, R a, EventRng<R> &rng, uint32_t it, R *out) {
+__device__ __forceinline__ bool upar_round(R x, R a, R la, EventRng<R> &rng, uint32_t it, R *out) {
   if (fabs(x) >= R(8)) {
     *out = upar_gauss(x, rng);
     return true;
   }
-  return upar_try(upar_env(x, a), a, rng, it, out);
+  return upar_try(upar_env(x, a, la), a, rng, it, out);
 }
 
 // Sect. 3.3.1 inverse CDFs.  Both are cbrt(A + B) - cbrt(A - B) with
@@ -736,6 +739,7 @@ __device__ __forceinline__ void relocate(const int32_t *__restrict__ nodes, int 
 // before the domain, so its domain distance is never the smaller one.
 template <class R> struct LeafRec {
   R nl, irho, kd, ux, uy, uz, bnd;
+  R lg;   // log10(irho) (double records; the float path takes its own logarithm)
 };
 
 template <class R>
@@ -745,13 +749,13 @@ __device__ __forceinline__ LeafRec<R> load_leaf(const void *leaves, int i) {
   if constexpr (sizeof(R) == 4) {
     const float4 a = *(const float4 *)p;
     const float4 b = *(const float4 *)(p + 4);
-    r.nl = a.x; r.irho = a.y; r.kd = a.z; r.ux = a.w; r.uy = b.x; r.uz = b.y; r.bnd = b.z;
+    r.nl = a.x; r.irho = a.y; r.kd = a.z; r.ux = a.w; r.uy = b.x; r.uz = b.y; r.bnd = b.z; r.lg = 0.0f;
   } else {
     const double2 a = *(const double2 *)p;
     const double2 b = *(const double2 *)(p + 2);
     const double2 c = *(const double2 *)(p + 4);
     const double2 d = *(const double2 *)(p + 6);
-    r.nl = a.x; r.irho = a.y; r.kd = b.x; r.ux = b.y; r.uy = c.x; r.uz = c.y; r.bnd = d.x;
+    r.nl = a.x; r.irho = a.y; r.kd = b.x; r.ux = b.y; r.uy = c.x; r.uz = c.y; r.bnd = d.x; r.lg = d.y;
   }
   return r;
 }

@@ -540,8 +540,10 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R, NL> &o, in
   auto u_mu = [&]() { return sizeof(R) == 8 ? r_late : rng.u(J_MU); };
   auto u_tau = [&]() { return sizeof(R) == 4 ? r_late : rng.u(J_TAU); };
   const R kin[3] = {s.k[0], s.k[1], s.k[2]};
+  // the pair perpendicular to k_in is formed where it is used (after the
+  // atom-velocity draw on the line branch, whose register peak it would
+  // otherwise raise)
   R e1[3], e2[3];
-  perp_basis(kin, e1, e2);
   PeelSrc<R> ps;
   ps.kin[0] = kin[0]; ps.kin[1] = kin[1]; ps.kin[2] = kin[2];
   ps.ux = s.lf.ux; ps.uy = s.lf.uy; ps.uz = s.lf.uz;
@@ -556,6 +558,7 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R, NL> &o, in
       peel_all<R, DEFER, NL>(pb, s.p, ps, pstk, stride, s.cnt, snk, &sc);
     }
     if (!pb.forward_only) {
+      perp_basis(kin, e1, e2);
       const R mu = mu_hg(u_mu(), R(pb.g_hg));
       R sp, cp;
       M<R>::sincos2pi(rng.u(J_PHI), &sp, &cp);
@@ -590,20 +593,24 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R, NL> &o, in
     }
     const LineK &ln = pb.lines[i];
     const R a = R(ln.alpha) * s.lf.irho;
+    // log10 a for the envelope: the double path adds the line's log10 alpha
+    // and the leaf's log10(1/rho) (its record holds it)
+    const R la = sizeof(R) == 8 ? R(ln.lalpha) + s.lf.lg : M<R>::log10(a);
     R upar;
     if constexpr (REGROUP) {
-      if (!upar_round<R>(x, a, rng, s.rej, &upar)) {
+      if (!upar_round<R>(x, a, la, rng, s.rej, &upar)) {
         if (++s.rej >= MAX_REJECT) return ST_STUCK;
         return ST_NONE;
       }
       s.upar_iters += s.rej + 1;
       s.rej = 0;
     } else {
-      if (!sample_upar<R>(x, a, rng, &s.upar_iters, &upar)) return ST_STUCK;
+      if (!sample_upar<R>(x, a, la, rng, &s.upar_iters, &upar)) return ST_STUCK;
     }
     // Gaussian u_perp (Box-Muller), restricted to |u_perp| >= x_crit while
     // core-skipping applies
     const R xc2 = pb.skip_tau > 0.0 ? core_skip_x2<R>(pb, ln, s.lf, s.c.level, a, x) : R(0);
+    perp_basis(kin, e1, e2);
     R sp, cp;
     M<R>::sincos2pi(rng.u(J_PERP2), &sp, &cp);
     const R rr = M<R>::sqrt(xc2 - M<R>::log(rng.u(J_PERP1)));
@@ -736,7 +743,10 @@ __device__ __forceinline__ void add_delta(SliceCount &a, const Lane<R> &s, const
 // deferred peel-off runs four (about 30 registers spill, and it is still
 // 8% faster than at three), the other float kernels three (no spills; at
 // four the batch and four-line kernels spill 40-70 registers and the batch
-// runs slower), the double kernels one.
+// runs slower), the single-problem double kernels with deferred peel-off
+// two (40-55 registers spill, and the dusty sphere runs 38% faster than at
+// one, where nothing spills), the other double kernels (batch, inline
+// walker; 90-200 registers would spill at two) one.
 #ifndef RMC_WAVES_F32_LEAN
 #define RMC_WAVES_F32_LEAN 4
 #endif
@@ -744,14 +754,17 @@ __device__ __forceinline__ void add_delta(SliceCount &a, const Lane<R> &s, const
 #define RMC_WAVES_F32 3
 #endif
 #ifndef RMC_WAVES_F64
-#define RMC_WAVES_F64 1
+#define RMC_WAVES_F64 2
+#endif
+#ifndef RMC_WAVES_F64_WIDE
+#define RMC_WAVES_F64_WIDE 1
 #endif
 template <class R, bool BATCH, bool DEFER, int NL> struct WavesPerEU;
 template <bool BATCH, bool DEFER, int NL> struct WavesPerEU<float, BATCH, DEFER, NL> {
   static constexpr int v = (!BATCH && DEFER && NL == 1) ? RMC_WAVES_F32_LEAN : RMC_WAVES_F32;
 };
 template <bool BATCH, bool DEFER, int NL> struct WavesPerEU<double, BATCH, DEFER, NL> {
-  static constexpr int v = RMC_WAVES_F64;
+  static constexpr int v = (!BATCH && DEFER) ? RMC_WAVES_F64 : RMC_WAVES_F64_WIDE;
 };
 
 // REGROUP: a line scattering whose rejection round fails stays pending and
@@ -958,6 +971,31 @@ __global__ void k_count_live(const SlotState *__restrict__ slots, int64_t n, uns
 __global__ void k_clear_slots(SlotState *__restrict__ slots, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) slots[i].active = 0;
+}
+
+// Parked packets gathered to the front: every active slot of src[0, n) is
+// copied to its own slot of dst (order not kept; a packet's walk does not
+// depend on the lane that runs it), one atomic per wave; *n_live counts
+// them.  Once every packet of a stream has started, the launches that
+// follow run on the gathered slots with as many waves as the packets fill,
+// so the last long walks share fewer SIMDs and each wave issues faster.
+__global__ void k_compact_slots(const SlotState *__restrict__ src, int64_t n, SlotState *__restrict__ dst,
+                                unsigned long long *n_live) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool act = i < n && src[i].active;
+  const unsigned long long m = __ballot(act);
+  if (m == 0ull) return;
+  const int lane = __lane_id();
+  const int leader = __ffsll((long long)m) - 1;
+  unsigned long long base = 0;
+  if (lane == leader) base = atomicAdd(n_live, (unsigned long long)__popcll(m));
+  base = __shfl(base, leader);
+  if (act) dst[base + (unsigned long long)__popcll(m & ((1ull << lane) - 1ull))] = src[i];
+}
+
+__global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
 }
 
 // Ray-cast pass over the peel-off rays queued by a transport launch.  A
@@ -1591,7 +1629,7 @@ __global__ void k_leaf_records(int64_t n, const double *__restrict__ raw, const 
     border = !(far2 < Rr * Rr);
   }
   const double rec[8] = {g[0] * box * irho, irho, g[5] * box, g[2] / vth_ref, g[3] / vth_ref, g[4] / vth_ref,
-                         border ? 1.0 : 0.0, 0.0};
+                         border ? 1.0 : 0.0, log10(irho)};
   R *o = leaves + (size_t)i * LEAF_STRIDE;
 #pragma unroll
   for (int q = 0; q < 8; ++q) o[q] = (R)rec[q];
@@ -1776,6 +1814,20 @@ int transport_blocks_per_cu(bool fp32, bool batch, bool defer, bool one_line, bo
 
 hipError_t launch_clear_slots(void *slots, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_clear_slots, dim3(blocks_for(n, 256)), dim3(256), 0, st, (SlotState *)slots, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact_slots(const void *src, int64_t n, void *dst, unsigned long long *n_live,
+                                hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_compact_slots, dim3(blocks_for(n, 256)), dim3(256), 0, st, (const SlotState *)src, n,
+                     (SlotState *)dst, n_live);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n, v);
   return hipGetLastError();
 }
 

@@ -28,6 +28,10 @@ int transport_blocks_per_cu(bool fp32, bool batch, bool defer, bool one_line, bo
                             int stack_levels);
 hipError_t launch_clear_slots(void *slots, int64_t n, hipStream_t st);
 hipError_t launch_count_live(const void *slots, int64_t n, unsigned long long *out, hipStream_t st);
+// active slots of src[0, n) copied to distinct slots of dst; *n_live += their count
+hipError_t launch_compact_slots(const void *src, int64_t n, void *dst, unsigned long long *n_live,
+                                hipStream_t st);
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
 hipError_t launch_trace(const ProblemK &pb, int64_t n, const double *orig, const double *dir,
                         int max_cells, int32_t *leaf, double *seg, int32_t *cnt, hipStream_t st);
 hipError_t launch_tau(bool fp32, const ProblemK &pb, int64_t n, const double *orig, const double *dir,

@@ -110,11 +110,12 @@ def test_batch_stream_equals_batch_run(orc):
             assert np.array_equal(pa[k], pb_[k]), k
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_batch_with_observers_equals_single_runs(orc, prec):
+@pytest.mark.parametrize("prec,compact", [("fp64", 1), ("fp32", 1), ("fp32", 0)])
+def test_batch_with_observers_equals_single_runs(orc, prec, compact):
     # problems with different observer counts and line sets in one batch:
     # the deferred peel-off rays of every problem land in that problem's
-    # cubes (queue entries carry their problem and observer)
+    # cubes (queue entries carry their problem and observer), with the
+    # batch's last packets gathered into fewer waves or not
     from paper_2001_11252_amd import rmc
     s0 = lambda ln, T: orc.line_quantities(ln, T)["sigma0"]
     probs = []
@@ -129,6 +130,7 @@ def test_batch_with_observers_equals_single_runs(orc, prec):
     seeds = [p.seed for p in probs]
     ctxs = [rmc.Context.from_problem(p, prec) for p in probs]
     ctxs[0].set_option(rmc.OPT_SLICE_ITERS, 64)
+    ctxs[0].set_option(rmc.OPT_COMPACT, compact)
     per, tot = rmc.batch_run(ctxs, seeds, npk)
     assert tot["peel_deferred"] > 0
     for p, c, st, n in zip(probs, ctxs, per, npk):

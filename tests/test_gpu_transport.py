@@ -524,3 +524,48 @@ def test_regrouped_rejection_rounds_give_the_same_packets(rmc, orc, prec):
         assert np.allclose(ca, cb, rtol=1e-5 if prec == "fp32" else 1e-12, atol=0)
     with pytest.raises(rmc.RmcError):
         b.set_option(rmc.OPT_REGROUP, 2)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_gathered_tail_gives_the_same_packets(rmc, orc, prec):
+    # RMC_OPT_COMPACT: once every packet has started, the packets still
+    # walking are gathered into the first lanes and the next launches run
+    # only the waves they fill.  Which lane runs a packet does not change
+    # its walk: every packet and count is that of the full grid, and the
+    # cubes agree up to the order of the additions (the ray-cast pass then
+    # sees regions of waves that were not launched, which must read empty).
+    pb = W.static_sphere(s0(orc), 3e4, 100.0, 6000, level=4, tau_dust=0.5)
+    pb.gas.v[:] = np.random.default_rng(9).standard_normal((pb.mesh.n, 3)) * 15e5
+    pb.observers = [W.Observer((0.0, 0.0, 1.0), 8, 8, 12, (-0.5, 0.5, -0.5, 0.5), -40, 40),
+                    W.Observer((0.6, 0.0, 0.8), 8, 8, 12, (-0.5, 0.5, -0.5, 0.5), -40, 40)]
+    runs = []
+    for compact in (0, 1):
+        c = rmc.Context.from_problem(pb, prec)
+        c.set_option(rmc.OPT_COMPACT, compact)
+        c.set_option(rmc.OPT_SLICE_ITERS, 97)
+        c.stream_begin(17, 0, 6000)
+        steps, ends = 0, 0
+        while True:
+            sl, rem = c.stream_step()
+            steps += 1
+            ends += sl["emitted"]
+            assert sl["escaped"] + sl["absorbed"] + sl["stuck"] == sl["emitted"]
+            if rem == 0:
+                break
+        st = c.stream_end()
+        assert ends == 6000 and steps > 20
+        runs.append((c, st))
+    (a, sa), (b, sb) = runs
+    pa, pbk = a.get_packets(), b.get_packets()
+    for k in pa:
+        assert np.array_equal(pa[k], pbk[k]), k
+    for k in ("emitted", "escaped", "absorbed", "stuck", "scatterings", "dust_scatterings", "crossings",
+              "peel_rays", "peel_crossings", "peel_dropped", "peel_deferred"):
+        assert sa[k] == sb[k], k
+    assert sb["peel_deferred"] > 0
+    for o in range(2):
+        ca, cb = a.get_cube(o), b.get_cube(o)
+        assert ca.sum() > 0
+        assert np.allclose(ca, cb, rtol=1e-5 if prec == "fp32" else 1e-12, atol=0)
+    with pytest.raises(rmc.RmcError):
+        b.set_option(rmc.OPT_COMPACT, 2)
