@@ -747,6 +747,7 @@ def complete_run(pb, P, rmc, torch, regroup=None, compact=None):
     # the tail: launches after the one in which 90% of the packets had ended
     k90 = next(i for i, (_, r, _) in enumerate(hist) if r <= 0.1 * P)
     t90 = hist[k90][0]
+    t_end = {f: next(h[0] for h in hist if h[1] <= (1.0 - f) * P) for f in (0.99, 0.999)}
     scat_tail = sum(h[2] for h in hist[k90 + 1:])
     rec = {"packets": P, "seconds": wall, "scatterings": st["scatterings"],
            "scatterings_per_s": st["scatterings"] / wall,
@@ -756,6 +757,8 @@ def complete_run(pb, P, rmc, torch, regroup=None, compact=None):
            "tail": {"seconds_to_90pct_ended": t90, "seconds_after": wall - t90,
                     "scatterings_after": scat_tail,
                     "gathered": 1 if compact is None else compact,
+                    "seconds_to_99pct_ended": t_end[0.99], "seconds_to_99.9pct_ended": t_end[0.999],
+                    "longest_walk_scatterings": int(out["n_scat"].max()),
                     "note": "the last 10% of the packets are the longest walks; they run on a "
                             "shrinking number of lanes (gathered: into the waves they fill, "
                             "RMC_OPT_COMPACT)"},
