@@ -68,7 +68,7 @@ enum {
   RMC_OPT_PEEL_DEFER = 6,    /* 1 (default): a peel-off ray whose optical
                                 depth does not reach the cut inside the leaf
                                 of its scattering is queued (device memory
-                                that grows on demand, at most 16 GiB) and
+                                that grows on demand, at most 32 GiB) and
                                 walked by a ray-cast pass after each
                                 transport launch; 0: walked inline by the
                                 transport kernel.  Results agree up to the

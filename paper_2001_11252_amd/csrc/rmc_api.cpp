@@ -956,7 +956,7 @@ void add_run_stats(rmc_run_stats &a, const rmc_run_stats &b) {
 }
 
 constexpr unsigned long long PQ_FIRST_CAP = 1024;          // jobs per region (one region per wave)
-constexpr unsigned long long PQ_MAX_BYTES = 16ull << 30;    // job buffer limit
+constexpr unsigned long long PQ_MAX_BYTES = 32ull << 30;    // job buffer limit
 static_assert(PQ_FIRST_CAP > 2 * 64 * MAX_OBS, "a region must hold one wave iteration of pushes");
 
 // Control block of the deferred peel-off queue, or null when peel-off rays
