@@ -411,6 +411,7 @@ void make_problem(rmc_ctx *c, int64_t first, int64_t n, uint64_t seed, ProblemK 
     k.inv_mu = std::sqrt(ln.mass_amu / c->lines[0].mass_amu);
     k.alpha = q.a;
     k.lalpha = std::log10(q.a);
+    k.ibmu = 1.0 / (pb.b_ref * k.mu);
     k.kfac = ln.abundance * q.sigma0;
     k.rec = H_PLANCK * q.nu0 / (ln.mass_amu * AMU_G * C_LIGHT * C_LIGHT);
     k.phase = ln.phase;

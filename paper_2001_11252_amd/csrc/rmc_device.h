@@ -41,6 +41,7 @@ enum {
 struct LineK {
   double delta, s, inv_s, inv_mu, mu, alpha, kfac;
   double lalpha;   // log10 alpha
+  double ibmu;     // 1 / (b_ref mu): v_th,line / c is b_ref mu rho
   double rec;      // h nu_i / (m_i c^2)
   int phase, recoil;
   // fluorescent channels: decay through channel j when the draw u lies at
@@ -269,6 +270,7 @@ template <> struct M<double> {
   static __device__ __forceinline__ double tan(double x) { return tan_halfpi(x); }
   static __device__ __forceinline__ void sincos2pi(double r, double *s, double *c) { sincos_turns(r, s, c); }
   static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+  static __device__ __forceinline__ double rsqrt(double x) { return 1.0 / ::sqrt(x); }
   static __device__ __forceinline__ double div(double a, double b) { return a / b; }
   static __device__ __forceinline__ double cbrt_pos(double x) { return ::cbrt(x); }
 };
@@ -297,6 +299,7 @@ template <> struct M<float> {
     *c = __builtin_amdgcn_cosf(r);
   }
   static __device__ __forceinline__ float rcp(float x) { return __frcp_rn(x); }
+  static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
   // a times the hardware reciprocal of b (about 1 ulp)
   static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
   // cube root of a positive normal number from the hardware log2 and exp2
@@ -316,7 +319,13 @@ template <class R> __device__ __forceinline__ R voigt_h(R a, R x) {
   R h = M<R>::exp(-x2);
   if (z > R(0)) {
     const R P = ((R(5.674) * z - R(9.207)) * z + R(4.421)) * z + R(0.1117);
-    const R q = M<R>::div(z * (R(1) + M<R>::div(R(21), x2)) * (a * R(1.0 / PI_D)), x2 + R(1)) * P;
+    R q;
+    if constexpr (sizeof(R) == 4) {
+      // (1 + 21/x^2) / (x^2 + 1) as one quotient: one reciprocal
+      q = M<R>::div(z * (x2 + R(21)) * (a * R(1.0 / PI_D)), x2 * (x2 + R(1))) * P;
+    } else {
+      q = M<R>::div(z * (R(1) + M<R>::div(R(21), x2)) * (a * R(1.0 / PI_D)), x2 + R(1)) * P;
+    }
     h += R(1.7724538509055160273) * q;
   }
   return h;
@@ -439,13 +448,16 @@ template <class R> __device__ __forceinline__ UparEnv<R> upar_env(R x, R a, R la
   e.th0 = M<R>::atan(M<R>::div(u0 - e.xa, a));
   const R e0 = M<R>::exp(-u0 * u0);
   const R hp = R(0.5 * PI_D);
-  e.p1 = M<R>::div(e.th0 + hp, (R(1) - e0) * e.th0 + (R(1) + e0) * hp);
+  const R D = (R(1) - e0) * e.th0 + (R(1) + e0) * hp;
+  e.p1 = M<R>::div(e.th0 + hp, D);
   e.u02 = u0 * u0;
   // float: one uniform picks the piece and, rescaled within it, the angle
   // (the same distribution with two uniforms per round, so that an event
-  // with one round fits in two Philox blocks); double: three per round
-  e.s1 = e.p1 > R(0) ? M<R>::div(e.th0 + hp, e.p1) : R(0);
-  e.s2 = e.p1 < R(1) ? M<R>::div(hp - e.th0, R(1) - e.p1) : R(0);
+  // with one round fits in two Philox blocks); double: three per round.
+  // The scales (th0 + pi/2)/p1 and (pi/2 - th0)/(1 - p1) are D and D/e0
+  // (1 - p1 = e0 (pi/2 - th0)/D); the second is not used when p1 is 1.
+  e.s1 = D;
+  e.s2 = e.p1 < R(1) ? M<R>::div(D, e0) : R(0);
   return e;
 }
 
@@ -530,7 +542,14 @@ __device__ __forceinline__ bool upar_round(R x, R a, R la, EventRng<R> &rng, uin
 template <class R> __device__ __forceinline__ R mu_dipole(R r, bool core) {
   const R B = (core ? R(6) : R(2)) * (R(2) * r - R(1));
   const R A = M<R>::sqrt(B * B + (core ? R(11.0 * 11.0 * 11.0 / 27.0) : R(1)));
-  return M<R>::cbrt_pos(A + B) - M<R>::cbrt_pos(A - B);
+  if constexpr (sizeof(R) == 4) {
+    // (A + B)(A - B) = C, so cbrt(A - B) = cbrt(C) / cbrt(A + B), with
+    // cbrt(C) = 11/3 (core) or 1 (wing): one cube root and a reciprocal
+    const R y = M<R>::cbrt_pos(A + B);
+    return y - M<R>::div(core ? R(11.0 / 3.0) : R(1), y);
+  } else {
+    return M<R>::cbrt_pos(A + B) - M<R>::cbrt_pos(A - B);
+  }
 }
 // Henyey-Greenstein inverse, with the square of the exact inverse.
 template <class R> __device__ __forceinline__ R mu_hg(R r, R g) {
@@ -551,7 +570,7 @@ template <class R> __device__ __forceinline__ void perp_basis(const R k[3], R e1
   R c0, c1, c2;
   if (fabs(k[2]) > R(0.9)) { c0 = R(0); c1 = k[2]; c2 = -k[1]; }
   else { c0 = k[1]; c1 = -k[0]; c2 = R(0); }
-  const R n = M<R>::div(R(1), M<R>::sqrt(c0 * c0 + c1 * c1 + c2 * c2));
+  const R n = M<R>::rsqrt(c0 * c0 + c1 * c1 + c2 * c2);
   e1[0] = c0 * n; e1[1] = c1 * n; e1[2] = c2 * n;
   e2[0] = k[1] * e1[2] - k[2] * e1[1];
   e2[1] = k[2] * e1[0] - k[0] * e1[2];

@@ -165,6 +165,7 @@ template <class R> struct PeelSrc {
   R U[3];          // atom velocity / v_th of the line (line)
   R bc;            // v_th,line,cell / c (line)
   R rho;           // sqrt(T/T_ref) (line)
+  R irho;          // 1/rho (line)
   int line, core;  // (fluorescent: core holds the channel)
   R ux, uy, uz;    // cell bulk velocity / v_th,ref
 };
@@ -289,7 +290,15 @@ __device__ void peel_all(const ProblemK &pb, const double p[3], const PeelSrc<R>
       const R dkU = (ko[0] - s.kin[0]) * s.U[0] + (ko[1] - s.kin[1]) * s.U[1] + (ko[2] - s.kin[2]) * s.U[2];
       const R g1 = R(1) + s.bc * s.x;
       const R Rr = ln.recoil ? (R(1) - mu) * R(ln.rec) * g1 : R(0);
-      const R xc = M<R>::div(s.x + g1 * dkU - M<R>::div(Rr, s.bc), R(1) + Rr);
+      R xc;
+      if constexpr (sizeof(R) == 4) {
+        // Rr < 3e-8 for any line and scatterer (h nu <= 13.6 eV, m c^2 >=
+        // 938 MeV): 1/(1 + Rr) = 1 - Rr to float precision, and
+        // Rr/bc = Rr irho / (b_ref mu)
+        xc = (s.x + g1 * dkU - Rr * R(ln.ibmu) * s.irho) * (R(1) - Rr);
+      } else {
+        xc = M<R>::div(s.x + g1 * dkU - M<R>::div(Rr, s.bc), R(1) + Rr);
+      }
       const R wo = ko[0] * s.ux + ko[1] * s.uy + ko[2] * s.uz;
       xo = (R(-ln.delta) + R(ln.mu) * s.rho * xc * (R(1) + R(pb.b_ref) * wo) + wo) * R(ln.inv_s);
     } else {
@@ -661,6 +670,7 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R, NL> &o, in
       ps.U[0] = U[0]; ps.U[1] = U[1]; ps.U[2] = U[2];
       ps.bc = bc;
       ps.rho = rho;
+      ps.irho = s.lf.irho;
       ps.line = i;
       ps.core = core;
       peel_all<R, DEFER, NL>(pb, s.p, ps, pstk, stride, s.cnt, snk, &sc);
@@ -677,7 +687,13 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R, NL> &o, in
       // denominator (Eq. for nu_out), then back to the external frame
       const R dkU = (s.k[0] - kin[0]) * U[0] + (s.k[1] - kin[1]) * U[1] + (s.k[2] - kin[2]) * U[2];
       const R Rr = ln.recoil ? (R(1) - mu) * R(ln.rec) * g1 : R(0);
-      const R xc = M<R>::div(x + g1 * dkU - M<R>::div(Rr, bc), R(1) + Rr);
+      R xc;
+      if constexpr (sizeof(R) == 4) {
+        // as in the peel-off: 1/(1 + Rr) = 1 - Rr and Rr/bc = Rr irho/(b_ref mu)
+        xc = (x + g1 * dkU - Rr * R(ln.ibmu) * s.lf.irho) * (R(1) - Rr);
+      } else {
+        xc = M<R>::div(x + g1 * dkU - M<R>::div(Rr, bc), R(1) + Rr);
+      }
       const R wn = s.k[0] * s.lf.ux + s.k[1] * s.lf.uy + s.k[2] * s.lf.uz;
       s.x = (R(-ln.delta) + R(ln.mu) * rho * xc * (R(1) + R(pb.b_ref) * wn) + wn) * R(ln.inv_s);
     }
