@@ -503,17 +503,14 @@ template <class R> __device__ __forceinline__ R upar_gauss(R x, EventRng<R> &rng
 #pragma clang fp contract(fast)
 
 template <class R>
-__device__ __forceinline__ bool sample_upar(R x, R a, R la, EventRng<R> &rng, uint32_t *iters, R *out) {
+__device__ __forceinline__ bool sample_upar(R x, R a, R la, EventRng<R> &rng, R *out) {
   if (fabs(x) >= R(8)) {
     *out = upar_gauss(x, rng);
     return true;
   }
   const UparEnv<R> e = upar_env(x, a, la);
   for (uint32_t it = 0; it < MAX_REJECT; ++it) {
-    if (upar_try(e, a, rng, it, out)) {
-      *iters += it + 1;
-      return true;
-    }
+    if (upar_try(e, a, rng, it, out)) return true;
   }
   *out = R(0);
   return false;

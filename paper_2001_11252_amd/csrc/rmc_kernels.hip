@@ -362,7 +362,7 @@ template <class R> struct Lane {
   double kd[3];    // direction used for geometry (unit in double)
   R x;
   double tau, path;
-  uint32_t event, upar_iters;
+  uint32_t event;
   uint32_t rej;    // regrouped loop: rejection rounds already run by the pending
                    // line scattering at p (0: none pending)
   int32_t nscat;
@@ -513,7 +513,6 @@ __device__ void emit(const ProblemK &pb, int64_t pid, Lane<R> &s, int *stk, int 
   s.path = 0.0;
   s.event = 0;
   s.nscat = 0;
-  s.upar_iters = 0;
   s.rej = 0;
   s.cnt = LaneCount{0, 0, 0, 0, 0};
   if (pb.n_obs) {
@@ -611,10 +610,9 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R, NL> &o, in
         if (++s.rej >= MAX_REJECT) return ST_STUCK;
         return ST_NONE;
       }
-      s.upar_iters += s.rej + 1;
       s.rej = 0;
     } else {
-      if (!sample_upar<R>(x, a, la, rng, &s.upar_iters, &upar)) return ST_STUCK;
+      if (!sample_upar<R>(x, a, la, rng, &upar)) return ST_STUCK;
     }
     // Gaussian u_perp (Box-Muller), restricted to |u_perp| >= x_crit while
     // core-skipping applies
@@ -712,7 +710,7 @@ struct SlotState {
   int64_t pid;
   int32_t prob, active, event, nscat;
   int32_t leaf, level, ox, oy, oz;
-  uint32_t dust, cross, peel_rays, peel_cross, peel_drop, iters;
+  uint32_t dust, cross, peel_rays, peel_cross, peel_drop;
   uint32_t rej;
 };
 
@@ -723,7 +721,7 @@ __device__ __forceinline__ void save_slot(SlotState &q, const Lane<R> &s, int pr
   q.prob = prob; q.active = 1; q.event = (int32_t)s.event; q.nscat = s.nscat;
   q.leaf = s.c.leaf; q.level = s.c.level; q.ox = s.c.ox; q.oy = s.c.oy; q.oz = s.c.oz;
   q.dust = s.cnt.dust_scat; q.cross = s.cnt.cross; q.peel_rays = s.cnt.peel_rays;
-  q.peel_cross = s.cnt.peel_cross; q.peel_drop = s.cnt.peel_drop; q.iters = s.upar_iters;
+  q.peel_cross = s.cnt.peel_cross; q.peel_drop = s.cnt.peel_drop;
   q.rej = s.rej;
 }
 
@@ -734,7 +732,7 @@ __device__ __forceinline__ void load_slot(const SlotState &q, Lane<R> &s, int *p
   *prob = q.prob; s.event = (uint32_t)q.event; s.nscat = q.nscat;
   s.c.leaf = q.leaf; s.c.level = q.level; s.c.ox = q.ox; s.c.oy = q.oy; s.c.oz = q.oz;
   s.cnt.dust_scat = q.dust; s.cnt.cross = q.cross; s.cnt.peel_rays = q.peel_rays;
-  s.cnt.peel_cross = q.peel_cross; s.cnt.peel_drop = q.peel_drop; s.upar_iters = q.iters;
+  s.cnt.peel_cross = q.peel_cross; s.cnt.peel_drop = q.peel_drop;
   s.rej = q.rej;
   set_geom_dir(s);
 }
