@@ -1150,10 +1150,12 @@ rmc_status stream_step(rmc_ctx *c, rmc_run_stats *slice, int64_t *remaining) {
     HIPCHK(c, launch_fill_u64(c->d_slice.as<unsigned long long>(), N_STATS + 3, 0ull, c->stream));
     // regions of waves not launched must read empty in the pass
     if (c->s_pq) HIPCHK(c, launch_fill_u32(c->pq_counts.as<uint32_t>(), (int64_t)c->pq_regions, 0u, c->stream));
+    // at most one wave per SIMD: the kernel compiled for one (no spills)
+    const bool lone = (int64_t)c->s_tail_grid * (c->block / 64) <= (int64_t)c->num_cus * 4;
     HIPCHK(c, launch_transport(f32, c->s_batch, c->s_defer, c->s_one_line, c->regroup != 0, c->s_probs,
                                c->s_starts, c->s_nprobs, c->d_next.as<unsigned long long>(), c->refill,
                                c->s_levels, c->s_tail_grid, c->block, c->slots.p, c->slice_iters,
-                               c->d_slice.as<unsigned long long>(), c->stream));
+                               c->d_slice.as<unsigned long long>(), c->stream, lone));
     HIPCHK(c, hipEventRecord(c->ev1, c->stream));
     if (c->s_pq) {
       const int grid = c->num_cus * peel_drain_blocks_per_cu(f32, c->s_batch, c->s_one_line, c->s_levels);

@@ -785,9 +785,14 @@ template <bool BATCH, bool DEFER, int NL> struct WavesPerEU<double, BATCH, DEFER
 // takes its next round at the next pass of the loop, where it runs in step
 // with the other lanes' events (upar_round), instead of the wave looping
 // until its last lane accepts.
-template <class R, bool BATCH, bool DEFER, int NL, bool REGROUP = false>
+// TAIL: the same kernel compiled for one wave per SIMD (registers to spare,
+// no spills), for the launches over gathered slots at the end of a run,
+// whose waves are no more than the SIMDs: each issues on its own, so its
+// latency, not the chip's throughput, sets the pace.
+template <class R, bool BATCH, bool DEFER, int NL, bool REGROUP = false, bool TAIL = false>
 __global__ void __launch_bounds__(256)
-    __attribute__((amdgpu_waves_per_eu(WavesPerEU<R, BATCH, DEFER, NL>::v, WavesPerEU<R, BATCH, DEFER, NL>::v)))
+    __attribute__((amdgpu_waves_per_eu(TAIL ? 1 : WavesPerEU<R, BATCH, DEFER, NL>::v,
+                                       TAIL ? 1 : WavesPerEU<R, BATCH, DEFER, NL>::v)))
     k_transport(const ProblemK *__restrict__ probs,
                                                    const int64_t *__restrict__ starts, int n_probs,
                                                    unsigned long long *__restrict__ next,
@@ -1748,23 +1753,25 @@ using TransportFn = void (*)(const ProblemK *, const int64_t *, int, unsigned lo
                             int, unsigned long long *);
 
 // The one-round-per-pass form (regroup) is built for the deferred
-// peel-off kernels only (the default).
+// peel-off kernels only (the default); the one-wave tail form for the
+// single-problem deferred kernels.
 template <class R, int NL>
-static TransportFn transport_fn(bool batch, bool defer, bool regroup) {
+static TransportFn transport_fn(bool batch, bool defer, bool regroup, bool tail) {
   if (batch) {
     if (!defer) return k_transport<R, true, false, NL>;
     return regroup ? k_transport<R, true, true, NL, true> : k_transport<R, true, true, NL>;
   }
   if (!defer) return k_transport<R, false, false, NL>;
+  if (tail) return regroup ? k_transport<R, false, true, NL, true, true> : k_transport<R, false, true, NL, false, true>;
   return regroup ? k_transport<R, false, true, NL, true> : k_transport<R, false, true, NL>;
 }
 
-static TransportFn transport_fn(bool fp32, bool batch, bool defer, bool one_line, bool regroup) {
+static TransportFn transport_fn(bool fp32, bool batch, bool defer, bool one_line, bool regroup, bool tail = false) {
   if (fp32)
-    return one_line ? transport_fn<float, 1>(batch, defer, regroup)
-                    : transport_fn<float, MAX_LINES>(batch, defer, regroup);
-  return one_line ? transport_fn<double, 1>(batch, defer, regroup)
-                  : transport_fn<double, MAX_LINES>(batch, defer, regroup);
+    return one_line ? transport_fn<float, 1>(batch, defer, regroup, tail)
+                    : transport_fn<float, MAX_LINES>(batch, defer, regroup, tail);
+  return one_line ? transport_fn<double, 1>(batch, defer, regroup, tail)
+                  : transport_fn<double, MAX_LINES>(batch, defer, regroup, tail);
 }
 
 static size_t transport_lds(int stack_levels, int block) {
@@ -1774,8 +1781,8 @@ static size_t transport_lds(int stack_levels, int block) {
 hipError_t launch_transport(bool fp32, bool batch, bool defer, bool one_line, bool regroup, const ProblemK *d_probs,
                             const int64_t *d_starts, int n_probs, unsigned long long *d_next, int refill_min,
                             int stack_levels, int grid, int block, void *slots, int budget,
-                            unsigned long long *slice, hipStream_t st) {
-  hipLaunchKernelGGL(transport_fn(fp32, batch, defer, one_line, regroup), dim3(grid), dim3(block),
+                            unsigned long long *slice, hipStream_t st, bool tail) {
+  hipLaunchKernelGGL(transport_fn(fp32, batch, defer, one_line, regroup, tail), dim3(grid), dim3(block),
                      transport_lds(stack_levels, block), st,
                      d_probs, d_starts, n_probs, d_next, refill_min, stack_levels, (SlotState *)slots, budget, slice);
   return hipGetLastError();

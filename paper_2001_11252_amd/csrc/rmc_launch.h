@@ -12,10 +12,12 @@ namespace rmc {
 // problem of the launch has a single line (a kernel specialised for it).
 // regroup (with defer): one rejection round of a line scattering per pass
 // of the loop, a rejected round leaving the event pending for the next.
+// tail (single problem, defer): the kernel compiled for one wave per SIMD,
+// for grids of at most one wave per SIMD.
 hipError_t launch_transport(bool fp32, bool batch, bool defer, bool one_line, bool regroup, const ProblemK *d_probs,
                             const int64_t *d_starts, int n_probs, unsigned long long *d_next, int refill_min,
                             int stack_levels, int grid, int block, void *slots, int budget,
-                            unsigned long long *slice, hipStream_t st);
+                            unsigned long long *slice, hipStream_t st, bool tail = false);
 size_t slot_bytes();
 // Ray-cast pass over the peel-off queue pq (a device PeelQueue), then the
 // queue reset; grid blocks of 256 threads.
