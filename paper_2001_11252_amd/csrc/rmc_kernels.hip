@@ -753,10 +753,10 @@ __device__ __forceinline__ void add_delta(SliceCount &a, const Lane<R> &s, const
 }
 
 // Waves per SIMD the transport kernel is compiled for (register budget,
-// chosen by measurement): the float single-problem, single-line kernel with
-// deferred peel-off runs four (about 30 registers spill, and it is still
-// 8% faster than at three), the other float kernels three (no spills; at
-// four the batch and four-line kernels spill 40-70 registers and the batch
+// chosen by measurement): the float single-problem kernels with deferred
+// peel-off run four (about 30 registers spill with one line, 40 with four,
+// and they are 8-9% faster than at three), the other float kernels three
+// (no spills; at four the batch kernels spill 50-90 registers and the batch
 // runs slower), the single-problem double kernels with deferred peel-off
 // two (40-55 registers spill, and the dusty sphere runs 38% faster than at
 // one, where nothing spills), the other double kernels (batch, inline
@@ -767,6 +767,9 @@ __device__ __forceinline__ void add_delta(SliceCount &a, const Lane<R> &s, const
 #ifndef RMC_WAVES_F32
 #define RMC_WAVES_F32 3
 #endif
+#ifndef RMC_WAVES_F32_MULTI
+#define RMC_WAVES_F32_MULTI 4
+#endif
 #ifndef RMC_WAVES_F64
 #define RMC_WAVES_F64 2
 #endif
@@ -775,7 +778,7 @@ __device__ __forceinline__ void add_delta(SliceCount &a, const Lane<R> &s, const
 #endif
 template <class R, bool BATCH, bool DEFER, int NL> struct WavesPerEU;
 template <bool BATCH, bool DEFER, int NL> struct WavesPerEU<float, BATCH, DEFER, NL> {
-  static constexpr int v = (!BATCH && DEFER && NL == 1) ? RMC_WAVES_F32_LEAN : RMC_WAVES_F32;
+  static constexpr int v = (!BATCH && DEFER) ? (NL == 1 ? RMC_WAVES_F32_LEAN : RMC_WAVES_F32_MULTI) : RMC_WAVES_F32;
 };
 template <bool BATCH, bool DEFER, int NL> struct WavesPerEU<double, BATCH, DEFER, NL> {
   static constexpr int v = (!BATCH && DEFER) ? RMC_WAVES_F64 : RMC_WAVES_F64_WIDE;
