@@ -429,12 +429,30 @@ void make_problem(rmc_ctx *c, int64_t first, int64_t n, uint64_t seed, ProblemK 
         k.sf[j] = l0 / lf;
       }
     }
+    k.f.delta = (float)k.delta;
+    k.f.s = (float)k.s;
+    k.f.inv_s = (float)k.inv_s;
+    k.f.inv_mu = (float)k.inv_mu;
+    k.f.mu = (float)k.mu;
+    k.f.alpha = (float)k.alpha;
+    k.f.kfac = (float)k.kfac;
+    k.f.ibmu = (float)k.ibmu;
+    k.f.rec = (float)k.rec;
+    k.f.a_res = (float)k.a_res;
+    k.f.a_cum0 = (float)k.a_cum0;
+    for (int j = 0; j < 2; ++j) {
+      k.f.xf0[j] = (float)k.xf0[j];
+      k.f.sf[j] = (float)k.sf[j];
+    }
   }
+  pb.b_ref_f = (float)pb.b_ref;
   pb.box_cm = c->box_cm;
   pb.domain = c->domain;
   for (int d = 0; d < 4; ++d) pb.dom[d] = c->dom[d];
   pb.albedo = c->albedo;
   pb.g_hg = c->g_hg;
+  pb.albedo_f = (float)pb.albedo;
+  pb.g_hg_f = (float)pb.g_hg;
   pb.forward_only = c->forward_only;
   pb.max_events = c->max_events;
   pb.skip_tau = c->skip_tau;
@@ -920,6 +938,7 @@ rmc_status rmc_add_observer(rmc_ctx *c, const double k[3], int nx, int ny, int n
   o.k.ny = ny;
   o.k.nbins = nbins;
   for (int d = 0; d < 3; ++d) o.k.kinv[d] = k[d] != 0.0 ? 1.0 / k[d] : 0.0;
+  for (int d = 0; d < 3; ++d) o.k.kf[d] = (float)o.k.k[d];
   o.k.su = nx / o.k.uspan;
   o.k.sv = ny / o.k.vspan;
   o.k.sx = nbins / o.k.xspan;

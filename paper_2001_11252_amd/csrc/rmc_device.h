@@ -51,13 +51,24 @@ struct LineK {
   // sf = lambda_ref / lambda_j (nu_j / nu_ref)
   int n_fluor;
   double a_res, a_cum0, xf0[2], sf[2];
+  // the same constants rounded to float on the host (as a conversion on the
+  // device would round them), for the float path
+  struct {
+    float delta, s, inv_s, inv_mu, mu, alpha, kfac, ibmu, rec, a_res, a_cum0, xf0[2], sf[2];
+  } f;
 };
+
+// A constant in the path's precision: the double, or its float copy.
+template <class R> __device__ __forceinline__ R cst(double d, float f);
+template <> __device__ __forceinline__ double cst<double>(double d, float) { return d; }
+template <> __device__ __forceinline__ float cst<float>(double, float f) { return f; }
 
 struct ObsK {
   double k[3], e1[3], e2[3];
   double u0, uspan, v0, vspan, x_min, xspan;
   double su, sv, sx;   // nx/uspan, ny/vspan, nbins/xspan (float path binning)
   double kinv[3];      // 1/k (0 where k is 0; float path ray walks)
+  float kf[3];         // k rounded to float
   int nx, ny, nbins, pad;
   void *cube;      // [ny][nx][nbins], float or double by precision
 };
@@ -127,6 +138,7 @@ struct ProblemK {
   int domain;
   double dom[4];
   double albedo, g_hg;
+  float b_ref_f, albedo_f, g_hg_f;  // b_ref, albedo and g_hg rounded to float
   int forward_only;
   int64_t max_events;
   double skip_tau, skip_frac; // core-skipping (skip_tau > 0: on)
@@ -192,9 +204,8 @@ enum {
 
 // Uniforms of one event.  Double: draw j uses the word pair (2(j%2),
 // 2(j%2)+1) of block j/2 and returns (2m+1) 2^-53 with m the top 52 bits.
-// Float: draw j uses word p%4 of block p/4, p = float_word(j) (below), and
-// returns (2m+1) 2^-24 with m
-// the top 23 bits.  Both lie strictly inside (0,1).
+// Float: (2m+1) 2^-24 with m 23 bits of the blocks' words, placed below.
+// Both lie strictly inside (0,1).
 template <class R> struct EventRng;
 
 template <> struct EventRng<double> {
@@ -220,40 +231,84 @@ template <> struct EventRng<double> {
   __device__ double u_small(uint32_t j) { return u(j); }
 };
 
-// Float: the slots of the first two blocks are placed by when an event
-// uses them, so that with one block kept each block of an event is
-// computed once: block 0 holds the channel, tau_event and the first
-// rejection round (or the albedo test, or the |x| >= 8 Gaussian pair),
-// block 1 the perpendicular velocities and the new direction; slot j sits
-// at word float_word(j) (nibble j of 0x32541760 for j < 8, j beyond).
-__device__ __forceinline__ uint32_t float_word(uint32_t j) {
-  return j < 8u ? (0x32541760u >> (4u * j)) & 15u : j;
-}
-
+// Float: a draw takes 23 bits, so a 32-bit word has 9 to spare.  Two blocks
+// hold every draw of an event up to its second rejection round:
+//   block 0  word 0 the channel (all 32 bits), the top 23 bits of word 1
+//            tau_event, of words 2 and 3 the first rejection round (or the
+//            albedo test, or the |x| >= 8 Gaussian pair); the direction
+//            cosine from the low 9 bits of words 1, 2, 3 (the top 23 of 27)
+//   block 1  the top 23 bits of words 0 and 1 the second rejection round,
+//            of words 2 and 3 the perpendicular velocities (emission: the
+//            source-spectrum pair); the azimuth from the low 9 bits of words
+//            0, 1, 2
+//   block k  (k >= 2) the top 23 bits of words 0 and 1: rejection round k
+// so the second rejection round costs no block of its own.  Draw j >= 8
+// (rounds beyond the first, and the decay draw far above them) is word
+// (j - 6) % 2 of block (j - 6) / 2.
 template <> struct EventRng<float> {
   uint2 key;
   uint32_t plo, phi, ev;
-  uint32_t cur;
-  uint4 w;
+  uint4 b0, b1;
+  bool have1;
   __device__ EventRng(uint64_t seed, uint64_t pid, uint32_t event)
       : key(make_uint2((uint32_t)seed, (uint32_t)(seed >> 32))), plo((uint32_t)pid),
-        phi((uint32_t)(pid >> 32)), ev(event), cur(0xffffffffu) {}
-  __device__ uint32_t word(uint32_t j) {
-    const uint32_t p = float_word(j);
-    const uint32_t b = p >> 2;
-    if (b != cur) {
-      w = philox4x32_10(make_uint4(plo, phi, ev, b), key);
-      cur = b;
-    }
-    const uint32_t q = p & 3;
-    return q == 0 ? w.x : (q == 1 ? w.y : (q == 2 ? w.z : w.w));
+        phi((uint32_t)(pid >> 32)), ev(event), have1(false) {
+    b0 = block(0);
   }
-  __device__ float u(uint32_t j) { return (float)(2u * (word(j) >> 9) + 1u) * 0x1p-24f; }
-  // Draw j for a comparison with a probability that may be far below the
-  // 2^-23 spacing of u (kappa_d / kappa in an optically thick line core):
-  // the whole 32-bit word, whose conversion is exact below 2^24, so near
-  // zero the draw is resolved to 2^-32.  Lies in [0, 1].
-  __device__ float u_small(uint32_t j) { return (float)word(j) * 0x1p-32f; }
+  __device__ uint4 block(uint32_t b) const { return philox4x32_10(make_uint4(plo, phi, ev, b), key); }
+  // block 1, computed once (where every lane of a branch that needs it is
+  // active, the block is computed once per wave)
+  __device__ void need1() {
+    if (!have1) {
+      b1 = block(1);
+      have1 = true;
+    }
+  }
+  static __device__ __forceinline__ float top(uint32_t w) { return (float)(2u * (w >> 9) + 1u) * 0x1p-24f; }
+  static __device__ __forceinline__ float low(uint32_t a, uint32_t b, uint32_t c) {
+    const uint32_t m = ((a & 511u) << 14) | ((b & 511u) << 5) | ((c & 511u) >> 4);
+    return (float)(2u * m + 1u) * 0x1p-24f;
+  }
+  // the pair of rejection round k (draws J_REJ + 2k and J_REJ + 2k + 1)
+  __device__ void round(uint32_t k, float *r1, float *r3) {
+    uint32_t x, y;
+    if (k == 0) {
+      x = b0.z;
+      y = b0.w;
+    } else if (k == 1) {
+      need1();
+      x = b1.x;
+      y = b1.y;
+    } else {
+      const uint4 w = block(k);
+      x = w.x;
+      y = w.y;
+    }
+    *r1 = top(x);
+    *r3 = top(y);
+  }
+  __device__ float u(uint32_t j) {
+    switch (j) {
+      case J_CHANNEL: return top(b0.x);
+      case J_TAU: return top(b0.y);
+      case J_MU: return low(b0.y, b0.z, b0.w);
+      case J_PHI: need1(); return low(b1.x, b1.y, b1.z);
+      case J_PERP1: need1(); return top(b1.z);
+      case J_PERP2: need1(); return top(b1.w);
+      case J_REJ: return top(b0.z);
+      case J_REJ + 1: return top(b0.w);
+      default: {
+        float r1, r3;
+        round((j - J_REJ) >> 1, &r1, &r3);
+        return (j & 1) ? r3 : r1;
+      }
+    }
+  }
+  // The channel draw, compared with a probability that may be far below
+  // the 2^-23 spacing of u (kappa_d / kappa in an optically thick line
+  // core): the whole 32-bit word, so near zero the draw is resolved to
+  // 2^-32.  Lies in [0, 1].
+  __device__ float u_small(uint32_t) { return (float)b0.x * 0x1p-32f; }
 };
 
 // ------------------------------------------------------------ math policy
@@ -461,26 +516,37 @@ template <class R> __device__ __forceinline__ UparEnv<R> upar_env(R x, R a, R la
   return e;
 }
 
+// One float round from its pair: r1 picks the piece and, rescaled within
+// it, the angle; r3 accepts or rejects.
+__device__ __forceinline__ bool upar_try_pair(const UparEnv<float> &e, float a, float r1, float r3, float *out) {
+  const float hp = float(0.5 * PI_D);
+  float th, lim;
+  if (r1 < e.p1) {
+    th = -hp + r1 * e.s1;
+    lim = 0.0f;
+  } else {
+    th = e.th0 + (r1 - e.p1) * e.s2;
+    lim = e.u02;
+  }
+  const float u = e.xa + a * M<float>::tan(th);
+  *out = e.sg * u;
+  return r3 < M<float>::exp(lim - u * u);
+}
+
 // Round `it` of the rejection draw (|x| < 8): true when it accepts, with
 // the velocity in *out.
 template <class R>
 __device__ __forceinline__ bool upar_try(const UparEnv<R> &e, R a, EventRng<R> &rng, uint32_t it, R *out) {
-  const R hp = R(0.5 * PI_D);
-  R th, lim, r3;
   if constexpr (sizeof(R) == 4) {
-    const R r1 = rng.u(J_REJ + 2 * it);
-    r3 = rng.u(J_REJ + 2 * it + 1);
-    if (r1 < e.p1) {
-      th = -hp + r1 * e.s1;
-      lim = R(0);
-    } else {
-      th = e.th0 + (r1 - e.p1) * e.s2;
-      lim = e.u02;
-    }
+    float r1, r3;
+    rng.round(it, &r1, &r3);
+    return upar_try_pair(e, a, r1, r3, out);
   } else {
+    const R hp = R(0.5 * PI_D);
+    R th, lim;
     const R r1 = rng.u(J_REJ + 3 * it);
     const R r2 = rng.u(J_REJ + 3 * it + 1);
-    r3 = rng.u(J_REJ + 3 * it + 2);
+    const R r3 = rng.u(J_REJ + 3 * it + 2);
     if (r1 < e.p1) {
       th = -hp + r2 * (e.th0 + hp);
       lim = R(0);
@@ -488,10 +554,10 @@ __device__ __forceinline__ bool upar_try(const UparEnv<R> &e, R a, EventRng<R> &
       th = e.th0 + r2 * (hp - e.th0);
       lim = e.u02;
     }
+    const R u = e.xa + a * M<R>::tan(th);
+    *out = e.sg * u;
+    return r3 < M<R>::exp(lim - u * u);
   }
-  const R u = e.xa + a * M<R>::tan(th);
-  *out = e.sg * u;
-  return r3 < M<R>::exp(lim - u * u);
 }
 
 // The |x| >= 8 branch: Gaussian of variance 1/2 centred at 1/x.
@@ -509,7 +575,23 @@ __device__ __forceinline__ bool sample_upar(R x, R a, R la, EventRng<R> &rng, R 
     return true;
   }
   const UparEnv<R> e = upar_env(x, a, la);
-  for (uint32_t it = 0; it < MAX_REJECT; ++it) {
+  uint32_t it = 0;
+  if constexpr (sizeof(R) == 4) {
+    // float: the first two rounds side by side (their draws are in blocks 0
+    // and 1, which the event computes anyway): a wave in which a few lanes
+    // reject the first round would run the second for them alone
+    float r1, r3, q1, q3, v0, v1;
+    rng.round(0, &r1, &r3);
+    rng.round(1, &q1, &q3);
+    const bool a0 = upar_try_pair(e, a, r1, r3, &v0);
+    const bool a1 = upar_try_pair(e, a, q1, q3, &v1);
+    if (a0 || a1) {
+      *out = a0 ? v0 : v1;
+      return true;
+    }
+    it = 2;
+  }
+  for (; it < MAX_REJECT; ++it) {
     if (upar_try(e, a, rng, it, out)) return true;
   }
   *out = R(0);
@@ -797,7 +879,7 @@ __device__ __forceinline__ void opacity(const ProblemK &pb, const LeafRec<R> &lf
                                         Opac<R, NL> &o) {
   const double wd = (double)k[0] * (double)lf.ux + (double)k[1] * (double)lf.uy + (double)k[2] * (double)lf.uz;
   o.w = (R)wd;
-  const R inv_den = M<R>::div(R(1), R(1) + R(pb.b_ref) * o.w);
+  const R inv_den = M<R>::div(R(1), R(1) + cst<R>(pb.b_ref, pb.b_ref_f) * o.w);
   o.kd = lf.kd;
   o.ktot = lf.kd;
 #pragma unroll
@@ -806,15 +888,15 @@ __device__ __forceinline__ void opacity(const ProblemK &pb, const LeafRec<R> &lf
     o.kl[i] = R(0);
     if (NL == 1 || i < pb.n_lines) {
       const LineK &ln = pb.lines[i];
-      o.x[i] = (R)(ln.delta + ln.s * x_ext - wd) * lf.irho * R(ln.inv_mu) * inv_den;
-      const R a = R(ln.alpha) * lf.irho;
+      o.x[i] = (R)(ln.delta + ln.s * x_ext - wd) * lf.irho * cst<R>(ln.inv_mu, ln.f.inv_mu) * inv_den;
+      const R a = cst<R>(ln.alpha, ln.f.alpha) * lf.irho;
       R H;
       // the accurate H is a double-path option (the float kernels stay free of it)
       if constexpr (sizeof(R) == 8)
         H = pb.voigt_exact ? voigt_h_exact(a, o.x[i]) : voigt_h<R>(a, o.x[i]);
       else
         H = voigt_h<R>(a, o.x[i]);
-      o.kl[i] = lf.nl * R(ln.kfac) * H;
+      o.kl[i] = lf.nl * cst<R>(ln.kfac, ln.f.kfac) * H;
       o.ktot += o.kl[i];
     }
   }
@@ -833,7 +915,7 @@ __device__ __forceinline__ void opacity(const ProblemK &pb, const LeafRec<R> &lf
 template <class R>
 __device__ __forceinline__ R core_skip_x2(const ProblemK &pb, const LineK &ln, const LeafRec<R> &lf, int level,
                                           R a, R x) {
-  const R tc = lf.nl * R(ln.kfac) * (R)ldexp(1.0, -level);
+  const R tc = lf.nl * cst<R>(ln.kfac, ln.f.kfac) * (R)ldexp(1.0, -level);
   const R ts = R(pb.skip_tau);
   if (!(tc > ts)) return R(0);
   const R xt2 = M<R>::log(M<R>::div(tc, ts));

@@ -273,7 +273,7 @@ __device__ void peel_all(const ProblemK &pb, const double p[3], const PeelSrc<R>
                          int stride, LaneCount &cnt, const PeelSink<R> &snk, const StartCell<R> *sc = nullptr) {
   for (int oi = 0; oi < pb.n_obs; ++oi) {
     const ObsK &ob = pb.obs[oi];
-    const R ko[3] = {(R)ob.k[0], (R)ob.k[1], (R)ob.k[2]};
+    const R ko[3] = {cst<R>(ob.k[0], ob.kf[0]), cst<R>(ob.k[1], ob.kf[1]), cst<R>(ob.k[2], ob.kf[2])};
     R xo, mu = R(0);
     if (s.kind == 0) {
       xo = s.x;
@@ -282,29 +282,29 @@ __device__ void peel_all(const ProblemK &pb, const double p[3], const PeelSrc<R>
       // in the atom frame, then through the cell's velocity
       const LineK &ln = pb.lines[s.line];
       const R ba = s.bc * (ko[0] * s.U[0] + ko[1] * s.U[1] + ko[2] * s.U[2]);
-      const R bw = R(pb.b_ref) * (ko[0] * s.ux + ko[1] * s.uy + ko[2] * s.uz);
-      xo = R(ln.xf0[s.core]) + M<R>::div(R(ln.sf[s.core]) * (ba + bw + ba * bw), R(pb.b_ref));
+      const R bw = cst<R>(pb.b_ref, pb.b_ref_f) * (ko[0] * s.ux + ko[1] * s.uy + ko[2] * s.uz);
+      xo = cst<R>(ln.xf0[s.core], ln.f.xf0[s.core]) + M<R>::div(cst<R>(ln.sf[s.core], ln.f.sf[s.core]) * (ba + bw + ba * bw), cst<R>(pb.b_ref, pb.b_ref_f));
     } else if (s.kind == 1) {
       const LineK &ln = pb.lines[s.line];
       mu = s.kin[0] * ko[0] + s.kin[1] * ko[1] + s.kin[2] * ko[2];
       const R dkU = (ko[0] - s.kin[0]) * s.U[0] + (ko[1] - s.kin[1]) * s.U[1] + (ko[2] - s.kin[2]) * s.U[2];
       const R g1 = R(1) + s.bc * s.x;
-      const R Rr = ln.recoil ? (R(1) - mu) * R(ln.rec) * g1 : R(0);
+      const R Rr = ln.recoil ? (R(1) - mu) * cst<R>(ln.rec, ln.f.rec) * g1 : R(0);
       R xc;
       if constexpr (sizeof(R) == 4) {
         // Rr < 3e-8 for any line and scatterer (h nu <= 13.6 eV, m c^2 >=
         // 938 MeV): 1/(1 + Rr) = 1 - Rr to float precision, and
         // Rr/bc = Rr irho / (b_ref mu)
-        xc = (s.x + g1 * dkU - Rr * R(ln.ibmu) * s.irho) * (R(1) - Rr);
+        xc = (s.x + g1 * dkU - Rr * cst<R>(ln.ibmu, ln.f.ibmu) * s.irho) * (R(1) - Rr);
       } else {
         xc = M<R>::div(s.x + g1 * dkU - M<R>::div(Rr, s.bc), R(1) + Rr);
       }
       const R wo = ko[0] * s.ux + ko[1] * s.uy + ko[2] * s.uz;
-      xo = (R(-ln.delta) + R(ln.mu) * s.rho * xc * (R(1) + R(pb.b_ref) * wo) + wo) * R(ln.inv_s);
+      xo = (-cst<R>(ln.delta, ln.f.delta) + cst<R>(ln.mu, ln.f.mu) * s.rho * xc * (R(1) + cst<R>(pb.b_ref, pb.b_ref_f) * wo) + wo) * cst<R>(ln.inv_s, ln.f.inv_s);
     } else {
       mu = s.kin[0] * ko[0] + s.kin[1] * ko[1] + s.kin[2] * ko[2];
       const R wo = ko[0] * s.ux + ko[1] * s.uy + ko[2] * s.uz;
-      const R b = R(pb.b_ref);
+      const R b = cst<R>(pb.b_ref, pb.b_ref_f);
       xo = M<R>::div(s.x + wo + b * s.x * wo - s.w, R(1) + b * s.w);
     }
     ++cnt.peel_rays;
@@ -326,7 +326,7 @@ __device__ void peel_all(const ProblemK &pb, const double p[3], const PeelSrc<R>
       const R P = ln.phase == PHASE_ISO ? R(0.5) : (s.core ? p_core(mu) : p_wing(mu));
       weight = P * R(1.0 / (2.0 * PI_D));
     } else {
-      weight = p_hg(mu, R(pb.g_hg)) * R(1.0 / (2.0 * PI_D));
+      weight = p_hg(mu, cst<R>(pb.g_hg, pb.g_hg_f)) * R(1.0 / (2.0 * PI_D));
     }
     if constexpr (DEFER && sizeof(R) == 4) {
       // the float ray-cast pass bins the ray from its start (and counts
@@ -540,12 +540,15 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R, NL> &o, in
   EventRng<R> rng(pb.seed, (uint64_t)s.pid, s.event);
   // kappa_d / kappa reaches ~1e-8 in optically thick line cores
   R r = rng.u_small(J_CHANNEL) * o.ktot;
-  // the generator keeps one Philox block: the draw of the channel's block
-  // that the event uses last is taken now, so that no block of the event is
-  // computed twice (tau_event in the float layout, the scattering angle in
-  // the double one)
+  // the double generator keeps one Philox block: the draw of the channel's
+  // block that the event uses last (the scattering angle) is taken now, so
+  // that no block of the event is computed twice; the float path takes the
+  // draws of block 0 it needs late now (tau_event and the scattering angle),
+  // which leaves that block's words dead after the first rejection round
   const R r_late = rng.u(sizeof(R) == 4 ? J_TAU : J_MU);
-  auto u_mu = [&]() { return sizeof(R) == 8 ? r_late : rng.u(J_MU); };
+  R r_mu = R(0);
+  if constexpr (sizeof(R) == 4) r_mu = rng.u(J_MU);
+  auto u_mu = [&]() { return sizeof(R) == 8 ? r_late : r_mu; };
   auto u_tau = [&]() { return sizeof(R) == 4 ? r_late : rng.u(J_TAU); };
   const R kin[3] = {s.k[0], s.k[1], s.k[2]};
   // the pair perpendicular to k_in is formed where it is used (after the
@@ -558,7 +561,7 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R, NL> &o, in
   ps.w = o.w;
   if (r < o.kd) {
     // dust (Sect. 3.2.2): absorbed with probability 1 - albedo, else HG
-    if (rng.u(J_ALBEDO) >= R(pb.albedo)) return ST_ABSORBED;
+    if (rng.u(J_ALBEDO) >= cst<R>(pb.albedo, pb.albedo_f)) return ST_ABSORBED;
     ++s.cnt.dust_scat;
     if (pb.n_obs) {
       ps.kind = 2;
@@ -567,7 +570,7 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R, NL> &o, in
     }
     if (!pb.forward_only) {
       perp_basis(kin, e1, e2);
-      const R mu = mu_hg(u_mu(), R(pb.g_hg));
+      const R mu = mu_hg(u_mu(), cst<R>(pb.g_hg, pb.g_hg_f));
       R sp, cp;
       M<R>::sincos2pi(rng.u(J_PHI), &sp, &cp);
       const R st = M<R>::sqrt(fmax(R(0), R(1) - mu * mu));
@@ -576,7 +579,7 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R, NL> &o, in
       set_geom_dir(s);
       // coherent in the cell frame
       const R wn = s.k[0] * s.lf.ux + s.k[1] * s.lf.uy + s.k[2] * s.lf.uz;
-      const R b = R(pb.b_ref);
+      const R b = cst<R>(pb.b_ref, pb.b_ref_f);
       s.x = M<R>::div(s.x + wn + b * s.x * wn - o.w, R(1) + b * o.w);
     }
   } else {
@@ -600,10 +603,24 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R, NL> &o, in
       }
     }
     const LineK &ln = pb.lines[i];
-    const R a = R(ln.alpha) * s.lf.irho;
+    const R a = cst<R>(ln.alpha, ln.f.alpha) * s.lf.irho;
     // log10 a for the envelope: the double path adds the line's log10 alpha
     // and the leaf's log10(1/rho) (its record holds it)
     const R la = sizeof(R) == 8 ? R(ln.lalpha) + s.lf.lg : M<R>::log10(a);
+    // float: block 1 (the second rejection round, the perpendicular
+    // velocities and the azimuth) for every lane of the branch at once, its
+    // outgoing draws taken now so that its words are dead after the
+    // sampler's second round
+    R r_p1 = R(0), r_p2 = R(0), r_phi = R(0);
+    if constexpr (sizeof(R) == 4) {
+      rng.need1();
+      r_p1 = rng.u(J_PERP1);
+      r_p2 = rng.u(J_PERP2);
+      r_phi = rng.u(J_PHI);
+    }
+    auto u_p1 = [&]() { return sizeof(R) == 4 ? r_p1 : rng.u(J_PERP1); };
+    auto u_p2 = [&]() { return sizeof(R) == 4 ? r_p2 : rng.u(J_PERP2); };
+    auto u_phi = [&]() { return sizeof(R) == 4 ? r_phi : rng.u(J_PHI); };
     R upar;
     if constexpr (REGROUP) {
       if (!upar_round<R>(x, a, la, rng, s.rej, &upar)) {
@@ -619,14 +636,14 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R, NL> &o, in
     const R xc2 = pb.skip_tau > 0.0 ? core_skip_x2<R>(pb, ln, s.lf, s.c.level, a, x) : R(0);
     perp_basis(kin, e1, e2);
     R sp, cp;
-    M<R>::sincos2pi(rng.u(J_PERP2), &sp, &cp);
-    const R rr = M<R>::sqrt(xc2 - M<R>::log(rng.u(J_PERP1)));
+    M<R>::sincos2pi(u_p2(), &sp, &cp);
+    const R rr = M<R>::sqrt(xc2 - M<R>::log(u_p1()));
     const R up1 = rr * cp, up2 = rr * sp;
     R U[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) U[d] = upar * kin[d] + up1 * e1[d] + up2 * e2[d];
     const R rho = M<R>::div(R(1), s.lf.irho);
-    const R bc = R(pb.b_ref) * R(ln.mu) * rho;
+    const R bc = cst<R>(pb.b_ref, pb.b_ref_f) * cst<R>(ln.mu, ln.f.mu) * rho;
     // frequency seen by the atom, nu_in (1 - k_in.v/c), within 0.2 dnu_D
     const R g1 = R(1) + bc * x;
     const int core = fabs(x - g1 * upar) < R(0.2);
@@ -637,7 +654,7 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R, NL> &o, in
     if constexpr (NL > 1) {
       if (ln.n_fluor > 0 && !pb.forward_only) {
         const R ud = rng.u(J_DECAY);
-        if (ud >= R(ln.a_res)) fch = (ln.n_fluor > 1 && ud >= R(ln.a_cum0)) ? 1 : 0;
+        if (ud >= cst<R>(ln.a_res, ln.f.a_res)) fch = (ln.n_fluor > 1 && ud >= cst<R>(ln.a_cum0, ln.f.a_cum0)) ? 1 : 0;
       }
     }
     ++s.nscat;
@@ -651,14 +668,14 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R, NL> &o, in
         peel_all<R, DEFER, NL>(pb, s.p, ps, pstk, stride, s.cnt, snk, &sc);
       }
       const R mu = R(2) * u_mu() - R(1);
-      M<R>::sincos2pi(rng.u(J_PHI), &sp, &cp);
+      M<R>::sincos2pi(u_phi(), &sp, &cp);
       const R st = M<R>::sqrt(fmax(R(0), R(1) - mu * mu));
 #pragma unroll
       for (int d = 0; d < 3; ++d) s.k[d] = mu * kin[d] + st * (cp * e1[d] + sp * e2[d]);
       set_geom_dir(s);
       const R ba = bc * (s.k[0] * U[0] + s.k[1] * U[1] + s.k[2] * U[2]);
-      const R bw = R(pb.b_ref) * (s.k[0] * s.lf.ux + s.k[1] * s.lf.uy + s.k[2] * s.lf.uz);
-      s.x = R(ln.xf0[fch]) + M<R>::div(R(ln.sf[fch]) * (ba + bw + ba * bw), R(pb.b_ref));
+      const R bw = cst<R>(pb.b_ref, pb.b_ref_f) * (s.k[0] * s.lf.ux + s.k[1] * s.lf.uy + s.k[2] * s.lf.uz);
+      s.x = cst<R>(ln.xf0[fch], ln.f.xf0[fch]) + M<R>::div(cst<R>(ln.sf[fch], ln.f.sf[fch]) * (ba + bw + ba * bw), cst<R>(pb.b_ref, pb.b_ref_f));
       s.tau = -(double)M<R>::log(u_tau());
       return ST_NONE;
     }
@@ -676,7 +693,7 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R, NL> &o, in
     if (!pb.forward_only) {
       const R ru = u_mu();
       const R mu = ln.phase == PHASE_ISO ? R(2) * ru - R(1) : mu_dipole(ru, core != 0);
-      M<R>::sincos2pi(rng.u(J_PHI), &sp, &cp);
+      M<R>::sincos2pi(u_phi(), &sp, &cp);
       const R st = M<R>::sqrt(fmax(R(0), R(1) - mu * mu));
 #pragma unroll
       for (int d = 0; d < 3; ++d) s.k[d] = mu * kin[d] + st * (cp * e1[d] + sp * e2[d]);
@@ -684,16 +701,16 @@ __device__ int interact(const ProblemK &pb, Lane<R> &s, const Opac<R, NL> &o, in
       // outgoing frequency, coherent in the atom frame, recoil in the
       // denominator (Eq. for nu_out), then back to the external frame
       const R dkU = (s.k[0] - kin[0]) * U[0] + (s.k[1] - kin[1]) * U[1] + (s.k[2] - kin[2]) * U[2];
-      const R Rr = ln.recoil ? (R(1) - mu) * R(ln.rec) * g1 : R(0);
+      const R Rr = ln.recoil ? (R(1) - mu) * cst<R>(ln.rec, ln.f.rec) * g1 : R(0);
       R xc;
       if constexpr (sizeof(R) == 4) {
         // as in the peel-off: 1/(1 + Rr) = 1 - Rr and Rr/bc = Rr irho/(b_ref mu)
-        xc = (x + g1 * dkU - Rr * R(ln.ibmu) * s.lf.irho) * (R(1) - Rr);
+        xc = (x + g1 * dkU - Rr * cst<R>(ln.ibmu, ln.f.ibmu) * s.lf.irho) * (R(1) - Rr);
       } else {
         xc = M<R>::div(x + g1 * dkU - M<R>::div(Rr, bc), R(1) + Rr);
       }
       const R wn = s.k[0] * s.lf.ux + s.k[1] * s.lf.uy + s.k[2] * s.lf.uz;
-      s.x = (R(-ln.delta) + R(ln.mu) * rho * xc * (R(1) + R(pb.b_ref) * wn) + wn) * R(ln.inv_s);
+      s.x = (-cst<R>(ln.delta, ln.f.delta) + cst<R>(ln.mu, ln.f.mu) * rho * xc * (R(1) + cst<R>(pb.b_ref, pb.b_ref_f) * wn) + wn) * cst<R>(ln.inv_s, ln.f.inv_s);
     }
   }
   s.tau = -(double)M<R>::log(u_tau());

@@ -59,16 +59,14 @@ def test_gpu_recoil_follows_the_outgoing_frequency_relation(orc, prec, phase, x_
     assert abs(shift.mean() + g_r * (nu_in / nu0) * np.mean(1 - mu)) < (1e-4 if prec == "fp64" else 1e-2) * g_r
 
 
-def _float_uniform(orc, seed, pid, event, j):
-    # the float path's draw j: word p % 4 of Philox block p / 4, top 23 bits,
-    # with p the slot's place in the float layout (slots 0..7 at words 0, 6,
-    # 7, 1, 4, 5, 2, 3: the channel, tau_event and the first rejection round
-    # in block 0, the perpendicular velocities and the direction in block 1)
-    p = (0, 6, 7, 1, 4, 5, 2, 3)[j] if j < 8 else j
-    ctr = [pid & 0xFFFFFFFF, pid >> 32, event, p >> 2]
+def _float_mu_uniform(orc, seed, pid, event):
+    # the float path's scattering-angle draw: 23 bits from the low 9 bits of
+    # words 1, 2 and 3 of Philox block 0 of the event (the top 23 of those 27)
+    ctr = [pid & 0xFFFFFFFF, pid >> 32, event, 0]
     key = [seed & 0xFFFFFFFF, seed >> 32]
-    w = int(orc.philox(ctr, key)[p & 3])
-    return (2 * (w >> 9) + 1) * 2.0 ** -24
+    w = [int(v) for v in orc.philox(ctr, key)]
+    m = ((w[1] & 511) << 14) | ((w[2] & 511) << 5) | ((w[3] & 511) >> 4)
+    return (2 * m + 1) * 2.0 ** -24
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -81,7 +79,7 @@ def test_gpu_lya_core_wing_switch(orc, prec, T, x_in):
         ru = np.array([orc.uniform(seed, i, 1, J_MU) for i in range(n)])
         tol = 1e-12
     else:
-        ru = np.array([_float_uniform(orc, seed, i, 1, J_MU) for i in range(n)])
+        ru = np.array([_float_mu_uniform(orc, seed, i, 1) for i in range(n)])
         tol = 2e-5
     mc, mw = _invert(_cdf_core, ru), _invert(_cdf_wing, ru)
     dc, dw = np.abs(mu - mc), np.abs(mu - mw)
