@@ -241,10 +241,11 @@ template <> struct EventRng<double> {
 //            of words 2 and 3 the perpendicular velocities (emission: the
 //            source-spectrum pair); the azimuth from the low 9 bits of words
 //            0, 1, 2
-//   block k  (k >= 2) the top 23 bits of words 0 and 1: rejection round k
+//   block b  (b >= 2) the top 23 bits of words 0 and 1 rejection round
+//            2b - 2, of words 2 and 3 round 2b - 1
 // so the second rejection round costs no block of its own.  Draw j >= 8
-// (rounds beyond the first, and the decay draw far above them) is word
-// (j - 6) % 2 of block (j - 6) / 2.
+// (rounds beyond the first, and the decay draw far above them) belongs to
+// round k = (j - 6) / 2 (its first or second draw as j is even or odd).
 template <> struct EventRng<float> {
   uint2 key;
   uint32_t plo, phi, ev;
@@ -280,9 +281,9 @@ template <> struct EventRng<float> {
       x = b1.x;
       y = b1.y;
     } else {
-      const uint4 w = block(k);
-      x = w.x;
-      y = w.y;
+      const uint4 w = block(1 + k / 2);
+      x = (k & 1) ? w.z : w.x;
+      y = (k & 1) ? w.w : w.y;
     }
     *r1 = top(x);
     *r3 = top(y);
@@ -589,10 +590,16 @@ __device__ __forceinline__ bool sample_upar(R x, R a, R la, EventRng<R> &rng, R 
       *out = a0 ? v0 : v1;
       return true;
     }
-    it = 2;
-  }
-  for (; it < MAX_REJECT; ++it) {
-    if (upar_try(e, a, rng, it, out)) return true;
+    // then two rounds per block
+    for (it = 2; it < MAX_REJECT; it += 2) {
+      const uint4 w = rng.block(1 + it / 2);
+      if (upar_try_pair(e, a, EventRng<float>::top(w.x), EventRng<float>::top(w.y), out)) return true;
+      if (upar_try_pair(e, a, EventRng<float>::top(w.z), EventRng<float>::top(w.w), out)) return true;
+    }
+  } else {
+    for (; it < MAX_REJECT; ++it) {
+      if (upar_try(e, a, rng, it, out)) return true;
+    }
   }
   *out = R(0);
   return false;
