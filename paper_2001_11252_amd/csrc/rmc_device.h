@@ -509,7 +509,8 @@ template <class R> __device__ __forceinline__ UparEnv<R> upar_env(R x, R a, R la
   e.u02 = u0 * u0;
   // float: one uniform picks the piece and, rescaled within it, the angle
   // (the same distribution with two uniforms per round, so that an event
-  // with one round fits in two Philox blocks); double: three per round.
+  // whose draw ends by its second round fits in two Philox blocks); double:
+  // three per round.
   // The scales (th0 + pi/2)/p1 and (pi/2 - th0)/(1 - p1) are D and D/e0
   // (1 - p1 = e0 (pi/2 - th0)/D); the second is not used when p1 is 1.
   e.s1 = D;
