@@ -102,6 +102,8 @@ struct rmc_ctx {
   double box_cm = 0.0;
   int64_t n_nodes = 0;
   DevBuf nodes;
+  DevBuf top;              // level-top_level cell table (empty: none)
+  int top_level = 0;
   // lines
   bool has_lines = false;
   int n_lines = 0;
@@ -397,6 +399,8 @@ void make_problem(rmc_ctx *c, int64_t first, int64_t n, uint64_t seed, ProblemK 
   pb.nodes = c->nodes.as<int32_t>();
   pb.leaves = c->leaves.p;
   pb.L = c->L;
+  pb.top = c->top_level > 0 ? c->top.as<int32_t>() : nullptr;
+  pb.top_level = c->top_level;
   pb.n_lines = c->n_lines;
   const LineQ q0 = line_q(c->lines[0], c->T_ref);
   pb.b_ref = q0.vth / C_LIGHT;
@@ -599,7 +603,7 @@ void rmc_destroy(rmc_ctx *c) {
   else (void)hipDeviceSynchronize();
   if (c->s_graph) (void)hipGraphExecDestroy(c->s_graph);
   if (c->s_graph2) (void)hipGraphExecDestroy(c->s_graph2);
-  DevBuf *bufs[] = {&c->nodes, &c->leaves, &c->spos, &c->sdir, &c->sx, &c->o_status, &c->o_x, &c->o_k,
+  DevBuf *bufs[] = {&c->nodes, &c->top, &c->leaves, &c->spos, &c->sdir, &c->sx, &c->o_status, &c->o_x, &c->o_k,
                     &c->o_pos, &c->o_nscat, &c->o_path, &c->d_stats, &c->d_next, &c->d_prob, &c->d_starts,
                     &c->tmp1, &c->tmp2, &c->tmp3, &c->tmp4, &c->tmp5, &c->tmp6, &c->b_probs, &c->b_starts,
                     &c->slots, &c->d_slice, &c->pq_ctl, &c->pq_jobs, &c->pq_counts, &c->tp_leaf,
@@ -737,6 +741,38 @@ rmc_status rmc_set_core_skip(rmc_ctx *c, double tau_skip, double frac) {
   return RMC_OK;
 }
 
+// Table of the level-T cells, T = min(L, TOP_LEVEL), from which point
+// location starts: each entry is the node at level T above the cell, or the
+// leaf (of level <= T) covering it, as -(leaf | level << TOP_LEVEL_SHIFT) - 1.
+// None (T = 0) for a single-leaf mesh or when leaf indices do not fit below
+// the level bits.
+static void build_top(const std::vector<int32_t> &nodes, int L, int64_t n_leaves, std::vector<int32_t> &top, int &T) {
+  top.clear();
+  T = 0;
+  if (L == 0 || n_leaves >= ((int64_t)1 << TOP_LEVEL_SHIFT)) return;
+  T = std::min(L, TOP_LEVEL);
+  const int side = 1 << T;
+  top.assign((size_t)side * side * side, 0);
+  for (int k = 0; k < side; ++k)
+    for (int j = 0; j < side; ++j)
+      for (int i = 0; i < side; ++i) {
+        int node = 0, e = 0;
+        bool leaf = false;
+        for (int lev = 0; lev < T; ++lev) {
+          const int sh = T - lev - 1;
+          const int oct = ((i >> sh) & 1) | (((j >> sh) & 1) << 1) | (((k >> sh) & 1) << 2);
+          const int32_t ch = nodes[(size_t)node * 8 + oct];
+          if (ch < 0) {
+            e = -((((-ch) - 1) | ((lev + 1) << TOP_LEVEL_SHIFT)) + 1);
+            leaf = true;
+            break;
+          }
+          node = ch;
+        }
+        top[((size_t)k * side + j) * side + i] = leaf ? e : node;
+      }
+}
+
 rmc_status rmc_set_mesh(rmc_ctx *c, int64_t n, const int8_t *level, const int32_t *ijk, double box_cm) {
   rmc_status r = enter(c);
   if (r) return r;
@@ -748,6 +784,14 @@ rmc_status rmc_set_mesh(rmc_ctx *c, int64_t n, const int8_t *level, const int32_
   if (r) return fail(c, r, "%s", msg.c_str());
   HIPCHK(c, c->nodes.ensure(std::max<size_t>(nodes.size() * 4, 32)));
   if (!nodes.empty()) HIPCHK(c, hipMemcpy(c->nodes.p, nodes.data(), nodes.size() * 4, hipMemcpyHostToDevice));
+  std::vector<int32_t> top;
+  int T = 0;
+  build_top(nodes, L, n, top, T);
+  if (!top.empty()) {
+    HIPCHK(c, c->top.ensure(top.size() * 4));
+    HIPCHK(c, hipMemcpy(c->top.p, top.data(), top.size() * 4, hipMemcpyHostToDevice));
+  }
+  c->top_level = T;
   HIPCHK(c, c->m_lv.ensure((size_t)n));
   HIPCHK(c, c->m_ijk.ensure((size_t)n * 12));
   HIPCHK(c, hipMemcpy(c->m_lv.p, level, (size_t)n, hipMemcpyHostToDevice));
@@ -1395,6 +1439,8 @@ rmc_status rmc_trace_cells(rmc_ctx *c, int64_t n, const double *orig, const doub
   std::memset(&pb, 0, sizeof pb);
   pb.nodes = c->nodes.as<int32_t>();
   pb.L = c->L;
+  pb.top = c->top_level > 0 ? c->top.as<int32_t>() : nullptr;
+  pb.top_level = c->top_level;
   pb.domain = c->domain;
   for (int d = 0; d < 4; ++d) pb.dom[d] = c->dom[d];
   const double *o = orig, *k = dir;

@@ -22,6 +22,10 @@
 namespace rmc {
 
 constexpr int MAX_LEVEL = 16;
+// Level of the table of cells that point location starts from, and where a
+// table entry for a leaf keeps the leaf's level (the leaf index below it)
+constexpr int TOP_LEVEL = 6;
+constexpr int TOP_LEVEL_SHIFT = 27;
 constexpr int MAX_LINES = 4;
 constexpr int MAX_OBS = 4;
 constexpr int LEAF_STRIDE = 8;   // values per leaf record (6 used, padded)
@@ -131,6 +135,11 @@ struct ProblemK {
   const int32_t *nodes;     // [n_nodes][8]: >=0 child node, <0: -(leaf+1)
   const void *leaves;       // [n_leaves][LEAF_STRIDE] float or double
   int L;                    // deepest leaf level
+  // the cells of level top_level (z-major, x fastest): >= 0 the node there,
+  // < 0 -(leaf | level << TOP_LEVEL_SHIFT) - 1 for the leaf (of level
+  // <= top_level) covering it; null: every descent starts at the root
+  const int32_t *top;
+  int top_level;
   int n_lines;
   LineK lines[MAX_LINES];
   double b_ref;             // v_th(T_ref, line 0) / c
@@ -826,15 +835,58 @@ __device__ __forceinline__ void descend(const int32_t *__restrict__ nodes, int L
   }
 }
 
+// Descend to the leaf holding X from its ancestor at level `from` (0: the
+// root).  Above the level-T table the start is X's entry in the table:
+// either the leaf covering X's level-T cell (a leaf of level <= T) or the
+// node there; below it, the ancestor recorded in the LDS stack.  With a
+// table the stack holds the nodes of levels T and deeper on the way to the
+// current leaf, and levels below T are never read (a move that leaves the
+// level-T cell starts from the table again).
+__device__ __forceinline__ void descend_from(const int32_t *__restrict__ nodes, const int32_t *__restrict__ top,
+                                             int T, int L, int from, const int X[3], int *stack, int stride,
+                                             Cell &c) {
+  int node = 0, level = 0;
+  if (top != nullptr && from < T) {
+    const int sh = L - T;
+    const int e = top[((X[2] >> sh) << (2 * T)) | ((X[1] >> sh) << T) | (X[0] >> sh)];
+    if (e < 0) {
+      const int v = -e - 1;
+      c.leaf = v & ((1 << TOP_LEVEL_SHIFT) - 1);
+      c.level = v >> TOP_LEVEL_SHIFT;
+      const int clr = ~((1 << (L - c.level)) - 1);
+      c.ox = X[0] & clr; c.oy = X[1] & clr; c.oz = X[2] & clr;
+      return;
+    }
+    node = e;
+    level = T;
+  } else if (from > 0) {
+    node = stack[from * stride];
+    level = from;
+  }
+  descend(nodes, L, node, level, X, stack, stride, c);
+}
+
+// The leaf holding X.
+__device__ __forceinline__ void locate(const int32_t *__restrict__ nodes, const int32_t *__restrict__ top, int T,
+                                       int L, const int X[3], int *stack, int stride, Cell &c) {
+  descend_from(nodes, top, T, L, 0, X, stack, stride, c);
+}
+
 // Move to the leaf holding X after leaving cell c: restart the descent at
-// the deepest common ancestor of c and X, read from the LDS stack.
-__device__ __forceinline__ void relocate(const int32_t *__restrict__ nodes, int L, const int X[3],
-                                         int *stack, int stride, Cell &c) {
+// the deepest common ancestor of c and X.
+__device__ __forceinline__ void relocate(const int32_t *__restrict__ nodes, const int32_t *__restrict__ top, int T,
+                                         int L, const int X[3], int *stack, int stride, Cell &c) {
   const unsigned diff = (unsigned)((X[0] ^ c.ox) | (X[1] ^ c.oy) | (X[2] ^ c.oz));
   if (diff == 0u) return;
   const int b = 31 - __builtin_clz(diff);
-  const int la = L - 1 - b;   // level of the common ancestor node
-  descend(nodes, L, stack[la * stride], la, X, stack, stride, c);
+  descend_from(nodes, top, T, L, L - 1 - b, X, stack, stride, c);   // from the common ancestor's level
+}
+
+__device__ __forceinline__ void locate(const ProblemK &pb, const int X[3], int *stack, int stride, Cell &c) {
+  locate(pb.nodes, pb.top, pb.top_level, pb.L, X, stack, stride, c);
+}
+__device__ __forceinline__ void relocate(const ProblemK &pb, const int X[3], int *stack, int stride, Cell &c) {
+  relocate(pb.nodes, pb.top, pb.top_level, pb.L, X, stack, stride, c);
 }
 
 #pragma clang fp contract(fast)

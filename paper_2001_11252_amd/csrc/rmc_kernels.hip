@@ -101,7 +101,7 @@ __device__ double ray_walk(const ProblemK &pb, double p[3], const double k[3], d
       for (int l = 0; l < c.level; ++l) stk[l * stride] = sc->stk[l * stride];
     }
     first = false;
-    relocate(pb.nodes, pb.L, X, stk, stride, c);
+    relocate(pb, X, stk, stride, c);
   }
   return tau;
 }
@@ -120,7 +120,7 @@ __device__ double ray_tau(const ProblemK &pb, const double p0[3], const double k
   } else {
     int X[3];
     if (!int_coords(pb.L, p, k, X)) return 0.0;
-    descend(pb.nodes, pb.L, 0, 0, X, stk, stride, c);
+    locate(pb, X, stk, stride, c);
   }
   return ray_walk<R, NL>(pb, p, k, x_ext, 0.0, 0u, tau_cut, stk, stride, ncross, c, sc, reuse, kinv);
 }
@@ -853,7 +853,7 @@ __global__ void __launch_bounds__(256)
       load_slot<R>(q, s, &prob);
       const ProblemK &pb = probs[BATCH ? prob : 0];
       const int X[3] = {s.c.ox, s.c.oy, s.c.oz};
-      descend(pb.nodes, pb.L, 0, 0, X, stk, stride, s.c);
+      locate(pb, X, stk, stride, s.c);
       s.lf = load_leaf<R>(pb.leaves, s.c.leaf);
       active = true;
       z = s;
@@ -891,7 +891,7 @@ __global__ void __launch_bounds__(256)
             z.cnt = LaneCount{0, 0, 0, 0, 0};
             int X[3];
             if (int_coords(pb.L, s.p, s.kd, X)) {
-              descend(pb.nodes, pb.L, 0, 0, X, stk, stride, s.c);
+              locate(pb, X, stk, stride, s.c);
               s.lf = load_leaf<R>(pb.leaves, s.c.leaf);
               active = true;
             } else {
@@ -962,7 +962,7 @@ __global__ void __launch_bounds__(256)
         if (!int_coords(pb.L, s.p, kd, X)) {
           st = ST_ESCAPED;
         } else {
-          relocate(pb.nodes, pb.L, X, stk, stride, s.c);
+          relocate(pb, X, stk, stride, s.c);
           s.lf = load_leaf<R>(pb.leaves, s.c.leaf);
         }
       }
@@ -1138,7 +1138,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DrainW
         int X[3];
         if (binned) {
           if (steps < MAX_CROSS && int_coords(pb.L, p, k, X)) {
-            descend(pb.nodes, pb.L, 0, 0, X, stk, stride, c);
+            locate(pb, X, stk, stride, c);
             active = true;
           } else if (tau < cut) {
             atomic_add_real((R *)ob.cube + elem, weight * M<R>::exp((R)(-tau)));
@@ -1182,7 +1182,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DrainW
         if (!int_coords(pb.L, p, k, X)) {
           done = true;
         } else {
-          relocate(pb.nodes, pb.L, X, stk, stride, c);
+          relocate(pb, X, stk, stride, c);
           if (++steps >= MAX_CROSS) done = true;
         }
       }
@@ -1243,7 +1243,7 @@ __global__ void k_trace(ProblemK pb, int64_t n, const double *__restrict__ orig,
   int cnt = 0;
   if (int_coords(pb.L, p, k, X)) {
     Cell c;
-    descend(pb.nodes, pb.L, 0, 0, X, stk, blockDim.x, c);
+    locate(pb, X, stk, blockDim.x, c);
     while (cnt < max_cells) {
       double face[3], lo[3], hi[3];
       int em;
@@ -1262,7 +1262,7 @@ __global__ void k_trace(ProblemK pb, int64_t n, const double *__restrict__ orig,
       p[0] = pn[0]; p[1] = pn[1]; p[2] = pn[2];
       wrap_slab(pb.domain, p, k);
       if (!int_coords(pb.L, p, k, X)) break;
-      relocate(pb.nodes, pb.L, X, stk, blockDim.x, c);
+      relocate(pb, X, stk, blockDim.x, c);
     }
   }
   n_out[r] = cnt;
@@ -1406,7 +1406,7 @@ __global__ void __launch_bounds__(256) k_image_bwd(ProblemK pb, int obs, int64_t
       p[0] = p0[0]; p[1] = p0[1]; p[2] = p0[2];
       int X[3];
       if (int_coords(pb.L, p, k, X)) {
-        descend(pb.nodes, pb.L, 0, 0, X, stk, blockDim.x, c);
+        locate(pb, X, stk, blockDim.x, c);
         walking = true;
       }
     }
@@ -1439,7 +1439,7 @@ __global__ void __launch_bounds__(256) k_image_bwd(ProblemK pb, int obs, int64_t
         if (!int_coords(pb.L, p, k, X)) {
           walking = false;
         } else {
-          relocate(pb.nodes, pb.L, X, stk, blockDim.x, c);
+          relocate(pb, X, stk, blockDim.x, c);
           if (++steps >= MAX_CROSS) walking = false;
         }
       }
@@ -1487,7 +1487,7 @@ __global__ void __launch_bounds__(256) k_image_fwd_tape(ProblemK pb, int obs, in
     xr = x_ext[r];
     int X[3];
     if (pix >= 0 && int_coords(pb.L, p, k, X)) {
-      descend(pb.nodes, pb.L, 0, 0, X, stk, blockDim.x, c);
+      locate(pb, X, stk, blockDim.x, c);
       walking = true;
     }
   }
@@ -1533,7 +1533,7 @@ __global__ void __launch_bounds__(256) k_image_fwd_tape(ProblemK pb, int obs, in
         if (!int_coords(pb.L, p, k, X) || nc >= MAX_CROSS) {
           walking = false;
         } else {
-          relocate(pb.nodes, pb.L, X, stk, blockDim.x, c);
+          relocate(pb, X, stk, blockDim.x, c);
         }
       }
     }
