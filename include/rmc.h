@@ -385,9 +385,10 @@ rmc_status rmc_batch_begin(rmc_ctx *const *problems, int n_problems, const uint6
 
 /* Pick the transport launch shape for a batch by measurement: every
  * candidate (threads per block x idle lanes a wave gathers before refilling
- * x loop iterations per launch) runs one untimed launch of this batch, then
- * `trial_slices` timed ones (their results are discarded), and the one with
- * the most scatterings plus
+ * x loop iterations per launch) runs the same stretch of this batch: 8192
+ * loop iterations per lane untimed, then `trial_slices` windows of 8192
+ * timed (their results are discarded; each launch timed whole,
+ * synchronisation included), and the one with the most scatterings plus
  * ray-cell crossings per second is kept as the options of problems[0] for
  * later rmc_batch_run calls.  best[3] (may be NULL) receives the chosen
  * {block, refill, slice_iters}. */

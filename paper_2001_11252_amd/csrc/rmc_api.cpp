@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -1875,19 +1876,28 @@ rmc_status autotune_trials(rmc_ctx *const *P, int np, const uint64_t *seeds, con
         c0->slice_iters = sl;
         r = batch_open(P, np, seeds, npk);
         if (r) return r;
-        // the stream's first launch (lanes starting their first packets) is
-        // left out, so that shapes are ranked in the state a run spends its
-        // time in
+        // every shape runs the same loop iterations per lane: an untimed
+        // start (lanes starting their first packets), then `trials` windows
+        // of 8192 iterations, each step timed whole (launches,
+        // synchronisation and counters), so that shapes are ranked on the
+        // same stretch of the run with what a shorter slice costs per unit
+        // of work beyond its kernel times
+        constexpr int64_t WINDOW = 8192;
         double work = 0.0, ms = 0.0;
-        for (int t = 0; t <= trials; ++t) {
+        int64_t done = 0;
+        const int64_t start = WINDOW, end = WINDOW * (1 + (int64_t)trials);
+        while (done < end) {
           rmc_run_stats st;
           int64_t rem = 0;
+          const auto t0 = std::chrono::steady_clock::now();
           r = stream_step(c0, &st, &rem);
           if (r) return r;
-          if (t > 0 || rem == 0) {
+          const double wall = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+          if (done >= start || rem == 0) {
             work += (double)st.scatterings + (double)st.crossings + (double)st.peel_crossings;
-            ms += st.kernel_ms + st.peel_pass_ms;
+            ms += wall;
           }
+          done += sl;
           if (rem == 0) break;
         }
         c0->s_open = false;
