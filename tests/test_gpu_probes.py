@@ -56,6 +56,10 @@ MESHES = {
     "graded": lambda: W.refined_mesh(1, 5, (lambda r: lambda lev, lo, hi: r.random(len(lo)) < 0.3)(
         np.random.default_rng(11))),
     "c2": W.c2_mesh,
+    # levels 2-10 about a small sphere's surface: leaves coarser than the
+    # level-6 cell table and up to four levels below it
+    "deep": lambda: W.refined_mesh(2, 10, lambda lev, lo, hi: (lambda nf: (nf[0] <= 0.06) & (nf[1] >= 0.06))(
+        W._near_far(np.array([0.43, 0.56, 0.52]), lo, hi))),
 }
 DOMAINS = {
     "box": W.Domain(W.DOM_BOX, (0, 0, 0, 0)),
