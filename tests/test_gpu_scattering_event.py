@@ -16,14 +16,16 @@ from tests.test_oracle_scattering_event import (C, H_PL, J_MU, _cdf_core, _cdf_w
 
 pytestmark = pytest.mark.gpu
 
+J_PHI = 2   # slot of the azimuth uniform of an event (the oracle's stream layout)
 
-def _gpu_first_scatterings(orc, prec, x_in, T, n, seed, phase, recoil):
+
+def _gpu_first_scatterings(orc, prec, x_in, T, n, seed, phase, recoil, direction=None):
     from paper_2001_11252_amd import rmc
     s0 = lambda ln, TT: orc.line_quantities(ln, TT)["sigma0"]
     line = replace(W.LYA, phase=phase, recoil=int(recoil))
     pb = W.static_sphere(s0, 1e10, T, n, level=0, line=line)
     rng = np.random.default_rng(seed)
-    d = rng.standard_normal((n, 3))
+    d = rng.standard_normal((n, 3)) if direction is None else np.tile(np.asarray(direction, float), (n, 1))
     d /= np.linalg.norm(d, axis=1)[:, None]
     if prec == "fp32":
         # float-representable directions, renormalised in double on the device
@@ -91,3 +93,43 @@ def test_gpu_lya_core_wing_switch(orc, prec, T, x_in):
     p = _core_probability(x_in, a, vth / C)
     f = core.mean()
     assert abs(f - p) < 3 * np.sqrt(p * (1 - p) / core.size) + 1e-5, (f, p)
+
+
+def _float_phi_uniform(orc, seed, pid, event):
+    # the float path's azimuth draw: 23 bits from the low 9 bits of words 0,
+    # 1 and 2 of Philox block 1 of the event (the top 23 of those 27)
+    ctr = [pid & 0xFFFFFFFF, pid >> 32, event, 1]
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    w = [int(v) for v in orc.philox(ctr, key)]
+    m = ((w[0] & 511) << 14) | ((w[1] & 511) << 5) | ((w[2] & 511) >> 4)
+    return (2 * m + 1) * 2.0 ** -24
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_gpu_azimuth_is_the_event_draw(orc, prec):
+    """The new direction's azimuth about k_in (Sect. 3.2.1: isotropic in the
+    plane perpendicular to k_in) is the event's azimuth draw: for k_in = +z
+    the perpendicular pair is e1 = +y, e2 = k_in x e1 = -x, so
+    k_out = (-sin theta sin 2 pi r, sin theta cos 2 pi r, cos theta) and
+    r = atan2(-k_x, k_y) / 2 pi (mod 1).  Isotropic phase, so the cosine is
+    2 r_mu - 1 with the event's cosine draw."""
+    n, seed = 20000, 71
+    _, k1, _ = _gpu_first_scatterings(orc, prec, 0.0, 1e4, n, seed, W.PHASE_ISO, False, direction=(0.0, 0.0, 1.0))
+    if prec == "fp64":
+        r_phi = np.array([orc.uniform(seed, i, 1, J_PHI) for i in range(n)])
+        r_mu = np.array([orc.uniform(seed, i, 1, J_MU) for i in range(n)])
+        tol_mu, tol_phi = 1e-14, 1e-12
+    else:
+        r_phi = np.array([_float_phi_uniform(orc, seed, i, 1) for i in range(n)])
+        r_mu = np.array([_float_mu_uniform(orc, seed, i, 1) for i in range(n)])
+        # hardware sine and cosine in turns and float products: a few 1e-7
+        tol_mu, tol_phi = 1e-6, 2e-5
+    assert np.max(np.abs(k1[:, 2] - (2 * r_mu - 1))) < tol_mu
+    st = np.hypot(k1[:, 0], k1[:, 1])
+    ok = st > 1e-3        # the azimuth of a direction near +-z is ill-conditioned
+    assert ok.mean() > 0.99
+    r = np.mod(np.arctan2(-k1[ok, 0], k1[ok, 1]) / (2 * np.pi), 1.0)
+    d = np.abs(r - r_phi[ok])
+    d = np.minimum(d, 1.0 - d)
+    assert np.max(d * st[ok]) < tol_phi, np.max(d * st[ok])
+
