@@ -173,6 +173,43 @@ def test_forward_path_precision_in_one_cell(rmc, orc, prec):
         assert inside.mean() >= frac, (tau0, np.percentile(np.abs(rel), 98))
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_forward_path_precision_on_a_256_cubed_mesh(rmc, orc, prec):
+    # the paper's second error-budget series (Sect. 4.5;
+    # tests/golden/path_precision_mesh): the same sphere on a regular mesh of
+    # 256^3 cells.  Positions here stay in global coordinates (no cell-frame
+    # conversion at crossings, the cause the paper gives for its offset), so
+    # the bound read from the paper is on the size of the error: the
+    # crossings' part, max(|lower|, upper) = 2e-13, plus the scatterings'
+    # part, the one-cell series' bound at the same tau0
+    # (tests/golden/path_precision), for 98% of the packets; and the median
+    # no larger than the paper's
+    from tests.analytic import golden
+    one_cell = {row[0]: max(abs(row[2]), abs(row[3])) for row in golden("path_precision")}
+    n = 2000
+    pb = W.static_sphere(s0(orc), 1.0, 1e4, n, level=8)
+    c = rmc.Context.from_problem(pb, prec, observers=False)
+    c.set_option(rmc.OPT_FORWARD_ONLY, 1)
+    sigma0 = s0(orc)(W.LYA, 1e4)
+    nl = pb.mesh.n
+    for tau0, frac, lo, hi, med in golden("path_precision_mesh"):
+        n_hi = tau0 / (sigma0 * 0.5 * pb.mesh.box_cm)
+        c.set_gas(np.full(nl, n_hi), np.full(nl, 1e4), np.zeros(3 * nl), np.zeros(nl))
+        st = c.run(6, 0, n)
+        check_conservation(st, n)
+        o = c.get_packets()
+        assert np.all(o["status"] == rmc.ST_ESCAPED)
+        assert st["crossings"] / n > 100       # a radius crosses 128 cells and more
+        if tau0 > 1e5:
+            assert o["n_scat"].mean() > 0.9 * tau0
+        rel = o["path"] / 0.5 - 1
+        bound = max(abs(lo), abs(hi)) + one_cell[tau0]
+        print(prec, tau0, "median", np.median(rel), "98% |rel|", np.percentile(np.abs(rel), 98))
+        assert (np.abs(rel) <= bound).mean() >= frac, (tau0, np.percentile(np.abs(rel), 98))
+        assert abs(np.median(rel)) <= med, (tau0, np.median(rel))
+    c.close()
+
+
 def test_fp32_slab_and_sphere_spectra_match_the_analytic_solutions(rmc, orc):
     # T = 10 K, tau0 = 1e6 (a tau0 = 1.5e4), isotropic, no recoil: the
     # Neufeld slab and Dijkstra sphere spectra the paper compares with

@@ -123,6 +123,26 @@ def test_forward_only_path_budget(orc, sigma0_oracle):
         assert np.percentile(np.abs(rel), 98) <= 4 * EPS * np.percentile(steps, 98), (level, tau0)
 
 
+def test_forward_only_path_budget_on_a_256_cubed_mesh(orc, sigma0_oracle):
+    # Sect. 4.5, second series (tests/golden/path_precision_mesh): the sphere
+    # on a regular 256^3 mesh.  The oracle keeps positions in global
+    # coordinates, so the paper's bound is read on the size of the error
+    # (crossings' part max(|lower|, upper) plus the one-cell series' bound
+    # at the same tau0) and on the median; tau0 = 1e6 is left to the GPU test
+    n = 1000
+    one_cell = {row[0]: max(abs(row[2]), abs(row[3])) for row in golden("path_precision")}
+    for tau0, frac, lo, hi, med in golden("path_precision_mesh"):
+        if tau0 > 100.0:
+            continue
+        pb = W.static_sphere(sigma0_oracle, tau0, 1e4, n, level=8)
+        r = orc.run(pb, 22, threads=8, forward_only=True)
+        assert np.all(r["status"] == 1)
+        assert r["stats"]["crossings"] / n > 100
+        rel = r["path"] / 0.5 - 1
+        assert (np.abs(rel) <= max(abs(lo), abs(hi)) + one_cell[tau0]).mean() >= frac, tau0
+        assert abs(np.median(rel)) <= med, (tau0, np.median(rel))
+
+
 def test_weight_conservation_and_peel_normalisation(orc, sigma0_oracle):
     # n_HI = kappa_d = 0: each emission sends exactly 1/(4 pi) per sr
     pb = W.static_sphere(sigma0_oracle, 1e4, 1e4, 500, level=3)
