@@ -128,7 +128,7 @@ def parse():
     ap.add_argument("--only", choices=["fp32", "fp64", "both"], default="both")
     ap.add_argument("--copy-gib", type=float, default=1.0, help="size of the copy used to measure HBM bandwidth")
     ap.add_argument("--workload", choices=["dusty_sphere", "shell", "batch", "adjoint", "core_skip",
-                                           "voigt_accuracy", "upar_cost", "c1_slab", "multi_species"],
+                                           "voigt_accuracy", "upar_cost", "c1_slab", "multi_species", "mesh_overhead"],
                     default="dusty_sphere",
                     help="dusty_sphere: the headline; the others: the other configurations")
     ap.add_argument("--skip-packets", type=int, default=4_000_000, help="core_skip: packets per complete run")
@@ -497,6 +497,68 @@ def bench_c1_slab(a, rmc, W):
                  cpu_baseline={"value": ref["stats"]["scatterings"] / dt, "unit": "scatterings/s", "cores": cores,
                                "kind": "oracle", "sample": f"the same {n} packets, complete: "
                                                            f"{ref['stats']['scatterings']} scatterings in {dt:.1f} s"})
+
+
+def bench_mesh_overhead(a, rmc, W):
+    """The cost of the mesh (the paper's timing beside its error budget,
+    Sect. 4.5): packets from the centre of a uniform sphere whose
+    scatterings keep their direction, the sphere in one cell and on a
+    256^3 mesh, at tau0 = 1e-10 (no scattering: the packet only crosses
+    cells) and 1e4 (ten thousand scatterings per packet), 1e6 packets (a
+    full GPU), both precisions.  Each step is a complete run; the line's
+    value is the FP32 crossings/s on the mesh at tau0 = 1e-10, a lower
+    bound on the traversal rate (the run's per-packet costs included)."""
+    import numpy as np
+    import torch
+    from oracle import oracle as O
+    cases = {}
+    sigma0 = rmc.sigma0(W.LYA, 1e4)
+    for level in (0, 8):
+        pb = W.static_sphere(rmc.sigma0, 1.0, 1e4, 1_000_000, level=level)
+        nl, R = pb.mesh.n, 0.5 * pb.mesh.box_cm
+        for prec in ("fp32", "fp64"):
+            ctx = rmc.Context.from_problem(pb, prec, observers=False)
+            ctx.set_stream(torch.cuda.current_stream())
+            ctx.set_option(rmc.OPT_FORWARD_ONLY, 1)
+            for tau0, n in ((1e-10, 1_000_000), (1e4, 1_000_000)):
+                ctx.set_gas(np.full(nl, tau0 / (sigma0 * R)), np.full(nl, 1e4), np.zeros(3 * nl), np.zeros(nl))
+                ctx.run(1, 0, min(n, 20_000))
+                torch.cuda.synchronize()
+                t0, tot = time.perf_counter(), {}
+                for s in range(a.steps):
+                    st = ctx.run(2 + s, 0, n)
+                    for k, v in st.items():
+                        tot[k] = tot.get(k, 0) + v
+                torch.cuda.synchronize()
+                wall = (time.perf_counter() - t0) / a.steps
+                key = f"{prec}_level{level}_tau{tau0:g}"
+                cases[key] = {"packets": n, "ms_per_run": 1e3 * wall, "us_per_packet": 1e6 * wall / n,
+                              "scatterings_per_s": tot["scatterings"] / a.steps / wall,
+                              "crossings_per_s": tot["crossings"] / a.steps / wall,
+                              "crossings_per_packet": tot["crossings"] / a.steps / n}
+                print(f"# mesh_overhead {key}: {cases[key]}", file=sys.stderr, flush=True)
+            ctx.close()
+    ratio = {f"{p}_tau{t:g}": cases[f"{p}_level8_tau{t:g}"]["us_per_packet"] / cases[f"{p}_level0_tau{t:g}"]["us_per_packet"]
+             for p in ("fp32", "fp64") for t in (1e-10, 1e4)}
+    # the oracle on the same mesh, no scattering: crossings/s on the host
+    # cores, its set-up (tree build) subtracted with a run of 1000 packets
+    cores = host_cores()[0]
+    runs = []
+    for m in (1000, 400_000):
+        pbo = W.static_sphere(rmc.sigma0, 1e-10, 1e4, m, level=8)
+        t1 = time.perf_counter()
+        r = O.run(pbo, 3, threads=cores, forward_only=True, with_cubes=False)
+        runs.append((time.perf_counter() - t1, r["stats"]["crossings"]))
+    dt, ncr = runs[1][0] - runs[0][0], runs[1][1] - runs[0][1]
+    main = cases["fp32_level8_tau1e-10"]
+    return _line("ray-cell crossings/s (1 GPU), FP32, packets crossing a 256^3 mesh without scattering",
+                 main["crossings_per_s"], "crossings/s", a.steps, 1, main["ms_per_run"], "f32",
+                 {"workload": "uniform_sphere_256cubed_forward_only", "parallelism": "none"}, None,
+                 cases=cases, mesh_over_one_cell_time_per_packet=ratio,
+                 cpu_baseline={"value": ncr / dt, "unit": "crossings/s", "cores": cores,
+                               "kind": "oracle", "sample": f"399000 packets of the same mesh at tau0 = 1e-10 "
+                                                           f"(a 400000-packet run less a 1000-packet one): "
+                                                           f"{ncr} crossings in {dt:.2f} s"})
 
 
 def bench_upar_cost(a, rmc, W):
@@ -896,7 +958,7 @@ def main():
         fn = {"shell": bench_shell, "batch": bench_batch, "adjoint": bench_adjoint,
               "core_skip": bench_core_skip, "voigt_accuracy": bench_voigt_accuracy,
               "upar_cost": bench_upar_cost, "c1_slab": bench_c1_slab,
-              "multi_species": bench_multi_species}[a.workload]
+              "multi_species": bench_multi_species, "mesh_overhead": bench_mesh_overhead}[a.workload]
         print(json.dumps(fn(a, rmc, W)), flush=True)
         return
     steps, warm, P = a.steps, a.warmup, a.packets
