@@ -390,7 +390,15 @@ template <class R> __device__ __forceinline__ void set_geom_dir(Lane<R> &s) {
 // counts in the problem's totals, and, in the launch's slice counters, the
 // packet and its status (its dropped peel-off deposits are reported in the
 // slice where it ends).
-template <class R>
+// Record a finished packet and count it.  The counts of the lanes that
+// finish here together are summed over the wave first, one atomic per
+// counter and wave: packets that end at once (short walks, a whole wave of
+// them per loop pass) would otherwise queue on the same few addresses, one
+// atomic per packet and counter.  Single-problem launches publish the
+// packets' work (scatterings, crossings, peel-off rays) with the launch's
+// slice totals at the end of the kernel; in batches, whose lanes change
+// problem, each packet adds its own to its problem's totals here.
+template <class R, bool BATCH>
 __device__ void finish(const ProblemK &pb, Lane<R> &s, int status, unsigned long long *slice) {
   const int64_t i = s.pid - pb.first;
   pb.status[i] = status;
@@ -404,18 +412,35 @@ __device__ void finish(const ProblemK &pb, Lane<R> &s, int status, unsigned long
   pb.nscat[i] = s.nscat;
   pb.path_out[i] = s.path;
   unsigned long long *st = pb.stats;
-  atomicAdd(st + S_EMITTED, 1ull);
-  atomicAdd(st + (status == ST_ESCAPED ? S_ESCAPED : (status == ST_ABSORBED ? S_ABSORBED : S_STUCK)), 1ull);
-  atomicAdd(st + S_SCAT, (unsigned long long)s.nscat);
-  if (s.cnt.dust_scat) atomicAdd(st + S_DUST_SCAT, (unsigned long long)s.cnt.dust_scat);
-  atomicAdd(st + S_CROSS, (unsigned long long)s.cnt.cross);
-  if (s.cnt.peel_rays) atomicAdd(st + S_PEEL_RAYS, (unsigned long long)s.cnt.peel_rays);
-  if (s.cnt.peel_cross) atomicAdd(st + S_PEEL_CROSS, (unsigned long long)s.cnt.peel_cross);
-  if (s.cnt.peel_drop) atomicAdd(st + S_PEEL_DROPPED, (unsigned long long)s.cnt.peel_drop);
   const int sk = status == ST_ESCAPED ? S_ESCAPED : (status == ST_ABSORBED ? S_ABSORBED : S_STUCK);
-  atomicAdd(slice + S_EMITTED, 1ull);
-  atomicAdd(slice + sk, 1ull);
-  if (s.cnt.peel_drop) atomicAdd(slice + S_PEEL_DROPPED, (unsigned long long)s.cnt.peel_drop);
+  const unsigned long long m = __ballot(true);
+  const unsigned long long me = __ballot(status == ST_ESCAPED), ma = __ballot(status == ST_ABSORBED);
+  const unsigned long long ms = m & ~(me | ma);
+  if (__lane_id() == __ffsll((long long)m) - 1) {
+    atomicAdd(slice + S_EMITTED, (unsigned long long)__popcll(m));
+    if (me) atomicAdd(slice + S_ESCAPED, (unsigned long long)__popcll(me));
+    if (ma) atomicAdd(slice + S_ABSORBED, (unsigned long long)__popcll(ma));
+    if (ms) atomicAdd(slice + S_STUCK, (unsigned long long)__popcll(ms));
+    if (!BATCH) {
+      atomicAdd(st + S_EMITTED, (unsigned long long)__popcll(m));
+      if (me) atomicAdd(st + S_ESCAPED, (unsigned long long)__popcll(me));
+      if (ma) atomicAdd(st + S_ABSORBED, (unsigned long long)__popcll(ma));
+      if (ms) atomicAdd(st + S_STUCK, (unsigned long long)__popcll(ms));
+    }
+  }
+  if (BATCH) {
+    atomicAdd(st + S_EMITTED, 1ull);
+    atomicAdd(st + sk, 1ull);
+    atomicAdd(st + S_SCAT, (unsigned long long)s.nscat);
+    if (s.cnt.dust_scat) atomicAdd(st + S_DUST_SCAT, (unsigned long long)s.cnt.dust_scat);
+    atomicAdd(st + S_CROSS, (unsigned long long)s.cnt.cross);
+    if (s.cnt.peel_rays) atomicAdd(st + S_PEEL_RAYS, (unsigned long long)s.cnt.peel_rays);
+    if (s.cnt.peel_cross) atomicAdd(st + S_PEEL_CROSS, (unsigned long long)s.cnt.peel_cross);
+  }
+  if (s.cnt.peel_drop) {
+    atomicAdd(st + S_PEEL_DROPPED, (unsigned long long)s.cnt.peel_drop);
+    atomicAdd(slice + S_PEEL_DROPPED, (unsigned long long)s.cnt.peel_drop);
+  }
 }
 
 // Emission (Sect. 2): position and frequency from the source list,
@@ -754,8 +779,9 @@ __device__ __forceinline__ void load_slot(const SlotState &q, Lane<R> &s, int *p
   set_geom_dir(s);
 }
 
-// Counters of work done inside one launch (packets that end in it are
-// counted by finish).
+// Counters of work done inside one launch, summed over the wave and
+// published at the kernel's end (the packets that end in it are counted by
+// finish).
 struct SliceCount {
   uint32_t scat, dust, cross, peel_rays, peel_cross;
 };
@@ -896,7 +922,7 @@ __global__ void __launch_bounds__(256)
               active = true;
             } else {
               add_delta(acc, s, z);
-              finish<R>(pb, s, ST_ESCAPED, slice);
+              finish<R, BATCH>(pb, s, ST_ESCAPED, slice);
             }
           }
         }
@@ -969,7 +995,7 @@ __global__ void __launch_bounds__(256)
     }
     if (st != ST_NONE) {
       add_delta(acc, s, z);
-      finish<R>(pb, s, st, slice);
+      finish<R, BATCH>(pb, s, st, slice);
       active = false;
     }
   }
@@ -995,7 +1021,10 @@ __global__ void __launch_bounds__(256)
   for (int j = 0; j < 5; ++j) {
     unsigned long long x = v[j];
     for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off);
-    if (lane == 0 && x) atomicAdd(slice + idx[j], x);
+    if (lane == 0 && x) {
+      atomicAdd(slice + idx[j], x);
+      if (!BATCH) atomicAdd(probs[0].stats + idx[j], x);
+    }
   }
 }
 
